@@ -1,0 +1,34 @@
+"""Plain CPU oracle for alternating cross interpolation (ACI).
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, obviously correct
+reference against which the HIP implementation is checked.  It may be
+imported only by ``tests/``, by ``__graft_entry__.smoke()`` and by the
+``cpu_baseline`` leg of ``bench.py``.  The product library never imports,
+links or calls it, and it shares no code with the HIP path.
+
+Everything is float64 (complex128 for complex inputs), written with NumPy
+and SciPy primitives (matmul, triangular solve) as single steps, following
+the algorithms of Appendix B of the paper in their order:
+
+* ``prrlu``           -- Alg. 2 (LDU with full pivoting, greedy maxvol)
+* ``cross_interpolate``, ``local_update`` -- Algs. 3 and 4
+* ``left_frame``, ``right_frame``         -- Alg. 5 / Eq. (framesrecursive)
+* ``aci``             -- Alg. 1 (initialisation, sweeps, convergence)
+* ``splitmix64``      -- the counter-based generator of the default Y_init
+* ``reference``       -- exact Kronecker-delta product and SVD rounding,
+                         an independent route to the Hadamard product
+
+Parity status of each function is stated in its docstring.
+"""
+
+from .prrlu import prrlu, PrrLU
+from .ci import cross_interpolate, local_update, left_frame, right_frame
+from .aci import aci, ACIResult, apply_op, default_init_ranks
+from .splitmix import splitmix64_stream, default_init
+from . import reference
+
+__all__ = [
+    "prrlu", "PrrLU", "cross_interpolate", "local_update", "left_frame",
+    "right_frame", "aci", "ACIResult", "apply_op", "default_init_ranks",
+    "splitmix64_stream", "default_init", "reference",
+]

@@ -181,3 +181,29 @@ def test_default_init_is_uniform_and_deterministic():
     z = splitmix64_stream(99, flat.size)
     np.testing.assert_array_equal(flat, [(v >> 11) * 2.0 ** -53 * 2 - 1 for v in z])
     assert np.all(flat >= -1) and np.all(flat < 1)
+
+
+def test_output_cores_solve_pivot_systems_at_labels():
+    """For every bond l of the final right-to-left sweep, the pivot matrix
+    P_l = f(x[I_l + J_{l+1}]) and the slice T_{l+1} = f(x[I_l + s + J_{l+2}]),
+    both evaluated by brute force at the returned multi-index labels, satisfy
+    P_l Y_{l+1} = T_{l+1} (Eq. ycicanonical with Y_{l+1} = P_l^{-1} T_{l+1});
+    and Y_1 = T_1 = f(x[s + J_2])."""
+    L = 9
+    x1, x2 = W.random_pair(L=L, chi=4, seeds=(63, 64))
+    res = aci([x1, x2], "product", 1e-10, 10, maxiter=4, seed=65)
+
+    def f_at(pts):
+        pts = np.array(pts)
+        return W.tt_eval(x1, pts) * W.tt_eval(x2, pts)
+
+    Y0 = res.cores[0]
+    T1 = f_at([(s,) + j for s in range(2) for j in res.J[2]]).reshape(Y0.shape)
+    np.testing.assert_allclose(Y0, T1, rtol=1e-12, atol=1e-14)
+    for l in range(1, L):
+        I, J1, J2 = res.I[l], res.J[l + 1], res.J[l + 2]
+        P = f_at([i + j for i in I for j in J1]).reshape(len(I), len(J1))
+        T = f_at([i + (s,) + j for i in I for s in range(2) for j in J2])
+        Yn = res.cores[l].reshape(len(I), -1)
+        np.testing.assert_allclose(P @ Yn, T.reshape(len(I), -1),
+                                   atol=1e-11 * np.abs(T).max())

@@ -1,0 +1,179 @@
+/*
+ * aci.h -- C ABI of the MI355X alternating cross interpolation (ACI) library.
+ *
+ * ACI (M. K. Ritter, "Fast elementwise operations on tensor trains with
+ * alternating cross interpolation") approximates an elementwise function
+ * f(x^1, ..., x^N) of N tensor trains directly as a tensor train y with
+ * ||y - f(x)||_max <= tol (section 2.1, Eq. ydef:maxnorm), by sweeping
+ * two-site local updates (Alg. 1).  Every step of the sweep runs in the
+ * library's own HIP kernels for gfx950.
+ *
+ * Conventions shared by every entry point:
+ *  - All tensors are row-major (C order).  A TT core of site l has shape
+ *    (r_{l-1}, d_l, r_l); r_0 = r_L = 1.
+ *  - Pointers documented as "device" must point to device memory of the
+ *    device that was current when the context was created; "host" pointers
+ *    point to host memory.  The library never takes ownership of caller
+ *    memory and never frees it.
+ *  - All work is ordered on the stream given to aci_ctx_create.  Entry
+ *    points return after the work they enqueue has completed.
+ *  - Every function returns an int status: ACI_OK (0), a positive warning
+ *    or a negative error.  No C++ exception crosses the ABI.  The text of
+ *    the last error is available from aci_last_error().
+ *  - Real data is IEEE binary64 (double).  Complex data is interleaved
+ *    binary64 pairs (re, im), i.e. C99 double complex.
+ */
+#ifndef ACI_H
+#define ACI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define ACI_OK 0
+#define ACI_W_NOT_CONVERGED 1   /* maxiter reached, or error estimate > tol at the rank cap */
+#define ACI_E_INVALID (-1)      /* bad argument: null pointer, shape mismatch, tol < 0, ... */
+#define ACI_E_DTYPE (-2)        /* unsupported dtype / precision combination */
+#define ACI_E_HIP (-3)          /* a HIP runtime call failed (text in aci_last_error) */
+#define ACI_E_NOMEM (-4)        /* device allocation failed, or output buffer too small */
+#define ACI_E_NUMERIC (-5)      /* NaN or Inf met in a two-site tensor */
+#define ACI_E_LIMIT (-6)        /* size beyond the compiled limits (see ACI_MAX_*) */
+#define ACI_E_TIMEOUT (-7)      /* a device-side wait exceeded its spin limit */
+
+/* ---- compiled limits ------------------------------------------------------ */
+#define ACI_MAX_SITES 128       /* L */
+#define ACI_MAX_DIM 4           /* local dimension d_l */
+#define ACI_MAX_RANK 512        /* maxrank (output bond dimension cap) */
+#define ACI_MAX_INPUTS 4        /* N */
+#define ACI_MAX_MATRIX 1024     /* rows and columns of a matricised two-site tensor */
+
+typedef enum { ACI_F64 = 0, ACI_C128 = 1 } aci_dtype;
+
+/* f of Eq. (localupdate), applied elementwise to the N two-site tensors:
+ * PRODUCT: ((x1*x2)*x3)...; SUM: ((x1+x2)+x3)...; ABS2_MUL (N = 1): |x|^2 x. */
+typedef enum { ACI_OP_PRODUCT = 0, ACI_OP_SUM = 1, ACI_OP_ABS2_MUL = 2 } aci_op;
+
+/* Precision of the contractions that form the two-site tensors.  The pivot
+ * search, the Schur updates, the pivot-matrix solve and the error estimate are
+ * always binary64. */
+typedef enum { ACI_PREC_FP64 = 0, ACI_PREC_FP32 = 1, ACI_PREC_BF16X3 = 2 } aci_precision;
+
+typedef struct aci_ctx aci_ctx;
+
+/* A tensor train held in caller device memory (the inputs x^n of section 2.1). */
+typedef struct {
+  int32_t L;                 /* number of sites, 2 <= L <= ACI_MAX_SITES */
+  const int32_t* d;          /* host, L local dimensions */
+  const int32_t* ranks;      /* host, L+1 bond ranks, ranks[0] = ranks[L] = 1 */
+  const void* const* cores;  /* host array of L device pointers; core l is
+                                ranks[l] x d[l] x ranks[l+1], C order */
+} aci_tt;
+
+typedef struct {
+  int32_t maxiter;       /* sweeps (Alg. 1 "maxiter"); <= 0 selects 20 */
+  uint64_t seed;         /* SplitMix64 seed of the default Y_init */
+  const aci_tt* init;    /* Y_init (section 2.6); NULL: random TT with ranks
+                            min_n r^n_l (capped at maxrank), entries uniform on
+                            [-1,1) drawn from SplitMix64(seed) site by site in
+                            C order (two draws re, im per complex entry) */
+  int32_t stop_rule;     /* 0: exclusive (default; never accept |pivot| <= tol
+                            after the first, error = largest remaining
+                            residual); 1: literal Alg. 2 (accept, then stop) */
+  int32_t precision;     /* aci_precision, default ACI_PREC_FP64 */
+  int32_t trace;         /* 1: record the pivots of every local update */
+  int32_t fixed_sweeps;  /* 1: run exactly maxiter sweeps, no early exit */
+} aci_options;
+
+/* Result of aci_elementwise.  Output cores are written compactly, site after
+ * site, into the caller's output buffer: core l starts at element
+ * core_offset[l] and has shape ranks[l] x d_l x ranks[l+1]. */
+typedef struct {
+  int32_t L;
+  int32_t sweeps;                       /* sweeps performed */
+  int32_t converged;                    /* 1 if the convergence test of Alg. 1 passed */
+  int32_t ranks[ACI_MAX_SITES + 1];     /* output bond ranks chi'_l */
+  double eps[ACI_MAX_SITES];            /* eps[l-1]: error estimate of the last
+                                           right-to-left update at bond l */
+  int64_t core_offset[ACI_MAX_SITES];   /* element offsets in the output buffer */
+  int64_t out_elems;                    /* elements written */
+  int32_t init_ranks[ACI_MAX_SITES + 1];/* |J_{l+1}| after the CI-canonical init */
+  double sweep_ms;                      /* device time of all sweeps (hipEvents) */
+  /* trace (options.trace = 1): one record per prrLU call, in call order:
+   * first the L-1 initialisation calls (sites L..2), then 2(L-1) per sweep. */
+  int32_t n_records;
+  int32_t record_stride;                /* = maxrank */
+  int32_t* rec_meta;                    /* host, n_records x 6:
+                                           kind (0 init, 1 L->R, 2 R->L), sweep,
+                                           bond (site for init), rank, m, n */
+  double* rec_eps;                      /* host, n_records */
+  int32_t* rec_rows;                    /* host, n_records x record_stride */
+  int32_t* rec_cols;                    /* host, n_records x record_stride */
+} aci_result;
+
+/* Context: owns the device workspace, bound to the current device and to
+ * `stream` (a hipStream_t; NULL = the null stream). */
+int aci_ctx_create(aci_ctx** ctx, void* stream);
+void aci_ctx_destroy(aci_ctx* ctx);
+const char* aci_last_error(const aci_ctx* ctx);
+
+/* Alg. 1: approximate f(x^1..x^N) as a TT with error estimate <= tol and bond
+ * dimensions <= maxrank.
+ *   inputs     host array of n_inputs TTs (device cores, dtype as given)
+ *   dtype      aci_dtype of the input cores and of the output
+ *   out        device buffer receiving the output cores; out_capacity is its
+ *              size in elements (double or double-complex).  A capacity of
+ *              L * d_max * maxrank^2 always suffices.
+ *   result     host struct filled on return; release with aci_result_free.
+ * Returns ACI_OK, ACI_W_NOT_CONVERGED, or an error. */
+int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype,
+                    int32_t op, double tol, int32_t maxrank, const aci_options* opt,
+                    void* out, int64_t out_capacity, aci_result* result);
+void aci_result_free(aci_result* result);
+
+/* ---- single steps of the local update (section 2.4-2.6, Algs. 2-5) ------- *
+ * These run exactly the kernels aci_elementwise uses, on caller data, for
+ * step-by-step checks.  All matrices are device, row-major, dtype as given. */
+
+/* Environment contractions (Eq. pifromframes, Alg. 5):
+ *   side 0 (left):  A = Lf (c x r0) * X (r0 x d r1)        -> A (c x d r1)
+ *   side 1 (right): B = X (r0 d x r1) * Rf (r1 x c)        -> B (r0 d x c)
+ * Each of the `count` contractions uses its own pointers; dims are shared. */
+int aci_env_contract(aci_ctx* ctx, int32_t dtype, int32_t side, int32_t count,
+                     const void* const* frames, const void* const* cores,
+                     void* const* out, int32_t c, int32_t r0, int32_t d, int32_t r1);
+
+/* Two-site tensor with f applied (Eq. pifromframes, Eq. localupdate):
+ *   M = f(A^1 B^1, ..., A^N B^N),  A^n: m x k[n] (ld k[n]), B^n: k[n] x n (ld n),
+ *   M: m x n with leading dimension ldm >= n. */
+int aci_pi_eval(aci_ctx* ctx, int32_t dtype, int32_t op, int32_t n_inputs,
+                const void* const* A, const void* const* B, const int32_t* k,
+                int32_t m, int32_t n, void* M, int32_t ldm);
+
+/* LDU with full pivoting (Alg. 2) of the m x n matrix M (ld ldm).  The input
+ * is not modified.  Outputs (device): rows[r], cols[r] = pivot row/column ids
+ * in pivot order, *rank (int32), *eps (double).  If Y is not NULL it receives
+ * the r x n matrix U_JJ^{-1} U (Alg. 3, right-interpolative factor), leading
+ * dimension ldy. */
+int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, int32_t ldm,
+              double tol, int32_t maxrank, int32_t stop_rule,
+              int32_t* rows, int32_t* cols, int32_t* rank, double* eps,
+              void* Y, int32_t ldy);
+
+/* Frame update by gathering (Alg. 5, truncation step).  src is h x w with
+ * leading dimension ld_src; idx (device) holds r indices, r read from the
+ * device int *rank:
+ *   side 0: out[k][c] = src[idx[k]][c]   (r x w result, leading dim ld_out)
+ *   side 1: out[i][k] = src[i][idx[k]]   (h x r result, leading dim ld_out) */
+int aci_gather(aci_ctx* ctx, int32_t dtype, int32_t side, const void* src, int32_t h,
+               int32_t w, int32_t ld_src, const int32_t* idx, const int32_t* rank, void* out,
+               int32_t ld_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACI_H */

@@ -150,9 +150,12 @@ def aci(inputs, op, tol, maxrank, maxiter=20, init=None, seed=0,
         g = G[l - 1]
         r0, d, c = g.shape
         M = g.reshape(r0, d * c)
-        lu = prrlu(M, tol, maxrank, rule=rule)
+        lu = prrlu(M, tol, maxrank, rule=rule, log_gaps=log_gaps)
         cols = lu.cols
         J[l] = [(int(q) // c,) + J[l + 1][int(q) % c] for q in cols]
+        trace.append(dict(sweep=0, dir="init", bond=l, rank=lu.rank, eps=lu.eps,
+                          rows=lu.rows.copy(), cols=lu.cols.copy(),
+                          min_gap=min(lu.gaps) if lu.gaps else None, shape=M.shape))
         A = M[:, cols]
         gl = G[l - 2]
         G[l - 2] = (gl.reshape(-1, gl.shape[2]) @ A).reshape(gl.shape[0], gl.shape[1], len(cols))

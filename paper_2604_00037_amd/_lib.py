@@ -1,0 +1,111 @@
+"""ctypes view of ``include/aci.h``.  Loads ``libaci.so`` from this package
+directory and fails loudly when it is missing: there is no fallback."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaci.so")
+
+MAX_SITES = 128
+MAX_INPUTS = 4
+
+ACI_OK = 0
+ACI_W_NOT_CONVERGED = 1
+STATUS_NAMES = {
+    0: "ACI_OK", 1: "ACI_W_NOT_CONVERGED", -1: "ACI_E_INVALID", -2: "ACI_E_DTYPE",
+    -3: "ACI_E_HIP", -4: "ACI_E_NOMEM", -5: "ACI_E_NUMERIC", -6: "ACI_E_LIMIT",
+    -7: "ACI_E_TIMEOUT",
+}
+
+EXPORTED = [
+    "aci_ctx_create", "aci_ctx_destroy", "aci_last_error", "aci_elementwise",
+    "aci_result_free", "aci_env_contract", "aci_pi_eval", "aci_prrlu", "aci_gather",
+]
+
+
+class AciTT(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32),
+        ("d", C.POINTER(C.c_int32)),
+        ("ranks", C.POINTER(C.c_int32)),
+        ("cores", C.POINTER(C.c_void_p)),
+    ]
+
+
+class AciOptions(C.Structure):
+    _fields_ = [
+        ("maxiter", C.c_int32),
+        ("seed", C.c_uint64),
+        ("init", C.POINTER(AciTT)),
+        ("stop_rule", C.c_int32),
+        ("precision", C.c_int32),
+        ("trace", C.c_int32),
+        ("fixed_sweeps", C.c_int32),
+    ]
+
+
+class AciResult(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32),
+        ("sweeps", C.c_int32),
+        ("converged", C.c_int32),
+        ("ranks", C.c_int32 * (MAX_SITES + 1)),
+        ("eps", C.c_double * MAX_SITES),
+        ("core_offset", C.c_int64 * MAX_SITES),
+        ("out_elems", C.c_int64),
+        ("init_ranks", C.c_int32 * (MAX_SITES + 1)),
+        ("sweep_ms", C.c_double),
+        ("n_records", C.c_int32),
+        ("record_stride", C.c_int32),
+        ("rec_meta", C.POINTER(C.c_int32)),
+        ("rec_eps", C.POINTER(C.c_double)),
+        ("rec_rows", C.POINTER(C.c_int32)),
+        ("rec_cols", C.POINTER(C.c_int32)),
+    ]
+
+
+class HipError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load the library once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2604_00037_amd.build` "
+            "(the HIP library is required; there is no CPU fallback)")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    i32 = C.c_int32
+    lib.aci_ctx_create.argtypes = [C.POINTER(vp), vp]
+    lib.aci_ctx_create.restype = C.c_int
+    lib.aci_ctx_destroy.argtypes = [vp]
+    lib.aci_ctx_destroy.restype = None
+    lib.aci_last_error.argtypes = [vp]
+    lib.aci_last_error.restype = C.c_char_p
+    lib.aci_elementwise.argtypes = [vp, C.POINTER(AciTT), i32, i32, i32, C.c_double, i32,
+                                    C.POINTER(AciOptions), vp, C.c_int64, C.POINTER(AciResult)]
+    lib.aci_elementwise.restype = C.c_int
+    lib.aci_result_free.argtypes = [C.POINTER(AciResult)]
+    lib.aci_result_free.restype = None
+    lib.aci_env_contract.argtypes = [vp, i32, i32, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                     i32, i32, i32, i32]
+    lib.aci_env_contract.restype = C.c_int
+    lib.aci_pi_eval.argtypes = [vp, i32, i32, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i32),
+                                i32, i32, vp, i32]
+    lib.aci_pi_eval.restype = C.c_int
+    lib.aci_prrlu.argtypes = [vp, i32, vp, i32, i32, i32, C.c_double, i32, i32, vp, vp, vp, vp, vp, i32]
+    lib.aci_prrlu.restype = C.c_int
+    lib.aci_gather.argtypes = [vp, i32, i32, vp, i32, i32, i32, vp, vp, vp, i32]
+    lib.aci_gather.restype = C.c_int
+    _lib = lib
+    return lib

@@ -1,0 +1,245 @@
+"""Python binding of the ACI library: argument marshalling over the C ABI.
+
+Device memory and streams come from PyTorch (HIP build); every step of the
+computation runs in the library's HIP kernels.  All tensors passed in must be
+contiguous float64 tensors on the current HIP device.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+
+OPS = {"product": 0, "sum": 1, "abs2_mul": 2}
+RULES = {"exclusive": 0, "literal": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+F64 = 0
+
+
+def _check(lib, ctx, status, allow_warning=True):
+    if status == 0 or (allow_warning and status > 0):
+        return status
+    msg = lib.aci_last_error(ctx).decode(errors="replace")
+    name = _lib.STATUS_NAMES.get(status, str(status))
+    raise _lib.HipError(f"{name}: {msg}")
+
+
+def _dev_tensor(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Context:
+    """Owns an ``aci_ctx`` bound to the current device and torch stream."""
+
+    def __init__(self, stream=None):
+        self.lib = _lib.load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _check(self.lib, None, self.lib.aci_ctx_create(C.byref(h), C.c_void_p(stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.aci_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = None
+
+
+def default_context():
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+def _tt_struct(cores, keep):
+    L = len(cores)
+    d = (C.c_int32 * L)(*[int(c.shape[1]) for c in cores])
+    ranks = (C.c_int32 * (L + 1))(*([int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]))
+    ptrs = (C.c_void_p * L)(*[c.data_ptr() for c in cores])
+    keep.extend([d, ranks, ptrs])
+    return _lib.AciTT(L, d, ranks, ptrs)
+
+
+@dataclass
+class Info:
+    status: int
+    sweeps: int
+    converged: bool
+    ranks: list
+    eps: list
+    init_ranks: list
+    sweep_ms: float
+    records: list = field(default_factory=list)
+
+
+def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
+                stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False, ctx=None):
+    """Alg. 1: returns (cores, info) with cores a list of device tensors of
+    shape (r_{l-1}, d_l, r_l) approximating op(inputs) elementwise."""
+    ctx = ctx or default_context()
+    lib = ctx.lib
+    if len(inputs) < 1:
+        raise ValueError("need at least one input TT")
+    keep = []
+    for n, X in enumerate(inputs):
+        for l, c in enumerate(X):
+            _dev_tensor(c, f"inputs[{n}][{l}]")
+            if c.dim() != 3:
+                raise ValueError("cores must be 3-dimensional")
+    tts = (_lib.AciTT * len(inputs))(*[_tt_struct(X, keep) for X in inputs])
+    opts = _lib.AciOptions()
+    opts.maxiter = maxiter
+    opts.seed = seed
+    opts.stop_rule = RULES[stop_rule]
+    opts.precision = PRECISIONS[precision]
+    opts.trace = 1 if trace else 0
+    opts.fixed_sweeps = 1 if fixed_sweeps else 0
+    if init is not None:
+        for l, c in enumerate(init):
+            _dev_tensor(c, f"init[{l}]")
+        init_tt = _tt_struct(init, keep)
+        keep.append(init_tt)
+        opts.init = C.pointer(init_tt)
+    L = len(inputs[0])
+    dmax = max(int(c.shape[1]) for c in inputs[0])
+    # capacity for every admissible rank profile (maxrank above the compiled
+    # limit is rejected by the library itself)
+    mr = min(int(maxrank), 512)
+    cap = L * dmax * mr * mr
+    out = torch.empty(cap, dtype=torch.float64, device=inputs[0][0].device)
+    res = _lib.AciResult()
+    status = lib.aci_elementwise(ctx.h, tts, len(inputs), F64, OPS[op], float(tol), int(maxrank),
+                                 C.byref(opts), C.c_void_p(out.data_ptr()), cap, C.byref(res))
+    try:
+        _check(lib, ctx.h, status)
+        ranks = [res.ranks[i] for i in range(L + 1)]
+        dims = [int(c.shape[1]) for c in inputs[0]]
+        cores = []
+        for l in range(L):
+            off = res.core_offset[l]
+            cnt = ranks[l] * dims[l] * ranks[l + 1]
+            cores.append(out[off:off + cnt].view(ranks[l], dims[l], ranks[l + 1]))
+        records = []
+        if trace:
+            stride = res.record_stride
+            for r in range(res.n_records):
+                meta = [res.rec_meta[6 * r + i] for i in range(6)]
+                rank = meta[3]
+                records.append(dict(
+                    kind=("init", "LR", "RL")[meta[0]], sweep=meta[1], bond=meta[2], rank=rank,
+                    m=meta[4], n=meta[5], eps=res.rec_eps[r],
+                    rows=[res.rec_rows[stride * r + i] for i in range(rank)],
+                    cols=[res.rec_cols[stride * r + i] for i in range(rank)]))
+        info = Info(status=status, sweeps=res.sweeps, converged=bool(res.converged),
+                    ranks=ranks, eps=[res.eps[i] for i in range(L - 1)],
+                    init_ranks=[res.init_ranks[i] for i in range(L + 1)],
+                    sweep_ms=res.sweep_ms, records=records)
+    finally:
+        lib.aci_result_free(C.byref(res))
+    return cores, info
+
+
+# ------------------------------------------------------------ single steps
+def env_contract(side, frames, cores, ctx=None):
+    """side "left": A = L X (c x d r1); side "right": B = X R (r0 d x c)."""
+    ctx = ctx or default_context()
+    n = len(frames)
+    outs = []
+    for F, X in zip(frames, cores):
+        _dev_tensor(F, "frame")
+        _dev_tensor(X, "core")
+    r0, d, r1 = (int(s) for s in cores[0].shape)
+    if side == "left":
+        c = int(frames[0].shape[0])
+        outs = [torch.empty(c, d * r1, dtype=torch.float64, device=cores[0].device) for _ in range(n)]
+    else:
+        c = int(frames[0].shape[1])
+        outs = [torch.empty(r0 * d, c, dtype=torch.float64, device=cores[0].device) for _ in range(n)]
+    fp = (C.c_void_p * n)(*[f.data_ptr() for f in frames])
+    cp = (C.c_void_p * n)(*[x.data_ptr() for x in cores])
+    op_ = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    st = ctx.lib.aci_env_contract(ctx.h, F64, 0 if side == "left" else 1, n, fp, cp, op_, c, r0, d, r1)
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return outs
+
+
+def pi_eval(op, A, B, ctx=None):
+    """M = op(A[0] @ B[0], A[1] @ B[1], ...) on the matrix cores."""
+    ctx = ctx or default_context()
+    n = len(A)
+    for a, b in zip(A, B):
+        _dev_tensor(a, "A")
+        _dev_tensor(b, "B")
+    m = int(A[0].shape[0])
+    ncol = int(B[0].shape[1])
+    M = torch.empty(m, ncol, dtype=torch.float64, device=A[0].device)
+    ap = (C.c_void_p * n)(*[a.data_ptr() for a in A])
+    bp = (C.c_void_p * n)(*[b.data_ptr() for b in B])
+    ks = (C.c_int32 * n)(*[int(a.shape[1]) for a in A])
+    st = ctx.lib.aci_pi_eval(ctx.h, F64, OPS[op], n, ap, bp, ks, m, ncol, C.c_void_p(M.data_ptr()), ncol)
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return M
+
+
+def prrlu(M, tol, maxrank, stop_rule="exclusive", want_y=False, ctx=None):
+    """Alg. 2 on the device matrix M.  Returns dict(rows, cols, rank, eps, Y)."""
+    ctx = ctx or default_context()
+    _dev_tensor(M, "M")
+    m, n = (int(s) for s in M.shape)
+    dev = M.device
+    kcap = max(1, min(m, n, maxrank))
+    rows = torch.full((kcap,), -1, dtype=torch.int32, device=dev)
+    cols = torch.full((kcap,), -1, dtype=torch.int32, device=dev)
+    rank = torch.zeros(1, dtype=torch.int32, device=dev)
+    eps = torch.zeros(1, dtype=torch.float64, device=dev)
+    Y = torch.zeros(kcap, n, dtype=torch.float64, device=dev) if want_y else None
+    st = ctx.lib.aci_prrlu(ctx.h, F64, C.c_void_p(M.data_ptr()), m, n, n, float(tol), int(maxrank),
+                           RULES[stop_rule], C.c_void_p(rows.data_ptr()), C.c_void_p(cols.data_ptr()),
+                           C.c_void_p(rank.data_ptr()), C.c_void_p(eps.data_ptr()),
+                           C.c_void_p(Y.data_ptr() if Y is not None else 0), n)
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    r = int(rank.item())
+    return dict(rows=rows[:r].cpu().numpy(), cols=cols[:r].cpu().numpy(), rank=r,
+                eps=float(eps.item()), Y=(Y[:r] if Y is not None else None))
+
+
+def gather(side, src, idx, ld_out=None, ctx=None):
+    """side "rows": out = src[idx, :]; side "cols": out = src[:, idx]."""
+    ctx = ctx or default_context()
+    _dev_tensor(src, "src")
+    h, w = (int(s) for s in src.shape)
+    idx_t = torch.as_tensor(idx, dtype=torch.int32, device=src.device).contiguous()
+    r = int(idx_t.numel())
+    rank = torch.tensor([r], dtype=torch.int32, device=src.device)
+    if side == "rows":
+        out = torch.zeros(r, w, dtype=torch.float64, device=src.device)
+        ld = w
+    else:
+        out = torch.zeros(h, r, dtype=torch.float64, device=src.device)
+        ld = r
+    st = ctx.lib.aci_gather(ctx.h, F64, 0 if side == "rows" else 1, C.c_void_p(src.data_ptr()), h, w, w,
+                            C.c_void_p(idx_t.data_ptr()), C.c_void_p(rank.data_ptr()),
+                            C.c_void_p(out.data_ptr()), max(ld, 1))
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return out

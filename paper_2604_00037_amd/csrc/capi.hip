@@ -1,0 +1,857 @@
+// C ABI and sweep driver of the ACI library (Alg. 1 of the paper).
+//
+// The host enqueues a whole sweep without waiting: every kernel reads the
+// ranks it depends on (|I_l|, |J_l|) from a small device array that the prrLU
+// kernels write, and every grid is sized for the largest shape the bond can
+// take.  The host synchronises once per sweep, to read the right-to-left
+// ranks and error estimates for the convergence test.
+//
+// Environment caching: left frames change only in left-to-right half sweeps
+// and right frames only in right-to-left ones, so A^n_l = L^n_{l-1} X^n_l
+// computed going right is reused going left, and B^n_l = X^n_{l+1} R^n_{l+2}
+// computed going left (or during initialisation) is reused going right.  Each
+// local update therefore runs one fresh environment contraction.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace aci;
+
+struct aci_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  uint32_t flag_next = 1;
+  // workspace of aci_elementwise (grown on demand)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // small persistent workspace of the single-step entry points
+  int* step_err = nullptr;     // [0] error flags, [1] abort word
+  uint64_t* step_xbuf = nullptr;
+  size_t step_xwords = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+constexpr uint32_t kSpinLimit = 1u << 22;   // polls before an exchange gives up
+
+int set_err(aci_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return set_err(ctx, ACI_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+uint32_t next_flag(aci_ctx* c) {
+  // each prrLU launch uses flags base .. base + min(m, n) <= base + 1024
+  uint32_t f = c->flag_next;
+  c->flag_next += 2048u;
+  if (c->flag_next < 2048u) c->flag_next = 1;  // wrapped
+  return f;
+}
+
+// ---- bump allocator: pass 0 sizes the workspace, pass 1 hands out pointers
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int sat_mul(int a, int b, int cap) {
+  long long v = (long long)a * b;
+  return v > cap ? cap : (int)v;
+}
+
+// SplitMix64 (S. Vigna): default Y_init entries, uniform on [-1, 1).
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (double)(next() >> 11) * 0x1.0p-53 * 2.0 - 1.0; }
+};
+
+struct Plan {
+  int L = 0, N = 0, op = 0, maxrank = 0, maxiter = 20, rule = 0;
+  bool trace = false, fixed = false;
+  double tol = 0.0;
+  int d[ACI_MAX_SITES + 1];                         // d[l], l = 1..L
+  int r[ACI_MAX_INPUTS][ACI_MAX_SITES + 1];         // r[n][l], l = 0..L
+  const double* X[ACI_MAX_INPUTS][ACI_MAX_SITES + 1];  // X[n][l], l = 1..L
+  int rho[ACI_MAX_SITES + 1];                       // Y_init ranks
+  const double* Yin[ACI_MAX_SITES + 1];             // Y_init cores (device)
+  int capI[ACI_MAX_SITES + 2], capJ[ACI_MAX_SITES + 2];
+  int D = 1;          // max local dimension
+  int ldm = 0;        // leading dimension of the two-site matrix
+  int ldR = 0;        // leading dimension of right frames
+  int n_rec = 0;
+  // device buffers
+  double* Lf[ACI_MAX_INPUTS][ACI_MAX_SITES + 1];
+  double* Rf[ACI_MAX_INPUTS][ACI_MAX_SITES + 2];
+  double* Ac[ACI_MAX_INPUTS][ACI_MAX_SITES + 1];
+  double* Bc[ACI_MAX_INPUTS][ACI_MAX_SITES + 1];
+  double* Mbuf = nullptr;
+  double* G[ACI_MAX_SITES + 1];
+  double* Gin[ACI_MAX_SITES + 1];
+  double* Atmp = nullptr;
+  double* Ycore[ACI_MAX_SITES + 1];
+  int* nI = nullptr;   // |I_l|, l = 0..L
+  int* nJ = nullptr;   // |J_l|, l = 1..L+1
+  int* prow = nullptr;
+  int* pcol = nullptr;
+  int* prank = nullptr;
+  double* peps = nullptr;
+  double* eps_bond = nullptr;
+  int* flags = nullptr;  // [0] error flags, [1] abort word
+  uint64_t* xbuf = nullptr;
+  size_t xbuf_words = 0;
+  int* tr_meta = nullptr;
+  double* tr_eps = nullptr;
+  int* tr_rows = nullptr;
+  int* tr_cols = nullptr;
+};
+
+void layout(Plan& p, Arena& A, bool gen_init) {
+  const int L = p.L;
+  for (int n = 0; n < p.N; ++n) {
+    for (int l = 0; l < L; ++l) p.Lf[n][l] = A.take<double>((size_t)p.capI[l] * p.r[n][l]);
+    for (int l = 2; l <= L + 1; ++l) p.Rf[n][l] = A.take<double>((size_t)p.r[n][l - 1] * p.ldR);
+    for (int l = 1; l < L; ++l) {
+      p.Ac[n][l] = A.take<double>((size_t)p.capI[l - 1] * p.d[l] * p.r[n][l]);
+      p.Bc[n][l] = A.take<double>((size_t)p.r[n][l] * p.d[l + 1] * p.capJ[l + 2]);
+    }
+  }
+  p.Mbuf = A.take<double>((size_t)p.ldm * p.ldm);
+  int rho_max = 1;
+  for (int l = 0; l <= L; ++l) rho_max = std::max(rho_max, p.rho[l]);
+  for (int l = 1; l <= L; ++l) {
+    p.G[l] = A.take<double>((size_t)p.rho[l - 1] * p.d[l] * p.rho[l]);
+    p.Gin[l] = gen_init ? A.take<double>((size_t)p.rho[l - 1] * p.d[l] * p.rho[l]) : nullptr;
+    p.Ycore[l] = A.take<double>((size_t)p.maxrank * p.d[l] * p.maxrank);
+  }
+  p.Atmp = A.take<double>((size_t)rho_max * p.ldR);
+  p.nI = A.take<int>(L + 2);
+  p.nJ = A.take<int>(L + 3);
+  p.prow = A.take<int>(p.maxrank + 1);
+  p.pcol = A.take<int>(p.maxrank + 1);
+  p.prank = A.take<int>(4);
+  p.peps = A.take<double>(4);
+  p.eps_bond = A.take<double>(L + 1);
+  p.flags = A.take<int>(4);
+  p.xbuf_words = prrlu_xbuf_words(p.ldm, p.ldm);
+  p.xbuf = A.take<uint64_t>(p.xbuf_words);
+  if (p.trace) {
+    p.tr_meta = A.take<int>((size_t)3 * p.n_rec);
+    p.tr_eps = A.take<double>(p.n_rec);
+    p.tr_rows = A.take<int>((size_t)p.n_rec * p.maxrank);
+    p.tr_cols = A.take<int>((size_t)p.n_rec * p.maxrank);
+  }
+}
+
+struct Enq {
+  aci_ctx* ctx;
+  Plan& p;
+  hipStream_t s;
+  int rec = 0;
+
+  int prrlu(const double* M, Dim m, Dim n, Dim ldm, int mmax, int nmax, int* rank2, double* eps2,
+            double* Y, Dim ldy) {
+    PrrluArgs a{};
+    a.M = M;
+    a.m = m;
+    a.n = n;
+    a.ldm = ldm;
+    a.tol = p.tol;
+    a.maxrank = p.maxrank;
+    a.rule = p.rule;
+    a.flag_base = next_flag(ctx);
+    a.spin_limit = kSpinLimit;
+    a.xbuf = p.xbuf;
+    a.xbuf_words = p.xbuf_words;
+    if (p.trace) {
+      a.rows = p.tr_rows + (size_t)rec * p.maxrank;
+      a.cols = p.tr_cols + (size_t)rec * p.maxrank;
+      a.eps = p.tr_eps + rec;
+      a.meta = p.tr_meta + (size_t)3 * rec;
+    } else {
+      a.rows = p.prow;
+      a.cols = p.pcol;
+      a.eps = p.peps;
+      a.meta = nullptr;
+    }
+    a.rank = p.prank;
+    a.rank2 = rank2;
+    a.eps2 = eps2;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.err = p.flags;
+    a.abort_word = p.flags + 1;
+    hipError_t e = launch_prrlu(a, mmax, nmax, s);
+    if (e != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("prrlu launch: ") + hipGetErrorString(e));
+    return ACI_OK;
+  }
+  const int* rows() const { return p.trace ? p.tr_rows + (size_t)rec * p.maxrank : p.prow; }
+  const int* cols() const { return p.trace ? p.tr_cols + (size_t)rec * p.maxrank : p.pcol; }
+};
+
+#define ENQ(call)                                                                   \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return set_err(ctx, ACI_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Initialisation (Alg. 1, first two loops): CI-canonical form of Y_init from
+// right to left, initial right frames R^n_l and the cached B^n_{l-1}.
+int enqueue_init(Enq& q) {
+  aci_ctx* ctx = q.ctx;
+  Plan& p = q.p;
+  hipStream_t s = q.s;
+  const int L = p.L;
+  for (int n = 0; n < p.N; ++n) {
+    ENQ(launch_fill(p.Lf[n][0], 1, 1.0, s));
+    ENQ(launch_fill(p.Rf[n][L + 1], 1, 1.0, s));
+  }
+  ENQ(launch_fill_int(p.nI, 1, 1, s));
+  ENQ(launch_fill_int(p.nJ + L + 1, 1, 1, s));
+  ENQ(launch_fill_int(p.flags, 4, 0, s));
+  for (int l = L; l >= 2; --l) {
+    const int dl = p.d[l];
+    const double* Msrc = (l == L) ? p.Yin[L] : p.G[l];
+    const Dim ncols = ddev(p.nJ + l + 1, dl);
+    // cross interpolation of the core matricised as rho_{l-1} x (d |J_{l+1}|)
+    int rc = q.prrlu(Msrc, dconst(p.rho[l - 1]), ncols, ncols, p.rho[l - 1], dl * p.capJ[l + 1],
+                     p.nJ + l, nullptr, nullptr, dconst(0));
+    if (rc) return rc;
+    const int* cols = q.cols();
+    if (l > 2) {
+      // G_{l-1} = Y_init_{l-1} * M[:, J_l]
+      GatherArgs g{};
+      g.count = 1;
+      g.side = 1;
+      g.idx = cols;
+      g.rank = p.nJ + l;
+      g.err = p.flags;
+      g.it[0] = GatherItem{Msrc, p.Atmp, ncols, dconst(p.ldR), dconst(p.rho[l - 1]), ncols};
+      ENQ(launch_gather(g, p.maxrank, p.rho[l - 1], s));
+      ContractArgs c{};
+      c.ngroup = 1;
+      c.err = nullptr;
+      Group& gr = c.g[0];
+      gr.nterm = 1;
+      gr.t[0] = Term{p.Yin[l - 1], p.Atmp, dconst(p.rho[l - 1]), dconst(p.rho[l - 1]), dconst(p.ldR)};
+      gr.C = p.G[l - 1];
+      gr.M = dconst(p.rho[l - 2] * p.d[l - 1]);
+      gr.N = ddev(p.nJ + l);
+      gr.ldc = ddev(p.nJ + l);
+      ENQ(launch_contract(OP_NONE, c, p.rho[l - 2] * p.d[l - 1], p.maxrank, s));
+    }
+    // B^n_{l-1} = X^n_l R^n_{l+1};  R^n_l = B^n_{l-1}[:, J_l]  (Alg. 5, Rightframe)
+    ContractArgs c{};
+    c.ngroup = p.N;
+    int mmax = 0;
+    for (int n = 0; n < p.N; ++n) {
+      Group& gr = c.g[n];
+      gr.nterm = 1;
+      gr.t[0] = Term{p.X[n][l], p.Rf[n][l + 1], dconst(p.r[n][l]), dconst(p.r[n][l]), dconst(p.ldR)};
+      gr.C = p.Bc[n][l - 1];
+      gr.M = dconst(p.r[n][l - 1] * dl);
+      gr.N = ddev(p.nJ + l + 1);
+      gr.ldc = ddev(p.nJ + l + 1);
+      mmax = std::max(mmax, p.r[n][l - 1] * dl);
+    }
+    ENQ(launch_contract(OP_NONE, c, mmax, p.capJ[l + 1], s));
+    GatherArgs g{};
+    g.count = p.N;
+    g.side = 1;
+    g.idx = cols;
+    g.rank = p.nJ + l;
+    g.err = p.flags;
+    int emax = 0;
+    for (int n = 0; n < p.N; ++n) {
+      g.it[n] = GatherItem{p.Bc[n][l - 1], p.Rf[n][l], ncols, dconst(p.ldR), dconst(p.r[n][l - 1]), ncols};
+      emax = std::max(emax, p.r[n][l - 1]);
+    }
+    ENQ(launch_gather(g, p.capJ[l], emax, s));
+    ++q.rec;
+  }
+  return ACI_OK;
+}
+
+// Two-site tensor of bond l with f applied (Eq. pifromframes, localupdate).
+int enqueue_pi(Enq& q, int l) {
+  aci_ctx* ctx = q.ctx;
+  Plan& p = q.p;
+  ContractArgs c{};
+  c.ngroup = 1;
+  c.err = p.flags;
+  Group& gr = c.g[0];
+  gr.nterm = p.N;
+  for (int n = 0; n < p.N; ++n)
+    gr.t[n] = Term{p.Ac[n][l], p.Bc[n][l], dconst(p.r[n][l]), dconst(p.r[n][l]),
+                   ddev(p.nJ + l + 2, p.d[l + 1])};
+  gr.C = p.Mbuf;
+  gr.M = ddev(p.nI + l - 1, p.d[l]);
+  gr.N = ddev(p.nJ + l + 2, p.d[l + 1]);
+  gr.ldc = dconst(p.ldm);
+  ENQ(launch_contract(p.op, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], q.s));
+  return ACI_OK;
+}
+
+int enqueue_sweep(Enq& q) {
+  aci_ctx* ctx = q.ctx;
+  Plan& p = q.p;
+  hipStream_t s = q.s;
+  const int L = p.L;
+  // ---- left to right
+  for (int l = 1; l <= L - 1; ++l) {
+    ContractArgs c{};
+    c.ngroup = p.N;
+    int nmax = 0;
+    for (int n = 0; n < p.N; ++n) {
+      Group& gr = c.g[n];
+      gr.nterm = 1;
+      const int w = p.d[l] * p.r[n][l];
+      gr.t[0] = Term{p.Lf[n][l - 1], p.X[n][l], dconst(p.r[n][l - 1]), dconst(p.r[n][l - 1]), dconst(w)};
+      gr.C = p.Ac[n][l];
+      gr.M = ddev(p.nI + l - 1);
+      gr.N = dconst(w);
+      gr.ldc = dconst(w);
+      nmax = std::max(nmax, w);
+    }
+    ENQ(launch_contract(OP_NONE, c, p.capI[l - 1], nmax, s));
+    int rc = enqueue_pi(q, l);
+    if (rc) return rc;
+    const int mmax = p.d[l] * p.capI[l - 1], nmax2 = p.d[l + 1] * p.capJ[l + 2];
+    rc = q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ddev(p.nJ + l + 2, p.d[l + 1]), dconst(p.ldm),
+                 mmax, nmax2, p.nI + l, nullptr, nullptr, dconst(0));
+    if (rc) return rc;
+    // L^n_l = A^n_l[I_l, :]  (Alg. 5, Leftframe)
+    GatherArgs g{};
+    g.count = p.N;
+    g.side = 0;
+    g.idx = q.rows();
+    g.rank = p.nI + l;
+    g.err = p.flags;
+    int emax = 0;
+    for (int n = 0; n < p.N; ++n) {
+      g.it[n] = GatherItem{p.Ac[n][l], p.Lf[n][l], dconst(p.r[n][l]), dconst(p.r[n][l]), dconst(p.r[n][l]),
+                           ddev(p.nI + l - 1, p.d[l])};
+      emax = std::max(emax, p.r[n][l]);
+    }
+    ENQ(launch_gather(g, p.capI[l], emax, s));
+    ++q.rec;
+  }
+  // ---- right to left
+  for (int l = L - 1; l >= 1; --l) {
+    ContractArgs c{};
+    c.ngroup = p.N;
+    int mmax = 0;
+    for (int n = 0; n < p.N; ++n) {
+      Group& gr = c.g[n];
+      gr.nterm = 1;
+      gr.t[0] = Term{p.X[n][l + 1], p.Rf[n][l + 2], dconst(p.r[n][l + 1]), dconst(p.r[n][l + 1]), dconst(p.ldR)};
+      gr.C = p.Bc[n][l];
+      gr.M = dconst(p.r[n][l] * p.d[l + 1]);
+      gr.N = ddev(p.nJ + l + 2);
+      gr.ldc = ddev(p.nJ + l + 2);
+      mmax = std::max(mmax, p.r[n][l] * p.d[l + 1]);
+    }
+    ENQ(launch_contract(OP_NONE, c, mmax, p.capJ[l + 2], s));
+    int rc = enqueue_pi(q, l);
+    if (rc) return rc;
+    const Dim ncols = ddev(p.nJ + l + 2, p.d[l + 1]);
+    rc = q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ncols, dconst(p.ldm), p.d[l] * p.capI[l - 1],
+                 p.d[l + 1] * p.capJ[l + 2], p.nJ + l + 1, p.eps_bond + (l - 1), p.Ycore[l + 1], ncols);
+    if (rc) return rc;
+    // R^n_{l+1} = B^n_l[:, J_{l+1}]  (Alg. 5, Rightframe)
+    GatherArgs g{};
+    g.count = p.N;
+    g.side = 1;
+    g.idx = q.cols();
+    g.rank = p.nJ + l + 1;
+    g.err = p.flags;
+    int emax = 0;
+    for (int n = 0; n < p.N; ++n) {
+      g.it[n] = GatherItem{p.Bc[n][l], p.Rf[n][l + 1], ncols, dconst(p.ldR), dconst(p.r[n][l]), ncols};
+      emax = std::max(emax, p.r[n][l]);
+    }
+    if (l == 1) {
+      // Y_1 = M[:, J_2] (the left factor of the last update, Alg. 3)
+      g.it[p.N] = GatherItem{p.Mbuf, p.Ycore[1], dconst(p.ldm), ddev(p.nJ + 2), dconst(p.d[1]), ncols};
+      g.count = p.N + 1;
+      emax = std::max(emax, p.d[1]);
+    }
+    ENQ(launch_gather(g, p.capJ[l + 1], emax, s));
+    ++q.rec;
+  }
+  return ACI_OK;
+}
+
+int validate_tt(aci_ctx* ctx, const aci_tt& t, int L) {
+  if (t.L != L || !t.d || !t.ranks || !t.cores) return set_err(ctx, ACI_E_INVALID, "TT description incomplete or L mismatch");
+  if (t.ranks[0] != 1 || t.ranks[L] != 1) return set_err(ctx, ACI_E_INVALID, "boundary ranks must be 1");
+  for (int l = 0; l < L; ++l) {
+    if (t.d[l] < 1 || t.d[l] > ACI_MAX_DIM) return set_err(ctx, ACI_E_LIMIT, "local dimension out of range");
+    if (t.ranks[l + 1] < 1) return set_err(ctx, ACI_E_INVALID, "ranks must be >= 1");
+    if (!t.cores[l]) return set_err(ctx, ACI_E_INVALID, "null core pointer");
+  }
+  return ACI_OK;
+}
+
+}  // namespace
+
+// =============================================================== C ABI
+extern "C" {
+
+int aci_ctx_create(aci_ctx** out, void* stream) {
+  if (!out) return ACI_E_INVALID;
+  *out = nullptr;
+  aci_ctx* ctx = new (std::nothrow) aci_ctx();
+  if (!ctx) return ACI_E_NOMEM;
+  ctx->stream = (hipStream_t)stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return ACI_E_HIP;
+  }
+  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+    delete ctx;
+    return ACI_E_HIP;
+  }
+  *out = ctx;
+  return ACI_OK;
+}
+
+void aci_ctx_destroy(aci_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->step_err) (void)hipFree(ctx->step_err);
+  if (ctx->step_xbuf) (void)hipFree(ctx->step_xbuf);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  delete ctx;
+}
+
+const char* aci_last_error(const aci_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void aci_result_free(aci_result* r) {
+  if (!r) return;
+  free(r->rec_meta);
+  free(r->rec_eps);
+  free(r->rec_rows);
+  free(r->rec_cols);
+  r->rec_meta = nullptr;
+  r->rec_eps = nullptr;
+  r->rec_rows = nullptr;
+  r->rec_cols = nullptr;
+  r->n_records = 0;
+}
+
+int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
+                    double tol, int32_t maxrank, const aci_options* opt, void* out, int64_t out_capacity,
+                    aci_result* result) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!inputs || !result || !out) return set_err(ctx, ACI_E_INVALID, "null argument");
+  std::memset(result, 0, sizeof(*result));
+  if (n_inputs < 1 || n_inputs > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
+  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64 cores are supported by this build");
+  if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL) return set_err(ctx, ACI_E_INVALID, "unknown op");
+  if (op == ACI_OP_ABS2_MUL && n_inputs != 1) return set_err(ctx, ACI_E_INVALID, "ABS2_MUL takes one input");
+  if (!(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "tol must be >= 0");
+  if (maxrank < 1) return set_err(ctx, ACI_E_INVALID, "maxrank must be >= 1");
+  if (maxrank > ACI_MAX_RANK) return set_err(ctx, ACI_E_LIMIT, "maxrank above ACI_MAX_RANK");
+  const int L = inputs[0].L;
+  if (L < 2 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
+  aci_options o{};
+  o.maxiter = 20;
+  if (opt) o = *opt;
+  if (o.maxiter <= 0) o.maxiter = 20;
+  if (o.precision != ACI_PREC_FP64) return set_err(ctx, ACI_E_DTYPE, "only ACI_PREC_FP64 is supported by this build");
+  if (o.stop_rule != 0 && o.stop_rule != 1) return set_err(ctx, ACI_E_INVALID, "stop_rule must be 0 or 1");
+
+  Plan* pp = new (std::nothrow) Plan();
+  if (!pp) return set_err(ctx, ACI_E_NOMEM, "host allocation");
+  std::unique_ptr<Plan> hold(pp);
+  Plan& p = *pp;
+  p.L = L;
+  p.N = n_inputs;
+  p.op = op;
+  p.tol = tol;
+  p.maxrank = maxrank;
+  p.maxiter = o.maxiter;
+  p.rule = o.stop_rule;
+  p.trace = o.trace != 0;
+  p.fixed = o.fixed_sweeps != 0;
+  for (int n = 0; n < n_inputs; ++n) {
+    int rc = validate_tt(ctx, inputs[n], L);
+    if (rc) return rc;
+    for (int l = 0; l < L; ++l)
+      if (inputs[n].d[l] != inputs[0].d[l]) return set_err(ctx, ACI_E_INVALID, "inputs differ in local dimensions");
+    for (int l = 0; l <= L; ++l) {
+      p.r[n][l] = inputs[n].ranks[l];
+      if (p.r[n][l] > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "input rank above limit");
+    }
+    for (int l = 1; l <= L; ++l) p.X[n][l] = (const double*)inputs[n].cores[l - 1];
+  }
+  p.D = 1;
+  for (int l = 1; l <= L; ++l) {
+    p.d[l] = inputs[0].d[l - 1];
+    p.D = std::max(p.D, p.d[l]);
+  }
+  p.d[0] = 1;
+  if ((long long)p.D * maxrank > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "d * maxrank above ACI_MAX_MATRIX");
+  // static bounds of |I_l| and |J_l|
+  p.capI[0] = 1;
+  for (int l = 1; l <= L; ++l) p.capI[l] = sat_mul(p.capI[l - 1], p.d[l], maxrank);
+  p.capJ[L + 1] = 1;
+  for (int l = L; l >= 1; --l) p.capJ[l] = sat_mul(p.capJ[l + 1], p.d[l], maxrank);
+  p.ldm = p.D * maxrank;
+  p.ldR = maxrank;
+  // initial guess
+  const bool gen_init = (o.init == nullptr);
+  if (!gen_init) {
+    int rc = validate_tt(ctx, *o.init, L);
+    if (rc) return rc;
+    for (int l = 0; l < L; ++l)
+      if (o.init->d[l] != p.d[l + 1]) return set_err(ctx, ACI_E_INVALID, "init local dimensions differ");
+    for (int l = 0; l <= L; ++l) {
+      p.rho[l] = o.init->ranks[l];
+      if (p.rho[l] > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "init rank above limit");
+    }
+  } else {
+    p.rho[0] = p.rho[L] = 1;
+    for (int l = 1; l < L; ++l) {
+      int mn = maxrank;
+      for (int n = 0; n < n_inputs; ++n) mn = std::min(mn, p.r[n][l]);
+      p.rho[l] = mn;
+    }
+  }
+  p.n_rec = (L - 1) * (1 + 2 * p.maxiter);
+
+  // ---- workspace
+  Arena sz;
+  layout(p, sz, gen_init);
+  const size_t need = sz.off + 256;
+  if (need > ctx->ws_bytes) {
+    if (ctx->ws) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(ctx->ws);
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    if (hipMalloc(&ctx->ws, need) != hipSuccess) return set_err(ctx, ACI_E_NOMEM, "workspace allocation failed");
+    ctx->ws_bytes = need;
+  }
+  Arena ar;
+  ar.base = (char*)ctx->ws;
+  layout(p, ar, gen_init);
+  hipStream_t s = ctx->stream;
+  if (gen_init) {
+    SplitMix64 rng{o.seed};
+    std::vector<double> h;
+    for (int l = 1; l <= L; ++l) {
+      const size_t cnt = (size_t)p.rho[l - 1] * p.d[l] * p.rho[l];
+      h.resize(cnt);
+      for (size_t i = 0; i < cnt; ++i) h[i] = rng.uniform();
+      HIPCHK(hipMemcpyAsync(p.Gin[l], h.data(), cnt * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+      p.Yin[l] = p.Gin[l];
+    }
+  } else {
+    for (int l = 1; l <= L; ++l) p.Yin[l] = (const double*)o.init->cores[l - 1];
+  }
+
+  Enq q{ctx, p, s, 0};
+  int rc = enqueue_init(q);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(result->init_ranks + 1, p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  result->init_ranks[0] = result->init_ranks[L] = 1;
+
+  std::vector<int> prev(result->init_ranks + 1, result->init_ranks + L);
+  std::vector<int> cur(L - 1);
+  std::vector<double> epsb(L - 1);
+  int sweeps = 0;
+  bool converged = false;
+  HIPCHK(hipEventRecord(ctx->ev0, s));
+  for (int it = 1; it <= p.maxiter; ++it) {
+    rc = enqueue_sweep(q);
+    if (rc) return rc;
+    sweeps = it;
+    if (!p.fixed) {
+      HIPCHK(hipMemcpyAsync(cur.data(), p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(epsb.data(), p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool grew = false;
+      double emax = 0.0;
+      for (int b = 0; b < L - 1; ++b) {
+        grew = grew || cur[b] > prev[b];
+        emax = std::max(emax, epsb[b]);
+      }
+      prev = cur;
+      if (!grew && emax <= tol) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  HIPCHK(hipEventRecord(ctx->ev1, s));
+  int flags[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(flags, p.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(cur.data(), p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(epsb.data(), p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  if (flags[0] & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "a pivot exchange exceeded its spin limit");
+  if (flags[0] & ERR_NONFINITE) return set_err(ctx, ACI_E_NUMERIC, "NaN or Inf in a two-site tensor");
+  if (flags[0] & ERR_LIMIT) return set_err(ctx, ACI_E_LIMIT, "a pivot index fell outside its matrix");
+  if (p.fixed) {
+    double emax = 0.0;
+    for (int b = 0; b < L - 1; ++b) emax = std::max(emax, epsb[b]);
+    converged = emax <= tol;
+  }
+
+  // ---- output cores, compacted site after site
+  result->L = L;
+  result->sweeps = sweeps;
+  result->converged = converged ? 1 : 0;
+  result->sweep_ms = ms;
+  result->ranks[0] = result->ranks[L] = 1;
+  for (int b = 1; b < L; ++b) {
+    result->ranks[b] = cur[b - 1];
+    result->eps[b - 1] = epsb[b - 1];
+  }
+  int64_t off = 0;
+  for (int l = 1; l <= L; ++l) off += (int64_t)result->ranks[l - 1] * p.d[l] * result->ranks[l];
+  if (off > out_capacity) return set_err(ctx, ACI_E_NOMEM, "output buffer too small");
+  off = 0;
+  for (int l = 1; l <= L; ++l) {
+    const int64_t cnt = (int64_t)result->ranks[l - 1] * p.d[l] * result->ranks[l];
+    result->core_offset[l - 1] = off;
+    const double* src = p.Ycore[l];
+    if (l == L) {
+      // Y_L of the bond L-1 update has shape rank x d x 1: same compact layout
+    }
+    HIPCHK(hipMemcpyAsync((double*)out + off, src, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    off += cnt;
+  }
+  result->out_elems = off;
+  if (p.trace) {
+    const int nr = q.rec;
+    result->n_records = nr;
+    result->record_stride = maxrank;
+    result->rec_meta = (int32_t*)calloc((size_t)nr * 6, sizeof(int32_t));
+    result->rec_eps = (double*)calloc(nr, sizeof(double));
+    result->rec_rows = (int32_t*)calloc((size_t)nr * maxrank, sizeof(int32_t));
+    result->rec_cols = (int32_t*)calloc((size_t)nr * maxrank, sizeof(int32_t));
+    std::vector<int> meta3((size_t)3 * nr);
+    if (!result->rec_meta || !result->rec_eps || !result->rec_rows || !result->rec_cols) {
+      aci_result_free(result);
+      return set_err(ctx, ACI_E_NOMEM, "host allocation of the trace");
+    }
+    HIPCHK(hipMemcpyAsync(meta3.data(), p.tr_meta, sizeof(int) * 3 * nr, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(result->rec_eps, p.tr_eps, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(result->rec_rows, p.tr_rows, sizeof(int) * (size_t)nr * maxrank, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(result->rec_cols, p.tr_cols, sizeof(int) * (size_t)nr * maxrank, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int r = 0;
+    for (int l = L; l >= 2; --l, ++r) {
+      int* m6 = result->rec_meta + 6 * r;
+      m6[0] = 0; m6[1] = 0; m6[2] = l;
+      m6[3] = meta3[3 * r]; m6[4] = meta3[3 * r + 1]; m6[5] = meta3[3 * r + 2];
+    }
+    for (int it = 1; it <= sweeps; ++it) {
+      for (int l = 1; l <= L - 1; ++l, ++r) {
+        int* m6 = result->rec_meta + 6 * r;
+        m6[0] = 1; m6[1] = it; m6[2] = l;
+        m6[3] = meta3[3 * r]; m6[4] = meta3[3 * r + 1]; m6[5] = meta3[3 * r + 2];
+      }
+      for (int l = L - 1; l >= 1; --l, ++r) {
+        int* m6 = result->rec_meta + 6 * r;
+        m6[0] = 2; m6[1] = it; m6[2] = l;
+        m6[3] = meta3[3 * r]; m6[4] = meta3[3 * r + 1]; m6[5] = meta3[3 * r + 2];
+      }
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return converged ? ACI_OK : ACI_W_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------------ single steps
+static int ensure_step_ws(aci_ctx* ctx) {
+  if (!ctx->step_err) {
+    if (hipMalloc(&ctx->step_err, 4 * sizeof(int)) != hipSuccess) return set_err(ctx, ACI_E_NOMEM, "step workspace");
+  }
+  const size_t words = prrlu_xbuf_words(ACI_MAX_MATRIX, ACI_MAX_MATRIX);
+  if (ctx->step_xwords < words) {
+    if (ctx->step_xbuf) (void)hipFree(ctx->step_xbuf);
+    ctx->step_xbuf = nullptr;
+    if (hipMalloc(&ctx->step_xbuf, words * sizeof(uint64_t)) != hipSuccess) return set_err(ctx, ACI_E_NOMEM, "step exchange buffer");
+    ctx->step_xwords = words;
+  }
+  return ACI_OK;
+}
+
+int aci_env_contract(aci_ctx* ctx, int32_t dtype, int32_t side, int32_t count, const void* const* frames,
+                     const void* const* cores, void* const* outp, int32_t c, int32_t r0, int32_t d, int32_t r1) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (count < 1 || count > ACI_MAX_INPUTS || !frames || !cores || !outp) return set_err(ctx, ACI_E_INVALID, "bad count or null");
+  if (c < 1 || r0 < 1 || d < 1 || r1 < 1) return set_err(ctx, ACI_E_INVALID, "bad dims");
+  ContractArgs a{};
+  a.ngroup = count;
+  int mmax, nmax;
+  for (int i = 0; i < count; ++i) {
+    if (!frames[i] || !cores[i] || !outp[i]) return set_err(ctx, ACI_E_INVALID, "null pointer");
+    Group& g = a.g[i];
+    g.nterm = 1;
+    g.C = (double*)outp[i];
+    if (side == 0) {
+      g.t[0] = Term{(const double*)frames[i], (const double*)cores[i], dconst(r0), dconst(r0), dconst(d * r1)};
+      g.M = dconst(c);
+      g.N = dconst(d * r1);
+      g.ldc = dconst(d * r1);
+    } else {
+      g.t[0] = Term{(const double*)cores[i], (const double*)frames[i], dconst(r1), dconst(r1), dconst(c)};
+      g.M = dconst(r0 * d);
+      g.N = dconst(c);
+      g.ldc = dconst(c);
+    }
+  }
+  if (side == 0) { mmax = c; nmax = d * r1; } else { mmax = r0 * d; nmax = c; }
+  HIPCHK(launch_contract(OP_NONE, a, mmax, nmax, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ACI_OK;
+}
+
+int aci_pi_eval(aci_ctx* ctx, int32_t dtype, int32_t op, int32_t n_inputs, const void* const* A,
+                const void* const* B, const int32_t* k, int32_t m, int32_t n, void* M, int32_t ldm) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (n_inputs < 1 || n_inputs > ACI_MAX_INPUTS || !A || !B || !k || !M) return set_err(ctx, ACI_E_INVALID, "bad arguments");
+  if (op == ACI_OP_ABS2_MUL && n_inputs != 1) return set_err(ctx, ACI_E_INVALID, "ABS2_MUL takes one input");
+  if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL) return set_err(ctx, ACI_E_INVALID, "op");
+  if (m < 1 || n < 1 || ldm < n) return set_err(ctx, ACI_E_INVALID, "bad dims");
+  ContractArgs a{};
+  a.ngroup = 1;
+  a.err = ctx->step_err;
+  int rc = ensure_step_ws(ctx);
+  if (rc) return rc;
+  a.err = ctx->step_err;
+  HIPCHK(launch_fill_int(ctx->step_err, 2, 0, ctx->stream));
+  Group& g = a.g[0];
+  g.nterm = n_inputs;
+  for (int i = 0; i < n_inputs; ++i) {
+    if (!A[i] || !B[i] || k[i] < 1) return set_err(ctx, ACI_E_INVALID, "bad term");
+    g.t[i] = Term{(const double*)A[i], (const double*)B[i], dconst(k[i]), dconst(k[i]), dconst(n)};
+  }
+  g.C = (double*)M;
+  g.M = dconst(m);
+  g.N = dconst(n);
+  g.ldc = dconst(ldm);
+  HIPCHK(launch_contract(op, a, m, n, ctx->stream));
+  int flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, ctx->step_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (flags & ERR_NONFINITE) return set_err(ctx, ACI_E_NUMERIC, "NaN or Inf in the two-site tensor");
+  return ACI_OK;
+}
+
+int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, int32_t ldm, double tol,
+              int32_t maxrank, int32_t stop_rule, int32_t* rows, int32_t* cols, int32_t* rank, double* eps,
+              void* Y, int32_t ldy) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (!M || !rows || !cols || !rank || !eps) return set_err(ctx, ACI_E_INVALID, "null pointer");
+  if (m < 1 || n < 1 || ldm < n || maxrank < 1 || !(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "bad dims or tolerance");
+  if (m > ACI_MAX_MATRIX || n > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "matrix above ACI_MAX_MATRIX");
+  if (stop_rule != 0 && stop_rule != 1) return set_err(ctx, ACI_E_INVALID, "stop_rule");
+  if (Y && ldy < n) return set_err(ctx, ACI_E_INVALID, "ldy < n");
+  int rc = ensure_step_ws(ctx);
+  if (rc) return rc;
+  HIPCHK(launch_fill_int(ctx->step_err, 2, 0, ctx->stream));
+  PrrluArgs a{};
+  a.M = (const double*)M;
+  a.m = dconst(m);
+  a.n = dconst(n);
+  a.ldm = dconst(ldm);
+  a.tol = tol;
+  a.maxrank = maxrank;
+  a.rule = stop_rule;
+  a.flag_base = next_flag(ctx);
+  a.spin_limit = kSpinLimit;
+  a.xbuf = ctx->step_xbuf;
+  a.xbuf_words = ctx->step_xwords;
+  a.rows = rows;
+  a.cols = cols;
+  a.rank = rank;
+  a.eps = eps;
+  a.Y = (double*)Y;
+  a.ldy = dconst(ldy);
+  a.err = ctx->step_err;
+  a.abort_word = ctx->step_err + 1;
+  HIPCHK(launch_prrlu(a, m, n, ctx->stream));
+  int flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, ctx->step_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (flags & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "pivot exchange timed out");
+  return ACI_OK;
+}
+
+int aci_gather(aci_ctx* ctx, int32_t dtype, int32_t side, const void* src, int32_t h, int32_t w, int32_t ld_src,
+               const int32_t* idx, const int32_t* rank, void* out, int32_t ld_out) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (!src || !idx || !rank || !out) return set_err(ctx, ACI_E_INVALID, "null pointer");
+  if (h < 1 || w < 1 || ld_src < w || ld_out < 1 || (side != 0 && side != 1)) return set_err(ctx, ACI_E_INVALID, "bad dims");
+  GatherArgs a{};
+  a.count = 1;
+  a.side = side;
+  a.idx = idx;
+  a.rank = rank;
+  a.it[0] = GatherItem{(const double*)src, (double*)out, dconst(ld_src), dconst(ld_out), dconst(side == 0 ? w : h),
+                       dconst(side == 0 ? h : w)};
+  int rc = ensure_step_ws(ctx);
+  if (rc) return rc;
+  HIPCHK(launch_fill_int(ctx->step_err, 2, 0, ctx->stream));
+  a.err = ctx->step_err;
+  HIPCHK(launch_gather(a, side == 0 ? h : w, side == 0 ? w : h, ctx->stream));
+  int flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, ctx->step_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (flags & ERR_LIMIT) return set_err(ctx, ACI_E_INVALID, "gather index out of range");
+  return ACI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Internal launch interface of the ACI kernels (host side).
+#pragma once
+
+#include "aci_common.h"
+
+namespace aci {
+
+// ---------------------------------------------------------------- contractions
+// One product term A (M x K, row-major, lda) times B (K x N, row-major, ldb).
+struct Term {
+  const double* A;
+  const double* B;
+  Dim K;
+  Dim lda;
+  Dim ldb;
+};
+
+// A group writes C = f(term_0, ..., term_{nterm-1}) (elementwise f) into one
+// M x N output.  Groups of one launch run side by side (grid z).
+struct Group {
+  Term t[ACI_MAX_INPUTS];
+  int nterm;
+  double* C;
+  Dim M;
+  Dim N;
+  Dim ldc;
+};
+
+struct ContractArgs {
+  Group g[ACI_MAX_INPUTS];
+  int ngroup;
+  int* err;  // ERR_NONFINITE is or-ed in when an output is NaN/Inf (may be null)
+};
+
+// op: OP_NONE (single term, plain GEMM), OP_PRODUCT, OP_SUM, OP_ABS2_MUL.
+// mmax/nmax bound the (possibly device-resident) output sizes of every group.
+hipError_t launch_contract(int op, const ContractArgs& args, int mmax, int nmax, hipStream_t s);
+
+// ------------------------------------------------------------------- prrLU
+struct PrrluArgs {
+  const double* M;
+  Dim m, n, ldm;
+  double tol;
+  int maxrank;
+  int rule;
+  int P;            // cooperating workgroups
+  int stride;       // launch stride: workgroup b is active iff b % stride == 0
+  uint64_t* xbuf;   // exchange words, 2 * P * xwords
+  size_t xbuf_words;  // capacity of xbuf
+  int xwords;       // words per exchange slot
+  uint32_t flag_base;
+  uint32_t spin_limit;
+  int* rows;        // out: pivot rows, pivot order
+  int* cols;        // out: pivot columns
+  int* rank;        // out: rank
+  int* rank2;       // out: optional second copy of the rank (bond state)
+  double* eps;      // out: error estimate
+  double* eps2;     // out: optional second copy
+  double* Y;        // out: optional U_JJ^{-1} U (rank x n, ldy)
+  Dim ldy;
+  int* meta;        // out: optional {rank, m, n} (trace)
+  int* err;
+  int* abort_word;
+};
+
+// Chooses the workgroup shape for mmax x nmax, launches cooperatively.
+hipError_t launch_prrlu(const PrrluArgs& a, int mmax, int nmax, hipStream_t s);
+// Exchange-buffer words needed for matrices up to mmax x nmax.
+size_t prrlu_xbuf_words(int mmax, int nmax);
+
+// ----------------------------------------------------------------- gathers
+struct GatherItem {
+  const double* src;
+  double* dst;
+  Dim ld_src;
+  Dim ld_dst;
+  Dim extent;        // side 0: row length; side 1: number of rows
+  Dim src_n;         // side 0: rows of src; side 1: columns of src (index bound)
+};
+struct GatherArgs {
+  GatherItem it[ACI_MAX_INPUTS + 1];
+  int count;
+  int side;          // 0: rows of src (dst row k = src row idx[k]); 1: columns
+  const int* idx;
+  const int* rank;   // number of gathered rows/columns (device)
+  int* err;          // ERR_LIMIT is or-ed in for an index out of range (may be null)
+};
+hipError_t launch_gather(const GatherArgs& a, int rmax, int extent_max, hipStream_t s);
+
+// Fill `count` doubles with `value` (used instead of a memset so the sweep can
+// be captured in a graph).
+hipError_t launch_fill(double* p, size_t count, double value, hipStream_t s);
+hipError_t launch_fill_int(int* p, size_t count, int value, hipStream_t s);
+
+}  // namespace aci

@@ -1,0 +1,122 @@
+"""End-to-end parity of the HIP sweep (aci_elementwise) with the oracle:
+identical pivot sets for every prrLU call of the run (initialisation and
+both half sweeps), identical ranks, error estimates and convergence, and
+output tensors within 1e-10 relative of the oracle's."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import compare_records, rel_max_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+aci = pytest.importorskip("paper_2604_00037_amd")
+
+
+def run_both(inputs, op, tol, maxrank, maxiter=20, init=None, seed=0, rule="exclusive"):
+    ref = oracle.aci(inputs, op, tol, maxrank, maxiter=maxiter, init=init, seed=seed, rule=rule,
+                     log_gaps=True)
+    cores, info = aci.elementwise([to_dev(x) for x in inputs], op, tol, maxrank, maxiter=maxiter,
+                                  init=None if init is None else to_dev(init), seed=seed,
+                                  stop_rule=rule, trace=True)
+    return ref, [c.cpu().numpy() for c in cores], info
+
+
+def check(ref, cores, info, label, full=True):
+    n = compare_records(info.records, ref.trace, label)
+    assert n == len(ref.trace), f"{label}: pivots diverged at a near tie (record {n})"
+    assert info.ranks[1:-1] == ref.ranks
+    assert info.init_ranks[1:-1] == ref.init_ranks
+    assert info.sweeps == ref.sweeps and info.converged == ref.converged
+    np.testing.assert_allclose(info.eps, ref.eps, rtol=1e-9, atol=1e-14)
+    for g, o in zip(cores, ref.cores):
+        assert g.shape == o.shape
+    if full:
+        y = W.tt_full(cores)
+        yr = W.tt_full(ref.cores)
+        assert rel_max_err(y, yr) <= 1e-10, label
+
+
+def test_random_pair_default_init():
+    x1, x2 = W.random_pair()
+    ref, cores, info = run_both([x1, x2], "product", 1e-12, 64, seed=1003)
+    check(ref, cores, info, "random pair L=12 chi=8")
+    f = W.tt_full(x1) * W.tt_full(x2)
+    assert rel_max_err(W.tt_full(cores), f) <= 1e-12
+    assert info.ranks[1:-1] == [2, 4, 8, 16, 32, 64, 32, 16, 8, 4, 2]
+
+
+def test_random_pair_explicit_init():
+    x1, x2 = W.random_pair(L=10, chi=6, seeds=(1011, 1012))
+    init = W.random_init(oracle.default_init_ranks([x1, x2], 36), 2, seed=1013)
+    ref, cores, info = run_both([x1, x2], "product", 1e-12, 36, init=init)
+    check(ref, cores, info, "explicit init")
+
+
+@pytest.mark.parametrize("op,n_in", [("sum", 2), ("product", 3), ("product", 1), ("abs2_mul", 1)])
+def test_ops_and_arity(op, n_in):
+    xs = [W.left_orthogonalise(W.random_tt(9, 2, 4, seed=200 + i)) for i in range(n_in)]
+    ref, cores, info = run_both(xs, op, 1e-12, 80, seed=7)
+    check(ref, cores, info, f"{op} N={n_in}")
+
+
+def test_rank_capped_not_converged():
+    x1, x2 = W.random_pair(L=12, chi=8, seeds=(1021, 1022))
+    ref, cores, info = run_both([x1, x2], "product", 1e-12, 12, maxiter=3, seed=3)
+    check(ref, cores, info, "capped")
+    assert not info.converged and info.status == 1
+
+
+def test_literal_rule():
+    x1, x2 = W.random_pair(L=9, chi=5, seeds=(1031, 1032))
+    ref, cores, info = run_both([x1, x2], "product", 1e-10, 25, seed=4, rule="literal")
+    check(ref, cores, info, "literal")
+
+
+def test_ragged_local_dimensions_and_odd_ranks():
+    rng = np.random.default_rng(8)
+    L = 7
+    dims = [2, 3, 2, 4, 3, 2, 3]
+    xs = []
+    for n in range(2):
+        ranks = [1, 3, 5, 7, 5, 6, 2, 1]
+        xs.append([rng.standard_normal((ranks[l], dims[l], ranks[l + 1])) for l in range(L)])
+    ref, cores, info = run_both(xs, "product", 1e-12, 40, seed=9)
+    check(ref, cores, info, "ragged")
+
+
+def test_fourier3d_small_grid():
+    """3D random Fourier fields (k^-5/3 spectrum) on a 16^3 quantics grid."""
+    u, v = W.fourier3d_pair(R=4, kmax=4, chi=24, seeds=(2001, 2002))
+    ref, cores, info = run_both([u, v], "product", 1e-8, 48, seed=11)
+    check(ref, cores, info, "fourier3d R=4")
+
+
+def test_nan_input_is_reported():
+    x1, x2 = W.random_pair(L=6, chi=3, seeds=(1041, 1042))
+    x1 = [c.copy() for c in x1]
+    x1[2][0, 0, 0] = np.nan
+    with pytest.raises(Exception, match="NUMERIC"):
+        aci.elementwise([to_dev(x1), to_dev(x2)], "product", 1e-10, 16)
+
+
+def test_invalid_arguments_are_rejected():
+    x1, x2 = W.random_pair(L=6, chi=3, seeds=(1043, 1044))
+    with pytest.raises(Exception, match="INVALID"):
+        aci.elementwise([to_dev(x1), to_dev(x2)], "abs2_mul", 1e-10, 16)
+    with pytest.raises(Exception, match="INVALID"):
+        aci.elementwise([to_dev(x1)], "product", -1.0, 16)
+    with pytest.raises(Exception, match="LIMIT"):
+        aci.elementwise([to_dev(x1)], "product", 1e-10, 100000)
+
+
+def test_repeat_runs_are_bitwise_identical():
+    x1, x2 = W.random_pair(L=10, chi=6, seeds=(1051, 1052))
+    a, ia = aci.elementwise([to_dev(x1), to_dev(x2)], "product", 1e-10, 30, seed=5)
+    b, ib = aci.elementwise([to_dev(x1), to_dev(x2)], "product", 1e-10, 30, seed=5)
+    assert ia.ranks == ib.ranks
+    for p, q in zip(a, b):
+        assert torch.equal(p, q)

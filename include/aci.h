@@ -86,6 +86,8 @@ typedef struct {
   int32_t precision;     /* aci_precision, default ACI_PREC_FP64 */
   int32_t trace;         /* 1: record the pivots of every local update */
   int32_t fixed_sweeps;  /* 1: run exactly maxiter sweeps, no early exit */
+  int32_t profile;       /* 1: time every kernel launch with HIP events
+                            (aci_sweep_stats.kernel_ms) */
 } aci_options;
 
 /* Result of aci_elementwise.  Output cores are written compactly, site after
@@ -113,6 +115,47 @@ typedef struct {
   int32_t* rec_rows;                    /* host, n_records x record_stride */
   int32_t* rec_cols;                    /* host, n_records x record_stride */
 } aci_result;
+
+/* Per-call statistics of aci_session_sweep.  Kernel classes: 0 = LDU with
+ * full pivoting (including the pivot-matrix solve), 1 = contractions
+ * (environments and two-site tensors with f), 2 = frame gathers.
+ * Algorithmic flops of the sweeps of this call, from the shapes and ranks
+ * actually met:
+ *   class 0: sum over updates of sum_{k<r} 2 (m-k-1)(n-k-1), plus
+ *            r (r-1) (n-r) for the right-to-left solve U_JJ^{-1} U;
+ *   class 1: 2 m k n for every matrix product (k the inner dimension). */
+typedef struct {
+  int32_t sweeps_done;               /* sweeps of the session so far */
+  int32_t converged;                 /* convergence test after the last sweep */
+  double kernel_ms[3];               /* device time per class (options.profile) */
+  int64_t launches[3];
+  double flops[3];
+  int32_t pivots;                    /* prrLU steps (pivots accepted) in this call */
+  int32_t ranks[ACI_MAX_SITES + 1];  /* right-to-left ranks after the last sweep */
+  double max_eps;                    /* largest right-to-left error estimate */
+} aci_sweep_stats;
+
+/* A sweep session keeps the state of Alg. 1 between calls (frames, index
+ * sets, cached environments) so that sweeps can be run one at a time, e.g.
+ * for timing or to stop on a custom criterion.  It owns its device
+ * workspace; the input cores must stay valid until aci_session_destroy. */
+typedef struct aci_session aci_session;
+
+/* Validates the problem exactly like aci_elementwise, allocates the
+ * workspace and runs the initialisation of Alg. 1 (CI-canonical Y_init and
+ * the initial right frames). */
+int aci_session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype,
+                       int32_t op, double tol, int32_t maxrank, const aci_options* opt,
+                       aci_session** session);
+/* Runs nsweeps sweeps (left-to-right then right-to-left) and the
+ * convergence test after each; stops early once converged unless
+ * options.fixed_sweeps.  stats may be NULL.  Returns ACI_OK when converged,
+ * ACI_W_NOT_CONVERGED otherwise, or an error. */
+int aci_session_sweep(aci_session* session, int32_t nsweeps, aci_sweep_stats* stats);
+/* Writes the current output cores (those of the last right-to-left half
+ * sweep) like aci_elementwise does. */
+int aci_session_result(aci_session* session, void* out, int64_t out_capacity, aci_result* result);
+void aci_session_destroy(aci_session* session);
 
 /* Context: owns the device workspace, bound to the current device and to
  * `stream` (a hipStream_t; NULL = the null stream). */

@@ -36,6 +36,7 @@ it empirically ("parity unpinned" beyond that).
 
 from __future__ import annotations
 
+import time
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -95,6 +96,7 @@ class ACIResult:
     J: list                   # J_1..J_{L+1} (index 0 unused)
     init_ranks: list
     trace: list = field(default_factory=list)
+    times: list = field(default_factory=list)   # wall clock after init and after each sweep
 
 
 def _pi_tensors(inputs, Lf, Rf, l):
@@ -163,6 +165,7 @@ def aci(inputs, op, tol, maxrank, maxiter=20, init=None, seed=0,
             Rf[n][l] = right_frame(inputs[n][l - 1], Rf[n][l + 1], cols)
     init_ranks = [len(J[l + 1]) for l in range(1, L)]
     rho_prev = list(init_ranks)
+    times = [time.perf_counter()]
 
     Y = [None] * L
     eps_rl = np.zeros(L - 1)
@@ -209,10 +212,12 @@ def aci(inputs, op, tol, maxrank, maxiter=20, init=None, seed=0,
                               rows=lu.rows.copy(), cols=lu.cols.copy(),
                               min_gap=min(lu.gaps) if lu.gaps else None,
                               shape=M.shape))
+        times.append(time.perf_counter())
         grew = any(rho[i] > rho_prev[i] for i in range(L - 1))
         rho_prev = list(rho)
         if not grew and eps_rl.max() <= tol:
             converged = True
             break
     return ACIResult(cores=Y, ranks=list(rho), eps=eps_rl.copy(), sweeps=sweeps,
-                     converged=converged, I=I, J=J, init_ranks=init_ranks, trace=trace)
+                     converged=converged, I=I, J=J, init_ranks=init_ranks, trace=trace,
+                     times=times)

@@ -7,8 +7,8 @@ its single steps.  The library must be built (``python -m
 paper_2604_00037_amd.build``); nothing falls back to the CPU.
 """
 
-from .aci import (Context, default_context, elementwise, env_contract, gather, pi_eval,
+from .aci import (Context, Session, default_context, elementwise, env_contract, gather, pi_eval,
                   prrlu)
 
-__all__ = ["Context", "default_context", "elementwise", "env_contract", "gather", "pi_eval",
+__all__ = ["Context", "Session", "default_context", "elementwise", "env_contract", "gather", "pi_eval",
            "prrlu"]

@@ -23,6 +23,7 @@ STATUS_NAMES = {
 EXPORTED = [
     "aci_ctx_create", "aci_ctx_destroy", "aci_last_error", "aci_elementwise",
     "aci_result_free", "aci_env_contract", "aci_pi_eval", "aci_prrlu", "aci_gather",
+    "aci_session_create", "aci_session_sweep", "aci_session_result", "aci_session_destroy",
 ]
 
 
@@ -44,6 +45,7 @@ class AciOptions(C.Structure):
         ("precision", C.c_int32),
         ("trace", C.c_int32),
         ("fixed_sweeps", C.c_int32),
+        ("profile", C.c_int32),
     ]
 
 
@@ -64,6 +66,19 @@ class AciResult(C.Structure):
         ("rec_eps", C.POINTER(C.c_double)),
         ("rec_rows", C.POINTER(C.c_int32)),
         ("rec_cols", C.POINTER(C.c_int32)),
+    ]
+
+
+class AciSweepStats(C.Structure):
+    _fields_ = [
+        ("sweeps_done", C.c_int32),
+        ("converged", C.c_int32),
+        ("kernel_ms", C.c_double * 3),
+        ("launches", C.c_int64 * 3),
+        ("flops", C.c_double * 3),
+        ("pivots", C.c_int32),
+        ("ranks", C.c_int32 * (MAX_SITES + 1)),
+        ("max_eps", C.c_double),
     ]
 
 
@@ -107,5 +122,14 @@ def load(path=LIB_PATH):
     lib.aci_prrlu.restype = C.c_int
     lib.aci_gather.argtypes = [vp, i32, i32, vp, i32, i32, i32, vp, vp, vp, i32]
     lib.aci_gather.restype = C.c_int
+    lib.aci_session_create.argtypes = [vp, C.POINTER(AciTT), i32, i32, i32, C.c_double, i32,
+                                       C.POINTER(AciOptions), C.POINTER(vp)]
+    lib.aci_session_create.restype = C.c_int
+    lib.aci_session_sweep.argtypes = [vp, i32, C.POINTER(AciSweepStats)]
+    lib.aci_session_sweep.restype = C.c_int
+    lib.aci_session_result.argtypes = [vp, vp, C.c_int64, C.POINTER(AciResult)]
+    lib.aci_session_result.restype = C.c_int
+    lib.aci_session_destroy.argtypes = [vp]
+    lib.aci_session_destroy.restype = None
     _lib = lib
     return lib

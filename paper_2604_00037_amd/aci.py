@@ -93,21 +93,7 @@ class Info:
     records: list = field(default_factory=list)
 
 
-def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
-                stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False, ctx=None):
-    """Alg. 1: returns (cores, info) with cores a list of device tensors of
-    shape (r_{l-1}, d_l, r_l) approximating op(inputs) elementwise."""
-    ctx = ctx or default_context()
-    lib = ctx.lib
-    if len(inputs) < 1:
-        raise ValueError("need at least one input TT")
-    keep = []
-    for n, X in enumerate(inputs):
-        for l, c in enumerate(X):
-            _dev_tensor(c, f"inputs[{n}][{l}]")
-            if c.dim() != 3:
-                raise ValueError("cores must be 3-dimensional")
-    tts = (_lib.AciTT * len(inputs))(*[_tt_struct(X, keep) for X in inputs])
+def _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, profile):
     opts = _lib.AciOptions()
     opts.maxiter = maxiter
     opts.seed = seed
@@ -115,49 +101,135 @@ def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed
     opts.precision = PRECISIONS[precision]
     opts.trace = 1 if trace else 0
     opts.fixed_sweeps = 1 if fixed_sweeps else 0
+    opts.profile = 1 if profile else 0
     if init is not None:
         for l, c in enumerate(init):
             _dev_tensor(c, f"init[{l}]")
         init_tt = _tt_struct(init, keep)
         keep.append(init_tt)
         opts.init = C.pointer(init_tt)
+    return opts
+
+
+def _inputs(inputs, keep):
+    if len(inputs) < 1:
+        raise ValueError("need at least one input TT")
+    for n, X in enumerate(inputs):
+        for l, c in enumerate(X):
+            _dev_tensor(c, f"inputs[{n}][{l}]")
+            if c.dim() != 3:
+                raise ValueError("cores must be 3-dimensional")
+    return (_lib.AciTT * len(inputs))(*[_tt_struct(X, keep) for X in inputs])
+
+
+def _out_buffer(inputs, maxrank):
     L = len(inputs[0])
     dmax = max(int(c.shape[1]) for c in inputs[0])
     # capacity for every admissible rank profile (maxrank above the compiled
     # limit is rejected by the library itself)
     mr = min(int(maxrank), 512)
     cap = L * dmax * mr * mr
-    out = torch.empty(cap, dtype=torch.float64, device=inputs[0][0].device)
+    return torch.empty(cap, dtype=torch.float64, device=inputs[0][0].device), cap
+
+
+def _unpack(res, out, dims, status, trace):
+    L = len(dims)
+    ranks = [res.ranks[i] for i in range(L + 1)]
+    cores = []
+    for l in range(L):
+        off = res.core_offset[l]
+        cnt = ranks[l] * dims[l] * ranks[l + 1]
+        cores.append(out[off:off + cnt].view(ranks[l], dims[l], ranks[l + 1]))
+    records = []
+    if trace:
+        stride = res.record_stride
+        for r in range(res.n_records):
+            meta = [res.rec_meta[6 * r + i] for i in range(6)]
+            rank = meta[3]
+            records.append(dict(
+                kind=("init", "LR", "RL")[meta[0]], sweep=meta[1], bond=meta[2], rank=rank,
+                m=meta[4], n=meta[5], eps=res.rec_eps[r],
+                rows=[res.rec_rows[stride * r + i] for i in range(rank)],
+                cols=[res.rec_cols[stride * r + i] for i in range(rank)]))
+    info = Info(status=status, sweeps=res.sweeps, converged=bool(res.converged),
+                ranks=ranks, eps=[res.eps[i] for i in range(L - 1)],
+                init_ranks=[res.init_ranks[i] for i in range(L + 1)],
+                sweep_ms=res.sweep_ms, records=records)
+    return cores, info
+
+
+def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
+                stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False, ctx=None):
+    """Alg. 1: returns (cores, info) with cores a list of device tensors of
+    shape (r_{l-1}, d_l, r_l) approximating op(inputs) elementwise."""
+    ctx = ctx or default_context()
+    lib = ctx.lib
+    keep = []
+    tts = _inputs(inputs, keep)
+    opts = _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, False)
+    out, cap = _out_buffer(inputs, maxrank)
     res = _lib.AciResult()
     status = lib.aci_elementwise(ctx.h, tts, len(inputs), F64, OPS[op], float(tol), int(maxrank),
                                  C.byref(opts), C.c_void_p(out.data_ptr()), cap, C.byref(res))
     try:
         _check(lib, ctx.h, status)
-        ranks = [res.ranks[i] for i in range(L + 1)]
-        dims = [int(c.shape[1]) for c in inputs[0]]
-        cores = []
-        for l in range(L):
-            off = res.core_offset[l]
-            cnt = ranks[l] * dims[l] * ranks[l + 1]
-            cores.append(out[off:off + cnt].view(ranks[l], dims[l], ranks[l + 1]))
-        records = []
-        if trace:
-            stride = res.record_stride
-            for r in range(res.n_records):
-                meta = [res.rec_meta[6 * r + i] for i in range(6)]
-                rank = meta[3]
-                records.append(dict(
-                    kind=("init", "LR", "RL")[meta[0]], sweep=meta[1], bond=meta[2], rank=rank,
-                    m=meta[4], n=meta[5], eps=res.rec_eps[r],
-                    rows=[res.rec_rows[stride * r + i] for i in range(rank)],
-                    cols=[res.rec_cols[stride * r + i] for i in range(rank)]))
-        info = Info(status=status, sweeps=res.sweeps, converged=bool(res.converged),
-                    ranks=ranks, eps=[res.eps[i] for i in range(L - 1)],
-                    init_ranks=[res.init_ranks[i] for i in range(L + 1)],
-                    sweep_ms=res.sweep_ms, records=records)
+        return _unpack(res, out, [int(c.shape[1]) for c in inputs[0]], status, trace)
     finally:
         lib.aci_result_free(C.byref(res))
-    return cores, info
+
+
+class Session:
+    """Alg. 1 one sweep at a time: the constructor runs the initialisation,
+    ``sweep(n)`` runs n sweeps, ``result()`` returns the current output."""
+
+    def __init__(self, inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
+                 stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False,
+                 profile=False, ctx=None):
+        self.ctx = ctx or default_context()
+        self.inputs = inputs            # the library reads these until close()
+        self.maxrank = maxrank
+        self.trace = trace
+        self._keep = []
+        tts = _inputs(inputs, self._keep)
+        opts = _options(self._keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps,
+                        profile)
+        self._init = init
+        h = C.c_void_p()
+        st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), F64, OPS[op], float(tol),
+                                             int(maxrank), C.byref(opts), C.byref(h))
+        _check(self.ctx.lib, self.ctx.h, st, allow_warning=False)
+        self.h = h
+
+    def sweep(self, n=1):
+        stats = _lib.AciSweepStats()
+        st = self.ctx.lib.aci_session_sweep(self.h, int(n), C.byref(stats))
+        _check(self.ctx.lib, self.ctx.h, st)
+        L = len(self.inputs[0])
+        return dict(status=st, sweeps_done=stats.sweeps_done, converged=bool(stats.converged),
+                    kernel_ms=list(stats.kernel_ms), launches=list(stats.launches),
+                    flops=list(stats.flops), pivots=stats.pivots,
+                    ranks=[stats.ranks[i] for i in range(L + 1)], max_eps=stats.max_eps)
+
+    def result(self):
+        out, cap = _out_buffer(self.inputs, self.maxrank)
+        res = _lib.AciResult()
+        st = self.ctx.lib.aci_session_result(self.h, C.c_void_p(out.data_ptr()), cap, C.byref(res))
+        try:
+            _check(self.ctx.lib, self.ctx.h, st)
+            return _unpack(res, out, [int(c.shape[1]) for c in self.inputs[0]], st, self.trace)
+        finally:
+            self.ctx.lib.aci_result_free(C.byref(res))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.aci_session_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------ single steps

@@ -30,14 +30,10 @@ struct aci_ctx {
   int device = 0;
   std::string err;
   uint32_t flag_next = 1;
-  // workspace of aci_elementwise (grown on demand)
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
   // small persistent workspace of the single-step entry points
   int* step_err = nullptr;     // [0] error flags, [1] abort word
   uint64_t* step_xbuf = nullptr;
   size_t step_xwords = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
 namespace {
@@ -133,6 +129,7 @@ struct Plan {
   double* tr_eps = nullptr;
   int* tr_rows = nullptr;
   int* tr_cols = nullptr;
+  int* meta = nullptr;   // {rank, m, n} of the init calls, then of the current sweep
 };
 
 void layout(Plan& p, Arena& A, bool gen_init) {
@@ -164,6 +161,7 @@ void layout(Plan& p, Arena& A, bool gen_init) {
   p.flags = A.take<int>(4);
   p.xbuf_words = prrlu_xbuf_words(p.ldm, p.ldm);
   p.xbuf = A.take<uint64_t>(p.xbuf_words);
+  p.meta = A.take<int>((size_t)3 * 3 * (L - 1));
   if (p.trace) {
     p.tr_meta = A.take<int>((size_t)3 * p.n_rec);
     p.tr_eps = A.take<double>(p.n_rec);
@@ -172,11 +170,44 @@ void layout(Plan& p, Arena& A, bool gen_init) {
   }
 }
 
+// Kernel classes of the profile (see aci_sweep_stats).
+enum { CLS_PRRLU = 0, CLS_CONTRACT = 1, CLS_GATHER = 2, NCLS = 3 };
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> cls;   // class of event pair i (events 2i, 2i+1)
+  size_t used = 0;
+};
+
 struct Enq {
   aci_ctx* ctx;
   Plan& p;
   hipStream_t s;
-  int rec = 0;
+  int rec = 0;          // prrLU calls so far (trace record index)
+  int slot = 0;         // meta slot: init calls 0..L-2, sweep calls L-1 ..
+  Prof* prof = nullptr;
+
+  int begin(int c) {
+    if (!prof || !prof->on) return ACI_OK;
+    if (prof->used + 2 > prof->pool.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return set_err(ctx, ACI_E_HIP, "hipEventCreate");
+        prof->pool.push_back(e);
+      }
+    }
+    prof->cls.push_back(c);
+    if (hipEventRecord(prof->pool[prof->used], s) != hipSuccess) return set_err(ctx, ACI_E_HIP, "hipEventRecord");
+    return ACI_OK;
+  }
+  int end() {
+    if (!prof || !prof->on) return ACI_OK;
+    if (hipEventRecord(prof->pool[prof->used + 1], s) != hipSuccess) return set_err(ctx, ACI_E_HIP, "hipEventRecord");
+    prof->used += 2;
+    return ACI_OK;
+  }
+  bool tracing() const { return p.trace && rec < p.n_rec; }
 
   int prrlu(const double* M, Dim m, Dim n, Dim ldm, int mmax, int nmax, int* rank2, double* eps2,
             double* Y, Dim ldy) {
@@ -192,17 +223,17 @@ struct Enq {
     a.spin_limit = kSpinLimit;
     a.xbuf = p.xbuf;
     a.xbuf_words = p.xbuf_words;
-    if (p.trace) {
+    if (tracing()) {
       a.rows = p.tr_rows + (size_t)rec * p.maxrank;
       a.cols = p.tr_cols + (size_t)rec * p.maxrank;
       a.eps = p.tr_eps + rec;
-      a.meta = p.tr_meta + (size_t)3 * rec;
     } else {
       a.rows = p.prow;
       a.cols = p.pcol;
       a.eps = p.peps;
-      a.meta = nullptr;
     }
+    a.meta = p.meta + (size_t)3 * slot;
+    a.meta2 = tracing() ? p.tr_meta + (size_t)3 * rec : nullptr;
     a.rank = p.prank;
     a.rank2 = rank2;
     a.eps2 = eps2;
@@ -210,12 +241,19 @@ struct Enq {
     a.ldy = ldy;
     a.err = p.flags;
     a.abort_word = p.flags + 1;
+    int rc = begin(CLS_PRRLU);
+    if (rc) return rc;
     hipError_t e = launch_prrlu(a, mmax, nmax, s);
     if (e != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("prrlu launch: ") + hipGetErrorString(e));
-    return ACI_OK;
+    return end();
   }
-  const int* rows() const { return p.trace ? p.tr_rows + (size_t)rec * p.maxrank : p.prow; }
-  const int* cols() const { return p.trace ? p.tr_cols + (size_t)rec * p.maxrank : p.pcol; }
+  // pointers the prrLU of the current record wrote its pivots to
+  const int* rows() const { return tracing() ? p.tr_rows + (size_t)rec * p.maxrank : p.prow; }
+  const int* cols() const { return tracing() ? p.tr_cols + (size_t)rec * p.maxrank : p.pcol; }
+  void next_record() {
+    ++rec;
+    ++slot;
+  }
 };
 
 #define ENQ(call)                                                                   \
@@ -223,6 +261,16 @@ struct Enq {
     hipError_t e_ = (call);                                                         \
     if (e_ != hipSuccess)                                                           \
       return set_err(ctx, ACI_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// a profiled launch of class `cls`
+#define ENQP(q, cls, call)            \
+  do {                                \
+    int rc_ = (q).begin(cls);         \
+    if (rc_) return rc_;              \
+    ENQ(call);                        \
+    rc_ = (q).end();                  \
+    if (rc_) return rc_;              \
   } while (0)
 
 // Initialisation (Alg. 1, first two loops): CI-canonical form of Y_init from
@@ -257,7 +305,7 @@ int enqueue_init(Enq& q) {
       g.rank = p.nJ + l;
       g.err = p.flags;
       g.it[0] = GatherItem{Msrc, p.Atmp, ncols, dconst(p.ldR), dconst(p.rho[l - 1]), ncols};
-      ENQ(launch_gather(g, p.maxrank, p.rho[l - 1], s));
+      ENQP(q, CLS_GATHER, launch_gather(g, p.maxrank, p.rho[l - 1], s));
       ContractArgs c{};
       c.ngroup = 1;
       c.err = nullptr;
@@ -268,7 +316,7 @@ int enqueue_init(Enq& q) {
       gr.M = dconst(p.rho[l - 2] * p.d[l - 1]);
       gr.N = ddev(p.nJ + l);
       gr.ldc = ddev(p.nJ + l);
-      ENQ(launch_contract(OP_NONE, c, p.rho[l - 2] * p.d[l - 1], p.maxrank, s));
+      ENQP(q, CLS_CONTRACT, launch_contract(OP_NONE, c, p.rho[l - 2] * p.d[l - 1], p.maxrank, s));
     }
     // B^n_{l-1} = X^n_l R^n_{l+1};  R^n_l = B^n_{l-1}[:, J_l]  (Alg. 5, Rightframe)
     ContractArgs c{};
@@ -284,7 +332,7 @@ int enqueue_init(Enq& q) {
       gr.ldc = ddev(p.nJ + l + 1);
       mmax = std::max(mmax, p.r[n][l - 1] * dl);
     }
-    ENQ(launch_contract(OP_NONE, c, mmax, p.capJ[l + 1], s));
+    ENQP(q, CLS_CONTRACT, launch_contract(OP_NONE, c, mmax, p.capJ[l + 1], s));
     GatherArgs g{};
     g.count = p.N;
     g.side = 1;
@@ -296,8 +344,8 @@ int enqueue_init(Enq& q) {
       g.it[n] = GatherItem{p.Bc[n][l - 1], p.Rf[n][l], ncols, dconst(p.ldR), dconst(p.r[n][l - 1]), ncols};
       emax = std::max(emax, p.r[n][l - 1]);
     }
-    ENQ(launch_gather(g, p.capJ[l], emax, s));
-    ++q.rec;
+    ENQP(q, CLS_GATHER, launch_gather(g, p.capJ[l], emax, s));
+    q.next_record();
   }
   return ACI_OK;
 }
@@ -318,7 +366,7 @@ int enqueue_pi(Enq& q, int l) {
   gr.M = ddev(p.nI + l - 1, p.d[l]);
   gr.N = ddev(p.nJ + l + 2, p.d[l + 1]);
   gr.ldc = dconst(p.ldm);
-  ENQ(launch_contract(p.op, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], q.s));
+  ENQP(q, CLS_CONTRACT, launch_contract(p.op, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], q.s));
   return ACI_OK;
 }
 
@@ -327,6 +375,7 @@ int enqueue_sweep(Enq& q) {
   Plan& p = q.p;
   hipStream_t s = q.s;
   const int L = p.L;
+  q.slot = L - 1;
   // ---- left to right
   for (int l = 1; l <= L - 1; ++l) {
     ContractArgs c{};
@@ -343,7 +392,7 @@ int enqueue_sweep(Enq& q) {
       gr.ldc = dconst(w);
       nmax = std::max(nmax, w);
     }
-    ENQ(launch_contract(OP_NONE, c, p.capI[l - 1], nmax, s));
+    ENQP(q, CLS_CONTRACT, launch_contract(OP_NONE, c, p.capI[l - 1], nmax, s));
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const int mmax = p.d[l] * p.capI[l - 1], nmax2 = p.d[l + 1] * p.capJ[l + 2];
@@ -363,8 +412,8 @@ int enqueue_sweep(Enq& q) {
                            ddev(p.nI + l - 1, p.d[l])};
       emax = std::max(emax, p.r[n][l]);
     }
-    ENQ(launch_gather(g, p.capI[l], emax, s));
-    ++q.rec;
+    ENQP(q, CLS_GATHER, launch_gather(g, p.capI[l], emax, s));
+    q.next_record();
   }
   // ---- right to left
   for (int l = L - 1; l >= 1; --l) {
@@ -381,7 +430,7 @@ int enqueue_sweep(Enq& q) {
       gr.ldc = ddev(p.nJ + l + 2);
       mmax = std::max(mmax, p.r[n][l] * p.d[l + 1]);
     }
-    ENQ(launch_contract(OP_NONE, c, mmax, p.capJ[l + 2], s));
+    ENQP(q, CLS_CONTRACT, launch_contract(OP_NONE, c, mmax, p.capJ[l + 2], s));
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const Dim ncols = ddev(p.nJ + l + 2, p.d[l + 1]);
@@ -406,8 +455,8 @@ int enqueue_sweep(Enq& q) {
       g.count = p.N + 1;
       emax = std::max(emax, p.d[1]);
     }
-    ENQ(launch_gather(g, p.capJ[l + 1], emax, s));
-    ++q.rec;
+    ENQP(q, CLS_GATHER, launch_gather(g, p.capJ[l + 1], emax, s));
+    q.next_record();
   }
   return ACI_OK;
 }
@@ -425,60 +474,28 @@ int validate_tt(aci_ctx* ctx, const aci_tt& t, int L) {
 
 }  // namespace
 
-// =============================================================== C ABI
-extern "C" {
+// =============================================================== sessions
+struct aci_session {
+  aci_ctx* ctx = nullptr;
+  std::unique_ptr<Plan> plan;
+  void* ws = nullptr;
+  int rec = 0;
+  int sweeps = 0;
+  bool converged = false;
+  bool fixed = false;
+  std::vector<int> prev;
+  int init_ranks[ACI_MAX_SITES + 1];
+  Prof prof;
+  double sweep_ms = 0.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
 
-int aci_ctx_create(aci_ctx** out, void* stream) {
-  if (!out) return ACI_E_INVALID;
-  *out = nullptr;
-  aci_ctx* ctx = new (std::nothrow) aci_ctx();
-  if (!ctx) return ACI_E_NOMEM;
-  ctx->stream = (hipStream_t)stream;
-  if (hipGetDevice(&ctx->device) != hipSuccess) {
-    delete ctx;
-    return ACI_E_HIP;
-  }
-  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
-    delete ctx;
-    return ACI_E_HIP;
-  }
-  *out = ctx;
-  return ACI_OK;
-}
+namespace {
 
-void aci_ctx_destroy(aci_ctx* ctx) {
-  if (!ctx) return;
-  (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->ws) (void)hipFree(ctx->ws);
-  if (ctx->step_err) (void)hipFree(ctx->step_err);
-  if (ctx->step_xbuf) (void)hipFree(ctx->step_xbuf);
-  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
-  delete ctx;
-}
-
-const char* aci_last_error(const aci_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
-
-void aci_result_free(aci_result* r) {
-  if (!r) return;
-  free(r->rec_meta);
-  free(r->rec_eps);
-  free(r->rec_rows);
-  free(r->rec_cols);
-  r->rec_meta = nullptr;
-  r->rec_eps = nullptr;
-  r->rec_rows = nullptr;
-  r->rec_cols = nullptr;
-  r->n_records = 0;
-}
-
-int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
-                    double tol, int32_t maxrank, const aci_options* opt, void* out, int64_t out_capacity,
-                    aci_result* result) {
-  if (!ctx) return ACI_E_INVALID;
-  ctx->err.clear();
-  if (!inputs || !result || !out) return set_err(ctx, ACI_E_INVALID, "null argument");
-  std::memset(result, 0, sizeof(*result));
+// Validation and static sizes shared by aci_elementwise and the sessions.
+int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op, double tol,
+                 int32_t maxrank, const aci_options& o, Plan& p) {
+  if (!inputs) return set_err(ctx, ACI_E_INVALID, "null inputs");
   if (n_inputs < 1 || n_inputs > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
   if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64 cores are supported by this build");
   if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL) return set_err(ctx, ACI_E_INVALID, "unknown op");
@@ -486,19 +503,10 @@ int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_
   if (!(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "tol must be >= 0");
   if (maxrank < 1) return set_err(ctx, ACI_E_INVALID, "maxrank must be >= 1");
   if (maxrank > ACI_MAX_RANK) return set_err(ctx, ACI_E_LIMIT, "maxrank above ACI_MAX_RANK");
-  const int L = inputs[0].L;
-  if (L < 2 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
-  aci_options o{};
-  o.maxiter = 20;
-  if (opt) o = *opt;
-  if (o.maxiter <= 0) o.maxiter = 20;
   if (o.precision != ACI_PREC_FP64) return set_err(ctx, ACI_E_DTYPE, "only ACI_PREC_FP64 is supported by this build");
   if (o.stop_rule != 0 && o.stop_rule != 1) return set_err(ctx, ACI_E_INVALID, "stop_rule must be 0 or 1");
-
-  Plan* pp = new (std::nothrow) Plan();
-  if (!pp) return set_err(ctx, ACI_E_NOMEM, "host allocation");
-  std::unique_ptr<Plan> hold(pp);
-  Plan& p = *pp;
+  const int L = inputs[0].L;
+  if (L < 2 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
   p.L = L;
   p.N = n_inputs;
   p.op = op;
@@ -526,16 +534,13 @@ int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_
   }
   p.d[0] = 1;
   if ((long long)p.D * maxrank > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "d * maxrank above ACI_MAX_MATRIX");
-  // static bounds of |I_l| and |J_l|
   p.capI[0] = 1;
   for (int l = 1; l <= L; ++l) p.capI[l] = sat_mul(p.capI[l - 1], p.d[l], maxrank);
   p.capJ[L + 1] = 1;
   for (int l = L; l >= 1; --l) p.capJ[l] = sat_mul(p.capJ[l + 1], p.d[l], maxrank);
   p.ldm = p.D * maxrank;
   p.ldR = maxrank;
-  // initial guess
-  const bool gen_init = (o.init == nullptr);
-  if (!gen_init) {
+  if (o.init) {
     int rc = validate_tt(ctx, *o.init, L);
     if (rc) return rc;
     for (int l = 0; l < L; ++l)
@@ -553,25 +558,116 @@ int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_
     }
   }
   p.n_rec = (L - 1) * (1 + 2 * p.maxiter);
+  return ACI_OK;
+}
 
-  // ---- workspace
+// Algorithmic flops of one prrLU record and of the contractions of its update.
+void account(const Plan& p, int kind, int bond, int r, int m, int n, aci_sweep_stats& st) {
+  double f = 0.0;
+  for (int k = 0; k < r; ++k) f += 2.0 * (double)(m - k - 1) * (double)(n - k - 1);
+  if (kind == 2 && n > r) f += (double)r * (r - 1) * (double)(n - r);
+  st.flops[CLS_PRRLU] += f;
+  st.pivots += r;
+  if (kind == 0) return;
+  const int l = bond;
+  const double cL = (double)m / p.d[l], cR = (double)n / p.d[l + 1];
+  double c = 0.0;
+  for (int q = 0; q < p.N; ++q) {
+    if (kind == 1)
+      c += 2.0 * cL * p.r[q][l - 1] * p.d[l] * p.r[q][l];
+    else
+      c += 2.0 * p.r[q][l] * p.d[l + 1] * p.r[q][l + 1] * cR;
+    c += 2.0 * (double)m * p.r[q][l] * (double)n;
+  }
+  st.flops[CLS_CONTRACT] += c;
+}
+
+}  // namespace
+
+// =============================================================== C ABI
+extern "C" {
+
+int aci_ctx_create(aci_ctx** out, void* stream) {
+  if (!out) return ACI_E_INVALID;
+  *out = nullptr;
+  aci_ctx* ctx = new (std::nothrow) aci_ctx();
+  if (!ctx) return ACI_E_NOMEM;
+  ctx->stream = (hipStream_t)stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return ACI_E_HIP;
+  }
+  *out = ctx;
+  return ACI_OK;
+}
+
+void aci_ctx_destroy(aci_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->step_err) (void)hipFree(ctx->step_err);
+  if (ctx->step_xbuf) (void)hipFree(ctx->step_xbuf);
+  delete ctx;
+}
+
+const char* aci_last_error(const aci_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void aci_result_free(aci_result* r) {
+  if (!r) return;
+  free(r->rec_meta);
+  free(r->rec_eps);
+  free(r->rec_rows);
+  free(r->rec_cols);
+  r->rec_meta = nullptr;
+  r->rec_eps = nullptr;
+  r->rec_rows = nullptr;
+  r->rec_cols = nullptr;
+  r->n_records = 0;
+}
+
+void aci_session_destroy(aci_session* S) {
+  if (!S) return;
+  if (S->ctx) (void)hipStreamSynchronize(S->ctx->stream);
+  if (S->ws) (void)hipFree(S->ws);
+  for (hipEvent_t e : S->prof.pool) (void)hipEventDestroy(e);
+  if (S->e0) (void)hipEventDestroy(S->e0);
+  if (S->e1) (void)hipEventDestroy(S->e1);
+  delete S;
+}
+
+int aci_session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
+                       double tol, int32_t maxrank, const aci_options* opt, aci_session** out) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!out) return set_err(ctx, ACI_E_INVALID, "null session pointer");
+  *out = nullptr;
+  aci_options o{};
+  o.maxiter = 20;
+  if (opt) o = *opt;
+  if (o.maxiter <= 0) o.maxiter = 20;
+  std::unique_ptr<aci_session> S(new (std::nothrow) aci_session());
+  if (!S) return set_err(ctx, ACI_E_NOMEM, "host allocation");
+  S->ctx = ctx;
+  S->plan.reset(new (std::nothrow) Plan());
+  if (!S->plan) return set_err(ctx, ACI_E_NOMEM, "host allocation");
+  Plan& p = *S->plan;
+  int rc = plan_problem(ctx, inputs, n_inputs, dtype, op, tol, maxrank, o, p);
+  if (rc) return rc;
+  S->fixed = p.fixed;
+  S->prof.on = o.profile != 0;
+  const bool gen_init = (o.init == nullptr);
   Arena sz;
   layout(p, sz, gen_init);
-  const size_t need = sz.off + 256;
-  if (need > ctx->ws_bytes) {
-    if (ctx->ws) {
-      (void)hipStreamSynchronize(ctx->stream);
-      (void)hipFree(ctx->ws);
-      ctx->ws = nullptr;
-      ctx->ws_bytes = 0;
-    }
-    if (hipMalloc(&ctx->ws, need) != hipSuccess) return set_err(ctx, ACI_E_NOMEM, "workspace allocation failed");
-    ctx->ws_bytes = need;
+  if (hipMalloc(&S->ws, sz.off + 256) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(ctx, ACI_E_NOMEM, "workspace allocation failed");
   }
   Arena ar;
-  ar.base = (char*)ctx->ws;
+  ar.base = (char*)S->ws;
   layout(p, ar, gen_init);
+  HIPCHK(hipEventCreate(&S->e0));
+  HIPCHK(hipEventCreate(&S->e1));
   hipStream_t s = ctx->stream;
+  const int L = p.L;
   if (gen_init) {
     SplitMix64 rng{o.seed};
     std::vector<double> h;
@@ -586,63 +682,106 @@ int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_
   } else {
     for (int l = 1; l <= L; ++l) p.Yin[l] = (const double*)o.init->cores[l - 1];
   }
-
-  Enq q{ctx, p, s, 0};
-  int rc = enqueue_init(q);
+  Enq q{ctx, p, s, 0, 0, nullptr};
+  rc = enqueue_init(q);
   if (rc) return rc;
-  HIPCHK(hipMemcpyAsync(result->init_ranks + 1, p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  result->init_ranks[0] = result->init_ranks[L] = 1;
-
-  std::vector<int> prev(result->init_ranks + 1, result->init_ranks + L);
-  std::vector<int> cur(L - 1);
-  std::vector<double> epsb(L - 1);
-  int sweeps = 0;
-  bool converged = false;
-  HIPCHK(hipEventRecord(ctx->ev0, s));
-  for (int it = 1; it <= p.maxiter; ++it) {
-    rc = enqueue_sweep(q);
-    if (rc) return rc;
-    sweeps = it;
-    if (!p.fixed) {
-      HIPCHK(hipMemcpyAsync(cur.data(), p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(epsb.data(), p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      bool grew = false;
-      double emax = 0.0;
-      for (int b = 0; b < L - 1; ++b) {
-        grew = grew || cur[b] > prev[b];
-        emax = std::max(emax, epsb[b]);
-      }
-      prev = cur;
-      if (!grew && emax <= tol) {
-        converged = true;
-        break;
-      }
-    }
-  }
-  HIPCHK(hipEventRecord(ctx->ev1, s));
+  S->rec = q.rec;
+  S->init_ranks[0] = S->init_ranks[L] = 1;
+  HIPCHK(hipMemcpyAsync(S->init_ranks + 1, p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
   int flags[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(flags, p.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (flags[0] & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "a pivot exchange exceeded its spin limit");
+  if (flags[0] & ERR_LIMIT) return set_err(ctx, ACI_E_LIMIT, "a pivot index fell outside its matrix");
+  S->prev.assign(S->init_ranks + 1, S->init_ranks + L);
+  *out = S.release();
+  return ACI_OK;
+}
+
+int aci_session_sweep(aci_session* S, int32_t nsweeps, aci_sweep_stats* stats) {
+  if (!S || !S->ctx) return ACI_E_INVALID;
+  aci_ctx* ctx = S->ctx;
+  ctx->err.clear();
+  if (nsweeps < 0) return set_err(ctx, ACI_E_INVALID, "nsweeps < 0");
+  Plan& p = *S->plan;
+  const int L = p.L;
+  hipStream_t s = ctx->stream;
+  aci_sweep_stats st{};
+  std::vector<int> cur(L - 1), meta((size_t)3 * 2 * (L - 1));
+  std::vector<double> epsb(L - 1);
+  for (int it = 0; it < nsweeps; ++it) {
+    S->prof.used = 0;
+    S->prof.cls.clear();
+    Enq q{ctx, p, s, S->rec, L - 1, &S->prof};
+    HIPCHK(hipEventRecord(S->e0, s));
+    int rc = enqueue_sweep(q);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(S->e1, s));
+    S->rec = q.rec;
+    int flags[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(cur.data(), p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(epsb.data(), p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(meta.data(), p.meta + 3 * (L - 1), sizeof(int) * meta.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(flags, p.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ++S->sweeps;
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, S->e0, S->e1));
+    S->sweep_ms += ms;
+    if (flags[0] & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "a pivot exchange exceeded its spin limit");
+    if (flags[0] & ERR_NONFINITE) return set_err(ctx, ACI_E_NUMERIC, "NaN or Inf in a two-site tensor");
+    if (flags[0] & ERR_LIMIT) return set_err(ctx, ACI_E_LIMIT, "a pivot index fell outside its matrix");
+    for (size_t i = 0; i < S->prof.cls.size(); ++i) {
+      float kms = 0.f;
+      HIPCHK(hipEventElapsedTime(&kms, S->prof.pool[2 * i], S->prof.pool[2 * i + 1]));
+      st.kernel_ms[S->prof.cls[i]] += kms;
+      st.launches[S->prof.cls[i]] += 1;
+    }
+    for (int u = 0; u < 2 * (L - 1); ++u) {
+      const int kind = u < L - 1 ? 1 : 2;
+      const int bond = u < L - 1 ? u + 1 : 2 * (L - 1) - u;
+      account(p, kind, bond, meta[3 * u], meta[3 * u + 1], meta[3 * u + 2], st);
+    }
+    bool grew = false;
+    double emax = 0.0;
+    for (int b = 0; b < L - 1; ++b) {
+      grew = grew || cur[b] > S->prev[b];
+      emax = std::max(emax, epsb[b]);
+    }
+    S->prev = cur;
+    S->converged = !grew && emax <= p.tol;
+    st.max_eps = emax;
+    if (S->converged && !S->fixed) break;
+  }
+  st.sweeps_done = S->sweeps;
+  st.converged = S->converged ? 1 : 0;
+  st.ranks[0] = st.ranks[L] = 1;
+  for (int b = 1; b < L; ++b) st.ranks[b] = S->prev[b - 1];
+  if (stats) *stats = st;
+  return S->converged ? ACI_OK : ACI_W_NOT_CONVERGED;
+}
+
+int aci_session_result(aci_session* S, void* out, int64_t out_capacity, aci_result* result) {
+  if (!S || !S->ctx) return ACI_E_INVALID;
+  aci_ctx* ctx = S->ctx;
+  ctx->err.clear();
+  if (!out || !result) return set_err(ctx, ACI_E_INVALID, "null argument");
+  std::memset(result, 0, sizeof(*result));
+  if (S->sweeps < 1) return set_err(ctx, ACI_E_INVALID, "no sweep has run");
+  Plan& p = *S->plan;
+  const int L = p.L;
+  const int maxrank = p.maxrank;
+  hipStream_t s = ctx->stream;
+  std::vector<int> cur(L - 1);
+  std::vector<double> epsb(L - 1);
   HIPCHK(hipMemcpyAsync(cur.data(), p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(epsb.data(), p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-  if (flags[0] & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "a pivot exchange exceeded its spin limit");
-  if (flags[0] & ERR_NONFINITE) return set_err(ctx, ACI_E_NUMERIC, "NaN or Inf in a two-site tensor");
-  if (flags[0] & ERR_LIMIT) return set_err(ctx, ACI_E_LIMIT, "a pivot index fell outside its matrix");
-  if (p.fixed) {
-    double emax = 0.0;
-    for (int b = 0; b < L - 1; ++b) emax = std::max(emax, epsb[b]);
-    converged = emax <= tol;
-  }
-
-  // ---- output cores, compacted site after site
   result->L = L;
-  result->sweeps = sweeps;
-  result->converged = converged ? 1 : 0;
-  result->sweep_ms = ms;
+  result->sweeps = S->sweeps;
+  result->converged = S->converged ? 1 : 0;
+  result->sweep_ms = S->sweep_ms;
+  std::memcpy(result->init_ranks, S->init_ranks, sizeof(int) * (L + 1));
   result->ranks[0] = result->ranks[L] = 1;
   for (int b = 1; b < L; ++b) {
     result->ranks[b] = cur[b - 1];
@@ -655,53 +794,72 @@ int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_
   for (int l = 1; l <= L; ++l) {
     const int64_t cnt = (int64_t)result->ranks[l - 1] * p.d[l] * result->ranks[l];
     result->core_offset[l - 1] = off;
-    const double* src = p.Ycore[l];
-    if (l == L) {
-      // Y_L of the bond L-1 update has shape rank x d x 1: same compact layout
-    }
-    HIPCHK(hipMemcpyAsync((double*)out + off, src, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync((double*)out + off, p.Ycore[l], cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
     off += cnt;
   }
   result->out_elems = off;
   if (p.trace) {
-    const int nr = q.rec;
+    const int nr = std::min(S->rec, p.n_rec);
     result->n_records = nr;
     result->record_stride = maxrank;
     result->rec_meta = (int32_t*)calloc((size_t)nr * 6, sizeof(int32_t));
     result->rec_eps = (double*)calloc(nr, sizeof(double));
     result->rec_rows = (int32_t*)calloc((size_t)nr * maxrank, sizeof(int32_t));
     result->rec_cols = (int32_t*)calloc((size_t)nr * maxrank, sizeof(int32_t));
-    std::vector<int> meta3((size_t)3 * nr);
     if (!result->rec_meta || !result->rec_eps || !result->rec_rows || !result->rec_cols) {
       aci_result_free(result);
       return set_err(ctx, ACI_E_NOMEM, "host allocation of the trace");
     }
-    HIPCHK(hipMemcpyAsync(meta3.data(), p.tr_meta, sizeof(int) * 3 * nr, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(result->rec_eps, p.tr_eps, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(result->rec_rows, p.tr_rows, sizeof(int) * (size_t)nr * maxrank, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(result->rec_cols, p.tr_cols, sizeof(int) * (size_t)nr * maxrank, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    std::vector<int> meta3((size_t)3 * nr);
+    HIPCHK(hipMemcpy(meta3.data(), p.tr_meta, sizeof(int) * 3 * nr, hipMemcpyDeviceToHost));
     int r = 0;
-    for (int l = L; l >= 2; --l, ++r) {
+    auto put = [&](int kind, int sweep, int bond) {
+      if (r >= nr) return;
       int* m6 = result->rec_meta + 6 * r;
-      m6[0] = 0; m6[1] = 0; m6[2] = l;
-      m6[3] = meta3[3 * r]; m6[4] = meta3[3 * r + 1]; m6[5] = meta3[3 * r + 2];
-    }
-    for (int it = 1; it <= sweeps; ++it) {
-      for (int l = 1; l <= L - 1; ++l, ++r) {
-        int* m6 = result->rec_meta + 6 * r;
-        m6[0] = 1; m6[1] = it; m6[2] = l;
-        m6[3] = meta3[3 * r]; m6[4] = meta3[3 * r + 1]; m6[5] = meta3[3 * r + 2];
-      }
-      for (int l = L - 1; l >= 1; --l, ++r) {
-        int* m6 = result->rec_meta + 6 * r;
-        m6[0] = 2; m6[1] = it; m6[2] = l;
-        m6[3] = meta3[3 * r]; m6[4] = meta3[3 * r + 1]; m6[5] = meta3[3 * r + 2];
-      }
+      m6[0] = kind;
+      m6[1] = sweep;
+      m6[2] = bond;
+      m6[3] = meta3[3 * r];
+      m6[4] = meta3[3 * r + 1];
+      m6[5] = meta3[3 * r + 2];
+      ++r;
+    };
+    for (int l = L; l >= 2; --l) put(0, 0, l);
+    for (int it = 1; it <= S->sweeps; ++it) {
+      for (int l = 1; l <= L - 1; ++l) put(1, it, l);
+      for (int l = L - 1; l >= 1; --l) put(2, it, l);
     }
   }
   HIPCHK(hipStreamSynchronize(s));
-  return converged ? ACI_OK : ACI_W_NOT_CONVERGED;
+  return S->converged ? ACI_OK : ACI_W_NOT_CONVERGED;
+}
+
+int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
+                    double tol, int32_t maxrank, const aci_options* opt, void* out, int64_t out_capacity,
+                    aci_result* result) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!result || !out) return set_err(ctx, ACI_E_INVALID, "null argument");
+  std::memset(result, 0, sizeof(*result));
+  aci_options o{};
+  o.maxiter = 20;
+  if (opt) o = *opt;
+  if (o.maxiter <= 0) o.maxiter = 20;
+  aci_session* S = nullptr;
+  int rc = aci_session_create(ctx, inputs, n_inputs, dtype, op, tol, maxrank, &o, &S);
+  if (rc < 0) return rc;
+  rc = aci_session_sweep(S, o.maxiter, nullptr);
+  if (rc < 0) {
+    aci_session_destroy(S);
+    return rc;
+  }
+  rc = aci_session_result(S, out, out_capacity, result);
+  aci_session_destroy(S);
+  return rc;
 }
 
 // ------------------------------------------------------------ single steps

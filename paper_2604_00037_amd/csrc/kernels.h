@@ -58,7 +58,8 @@ struct PrrluArgs {
   double* eps2;     // out: optional second copy
   double* Y;        // out: optional U_JJ^{-1} U (rank x n, ldy)
   Dim ldy;
-  int* meta;        // out: optional {rank, m, n} (trace)
+  int* meta;        // out: optional {rank, m, n}
+  int* meta2;       // out: optional second copy (trace)
   int* err;
   int* abort_word;
 };

@@ -398,6 +398,11 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
       a.meta[1] = m;
       a.meta[2] = n;
     }
+    if (a.meta2) {
+      a.meta2[0] = final_rank;
+      a.meta2[1] = m;
+      a.meta2[2] = n;
+    }
   }
 }
 

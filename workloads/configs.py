@@ -56,8 +56,7 @@ def _compress(grid, R, ndim, chi, device):
     if device is None:
         flat = np.ascontiguousarray(q).reshape(-1)
         return tt_svd(flat, 2, chi, rtol=1e-14)
-    flat = q.contiguous().reshape(-1)
-    return tt_svd(flat, 2, chi, rtol=1e-14, method="gram")
+    return tt_svd(q, 2, chi, rtol=1e-14, method="gram")
 
 
 def fourier3d_pair(R=10, kmax=32, chi=128, seeds=(2001, 2002), device=None):

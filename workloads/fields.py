@@ -22,13 +22,36 @@ def quantics_points_1d(R, x_min=0.0, x_max=1.0):
 
 
 def grid_to_quantics(F, R, ndim):
-    """Dense grid array of shape ``(2^R,)*ndim`` (numpy or torch) -> tensor of
-    shape ``(2,)*(ndim*R)`` in interleaved site order."""
-    t = F.reshape((2,) * (ndim * R))
-    perm = [a * R + b for b in range(R) for a in range(ndim)]
-    if isinstance(t, np.ndarray):
+    """Dense grid array of shape ``(2^R,)*ndim`` -> interleaved quantics order.
+
+    numpy input: a tensor of shape ``(2,)*(ndim*R)`` (a transposed view).
+    torch input: a flat contiguous tensor of 2^(ndim R) entries in C order
+    over the sites (built by a chunked gather, since torch tensors are
+    limited to 16 dimensions)."""
+    if isinstance(F, np.ndarray):
+        t = F.reshape((2,) * (ndim * R))
+        perm = [a * R + b for b in range(R) for a in range(ndim)]
         return np.transpose(t, perm)
-    return t.permute(*perm)
+    import torch
+    flat = F.reshape(-1)
+    total = flat.numel()
+    out = torch.empty_like(flat)
+    n = 2 ** R
+    chunk = 1 << 24
+    for start in range(0, total, chunk):
+        q = torch.arange(start, min(start + chunk, total), device=flat.device, dtype=torch.int64)
+        # quantics index q: site ndim*b + a (b = bit level from the top) holds
+        # bit R-1-b of axis a; the last site is the least significant digit
+        src = torch.zeros_like(q)
+        for a in range(ndim):
+            coord = torch.zeros_like(q)
+            for b in range(R):
+                site = ndim * b + a
+                bit = (q >> (ndim * R - 1 - site)) & 1
+                coord |= bit << (R - 1 - b)
+            src = src * n + coord
+        out[start:start + q.numel()] = flat[src]
+    return out
 
 
 def quantics_to_grid(T, R, ndim):

@@ -127,7 +127,10 @@ def tt_svd(full, d, maxrank, rtol=0.0, method="auto"):
             lam = lam[::-1]
             U = U[:, ::-1]
             sv = np.sqrt(np.maximum(lam, 0.0))
-            k = _keep(sv, maxrank, rtol)
+            # Gram eigenvalues carry round-off of order eps * lambda_max, so
+            # singular values below ~sqrt(eps) sigma_max are not resolved; the
+            # rank can never exceed the smaller side of W
+            k = _keep(sv, min(maxrank, W.shape[0], W.shape[1]), max(rtol, 1e-7))
             core = np.ascontiguousarray(U[:, :k])
             if is_torch:
                 import torch

@@ -2,25 +2,25 @@
 // search) of a matricised two-site tensor, with the right-interpolative
 // factor B = U_JJ^{-1} U of Alg. 3 formed on the fly.
 //
-// Layout.  P cooperating workgroups of WAVES waves share the m x n matrix by
-// rows: global row i lives in workgroup i % P, wave (i / P) % WAVES, register
-// slot (i / P) / WAVES; lane l holds columns l, l+64, ...  The residual never
-// leaves the registers.
+// Layout.  P cooperating workgroups of four waves (one per SIMD, one group
+// per CU) share the m x n matrix by rows: global row i lives in workgroup
+// i % P, wave (i / P) % 4, register slot (i / P) / 4; lane l holds columns
+// l, l+64, ...  The residual never leaves the registers.
 //
 // One pivot step.  Each workgroup reduces the largest |residual| of its alive
 // entries (ties: smallest row, then smallest column) and publishes that
-// candidate together with the candidate's whole row as flagged 64-bit words
-// (see aci_common.h).  Every workgroup reads all P candidates, picks the same
-// winner (p, q, pivot) and takes row p from the winner's slot, so one
-// exchange per pivot replaces a grid barrier.  With P == 1 the exchange goes
-// through LDS.  The Schur complement update of Alg. 2 is applied to the alive
-// rows as s - (s_q / pivot) * u_j with the product rounded before the
-// subtraction (floating-point contraction is off in this file), which is the
-// rounding of the CPU reference, so pivots agree bit for bit on equal input.
-// Column q of the alive rows is set to zero; the row p either dies (left-to-
-// right updates) or becomes the next row of B, normalised by the pivot.  Rows
-// of B are kept reduced against every later pivot row (Gauss-Jordan), which
-// gives U_JJ^{-1} U with B[:, J] = identity.
+// candidate together with the candidate's row as flagged 64-bit words (see
+// aci_common.h).  Every workgroup reads the P candidates, picks the same
+// winner (p, q, pivot) and reads row p from the winner's slot: two round
+// trips through the XCD's L2 per pivot replace grid barriers.  With P == 1
+// the exchange stays in LDS.  The Schur complement update of Alg. 2 is
+// applied to the alive rows as s - (s_q / pivot) * u_j with the product
+// rounded before the subtraction (floating-point contraction is off in this
+// file), which is the rounding of the CPU reference, so pivots agree bit for
+// bit on equal input.  Column q of the alive rows is set to zero; row p either
+// dies (left-to-right updates) or becomes the next row of B, normalised by the
+// pivot.  Rows of B are kept reduced against every later pivot row
+// (Gauss-Jordan), which gives U_JJ^{-1} U with B[:, J] = identity.
 #include <climits>
 
 #include "kernels.h"
@@ -31,35 +31,143 @@ namespace aci {
 
 namespace {
 
-enum : int { ROW_ALIVE = 0, ROW_PIVOT = 1, ROW_DEAD = 2 };
+constexpr int WAVES = 4;
+constexpr int NT = WAVES * 64;
 
-__device__ __forceinline__ void amax_combine(double& k1, int& i1, double k2, int i2) {
-  if (k2 > k1 || (k2 == k1 && i2 < i1)) {
-    k1 = k2;
-    i1 = i2;
-  }
+// ---- wave-wide reductions with DPP row shifts and row broadcasts ----------
+// After row_shr 1, 2, 4, 8 lane 15 of every 16-lane row holds the row's
+// reduction; row_bcast 15 and 31 fold the rows so that lane 63 holds the
+// wave's.  Lanes without a DPP source keep their own value (bound_ctrl off).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWMASK, 0xf, false);
 }
 
-__device__ __forceinline__ void wave_amax(double& k, int& i) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    double k2 = __shfl_xor(k, off);
-    int i2 = __shfl_xor(i, off);
-    amax_combine(k, i, k2, i2);
-  }
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = dpp_i32<CTRL, ROWMASK>(__double2loint(v));
+  const int hi = dpp_i32<CTRL, ROWMASK>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0x111, 0xf>(v));
+  v = fmax(v, dpp_f64<0x112, 0xf>(v));
+  v = fmax(v, dpp_f64<0x114, 0xf>(v));
+  v = fmax(v, dpp_f64<0x118, 0xf>(v));
+  v = fmax(v, dpp_f64<0x142, 0xa>(v));
+  v = fmax(v, dpp_f64<0x143, 0xc>(v));
+  return readlane_f64(v, 63);
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+  v = min(v, dpp_i32<0x111, 0xf>(v));
+  v = min(v, dpp_i32<0x112, 0xf>(v));
+  v = min(v, dpp_i32<0x114, 0xf>(v));
+  v = min(v, dpp_i32<0x118, 0xf>(v));
+  v = min(v, dpp_i32<0x142, 0xa>(v));
+  v = min(v, dpp_i32<0x143, 0xc>(v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Largest key over the wave; among equal keys the smallest packed index
+// (row << 16 | column).  The result is uniform across the wave.
+__device__ __forceinline__ void wave_argmax(double& k, int& i) {
+  const double mk = wave_max_f64(k);
+  const int c = wave_min_i32(k == mk ? i : INT_MAX);
+  k = mk;
+  i = c;
+}
+
+// Value of column slot qb held by lane ql (both uniform), broadcast to the
+// wave.  The slot is chosen by uniform branches, so one readlane pair runs.
 template <int CS>
-__device__ __forceinline__ double pick(const double (&row)[CS], int b) {
+__device__ __forceinline__ double lane_pick(const double (&row)[CS], int qb, int ql) {
   double r = 0.0;
 #pragma unroll
   for (int c = 0; c < CS; ++c)
-    if (c == b) r = row[c];
+    if (c == qb) r = readlane_f64(row[c], ql);
   return r;
 }
 
-template <int WAVES, int RS, int CS, bool SOLO>
-__global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
+// XCD (XCC) the workgroup runs on.
+__device__ __forceinline__ int hw_xcc_id() {
+  uint32_t v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return (int)(v & 0xf);
+}
+
+// Exchange store.  Loads are always agent-scope (they bypass the CU's L1 and
+// read the XCD's L2).  When every cooperating group runs on the same XCD a
+// workgroup-scope store suffices: the L1 is write-through, so the word lands
+// in the shared L2 where those loads find it, and it is not pushed further
+// out.  Groups spread over several XCDs use agent-scope stores.
+__device__ __forceinline__ void xw_put(uint64_t* p, uint32_t data, uint32_t flag, bool same_xcd) {
+  const uint64_t v = ((uint64_t)flag << 32) | (uint64_t)data;
+  if (same_xcd)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Poll `cnt` flagged words src[0 .. cnt) (thread t takes words t, t + NT, ...)
+// until their flags match, then store the payloads to dst.  Returns false
+// after a timeout; the abort word is then set for every waiting wave.
+template <int MAXW>
+__device__ __forceinline__ bool poll_words(const uint64_t* src, int cnt, uint32_t flag, int* abort_word,
+                                           uint32_t limit, uint32_t* dst) {
+  uint64_t raw[MAXW];
+#pragma unroll
+  for (int i = 0; i < MAXW; ++i) {
+    const int t = threadIdx.x + NT * i;
+    raw[i] = t < cnt ? __hip_atomic_load(src + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : ((uint64_t)flag << 32);
+  }
+  uint32_t spins = 0;
+  bool ok = true;
+  while (true) {
+    bool all = true;
+#pragma unroll
+    for (int i = 0; i < MAXW; ++i) {
+      const int t = threadIdx.x + NT * i;
+      if (t < cnt && (uint32_t)(raw[i] >> 32) != flag) {
+        all = false;
+        raw[i] = __hip_atomic_load(src + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (all) break;
+    ++spins;
+    if ((spins & 255u) == 0u) {
+      if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = false; break; }
+      if (spins >= limit) {
+        __hip_atomic_store(abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = false;
+        break;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MAXW; ++i) {
+    const int t = threadIdx.x + NT * i;
+    if (t < cnt) dst[t] = (uint32_t)raw[i];
+  }
+  return ok;
+}
+
+// LDS of a cooperative launch: candidate words at [0, kCandWords), the
+// winner's row after them.
+constexpr int kCandWords = 256;
+// a step index no pivot step uses (steps stay below ACI_MAX_MATRIX)
+constexpr uint32_t kXccFlagOffset = 1536;
+
+template <int RS, int CS, bool SOLO>
+__global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
   if (blockIdx.x % a.stride) return;
   const int w = blockIdx.x / a.stride;
   const int P = a.P;
@@ -69,45 +177,82 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool needY = a.Y != nullptr;
   const int ldy = needY ? dget(a.ldy) : 0;
+  // slot of group g in the exchange buffer: words [g per, g per + 3) hold the
+  // candidate (key lo, key hi, index), then 2n words its row (lo, hi)
+  const int per = 3 + 2 * n;
 
   __shared__ double red_k[2][WAVES];
   __shared__ int red_i[2][WAVES];
   __shared__ int red_f[2][WAVES];
-  __shared__ double srow[SOLO ? 64 * CS : 1];
+  extern __shared__ uint32_t xs[];
+  uint32_t* xrow = xs + kCandWords;
 
   double s[RS][CS];
-  int state[RS], rowid[RS], pstep[RS];
+  // row slot r of this wave holds global row w + P (wv + 4 r).  Row states
+  // are wave-uniform bit sets: alive rows take part in the pivot search and
+  // the Schur update, B rows (right-to-left updates only) in the
+  // Gauss-Jordan reduction; pstep[r] is the pivot step of a B row.
+  uint32_t alive = 0u, brows = 0u;
+  int pstep[RS];
+  const int row0 = w + P * wv, rstride = P * WAVES;
   bool cv[CS];
 #pragma unroll
   for (int b = 0; b < CS; ++b) cv[b] = (lane + 64 * b) < n;
 
-  double bk = -1.0;
-  int bi = INT_MAX;
+  // rm[r]: largest |entry| of row slot r in this lane (-1 when the row is not
+  // alive).  Entries of columns >= n and of eliminated columns are zero.
+  double rm[RS];
 #pragma unroll
   for (int r = 0; r < RS; ++r) {
-    const int i = w + P * (wv + WAVES * r);
-    rowid[r] = i;
-    state[r] = i < m ? ROW_ALIVE : ROW_DEAD;
+    const int i = row0 + rstride * r;
+    if (i < m) alive |= 1u << r;
     pstep[r] = -1;
+    rm[r] = -1.0;
 #pragma unroll
     for (int b = 0; b < CS; ++b) {
       const int j = lane + 64 * b;
       double v = 0.0;
       if (i < m && cv[b]) v = a.M[(size_t)i * ldm + j];
       s[r][b] = v;
-      if (i < m && cv[b]) {
-        const double kv = fabs(v);
-        if (kv > bk) {
-          bk = kv;
-          bi = (i << 16) | j;
-        }
-      }
+      if (i < m) rm[r] = fmax(rm[r], fabs(v));
     }
+  }
+
+  alive = __builtin_amdgcn_readfirstlane(alive);
+  bool failed = false;
+  bool same_xcd = false;
+  if (!SOLO) {
+    // which XCD each group runs on, exchanged once at agent scope through
+    // word 0 of the parity-1 slots (overwritten by step 1 only after every
+    // group has passed step 0, hence this exchange)
+    const uint32_t xf = a.flag_base + kXccFlagOffset;
+    uint64_t* slots1 = a.xbuf + (size_t)P * a.xwords;
+    if (threadIdx.x == 0) xw_put(slots1 + (size_t)w * per, (uint32_t)hw_xcc_id(), xf, false);
+    bool ok = true;
+    if (threadIdx.x < P) {
+      const uint64_t* src = slots1 + (size_t)threadIdx.x * per;
+      uint64_t v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t spins = 0;
+      while ((uint32_t)(v >> 32) != xf) {
+        ++spins;
+        if ((spins & 255u) == 0u) {
+          if (__hip_atomic_load(a.abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || spins >= a.spin_limit) {
+            __hip_atomic_store(a.abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
+          }
+        }
+        v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      xs[threadIdx.x] = ok ? (uint32_t)v : 0xffffffffu - threadIdx.x;
+    }
+    if (!ok) failed = true;
+    __syncthreads();
+    same_xcd = __ballot(lane < P && xs[lane] != xs[0]) == 0;
   }
 
   int k = 0;
   double eps = 0.0;
-  bool failed = false;
   int final_rank = 0;
   while (true) {
     if (k == kmax) {
@@ -116,25 +261,36 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
       break;
     }
     const int par = k & 1;
-    // ---- workgroup candidate
-    wave_amax(bk, bi);
+    // ---- wave candidate: the largest key, then the smallest index holding
+    // it.  Only rows in which some lane holds the wave's maximum are scanned.
+    double bk = rm[0];
+#pragma unroll
+    for (int r = 1; r < RS; ++r) bk = fmax(bk, rm[r]);
+    bk = wave_max_f64(bk);
+    int bi = INT_MAX;
+    bool found = false;
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      if (!found && __ballot(rm[r] == bk) != 0) {
+        if (rm[r] == bk) {
+#pragma unroll
+          for (int b = CS - 1; b >= 0; --b)
+            if (fabs(s[r][b]) == bk) bi = ((row0 + rstride * r) << 16) | (lane + 64 * b);
+        }
+        found = true;
+      }
+    }
+    bi = wave_min_i32(bi);
     if (lane == 0) {
       red_k[par][wv] = bk;
       red_i[par][wv] = bi;
       red_f[par][wv] = failed ? 1 : 0;
     }
     __syncthreads();
-    double ck = -1.0;
-    int ci = INT_MAX;
-    int anyfail = 0;
-    if (lane < WAVES) {
-      ck = red_k[par][lane];
-      ci = red_i[par][lane];
-      anyfail = red_f[par][lane];
-    }
-    wave_amax(ck, ci);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) anyfail |= __shfl_xor(anyfail, off);
+    double ck = lane < WAVES ? red_k[par][lane] : -1.0;
+    int ci = lane < WAVES ? red_i[par][lane] : INT_MAX;
+    const bool anyfail = __ballot(lane < WAVES && red_f[par][lane] != 0) != 0;
+    wave_argmax(ck, ci);
     if (anyfail) {
       // an exchange timed out: leave with an error (uniform across the group)
       final_rank = k;
@@ -148,11 +304,11 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
     int widx;
     double u[CS];
     if (SOLO) {
+      double* srow = reinterpret_cast<double*>(xrow);
       v = ck;
       widx = ci;
-      const int p = widx >> 16;
       if (v >= 0.0) {
-        const int rho = p / P;
+        const int rho = widx >> 16;
         if (wv == rho % WAVES) {
           const int r0 = rho / WAVES;
 #pragma unroll
@@ -169,10 +325,10 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
     } else {
       const uint32_t flag = a.flag_base + (uint32_t)k;
       uint64_t* slot_base = a.xbuf + (size_t)par * P * a.xwords;
-      uint64_t* mine = slot_base + (size_t)w * a.xwords;
+      uint64_t* mine = slot_base + (size_t)w * per;
       if (wv == 0 && lane < 3) {
         const uint32_t d = lane == 0 ? lo32(ck) : (lane == 1 ? hi32(ck) : (uint32_t)ci);
-        xw_store(mine + lane, d, flag);
+        xw_put(mine + lane, d, flag, same_xcd);
       }
       if (ck >= 0.0) {
         const int rho = ((ci >> 16) - w) / P;
@@ -185,108 +341,67 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
               for (int b = 0; b < CS; ++b)
                 if (cv[b]) {
                   const int j = lane + 64 * b;
-                  xw_store(mine + 4 + 2 * j, lo32(s[r][b]), flag);
-                  xw_store(mine + 5 + 2 * j, hi32(s[r][b]), flag);
+                  xw_put(mine + 3 + 2 * j, lo32(s[r][b]), flag, same_xcd);
+                  xw_put(mine + 4 + 2 * j, hi32(s[r][b]), flag, same_xcd);
                 }
             }
         }
       }
-      // all candidates: lane t < P reads the three words of workgroup t
-      double tk = -1.0;
-      int ti = INT_MAX;
+      // round trip 1: the P candidates (thread t < 3P reads one word)
       bool ok = true;
-      if (lane < P) {
-        const uint64_t* sl = slot_base + (size_t)lane * a.xwords;
-        uint64_t c3[3];
-#pragma unroll
-        for (int h = 0; h < 3; ++h)
-          c3[h] = __hip_atomic_load(sl + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x < 3 * P) {
+        const int g = threadIdx.x / 3;
+        const uint64_t* src = slot_base + (size_t)g * per + (threadIdx.x - 3 * g);
+        uint64_t raw = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t spins = 0;
-        while (true) {
-          bool all = true;
-#pragma unroll
-          for (int h = 0; h < 3; ++h)
-            if ((uint32_t)(c3[h] >> 32) != flag) {
-              all = false;
-              c3[h] = __hip_atomic_load(sl + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-          if (all) break;
+        while ((uint32_t)(raw >> 32) != flag) {
           ++spins;
-          if ((spins & 1023u) == 0u) {
-            if (__hip_atomic_load(a.abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = false; break; }
-            if (spins >= a.spin_limit) {
+          if ((spins & 255u) == 0u) {
+            if (__hip_atomic_load(a.abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || spins >= a.spin_limit) {
               __hip_atomic_store(a.abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               ok = false;
               break;
             }
           }
+          raw = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (ok) {
-          tk = join64((uint32_t)c3[0], (uint32_t)c3[1]);
-          ti = (int)(uint32_t)c3[2];
-        }
+        xs[threadIdx.x] = (uint32_t)raw;
       }
-      ok = __ballot(!ok) == 0;
-      wave_amax(tk, ti);
+      if (!ok) failed = true;
+      __syncthreads();
+      double tk = -1.0;
+      int ti = INT_MAX;
+      if (lane < P) {
+        tk = join64(xs[3 * lane], xs[3 * lane + 1]);
+        ti = (int)xs[3 * lane + 2];
+      }
+      wave_argmax(tk, ti);
       v = tk;
       widx = ti;
-      int p = widx >> 16;
-      if (!(v >= 0.0) || p < 0 || p >= m || (widx & 0xffff) >= n) {
+      const int p0 = widx >> 16;
+      if (!(v >= 0.0) || p0 < 0 || p0 >= m || (widx & 0xffff) >= n) {
         // only reachable after a timeout; keep every index in range
-        ok = false;
+        failed = true;
         v = 0.0;
         widx = 0;
-        p = 0;
       }
-      // the winner's row
-      const uint64_t* ws = slot_base + (size_t)(p % P) * a.xwords;
-      uint64_t raw[2 * CS];
+      // round trip 2: the winner's row (already published with its candidate)
+      const int wg = (widx >> 16) % P;
+      ok = poll_words<(128 * CS + NT - 1) / NT>(slot_base + (size_t)wg * per + 3, 2 * n, flag, a.abort_word,
+                                                a.spin_limit, xrow);
+      if (!ok) failed = true;
+      __syncthreads();
 #pragma unroll
       for (int b = 0; b < CS; ++b) {
         const int j = lane + 64 * b;
-        if (cv[b]) {
-          raw[2 * b] = __hip_atomic_load(ws + 4 + 2 * j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          raw[2 * b + 1] = __hip_atomic_load(ws + 5 + 2 * j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          raw[2 * b] = (uint64_t)flag << 32;
-          raw[2 * b + 1] = (uint64_t)flag << 32;
-        }
+        u[b] = cv[b] ? join64(xrow[2 * j], xrow[2 * j + 1]) : 0.0;
       }
-      uint32_t spins = 0;
-      while (ok) {
-        bool all = true;
-#pragma unroll
-        for (int b = 0; b < CS; ++b) {
-          const int j = lane + 64 * b;
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            if ((uint32_t)(raw[2 * b + h] >> 32) != flag) {
-              all = false;
-              raw[2 * b + h] = __hip_atomic_load(ws + 4 + 2 * j + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        if (all) break;
-        ++spins;
-        if ((spins & 1023u) == 0u) {
-          if (__hip_atomic_load(a.abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = false;
-          if (spins >= a.spin_limit) {
-            __hip_atomic_store(a.abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-          }
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < CS; ++b)
-        u[b] = cv[b] ? join64((uint32_t)raw[2 * b], (uint32_t)raw[2 * b + 1]) : 0.0;
-      ok = __ballot(!ok) == 0;
-      if (!ok) {
-        // keep going with zeros until the whole group agrees to stop
-        failed = true;
+      if (failed) {
         v = 0.0;
         widx = 0;
 #pragma unroll
         for (int b = 0; b < CS; ++b) u[b] = 0.0;
-        if (lane == 0 && a.err) atomicOr(a.err, ERR_TIMEOUT);
+        if (threadIdx.x == 0 && a.err) atomicOr(a.err, ERR_TIMEOUT);
       }
     }
 
@@ -304,7 +419,7 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
       final_rank = k;
       break;
     }
-    const double piv = __shfl(pick<CS>(u, qb), ql);
+    const double piv = lane_pick<CS>(u, qb, ql);
     if (w == 0 && threadIdx.x == 0) {
       a.rows[k] = p;
       a.cols[k] = q;
@@ -314,8 +429,8 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
       // cell, B = unit row e_q, error 0
 #pragma unroll
       for (int r = 0; r < RS; ++r)
-        if (rowid[r] == p && needY) {
-          state[r] = ROW_PIVOT;
+        if (row0 + rstride * r == p && needY) {
+          brows |= 1u << r;
           pstep[r] = 0;
 #pragma unroll
           for (int b = 0; b < CS; ++b) s[r][b] = (lane + 64 * b == q) ? 1.0 : 0.0;
@@ -325,47 +440,71 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
       break;
     }
 
-    // ---- elimination, fused with the next step's local argmax
-    double uh[CS];
-    if (needY) {
+    // ---- elimination, fused with the next step's local maxima
+    // slot of the pivot row in this wave (-1: another wave or group owns it)
+    const int rp = ((p - row0) % rstride == 0 && p >= row0) ? (p - row0) / rstride : -1;
+    // multipliers s_iq / pivot of the rows: one vector division with lane r
+    // dividing row r's entry (correctly rounded, like a scalar division)
+    double quo;
+    {
+      double num = 0.0;
 #pragma unroll
-      for (int b = 0; b < CS; ++b) uh[b] = u[b] / piv;
+      for (int c = 0; c < CS; ++c)
+        if (c == qb) {
+#pragma unroll
+          for (int r = 0; r < RS; ++r) {
+            const double sq = readlane_f64(s[r][c], ql);
+            num = lane == r ? sq : num;
+          }
+        }
+      quo = num / piv;
     }
-    bk = -1.0;
-    bi = INT_MAX;
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
-      if (state[r] == ROW_ALIVE) {
-        if (rowid[r] == p) {
+      if ((alive >> r) & 1u) {
+        if (r == rp) {
+          rm[r] = -1.0;
+          alive &= ~(1u << r);
           if (needY) {
-            state[r] = ROW_PIVOT;
+            brows |= 1u << r;
             pstep[r] = k;
 #pragma unroll
             for (int b = 0; b < CS; ++b) s[r][b] = s[r][b] / piv;
-          } else {
-            state[r] = ROW_DEAD;
           }
         } else {
-          const double c = __shfl(pick<CS>(s[r], qb), ql) / piv;
+          const double c = readlane_f64(quo, r);
 #pragma unroll
           for (int b = 0; b < CS; ++b) {
             const double t = c * u[b];
-            double x = s[r][b] - t;
-            if (b == qb && lane == ql) x = 0.0;
-            s[r][b] = x;
-            const double kv = fabs(x);
-            if (cv[b] && kv > bk) {
-              bk = kv;
-              bi = (rowid[r] << 16) | (lane + 64 * b);
-            }
+            s[r][b] = s[r][b] - t;
           }
-        }
-      } else if (state[r] == ROW_PIVOT) {
-        const double c = __shfl(pick<CS>(s[r], qb), ql);
+          // eliminated column q: exactly zero from now on
 #pragma unroll
-        for (int b = 0; b < CS; ++b) {
-          const double t = c * uh[b];
-          s[r][b] = s[r][b] - t;
+          for (int b = 0; b < CS; ++b)
+            if (b == qb) s[r][b] = lane == ql ? 0.0 : s[r][b];
+          double mx = 0.0;
+#pragma unroll
+          for (int b = 0; b < CS; ++b) mx = fmax(mx, fabs(s[r][b]));
+          rm[r] = mx;
+        }
+      }
+    }
+    alive = __builtin_amdgcn_readfirstlane(alive);
+    if (needY) {
+      brows = __builtin_amdgcn_readfirstlane(brows);
+      // rows of B chosen at earlier steps: reduce them against the new pivot
+      // row normalised by the pivot (Gauss-Jordan), so that B[:, J] = I
+#pragma unroll
+      for (int b = 0; b < CS; ++b) u[b] = u[b] / piv;
+#pragma unroll
+      for (int r = 0; r < RS; ++r) {
+        if (((brows >> r) & 1u) && r != rp) {
+          const double c = lane_pick<CS>(s[r], qb, ql);
+#pragma unroll
+          for (int b = 0; b < CS; ++b) {
+            const double t = c * u[b];
+            s[r][b] = s[r][b] - t;
+          }
         }
       }
     }
@@ -382,7 +521,7 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
   if (needY) {
 #pragma unroll
     for (int r = 0; r < RS; ++r)
-      if (state[r] == ROW_PIVOT && pstep[r] >= 0 && pstep[r] < final_rank) {
+      if (((brows >> r) & 1u) && pstep[r] >= 0 && pstep[r] < final_rank) {
 #pragma unroll
         for (int b = 0; b < CS; ++b)
           if (cv[b]) a.Y[(size_t)pstep[r] * ldy + lane + 64 * b] = s[r][b];
@@ -406,22 +545,33 @@ __global__ __launch_bounds__(WAVES * 64) void prrlu_kernel(PrrluArgs a) {
   }
 }
 
-// Register shapes: CS column slots per lane (n <= 64 CS), RS row slots per
-// wave.  Only shapes that fit the register file without spilling are built:
-// with 16 waves a lane has 128 VGPRs, with 8 waves 256.
-struct Shape {
-  int cs, waves, rs_max;
-};
-constexpr Shape kShapes[] = {{1, 16, 4}, {2, 16, 4}, {4, 16, 2}, {6, 16, 2}, {8, 16, 1}, {12, 8, 2}, {16, 8, 1}};
-
-// Resident workgroups per CU of one kernel instance (cached).
-int resident_per_cu(const void* fn, int block) {
+// Resident workgroups per CU of one kernel instance.
+int resident_per_cu(const void* fn, size_t lds) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, 0) != hipSuccess) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, lds) != hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }
   return nb < 1 ? 1 : nb;
+}
+
+// LDS a cooperative launch requests: more than half of a CU's LDS when a
+// group may take that much, so that no two cooperating groups share a CU (and
+// its SIMDs); otherwise just what the kernel uses.
+size_t group_lds(size_t need) {
+  static size_t v = 0;
+  if (!v) {
+    int dev = 0, per_block = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      per_block = per_cu = 0;
+    }
+    const size_t want = (size_t)per_cu / 2 + 1024;
+    v = (per_cu > 0 && (size_t)per_block >= want) ? want : 1;
+  }
+  return v > need ? v : need;
 }
 
 int cus_per_xcd() {
@@ -437,20 +587,35 @@ int cus_per_xcd() {
   return v;
 }
 
-template <int WAVES, int RS, int CS>
+// Register shapes: CS column slots per lane (n <= 64 CS), RS row slots per
+// wave (rows per group = 4 RS).
+struct Shape {
+  int cs, rs_max;
+};
+constexpr Shape kShapes[] = {{1, 16}, {2, 16}, {4, 16}, {6, 8}, {8, 8}, {12, 4}, {16, 4}};
+
+template <int RS, int CS>
 hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
-  const void* fn = a.P == 1 ? (const void*)prrlu_kernel<WAVES, RS, CS, true>
-                            : (const void*)prrlu_kernel<WAVES, RS, CS, false>;
-  static int per_cu = resident_per_cu((const void*)prrlu_kernel<WAVES, RS, CS, false>, WAVES * 64);
   PrrluArgs args = a;
+  dim3 block(NT);
+  if (a.P == 1) {
+    args.stride = 1;
+    void* kp[] = {&args};
+    const size_t lds = (size_t)(kCandWords + 128 * CS) * 4;
+    hipError_t e = hipLaunchCooperativeKernel((const void*)prrlu_kernel<RS, CS, true>, dim3(1), block, kp,
+                                              (unsigned)lds, s);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
+  }
+  const void* fn = (const void*)prrlu_kernel<RS, CS, false>;
+  const size_t lds = group_lds((size_t)(kCandWords + 128 * CS) * 4);
+  static int per_cu = resident_per_cu(fn, lds);
   // Workgroups are dealt to the 8 XCDs round robin, so launching 8x the
   // groups and keeping every 8th puts the cooperating groups on one XCD,
-  // which shortens the exchange latency.  Only when they all fit there.
-  args.stride = (a.P > 1 && a.P <= per_cu * cus_per_xcd()) ? 8 : 1;
-  dim3 block(WAVES * 64);
-  dim3 grid(args.P * args.stride);
+  // which lets the exchange stay in that XCD's L2.  Only when they all fit.
+  args.stride = (a.P <= per_cu * cus_per_xcd()) ? 8 : 1;
   void* kp[] = {&args};
-  hipError_t e = hipLaunchCooperativeKernel(fn, grid, block, kp, 0, s);
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(args.P * args.stride), block, kp, (unsigned)lds, s);
   if (e != hipSuccess) (void)hipGetLastError();
   return e;
 }
@@ -461,18 +626,20 @@ const Shape* pick_shape(int nmax) {
   return nullptr;
 }
 
-// rows per workgroup: as few register slots as keep the group count small
+// Rows per group: the fewest register slots that keep the group count at or
+// below the target (more groups spread the elimination over more CUs, fewer
+// shorten the exchange).
 int pick_rs(const Shape& sh, int mmax) {
-  const int target_p = 8;
+  const int target_p = 12;
   int rs = 1;
-  while (rs < sh.rs_max && (mmax + sh.waves * rs - 1) / (sh.waves * rs) > target_p) rs *= 2;
+  while (rs < sh.rs_max && (mmax + WAVES * rs - 1) / (WAVES * rs) > target_p) rs *= 2;
   return rs;
 }
 
 }  // namespace
 
 size_t prrlu_xbuf_words(int mmax, int nmax) {
-  // every launch uses at most 64 groups and the column slots of nmax
+  // every launch uses at most 64 groups of at most 4 + 2n words per parity
   (void)mmax;
   const Shape* sh = pick_shape(nmax < 1 ? 1 : nmax);
   if (!sh) sh = &kShapes[sizeof(kShapes) / sizeof(kShapes[0]) - 1];
@@ -485,25 +652,40 @@ hipError_t launch_prrlu(const PrrluArgs& a0, int mmax, int nmax, hipStream_t s) 
   if (!sh) return hipErrorInvalidValue;
   PrrluArgs a = a0;
   const int rs = pick_rs(*sh, mmax);
-  a.P = (mmax + sh->waves * rs - 1) / (sh->waves * rs);
+  a.P = (mmax + WAVES * rs - 1) / (WAVES * rs);
   if (a.P > 64) return hipErrorInvalidValue;
   a.xwords = 4 + 2 * 64 * sh->cs;
   if ((size_t)2 * a.P * a.xwords > a.xbuf_words) return hipErrorInvalidValue;
-  switch (sh->cs * 8 + rs) {
-    case 1 * 8 + 1: return launch_shape<16, 1, 1>(a, s);
-    case 1 * 8 + 2: return launch_shape<16, 2, 1>(a, s);
-    case 1 * 8 + 4: return launch_shape<16, 4, 1>(a, s);
-    case 2 * 8 + 1: return launch_shape<16, 1, 2>(a, s);
-    case 2 * 8 + 2: return launch_shape<16, 2, 2>(a, s);
-    case 2 * 8 + 4: return launch_shape<16, 4, 2>(a, s);
-    case 4 * 8 + 1: return launch_shape<16, 1, 4>(a, s);
-    case 4 * 8 + 2: return launch_shape<16, 2, 4>(a, s);
-    case 6 * 8 + 1: return launch_shape<16, 1, 6>(a, s);
-    case 6 * 8 + 2: return launch_shape<16, 2, 6>(a, s);
-    case 8 * 8 + 1: return launch_shape<16, 1, 8>(a, s);
-    case 12 * 8 + 1: return launch_shape<8, 1, 12>(a, s);
-    case 12 * 8 + 2: return launch_shape<8, 2, 12>(a, s);
-    case 16 * 8 + 1: return launch_shape<8, 1, 16>(a, s);
+  switch (sh->cs * 32 + rs) {
+    case 1 * 32 + 1: return launch_shape<1, 1>(a, s);
+    case 1 * 32 + 2: return launch_shape<2, 1>(a, s);
+    case 1 * 32 + 4: return launch_shape<4, 1>(a, s);
+    case 1 * 32 + 8: return launch_shape<8, 1>(a, s);
+    case 1 * 32 + 16: return launch_shape<16, 1>(a, s);
+    case 2 * 32 + 1: return launch_shape<1, 2>(a, s);
+    case 2 * 32 + 2: return launch_shape<2, 2>(a, s);
+    case 2 * 32 + 4: return launch_shape<4, 2>(a, s);
+    case 2 * 32 + 8: return launch_shape<8, 2>(a, s);
+    case 2 * 32 + 16: return launch_shape<16, 2>(a, s);
+    case 4 * 32 + 1: return launch_shape<1, 4>(a, s);
+    case 4 * 32 + 2: return launch_shape<2, 4>(a, s);
+    case 4 * 32 + 4: return launch_shape<4, 4>(a, s);
+    case 4 * 32 + 8: return launch_shape<8, 4>(a, s);
+    case 4 * 32 + 16: return launch_shape<16, 4>(a, s);
+    case 6 * 32 + 1: return launch_shape<1, 6>(a, s);
+    case 6 * 32 + 2: return launch_shape<2, 6>(a, s);
+    case 6 * 32 + 4: return launch_shape<4, 6>(a, s);
+    case 6 * 32 + 8: return launch_shape<8, 6>(a, s);
+    case 8 * 32 + 1: return launch_shape<1, 8>(a, s);
+    case 8 * 32 + 2: return launch_shape<2, 8>(a, s);
+    case 8 * 32 + 4: return launch_shape<4, 8>(a, s);
+    case 8 * 32 + 8: return launch_shape<8, 8>(a, s);
+    case 12 * 32 + 1: return launch_shape<1, 12>(a, s);
+    case 12 * 32 + 2: return launch_shape<2, 12>(a, s);
+    case 12 * 32 + 4: return launch_shape<4, 12>(a, s);
+    case 16 * 32 + 1: return launch_shape<1, 16>(a, s);
+    case 16 * 32 + 2: return launch_shape<2, 16>(a, s);
+    case 16 * 32 + 4: return launch_shape<4, 16>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

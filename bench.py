@@ -61,19 +61,166 @@ def cpu_baseline(u, v):
     except Exception:
         threads = os.cpu_count() or 1
     t = time.perf_counter()
-    res = oracle.aci([u, v], "product", TOL, MAXRANK, maxiter=2, seed=INIT_SEED)
+    res = oracle.aci([u, v], "product", TOL, MAXRANK, maxiter=3, seed=INIT_SEED)
     total = time.perf_counter() - t
-    sweep_s = res.times[2] - res.times[1] if len(res.times) >= 3 else res.times[-1] - res.times[0]
-    log(f"oracle: init+2 sweeps {total:.1f} s, second sweep {sweep_s:.2f} s")
+    sweep_s = (res.times[3] - res.times[1]) / 2
+    log(f"oracle: init+3 sweeps {total:.1f} s, mean of sweeps 2-3 {sweep_s:.2f} s")
     return {
         "value": 1.0 / sweep_s,
         "unit": "sweeps/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"initialisation + 2 sweeps of the same workload ({total:.1f} s); "
-                  f"rate from the second, rank-saturated sweep ({sweep_s:.2f} s); "
+        "sample": f"initialisation + 3 sweeps of the same workload ({total:.1f} s); "
+                  f"rate from sweeps 2-3, at saturated ranks ({sweep_s:.2f} s each); "
                   "NumPy float64, BLAS threads as reported by threadpoolctl",
     }
+
+
+def roofline(launches):
+    """Roofline entry of the dominant kernel instance (most device time in the
+    timed sweeps): algorithmic flops per launch over the mean launch time,
+    both from the library's launch log (HIP events on its stream)."""
+    by = {}
+    for r in launches:
+        e = by.setdefault(r["kernel"], {"kind": r["kind"], "n": 0, "us": 0.0, "flops": 0.0})
+        e["n"] += 1
+        e["us"] += r["us"]
+        e["flops"] += r["flops"]
+    name = max(by, key=lambda k: by[k]["us"])
+    e = by[name]
+    avg_us = e["us"] / e["n"]
+    per_launch = e["flops"] / e["n"]
+    achieved = per_launch / (avg_us * 1e-6) / 1e12
+    if e["kind"] == "prrlu":
+        bound, peak = "alu", PEAK_FP64_VALU
+    else:
+        bound, peak = "mfma", PEAK_FP64_MFMA
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None, "kernel": name, "launches": e["n"],
+            "avg_launch_us": avg_us, "flops_per_launch": per_launch,
+            "share_of_kernel_time": e["us"] / sum(v["us"] for v in by.values())}
+
+
+def summarize_rocprof(directory, bench_json):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run of this
+    script: the per-kernel statistics of the library's kernels over the whole
+    run, and the mean duration of the dominant instance over its dispatches
+    in the timed sweeps (its last `launches` dispatches), next to the mean the
+    run measured itself with HIP events."""
+    import csv
+    with open(bench_json) as f:
+        line = [x for x in f.read().splitlines() if x.startswith("{")][-1]
+    b = json.loads(line)
+    roof = b["roofline"]
+    out = ["| kernel | calls | total ms | mean us | min us | max us |", "|---|---|---|---|---|---|"]
+    with open(os.path.join(directory, "run_kernel_stats.csv")) as f:
+        for row in csv.DictReader(f):
+            if "aci::" not in row["Name"]:
+                continue
+            nm = row["Name"].replace("void aci::(anonymous namespace)::", "").replace("aci::(anonymous namespace)::", "")
+            nm = nm.split("(")[0]
+            out.append(f"| `{nm}` | {row['Calls']} | {float(row['TotalDurationNs']) / 1e6:.3f} | "
+                       f"{float(row['AverageNs']) / 1e3:.1f} | {float(row['MinNs']) / 1e3:.1f} | "
+                       f"{float(row['MaxNs']) / 1e3:.1f} |")
+    durs = []
+    with open(os.path.join(directory, "run_kernel_trace.csv")) as f:
+        for row in csv.DictReader(f):
+            if roof["kernel"] + "(" in row["Kernel_Name"]:
+                durs.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"]) - int(row["Start_Timestamp"])))
+    durs.sort()
+    timed = [d for _, d in durs[-roof["launches"]:]]
+    mean_us = sum(timed) / len(timed) / 1e3
+    out += ["", f"Dominant instance `{roof['kernel']}`: {len(durs)} dispatches in the run; "
+                f"the last {len(timed)} (the timed sweeps) average **{mean_us:.1f} us** in the trace, "
+                f"against **{roof['avg_launch_us']:.1f} us** measured by the run itself with HIP events "
+                f"({100 * (roof['avg_launch_us'] / mean_us - 1):+.1f} %).",
+            f"Algorithmic flops per launch {roof['flops_per_launch']:.4g}; "
+            f"{roof['achieved']:.4g} {roof['unit']} against a peak of {roof['peak']} ({roof['bound']}).",
+            f"Run: {b['value']:.2f} {b['unit']}, {b['ms_per_step']:.2f} ms per sweep."]
+    return "\n".join(out)
+
+
+KERNEL_SOURCES = {
+    "prrlu": ["paper_2604_00037_amd/csrc/prrlu.hip", "paper_2604_00037_amd/csrc/kernels.h",
+              "paper_2604_00037_amd/csrc/aci_common.h"],
+    "contract": ["paper_2604_00037_amd/csrc/contract.hip", "paper_2604_00037_amd/csrc/kernels.h",
+                 "paper_2604_00037_amd/csrc/aci_common.h"],
+}
+CALIB_BYTES = 256 << 20
+
+
+def source_hash(kind):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kind, []):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_counters(directory, counter):
+    """Per-dispatch values of one counter from a rocprofv3 --pmc run, in
+    dispatch order: [(kernel name, value)]."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    rows = []
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] == counter:
+                    rows.append((int(row["Dispatch_Id"]), row["Kernel_Name"], float(row["Counter_Value"])))
+    rows.sort()
+    return [(k, v) for _, k, v in rows]
+
+
+def summarize_pmc(fetch_dir, write_dir, bench_json):
+    """HBM traffic of the dominant kernel instance from two rocprofv3 --pmc
+    runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the
+    same counters read for a plain copy of CALIB_BYTES (bench.py
+    --pmc-calibration appends three such copies)."""
+    with open(bench_json) as f:
+        line = [x for x in f.read().splitlines() if x.startswith("{")][-1]
+    b = json.loads(line)
+    name = b["roofline"]["kernel"]
+    kind = name.split("_")[0]
+    res = {"kernel": name, "source_hash": source_hash(kind)}
+    lines = []
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = read_counters(d, counter)
+        mine = [v for k, v in rows if name + "(" in k]
+        copy = [v for _, v in rows[-3:]]        # the three calibration copies end the run
+        kib_launch = sum(mine) / len(mine)
+        kib_copy = sum(copy) / len(copy)
+        factor = kib_copy * 1024.0 / CALIB_BYTES
+        res[counter.lower()] = kib_launch * 1024.0 / factor
+        res[counter.lower() + "_raw_kib"] = kib_launch
+        res[counter.lower() + "_copy_factor"] = factor
+        lines.append(f"| {counter} | {len(mine)} | {kib_launch:.1f} | {kib_copy:.1f} | {factor:.3f} | "
+                     f"{res[counter.lower()] / 1e6:.3f} |")
+    res["traffic"] = res["fetch_size"] + res["write_size"]
+    out = [f"HBM traffic of `{name}` per dispatch.", "",
+           "| counter | dispatches | KiB per dispatch | KiB for a 256 MiB copy | factor | MB per dispatch (scaled) |",
+           "|---|---|---|---|---|---|"] + lines + [
+           "", f"Scaled traffic per launch: {res['traffic'] / 1e6:.3f} MB.", "",
+           "```json", json.dumps(res), "```"]
+    return "\n".join(out)
+
+
+def measured_traffic(kernel):
+    """Bytes per launch of `kernel` from the committed counter summaries, if
+    they were taken on the current source of that kernel; else None."""
+    import glob
+    kind = kernel.split("_")[0]
+    for fn in sorted(glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md"))):
+        with open(fn) as f:
+            txt = f.read()
+        if "```json" not in txt:
+            continue
+        blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+        if blob.get("kernel") == kernel and blob.get("source_hash") == source_hash(kind):
+            return blob["traffic"]
+    return None
 
 
 def main():
@@ -83,7 +230,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--bits", type=int, default=10, help="quantics bits per axis (L = 3 * bits)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-rocprof", metavar="DIR",
+                    help="print a summary of a rocprofv3 run of this script (needs --bench-json) and exit")
+    ap.add_argument("--bench-json", metavar="FILE", help="output of the profiled run")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the traffic summary of two rocprofv3 --pmc runs (needs --bench-json) and exit")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="after the timed sweeps, copy 256 MiB three times (counter calibration)")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        print(summarize_rocprof(args.summarize_rocprof, args.bench_json))
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.bench_json))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the sweep of a single product does not shard "
               "across GPUs (run it with --gpus 1)", file=sys.stderr)
@@ -115,6 +275,7 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     log(f"timed: {args.steps} sweeps in {elapsed:.3f} s; ranks {st['ranks']}; max eps {st['max_eps']:.3e}")
 
+    launches = sess.launches()
     names = ["prrlu", "contract", "gather"]
     kern = {}
     for i, nm in enumerate(names):
@@ -124,19 +285,15 @@ def main():
                     "flops": st["flops"][i]}
     prr_tf = st["flops"][0] / (st["kernel_ms"][0] * 1e-3) / 1e12 if st["kernel_ms"][0] else 0.0
     con_tf = st["flops"][1] / (st["kernel_ms"][1] * 1e-3) / 1e12 if st["kernel_ms"][1] else 0.0
-    dominant = max(range(3), key=lambda i: st["kernel_ms"][i])
-    if dominant == 0:
-        roof = {"kernel": "prrlu_kernel (LDU with full pivoting + pivot-matrix solve)",
-                "bound": "alu", "achieved": prr_tf, "peak": PEAK_FP64_VALU, "unit": "TFLOP/s",
-                "frac": prr_tf / PEAK_FP64_VALU, "traffic": None,
-                "per_launch_flops": st["flops"][0] / max(1, st["launches"][0]),
-                "avg_launch_us": kern["prrlu"]["avg_us"],
-                "us_per_pivot": 1e3 * st["kernel_ms"][0] / max(1, st["pivots"])}
-    else:
-        roof = {"kernel": "contract_kernel (MFMA f64)", "bound": "mfma", "achieved": con_tf,
-                "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": con_tf / PEAK_FP64_MFMA,
-                "traffic": None, "per_launch_flops": st["flops"][1] / max(1, st["launches"][1]),
-                "avg_launch_us": kern["contract"]["avg_us"]}
+    roof = roofline(launches)
+    roof["traffic"] = measured_traffic(roof["kernel"])
+    if args.pmc_calibration:
+        src = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     out = {
         "metric": METRIC,

@@ -135,6 +135,26 @@ typedef struct {
   double max_eps;                    /* largest right-to-left error estimate */
 } aci_sweep_stats;
 
+/* One kernel launch of a profiled aci_session_sweep call (options.profile).
+ * kind: 0 LDU with full pivoting, 1 contraction, 2 frame gather.
+ * variant: kind 0: 10000*solo + 100*RS + CS, the instance
+ *          prrlu_kernel<RS, CS, solo> (RS row slots per wave, CS column
+ *          slots per lane, solo = one workgroup); kind 1: the operation of
+ *          the fused epilogue (-1 none, else aci_op), instance
+ *          contract_kernel<variant>; kind 2: 0.
+ * part: kind 1 only: 1 environment product, 2 two-site tensor (with f).
+ * update: local update within its sweep, 0..2(L-1)-1 (left-to-right first).
+ * flops: algorithmic flops of this launch, counted as in aci_sweep_stats. */
+typedef struct {
+  int32_t kind;
+  int32_t variant;
+  int32_t part;
+  int32_t sweep;                     /* sweep index within the session, from 0 */
+  int32_t update;
+  float us;                          /* device time from HIP events on the stream */
+  double flops;
+} aci_launch;
+
 /* A sweep session keeps the state of Alg. 1 between calls (frames, index
  * sets, cached environments) so that sweeps can be run one at a time, e.g.
  * for timing or to stop on a custom criterion.  It owns its device
@@ -155,6 +175,10 @@ int aci_session_sweep(aci_session* session, int32_t nsweeps, aci_sweep_stats* st
 /* Writes the current output cores (those of the last right-to-left half
  * sweep) like aci_elementwise does. */
 int aci_session_result(aci_session* session, void* out, int64_t out_capacity, aci_result* result);
+/* Copies the launch log of the most recent aci_session_sweep call (empty
+ * unless options.profile) into out[0 .. min(capacity, count)); *count gets
+ * the number of launches.  out may be NULL to query the count. */
+int aci_session_launches(aci_session* session, aci_launch* out, int32_t capacity, int32_t* count);
 void aci_session_destroy(aci_session* session);
 
 /* Context: owns the device workspace, bound to the current device and to

@@ -23,7 +23,8 @@ STATUS_NAMES = {
 EXPORTED = [
     "aci_ctx_create", "aci_ctx_destroy", "aci_last_error", "aci_elementwise",
     "aci_result_free", "aci_env_contract", "aci_pi_eval", "aci_prrlu", "aci_gather",
-    "aci_session_create", "aci_session_sweep", "aci_session_result", "aci_session_destroy",
+    "aci_session_create", "aci_session_sweep", "aci_session_result", "aci_session_launches",
+    "aci_session_destroy",
 ]
 
 
@@ -82,6 +83,18 @@ class AciSweepStats(C.Structure):
     ]
 
 
+class AciLaunch(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32),
+        ("variant", C.c_int32),
+        ("part", C.c_int32),
+        ("sweep", C.c_int32),
+        ("update", C.c_int32),
+        ("us", C.c_float),
+        ("flops", C.c_double),
+    ]
+
+
 class HipError(RuntimeError):
     pass
 
@@ -129,6 +142,8 @@ def load(path=LIB_PATH):
     lib.aci_session_sweep.restype = C.c_int
     lib.aci_session_result.argtypes = [vp, vp, C.c_int64, C.POINTER(AciResult)]
     lib.aci_session_result.restype = C.c_int
+    lib.aci_session_launches.argtypes = [vp, C.POINTER(AciLaunch), i32, C.POINTER(i32)]
+    lib.aci_session_launches.restype = C.c_int
     lib.aci_session_destroy.argtypes = [vp]
     lib.aci_session_destroy.restype = None
     _lib = lib

@@ -178,6 +178,18 @@ def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed
         lib.aci_result_free(C.byref(res))
 
 
+def kernel_name(kind, variant):
+    """Kernel instance behind a launch-log entry, spelled as in the device
+    profiler's kernel names."""
+    if kind == 0:
+        solo, rest = divmod(variant, 10000)
+        rs, cs = divmod(rest, 100)
+        return f"prrlu_kernel<{rs}, {cs}, {'true' if solo else 'false'}>"
+    if kind == 1:
+        return f"contract_kernel<{variant}>"
+    return "gather_kernel"
+
+
 class Session:
     """Alg. 1 one sweep at a time: the constructor runs the initialisation,
     ``sweep(n)`` runs n sweeps, ``result()`` returns the current output."""
@@ -209,6 +221,22 @@ class Session:
                     kernel_ms=list(stats.kernel_ms), launches=list(stats.launches),
                     flops=list(stats.flops), pivots=stats.pivots,
                     ranks=[stats.ranks[i] for i in range(L + 1)], max_eps=stats.max_eps)
+
+    def launches(self):
+        """Launch log of the last ``sweep`` call (needs ``profile=True``): one
+        dict per kernel launch with the kernel instance name as the device
+        profiler reports it, the update it belongs to, its device time (us)
+        and its algorithmic flops."""
+        lib = self.ctx.lib
+        n = C.c_int32(0)
+        _check(lib, self.ctx.h, lib.aci_session_launches(self.h, None, 0, C.byref(n)))
+        buf = (_lib.AciLaunch * max(1, n.value))()
+        _check(lib, self.ctx.h, lib.aci_session_launches(self.h, buf, n.value, C.byref(n)))
+        out = []
+        for r in buf[:n.value]:
+            out.append(dict(kind=("prrlu", "contract", "gather")[r.kind], kernel=kernel_name(r.kind, r.variant),
+                            part=r.part, sweep=r.sweep, update=r.update, us=float(r.us), flops=r.flops))
+        return out
 
     def result(self):
         out, cap = _out_buffer(self.inputs, self.maxrank)

@@ -176,8 +176,16 @@ enum { CLS_PRRLU = 0, CLS_CONTRACT = 1, CLS_GATHER = 2, NCLS = 3 };
 struct Prof {
   bool on = false;
   std::vector<hipEvent_t> pool;
-  std::vector<int> cls;   // class of event pair i (events 2i, 2i+1)
+  // per event pair i (events 2i, 2i+1): class, instance, part, meta slot
+  std::vector<int> cls, variant, part, slot;
   size_t used = 0;
+  void clear() {
+    used = 0;
+    cls.clear();
+    variant.clear();
+    part.clear();
+    slot.clear();
+  }
 };
 
 struct Enq {
@@ -188,7 +196,7 @@ struct Enq {
   int slot = 0;         // meta slot: init calls 0..L-2, sweep calls L-1 ..
   Prof* prof = nullptr;
 
-  int begin(int c) {
+  int begin(int c, int variant = 0, int part = 0) {
     if (!prof || !prof->on) return ACI_OK;
     if (prof->used + 2 > prof->pool.size()) {
       for (int i = 0; i < 64; ++i) {
@@ -198,6 +206,9 @@ struct Enq {
       }
     }
     prof->cls.push_back(c);
+    prof->variant.push_back(variant);
+    prof->part.push_back(part);
+    prof->slot.push_back(slot);
     if (hipEventRecord(prof->pool[prof->used], s) != hipSuccess) return set_err(ctx, ACI_E_HIP, "hipEventRecord");
     return ACI_OK;
   }
@@ -241,7 +252,7 @@ struct Enq {
     a.ldy = ldy;
     a.err = p.flags;
     a.abort_word = p.flags + 1;
-    int rc = begin(CLS_PRRLU);
+    int rc = begin(CLS_PRRLU, prrlu_variant(mmax, nmax));
     if (rc) return rc;
     hipError_t e = launch_prrlu(a, mmax, nmax, s);
     if (e != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("prrlu launch: ") + hipGetErrorString(e));
@@ -263,15 +274,16 @@ struct Enq {
       return set_err(ctx, ACI_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// a profiled launch of class `cls`
-#define ENQP(q, cls, call)            \
-  do {                                \
-    int rc_ = (q).begin(cls);         \
-    if (rc_) return rc_;              \
-    ENQ(call);                        \
-    rc_ = (q).end();                  \
-    if (rc_) return rc_;              \
+// a profiled launch of class `cls` (instance `var`, part `part` of the update)
+#define ENQPV(q, cls, var, part, call)       \
+  do {                                       \
+    int rc_ = (q).begin(cls, var, part);     \
+    if (rc_) return rc_;                     \
+    ENQ(call);                               \
+    rc_ = (q).end();                         \
+    if (rc_) return rc_;                     \
   } while (0)
+#define ENQP(q, cls, call) ENQPV(q, cls, 0, 0, call)
 
 // Initialisation (Alg. 1, first two loops): CI-canonical form of Y_init from
 // right to left, initial right frames R^n_l and the cached B^n_{l-1}.
@@ -366,7 +378,7 @@ int enqueue_pi(Enq& q, int l) {
   gr.M = ddev(p.nI + l - 1, p.d[l]);
   gr.N = ddev(p.nJ + l + 2, p.d[l + 1]);
   gr.ldc = dconst(p.ldm);
-  ENQP(q, CLS_CONTRACT, launch_contract(p.op, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], q.s));
+  ENQPV(q, CLS_CONTRACT, p.op, 2, launch_contract(p.op, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], q.s));
   return ACI_OK;
 }
 
@@ -392,7 +404,7 @@ int enqueue_sweep(Enq& q) {
       gr.ldc = dconst(w);
       nmax = std::max(nmax, w);
     }
-    ENQP(q, CLS_CONTRACT, launch_contract(OP_NONE, c, p.capI[l - 1], nmax, s));
+    ENQPV(q, CLS_CONTRACT, OP_NONE, 1, launch_contract(OP_NONE, c, p.capI[l - 1], nmax, s));
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const int mmax = p.d[l] * p.capI[l - 1], nmax2 = p.d[l + 1] * p.capJ[l + 2];
@@ -430,7 +442,7 @@ int enqueue_sweep(Enq& q) {
       gr.ldc = ddev(p.nJ + l + 2);
       mmax = std::max(mmax, p.r[n][l] * p.d[l + 1]);
     }
-    ENQP(q, CLS_CONTRACT, launch_contract(OP_NONE, c, mmax, p.capJ[l + 2], s));
+    ENQPV(q, CLS_CONTRACT, OP_NONE, 1, launch_contract(OP_NONE, c, mmax, p.capJ[l + 2], s));
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const Dim ncols = ddev(p.nJ + l + 2, p.d[l + 1]);
@@ -486,6 +498,7 @@ struct aci_session {
   std::vector<int> prev;
   int init_ranks[ACI_MAX_SITES + 1];
   Prof prof;
+  std::vector<aci_launch> log;   // launches of the last aci_session_sweep call
   double sweep_ms = 0.0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
 };
@@ -562,24 +575,39 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
 }
 
 // Algorithmic flops of one prrLU record and of the contractions of its update.
-void account(const Plan& p, int kind, int bond, int r, int m, int n, aci_sweep_stats& st) {
+// Algorithmic flops of one part of a local update (kind 1 left-to-right, 2
+// right-to-left, at bond `bond`, with prrLU rank r on an m x n matrix):
+// part 0 the LDU (plus the pivot-matrix solve right to left), 1 the fresh
+// environment product, 2 the two-site tensors.
+double update_flops(const Plan& p, int kind, int bond, int r, int m, int n, int part) {
   double f = 0.0;
-  for (int k = 0; k < r; ++k) f += 2.0 * (double)(m - k - 1) * (double)(n - k - 1);
-  if (kind == 2 && n > r) f += (double)r * (r - 1) * (double)(n - r);
-  st.flops[CLS_PRRLU] += f;
-  st.pivots += r;
-  if (kind == 0) return;
+  if (part == 0) {
+    for (int k = 0; k < r; ++k) f += 2.0 * (double)(m - k - 1) * (double)(n - k - 1);
+    if (kind == 2 && n > r) f += (double)r * (r - 1) * (double)(n - r);
+    return f;
+  }
   const int l = bond;
   const double cL = (double)m / p.d[l], cR = (double)n / p.d[l + 1];
-  double c = 0.0;
   for (int q = 0; q < p.N; ++q) {
-    if (kind == 1)
-      c += 2.0 * cL * p.r[q][l - 1] * p.d[l] * p.r[q][l];
+    if (part == 1)
+      f += kind == 1 ? 2.0 * cL * p.r[q][l - 1] * p.d[l] * p.r[q][l]
+                     : 2.0 * p.r[q][l] * p.d[l + 1] * p.r[q][l + 1] * cR;
     else
-      c += 2.0 * p.r[q][l] * p.d[l + 1] * p.r[q][l + 1] * cR;
-    c += 2.0 * (double)m * p.r[q][l] * (double)n;
+      f += 2.0 * (double)m * p.r[q][l] * (double)n;
   }
-  st.flops[CLS_CONTRACT] += c;
+  return f;
+}
+
+void account(const Plan& p, int kind, int bond, int r, int m, int n, aci_sweep_stats& st) {
+  st.flops[CLS_PRRLU] += update_flops(p, kind, bond, r, m, n, 0);
+  st.pivots += r;
+  st.flops[CLS_CONTRACT] += update_flops(p, kind, bond, r, m, n, 1) + update_flops(p, kind, bond, r, m, n, 2);
+}
+
+// kind and bond of local update u of a sweep
+void update_of(int L, int u, int& kind, int& bond) {
+  kind = u < L - 1 ? 1 : 2;
+  bond = u < L - 1 ? u + 1 : 2 * (L - 1) - u;
 }
 
 }  // namespace
@@ -622,6 +650,14 @@ void aci_result_free(aci_result* r) {
   r->rec_rows = nullptr;
   r->rec_cols = nullptr;
   r->n_records = 0;
+}
+
+int aci_session_launches(aci_session* S, aci_launch* out, int32_t capacity, int32_t* count) {
+  if (!S || !count || capacity < 0) return ACI_E_INVALID;
+  *count = (int32_t)S->log.size();
+  if (out)
+    for (int32_t i = 0; i < capacity && i < *count; ++i) out[i] = S->log[i];
+  return ACI_OK;
 }
 
 void aci_session_destroy(aci_session* S) {
@@ -709,9 +745,9 @@ int aci_session_sweep(aci_session* S, int32_t nsweeps, aci_sweep_stats* stats) {
   aci_sweep_stats st{};
   std::vector<int> cur(L - 1), meta((size_t)3 * 2 * (L - 1));
   std::vector<double> epsb(L - 1);
+  S->log.clear();
   for (int it = 0; it < nsweeps; ++it) {
-    S->prof.used = 0;
-    S->prof.cls.clear();
+    S->prof.clear();
     Enq q{ctx, p, s, S->rec, L - 1, &S->prof};
     HIPCHK(hipEventRecord(S->e0, s));
     int rc = enqueue_sweep(q);
@@ -734,12 +770,27 @@ int aci_session_sweep(aci_session* S, int32_t nsweeps, aci_sweep_stats* stats) {
     for (size_t i = 0; i < S->prof.cls.size(); ++i) {
       float kms = 0.f;
       HIPCHK(hipEventElapsedTime(&kms, S->prof.pool[2 * i], S->prof.pool[2 * i + 1]));
-      st.kernel_ms[S->prof.cls[i]] += kms;
-      st.launches[S->prof.cls[i]] += 1;
+      const int c = S->prof.cls[i];
+      st.kernel_ms[c] += kms;
+      st.launches[c] += 1;
+      aci_launch rec{};
+      rec.kind = c;
+      rec.variant = S->prof.variant[i];
+      rec.part = S->prof.part[i];
+      rec.sweep = S->sweeps - 1;
+      rec.update = S->prof.slot[i] - (L - 1);
+      rec.us = 1e3f * kms;
+      if (rec.update >= 0 && rec.update < 2 * (L - 1) && c != CLS_GATHER) {
+        int kind, bond;
+        update_of(L, rec.update, kind, bond);
+        const int* mt = meta.data() + 3 * rec.update;
+        rec.flops = update_flops(p, kind, bond, mt[0], mt[1], mt[2], c == CLS_PRRLU ? 0 : rec.part);
+      }
+      S->log.push_back(rec);
     }
     for (int u = 0; u < 2 * (L - 1); ++u) {
-      const int kind = u < L - 1 ? 1 : 2;
-      const int bond = u < L - 1 ? u + 1 : 2 * (L - 1) - u;
+      int kind, bond;
+      update_of(L, u, kind, bond);
       account(p, kind, bond, meta[3 * u], meta[3 * u + 1], meta[3 * u + 2], st);
     }
     bool grew = false;

@@ -68,6 +68,9 @@ struct PrrluArgs {
 hipError_t launch_prrlu(const PrrluArgs& a, int mmax, int nmax, hipStream_t s);
 // Exchange-buffer words needed for matrices up to mmax x nmax.
 size_t prrlu_xbuf_words(int mmax, int nmax);
+// Instance launch_prrlu picks for these bounds: 10000*solo + 100*RS + CS, or
+// -1 if the bounds are out of range.
+int prrlu_variant(int mmax, int nmax);
 
 // ----------------------------------------------------------------- gathers
 struct GatherItem {

@@ -626,11 +626,12 @@ const Shape* pick_shape(int nmax) {
   return nullptr;
 }
 
-// Rows per group: the fewest register slots that keep the group count at or
-// below the target (more groups spread the elimination over more CUs, fewer
-// shorten the exchange).
+// Rows per group: the fewest register slots that keep the group count within
+// one XCD (one group per CU).  More groups spread the elimination over more
+// CUs; past one XCD the exchange has to go through device-scope memory, which
+// costs more than the shorter update saves.
 int pick_rs(const Shape& sh, int mmax) {
-  const int target_p = 12;
+  const int target_p = cus_per_xcd();
   int rs = 1;
   while (rs < sh.rs_max && (mmax + WAVES * rs - 1) / (WAVES * rs) > target_p) rs *= 2;
   return rs;
@@ -644,6 +645,15 @@ size_t prrlu_xbuf_words(int mmax, int nmax) {
   const Shape* sh = pick_shape(nmax < 1 ? 1 : nmax);
   if (!sh) sh = &kShapes[sizeof(kShapes) / sizeof(kShapes[0]) - 1];
   return (size_t)2 * 64 * (4 + 2 * 64 * sh->cs);
+}
+
+int prrlu_variant(int mmax, int nmax) {
+  if (mmax < 1 || nmax < 1 || mmax > ACI_MAX_MATRIX || nmax > ACI_MAX_MATRIX) return -1;
+  const Shape* sh = pick_shape(nmax);
+  if (!sh) return -1;
+  const int rs = pick_rs(*sh, mmax);
+  const int P = (mmax + WAVES * rs - 1) / (WAVES * rs);
+  return (P == 1 ? 10000 : 0) + 100 * rs + sh->cs;
 }
 
 hipError_t launch_prrlu(const PrrluArgs& a0, int mmax, int nmax, hipStream_t s) {

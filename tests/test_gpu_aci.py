@@ -120,3 +120,28 @@ def test_repeat_runs_are_bitwise_identical():
     assert ia.ranks == ib.ranks
     for p, q in zip(a, b):
         assert torch.equal(p, q)
+
+
+def test_session_launch_log_matches_sweep_stats():
+    """The per-launch log of a profiled sweep: one LDU, two contractions (the
+    fresh environment and the two-site tensors) and one gather per local
+    update, and per-class sums equal to the call's statistics."""
+    x1, x2 = W.random_pair(L=10, chi=6, seeds=(1061, 1062))
+    L = len(x1)
+    s = aci.Session([to_dev(x1), to_dev(x2)], "product", 1e-10, 30, maxiter=3, seed=7,
+                    fixed_sweeps=True, profile=True)
+    try:
+        st = s.sweep(2)
+        log = s.launches()
+    finally:
+        s.close()
+    assert len(log) == 2 * 4 * 2 * (L - 1)
+    for sw in (st["sweeps_done"] - 2, st["sweeps_done"] - 1):
+        for u in range(2 * (L - 1)):
+            kinds = sorted((r["kind"], r["part"]) for r in log if r["sweep"] == sw and r["update"] == u)
+            assert kinds == [("contract", 1), ("contract", 2), ("gather", 0), ("prrlu", 0)]
+    for i, kind in enumerate(("prrlu", "contract")):
+        assert sum(r["flops"] for r in log if r["kind"] == kind) == pytest.approx(st["flops"][i], rel=1e-12)
+    for i, kind in enumerate(("prrlu", "contract", "gather")):
+        assert sum(r["us"] for r in log if r["kind"] == kind) == pytest.approx(1e3 * st["kernel_ms"][i], rel=1e-4)
+    assert all(r["kernel"].startswith("prrlu_kernel<") for r in log if r["kind"] == "prrlu")

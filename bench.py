@@ -46,7 +46,7 @@ def log(msg):
 def make_inputs(R, device):
     import workloads as W
     t = time.perf_counter()
-    u, v = W.fourier3d_pair(R=R, kmax=KMAX, chi=CHI, seeds=SEEDS, device=device)
+    u, v = W.fourier3d_pair(R=R, kmax=KMAX, chi=CHI, seeds=SEEDS, device=device, progress=log)
     log(f"inputs generated in {time.perf_counter() - t:.1f} s; ranks u {W.tt_ranks(u)}")
     return u, v
 
@@ -177,8 +177,8 @@ def read_counters(directory, counter):
 def summarize_pmc(fetch_dir, write_dir, bench_json):
     """HBM traffic of the dominant kernel instance from two rocprofv3 --pmc
     runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the
-    same counters read for a plain copy of CALIB_BYTES (bench.py
-    --pmc-calibration appends three such copies)."""
+    same counters read for a plain elementwise pass over CALIB_BYTES
+    (bench.py --pmc-calibration ends the run with three of them)."""
     with open(bench_json) as f:
         line = [x for x in f.read().splitlines() if x.startswith("{")][-1]
     b = json.loads(line)
@@ -200,7 +200,7 @@ def summarize_pmc(fetch_dir, write_dir, bench_json):
                      f"{res[counter.lower()] / 1e6:.3f} |")
     res["traffic"] = res["fetch_size"] + res["write_size"]
     out = [f"HBM traffic of `{name}` per dispatch.", "",
-           "| counter | dispatches | KiB per dispatch | KiB for a 256 MiB copy | factor | MB per dispatch (scaled) |",
+           "| counter | dispatches | KiB per dispatch | KiB for a 256 MiB pass | factor | MB per dispatch (scaled) |",
            "|---|---|---|---|---|---|"] + lines + [
            "", f"Scaled traffic per launch: {res['traffic'] / 1e6:.3f} MB.", "",
            "```json", json.dumps(res), "```"]
@@ -236,7 +236,8 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the traffic summary of two rocprofv3 --pmc runs (needs --bench-json) and exit")
     ap.add_argument("--pmc-calibration", action="store_true",
-                    help="after the timed sweeps, copy 256 MiB three times (counter calibration)")
+                    help="after the timed sweeps, read and write 256 MiB three times with an "
+                         "elementwise kernel (counter calibration)")
     args = ap.parse_args()
     if args.summarize_rocprof:
         print(summarize_rocprof(args.summarize_rocprof, args.bench_json))
@@ -291,7 +292,7 @@ def main():
         src = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)         # a plain elementwise read + write
         torch.cuda.synchronize()
         del src, dst
 

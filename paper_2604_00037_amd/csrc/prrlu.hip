@@ -627,12 +627,17 @@ const Shape* pick_shape(int nmax) {
 }
 
 // Rows per group: the fewest register slots that keep the group count within
-// one XCD (one group per CU).  More groups spread the elimination over more
+// one XCD (one group per CU), unless one group can hold all rows.  More groups spread the elimination over more
 // CUs; past one XCD the exchange has to go through device-scope memory, which
 // costs more than the shorter update saves.
 int pick_rs(const Shape& sh, int mmax) {
-  const int target_p = cus_per_xcd();
+  // one workgroup when the rows fit in its registers: the exchange then
+  // stays in LDS, which beats any split of so few rows over several CUs
   int rs = 1;
+  while (rs < sh.rs_max && WAVES * rs < mmax) rs *= 2;
+  if (WAVES * rs >= mmax) return rs;
+  const int target_p = cus_per_xcd();
+  rs = 1;
   while (rs < sh.rs_max && (mmax + WAVES * rs - 1) / (WAVES * rs) > target_p) rs *= 2;
   return rs;
 }

@@ -1,0 +1,31 @@
+"""Input generators: the torch (device) path of the quantics reordering
+agrees with the numpy definition (a transpose of the bit axes)."""
+
+import numpy as np
+import pytest
+
+from workloads.fields import grid_to_quantics, quantics_to_grid
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("R,ndim", [(3, 3), (4, 2), (2, 3), (5, 1)])
+def test_torch_quantics_order_matches_numpy(R, ndim):
+    F = np.random.default_rng(R * 10 + ndim).standard_normal((2 ** R,) * ndim)
+    ref = np.ascontiguousarray(grid_to_quantics(F, R, ndim)).reshape(-1)
+    got = grid_to_quantics(torch.from_numpy(F), R, ndim).numpy()
+    assert np.array_equal(ref, got)
+    assert np.array_equal(quantics_to_grid(got, R, ndim), F)
+
+
+def test_interleaved_site_holds_axis_bit():
+    # site ndim*b + a holds bit b (most significant first) of axis a
+    R, ndim = 3, 2
+    n = 2 ** R
+    x = np.arange(n)
+    F = x[:, None] * 1000 + x[None, :]          # encodes (i0, i1)
+    Q = grid_to_quantics(F, R, ndim)
+    for idx in np.ndindex(*Q.shape):
+        i0 = sum(idx[ndim * b + 0] << (R - 1 - b) for b in range(R))
+        i1 = sum(idx[ndim * b + 1] << (R - 1 - b) for b in range(R))
+        assert Q[idx] == i0 * 1000 + i1

@@ -59,12 +59,16 @@ def _compress(grid, R, ndim, chi, device):
     return tt_svd(q, 2, chi, rtol=1e-14, method="gram")
 
 
-def fourier3d_pair(R=10, kmax=32, chi=128, seeds=(2001, 2002), device=None):
+def fourier3d_pair(R=10, kmax=32, chi=128, seeds=(2001, 2002), device=None, progress=None):
     out = []
     for s in seeds:
         g = fourier3d_full(R, kmax, s, device=device)
+        if progress:
+            progress(f"field seed {s} sampled")
         out.append(_compress(g, R, 3, chi, device))
         del g
+        if progress:
+            progress(f"field seed {s} compressed")
     return tuple(out)
 
 

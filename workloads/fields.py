@@ -37,20 +37,33 @@ def grid_to_quantics(F, R, ndim):
     total = flat.numel()
     out = torch.empty_like(flat)
     n = 2 ** R
-    chunk = 1 << 24
+    nbits = ndim * R
+    # bit t of the quantics index (t = 0 least significant) is site
+    # s = nbits - 1 - t, i.e. bit R-1-b of axis a with s = ndim*b + a; its
+    # weight in the C-order grid index is 2^(R-1-b) * n^(ndim-1-a).  The
+    # grid index is linear in these bits, so two tables over the low and the
+    # high half of the bits give it with one add.
+    h = nbits // 2
+    weights = []
+    for t in range(nbits):
+        s_ = nbits - 1 - t
+        a, b = s_ % ndim, s_ // ndim
+        weights.append((2 ** (R - 1 - b)) * n ** (ndim - 1 - a))
+
+    def table(lo_bit, nb):
+        v = np.zeros(2 ** nb, dtype=np.int64)
+        for t in range(nb):
+            v[(np.arange(2 ** nb) >> t) & 1 == 1] += weights[lo_bit + t]
+        return torch.from_numpy(v).to(flat.device)
+
+    t_lo = table(0, h)
+    t_hi = table(h, nbits - h)
+    chunk = 1 << 26
     for start in range(0, total, chunk):
         q = torch.arange(start, min(start + chunk, total), device=flat.device, dtype=torch.int64)
-        # quantics index q: site ndim*b + a (b = bit level from the top) holds
-        # bit R-1-b of axis a; the last site is the least significant digit
-        src = torch.zeros_like(q)
-        for a in range(ndim):
-            coord = torch.zeros_like(q)
-            for b in range(R):
-                site = ndim * b + a
-                bit = (q >> (ndim * R - 1 - site)) & 1
-                coord |= bit << (R - 1 - b)
-            src = src * n + coord
+        src = t_hi[q >> h] + t_lo[q & ((1 << h) - 1)]
         out[start:start + q.numel()] = flat[src]
+        del q, src
     return out
 
 

@@ -31,6 +31,9 @@ if ROOT not in sys.path:
 METRIC = "ACI sweeps/s + contraction TFLOP/s vs plain FP64 GPU ACI at rel err 1e-8"
 PEAK_FP64_VALU = 78.6      # TFLOP/s, MI355X FP64 vector
 PEAK_FP64_MFMA = 78.6      # TFLOP/s, MI355X FP64 matrix
+PEAK_MFMA = {"fp64": 78.6, "fp32": 157.3,
+             # bf16x3 runs three bf16 products per algorithmic product
+             "bf16x3": 2500.0 / 3}
 TOL = 1e-8
 MAXRANK = 192
 CHI = 128
@@ -223,6 +226,32 @@ def measured_traffic(kernel):
     return None
 
 
+def time_mode(aci, inputs, precision, steps, warmup):
+    """Sweeps/s with the contractions in a lower precision (the LDU, the
+    solve and the error estimate stay FP64); the precision ladder is held
+    (no switch to FP64) so that every timed sweep runs in that precision."""
+    import torch
+    total = steps + warmup
+    sess = aci.Session(inputs, "product", TOL, MAXRANK, maxiter=total, seed=INIT_SEED, fixed_sweeps=True,
+                       profile=True, precision=precision, low_precision_sweeps=-1)
+    if warmup:
+        sess.sweep(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sess.sweep(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sess.close()
+    con_tf = st["flops"][1] / (st["kernel_ms"][1] * 1e-3) / 1e12 if st["kernel_ms"][1] else 0.0
+    log(f"{precision}: {steps} sweeps in {elapsed:.3f} s; contractions {con_tf:.2f} TFLOP/s; "
+        f"max eps {st['max_eps']:.3e}")
+    return {"sweeps_per_s": steps / elapsed, "ms_per_sweep": 1e3 * elapsed / steps,
+            "contraction_tflops": con_tf, "contraction_frac": con_tf / PEAK_MFMA[precision],
+            "contraction_ms_per_sweep": st["kernel_ms"][1] / steps,
+            "prrlu_ms_per_sweep": st["kernel_ms"][0] / steps, "max_eps": st["max_eps"],
+            "ranks": st["ranks"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +259,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--bits", type=int, default=10, help="quantics bits per axis (L = 3 * bits)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16x3 contraction modes")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print a summary of a rocprofv3 run of this script (needs --bench-json) and exit")
     ap.add_argument("--bench-json", metavar="FILE", help="output of the profiled run")
@@ -326,6 +356,12 @@ def main():
         "max_eps": st["max_eps"],
     }
     sess.close()
+    out["modes"] = {"fp64": {"sweeps_per_s": out["value"], "ms_per_sweep": ms_per_step,
+                             "contraction_tflops": con_tf,
+                             "contraction_frac": con_tf / PEAK_MFMA["fp64"]}}
+    if not args.no_mixed:
+        for prec in ("fp32", "bf16x3"):
+            out["modes"][prec] = time_mode(aci, inputs, prec, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u, v)
         out["speedup_vs_cpu_oracle"] = out["value"] / out["cpu_baseline"]["value"]

@@ -83,11 +83,21 @@ typedef struct {
   int32_t stop_rule;     /* 0: exclusive (default; never accept |pivot| <= tol
                             after the first, error = largest remaining
                             residual); 1: literal Alg. 2 (accept, then stop) */
-  int32_t precision;     /* aci_precision, default ACI_PREC_FP64 */
+  int32_t precision;     /* aci_precision of the contractions (environments and
+                            two-site tensors); the LDU, the solve and the error
+                            estimate are FP64 in every mode.  FP32 / BF16X3
+                            start a precision ladder: low-precision sweeps
+                            never count as converged; the sweeps switch to FP64
+                            after a low-precision sweep that kept the
+                            right-to-left ranks, or after low_precision_sweeps
+                            of them.  aci_elementwise always ends with an FP64
+                            sweep. */
   int32_t trace;         /* 1: record the pivots of every local update */
   int32_t fixed_sweeps;  /* 1: run exactly maxiter sweeps, no early exit */
   int32_t profile;       /* 1: time every kernel launch with HIP events
                             (aci_sweep_stats.kernel_ms) */
+  int32_t low_precision_sweeps; /* ladder limit: 0 selects 4; < 0 never leaves
+                            the low precision (sessions only, for timing) */
 } aci_options;
 
 /* Result of aci_elementwise.  Output cores are written compactly, site after
@@ -133,15 +143,17 @@ typedef struct {
   int32_t pivots;                    /* prrLU steps (pivots accepted) in this call */
   int32_t ranks[ACI_MAX_SITES + 1];  /* right-to-left ranks after the last sweep */
   double max_eps;                    /* largest right-to-left error estimate */
+  int32_t last_precision;            /* aci_precision of the last sweep run */
 } aci_sweep_stats;
 
 /* One kernel launch of a profiled aci_session_sweep call (options.profile).
  * kind: 0 LDU with full pivoting, 1 contraction, 2 frame gather.
  * variant: kind 0: 10000*solo + 100*RS + CS, the instance
  *          prrlu_kernel<RS, CS, solo> (RS row slots per wave, CS column
- *          slots per lane, solo = one workgroup); kind 1: the operation of
- *          the fused epilogue (-1 none, else aci_op), instance
- *          contract_kernel<variant>; kind 2: 0.
+ *          slots per lane, solo = one workgroup); kind 1:
+ *          100*precision + op + 1 with op the fused epilogue (-1 none, else
+ *          aci_op): instance contract_kernel<op> (FP64) or
+ *          contract_lp_kernel<op, precision>; kind 2: 0.
  * part: kind 1 only: 1 environment product, 2 two-site tensor (with f).
  * update: local update within its sweep, 0..2(L-1)-1 (left-to-right first).
  * flops: algorithmic flops of this launch, counted as in aci_sweep_stats. */
@@ -208,17 +220,20 @@ void aci_result_free(aci_result* result);
 /* Environment contractions (Eq. pifromframes, Alg. 5):
  *   side 0 (left):  A = Lf (c x r0) * X (r0 x d r1)        -> A (c x d r1)
  *   side 1 (right): B = X (r0 d x r1) * Rf (r1 x c)        -> B (r0 d x c)
- * Each of the `count` contractions uses its own pointers; dims are shared. */
+ * Each of the `count` contractions uses its own pointers; dims are shared.
+ * precision: aci_precision of the products (operands and result FP64). */
 int aci_env_contract(aci_ctx* ctx, int32_t dtype, int32_t side, int32_t count,
                      const void* const* frames, const void* const* cores,
-                     void* const* out, int32_t c, int32_t r0, int32_t d, int32_t r1);
+                     void* const* out, int32_t c, int32_t r0, int32_t d, int32_t r1,
+                     int32_t precision);
 
 /* Two-site tensor with f applied (Eq. pifromframes, Eq. localupdate):
  *   M = f(A^1 B^1, ..., A^N B^N),  A^n: m x k[n] (ld k[n]), B^n: k[n] x n (ld n),
- *   M: m x n with leading dimension ldm >= n. */
+ *   M: m x n with leading dimension ldm >= n.
+ * precision: aci_precision of the products; f is applied in FP64. */
 int aci_pi_eval(aci_ctx* ctx, int32_t dtype, int32_t op, int32_t n_inputs,
                 const void* const* A, const void* const* B, const int32_t* k,
-                int32_t m, int32_t n, void* M, int32_t ldm);
+                int32_t m, int32_t n, void* M, int32_t ldm, int32_t precision);
 
 /* LDU with full pivoting (Alg. 2) of the m x n matrix M (ld ldm).  The input
  * is not modified.  Outputs (device): rows[r], cols[r] = pivot row/column ids

@@ -47,6 +47,7 @@ class AciOptions(C.Structure):
         ("trace", C.c_int32),
         ("fixed_sweeps", C.c_int32),
         ("profile", C.c_int32),
+        ("low_precision_sweeps", C.c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ class AciSweepStats(C.Structure):
         ("pivots", C.c_int32),
         ("ranks", C.c_int32 * (MAX_SITES + 1)),
         ("max_eps", C.c_double),
+        ("last_precision", C.c_int32),
     ]
 
 
@@ -126,10 +128,10 @@ def load(path=LIB_PATH):
     lib.aci_result_free.argtypes = [C.POINTER(AciResult)]
     lib.aci_result_free.restype = None
     lib.aci_env_contract.argtypes = [vp, i32, i32, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
-                                     i32, i32, i32, i32]
+                                     i32, i32, i32, i32, i32]
     lib.aci_env_contract.restype = C.c_int
     lib.aci_pi_eval.argtypes = [vp, i32, i32, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i32),
-                                i32, i32, vp, i32]
+                                i32, i32, vp, i32, i32]
     lib.aci_pi_eval.restype = C.c_int
     lib.aci_prrlu.argtypes = [vp, i32, vp, i32, i32, i32, C.c_double, i32, i32, vp, vp, vp, vp, vp, i32]
     lib.aci_prrlu.restype = C.c_int

@@ -93,8 +93,10 @@ class Info:
     records: list = field(default_factory=list)
 
 
-def _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, profile):
+def _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, profile,
+             low_precision_sweeps=0):
     opts = _lib.AciOptions()
+    opts.low_precision_sweeps = int(low_precision_sweeps)
     opts.maxiter = maxiter
     opts.seed = seed
     opts.stop_rule = RULES[stop_rule]
@@ -159,14 +161,16 @@ def _unpack(res, out, dims, status, trace):
 
 
 def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
-                stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False, ctx=None):
+                stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False,
+                low_precision_sweeps=0, ctx=None):
     """Alg. 1: returns (cores, info) with cores a list of device tensors of
     shape (r_{l-1}, d_l, r_l) approximating op(inputs) elementwise."""
     ctx = ctx or default_context()
     lib = ctx.lib
     keep = []
     tts = _inputs(inputs, keep)
-    opts = _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, False)
+    opts = _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, False,
+                    low_precision_sweeps)
     out, cap = _out_buffer(inputs, maxrank)
     res = _lib.AciResult()
     status = lib.aci_elementwise(ctx.h, tts, len(inputs), F64, OPS[op], float(tol), int(maxrank),
@@ -186,7 +190,9 @@ def kernel_name(kind, variant):
         rs, cs = divmod(rest, 100)
         return f"prrlu_kernel<{rs}, {cs}, {'true' if solo else 'false'}>"
     if kind == 1:
-        return f"contract_kernel<{variant}>"
+        prec, op = divmod(variant, 100)
+        op -= 1
+        return f"contract_kernel<{op}>" if prec == 0 else f"contract_lp_kernel<{op}, {prec}>"
     return "gather_kernel"
 
 
@@ -196,7 +202,7 @@ class Session:
 
     def __init__(self, inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
                  stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False,
-                 profile=False, ctx=None):
+                 profile=False, low_precision_sweeps=0, ctx=None):
         self.ctx = ctx or default_context()
         self.inputs = inputs            # the library reads these until close()
         self.maxrank = maxrank
@@ -204,7 +210,7 @@ class Session:
         self._keep = []
         tts = _inputs(inputs, self._keep)
         opts = _options(self._keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps,
-                        profile)
+                        profile, low_precision_sweeps)
         self._init = init
         h = C.c_void_p()
         st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), F64, OPS[op], float(tol),
@@ -220,7 +226,8 @@ class Session:
         return dict(status=st, sweeps_done=stats.sweeps_done, converged=bool(stats.converged),
                     kernel_ms=list(stats.kernel_ms), launches=list(stats.launches),
                     flops=list(stats.flops), pivots=stats.pivots,
-                    ranks=[stats.ranks[i] for i in range(L + 1)], max_eps=stats.max_eps)
+                    ranks=[stats.ranks[i] for i in range(L + 1)], max_eps=stats.max_eps,
+                    last_precision=[k for k, v in PRECISIONS.items() if v == stats.last_precision][0])
 
     def launches(self):
         """Launch log of the last ``sweep`` call (needs ``profile=True``): one
@@ -261,7 +268,7 @@ class Session:
 
 
 # ------------------------------------------------------------ single steps
-def env_contract(side, frames, cores, ctx=None):
+def env_contract(side, frames, cores, precision="fp64", ctx=None):
     """side "left": A = L X (c x d r1); side "right": B = X R (r0 d x c)."""
     ctx = ctx or default_context()
     n = len(frames)
@@ -279,12 +286,13 @@ def env_contract(side, frames, cores, ctx=None):
     fp = (C.c_void_p * n)(*[f.data_ptr() for f in frames])
     cp = (C.c_void_p * n)(*[x.data_ptr() for x in cores])
     op_ = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
-    st = ctx.lib.aci_env_contract(ctx.h, F64, 0 if side == "left" else 1, n, fp, cp, op_, c, r0, d, r1)
+    st = ctx.lib.aci_env_contract(ctx.h, F64, 0 if side == "left" else 1, n, fp, cp, op_, c, r0, d, r1,
+                                  PRECISIONS[precision])
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     return outs
 
 
-def pi_eval(op, A, B, ctx=None):
+def pi_eval(op, A, B, precision="fp64", ctx=None):
     """M = op(A[0] @ B[0], A[1] @ B[1], ...) on the matrix cores."""
     ctx = ctx or default_context()
     n = len(A)
@@ -297,7 +305,8 @@ def pi_eval(op, A, B, ctx=None):
     ap = (C.c_void_p * n)(*[a.data_ptr() for a in A])
     bp = (C.c_void_p * n)(*[b.data_ptr() for b in B])
     ks = (C.c_int32 * n)(*[int(a.shape[1]) for a in A])
-    st = ctx.lib.aci_pi_eval(ctx.h, F64, OPS[op], n, ap, bp, ks, m, ncol, C.c_void_p(M.data_ptr()), ncol)
+    st = ctx.lib.aci_pi_eval(ctx.h, F64, OPS[op], n, ap, bp, ks, m, ncol, C.c_void_p(M.data_ptr()), ncol,
+                             PRECISIONS[precision])
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     return M
 

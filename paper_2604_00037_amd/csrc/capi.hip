@@ -93,6 +93,9 @@ struct SplitMix64 {
 
 struct Plan {
   int L = 0, N = 0, op = 0, maxrank = 0, maxiter = 20, rule = 0;
+  int prec_req = PREC_FP64;   // requested contraction precision
+  int prec = PREC_FP64;       // precision of the sweep being enqueued
+  int low_max = 4;            // ladder: most low-precision sweeps (< 0: no limit)
   bool trace = false, fixed = false;
   double tol = 0.0;
   int d[ACI_MAX_SITES + 1];                         // d[l], l = 1..L
@@ -169,6 +172,9 @@ void layout(Plan& p, Arena& A, bool gen_init) {
     p.tr_cols = A.take<int>((size_t)p.n_rec * p.maxrank);
   }
 }
+
+// Launch-log instance code of a contraction (see aci_launch).
+int contract_variant(int op, int prec) { return 100 * prec + op + 1; }
 
 // Kernel classes of the profile (see aci_sweep_stats).
 enum { CLS_PRRLU = 0, CLS_CONTRACT = 1, CLS_GATHER = 2, NCLS = 3 };
@@ -328,7 +334,8 @@ int enqueue_init(Enq& q) {
       gr.M = dconst(p.rho[l - 2] * p.d[l - 1]);
       gr.N = ddev(p.nJ + l);
       gr.ldc = ddev(p.nJ + l);
-      ENQP(q, CLS_CONTRACT, launch_contract(OP_NONE, c, p.rho[l - 2] * p.d[l - 1], p.maxrank, s));
+      ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, PREC_FP64), 1,
+            launch_contract(OP_NONE, PREC_FP64, c, p.rho[l - 2] * p.d[l - 1], p.maxrank, s));
     }
     // B^n_{l-1} = X^n_l R^n_{l+1};  R^n_l = B^n_{l-1}[:, J_l]  (Alg. 5, Rightframe)
     ContractArgs c{};
@@ -344,7 +351,7 @@ int enqueue_init(Enq& q) {
       gr.ldc = ddev(p.nJ + l + 1);
       mmax = std::max(mmax, p.r[n][l - 1] * dl);
     }
-    ENQP(q, CLS_CONTRACT, launch_contract(OP_NONE, c, mmax, p.capJ[l + 1], s));
+    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, PREC_FP64), 1, launch_contract(OP_NONE, PREC_FP64, c, mmax, p.capJ[l + 1], s));
     GatherArgs g{};
     g.count = p.N;
     g.side = 1;
@@ -378,7 +385,8 @@ int enqueue_pi(Enq& q, int l) {
   gr.M = ddev(p.nI + l - 1, p.d[l]);
   gr.N = ddev(p.nJ + l + 2, p.d[l + 1]);
   gr.ldc = dconst(p.ldm);
-  ENQPV(q, CLS_CONTRACT, p.op, 2, launch_contract(p.op, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], q.s));
+  ENQPV(q, CLS_CONTRACT, contract_variant(p.op, p.prec), 2,
+        launch_contract(p.op, p.prec, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], q.s));
   return ACI_OK;
 }
 
@@ -404,7 +412,7 @@ int enqueue_sweep(Enq& q) {
       gr.ldc = dconst(w);
       nmax = std::max(nmax, w);
     }
-    ENQPV(q, CLS_CONTRACT, OP_NONE, 1, launch_contract(OP_NONE, c, p.capI[l - 1], nmax, s));
+    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec), 1, launch_contract(OP_NONE, p.prec, c, p.capI[l - 1], nmax, s));
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const int mmax = p.d[l] * p.capI[l - 1], nmax2 = p.d[l + 1] * p.capJ[l + 2];
@@ -442,7 +450,7 @@ int enqueue_sweep(Enq& q) {
       gr.ldc = ddev(p.nJ + l + 2);
       mmax = std::max(mmax, p.r[n][l] * p.d[l + 1]);
     }
-    ENQPV(q, CLS_CONTRACT, OP_NONE, 1, launch_contract(OP_NONE, c, mmax, p.capJ[l + 2], s));
+    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec), 1, launch_contract(OP_NONE, p.prec, c, mmax, p.capJ[l + 2], s));
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const Dim ncols = ddev(p.nJ + l + 2, p.d[l + 1]);
@@ -495,6 +503,7 @@ struct aci_session {
   int sweeps = 0;
   bool converged = false;
   bool fixed = false;
+  int low_done = 0;              // low-precision sweeps run so far
   std::vector<int> prev;
   int init_ranks[ACI_MAX_SITES + 1];
   Prof prof;
@@ -516,7 +525,8 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
   if (!(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "tol must be >= 0");
   if (maxrank < 1) return set_err(ctx, ACI_E_INVALID, "maxrank must be >= 1");
   if (maxrank > ACI_MAX_RANK) return set_err(ctx, ACI_E_LIMIT, "maxrank above ACI_MAX_RANK");
-  if (o.precision != ACI_PREC_FP64) return set_err(ctx, ACI_E_DTYPE, "only ACI_PREC_FP64 is supported by this build");
+  if (o.precision != ACI_PREC_FP64 && o.precision != ACI_PREC_FP32 && o.precision != ACI_PREC_BF16X3)
+    return set_err(ctx, ACI_E_DTYPE, "unknown precision");
   if (o.stop_rule != 0 && o.stop_rule != 1) return set_err(ctx, ACI_E_INVALID, "stop_rule must be 0 or 1");
   const int L = inputs[0].L;
   if (L < 2 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
@@ -529,6 +539,9 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
   p.rule = o.stop_rule;
   p.trace = o.trace != 0;
   p.fixed = o.fixed_sweeps != 0;
+  p.prec_req = o.precision;
+  p.prec = o.precision;
+  p.low_max = o.low_precision_sweeps == 0 ? 4 : o.low_precision_sweeps;
   for (int n = 0; n < n_inputs; ++n) {
     int rc = validate_tt(ctx, inputs[n], L);
     if (rc) return rc;
@@ -748,6 +761,7 @@ int aci_session_sweep(aci_session* S, int32_t nsweeps, aci_sweep_stats* stats) {
   S->log.clear();
   for (int it = 0; it < nsweeps; ++it) {
     S->prof.clear();
+    const int swept_prec = p.prec;
     Enq q{ctx, p, s, S->rec, L - 1, &S->prof};
     HIPCHK(hipEventRecord(S->e0, s));
     int rc = enqueue_sweep(q);
@@ -800,8 +814,18 @@ int aci_session_sweep(aci_session* S, int32_t nsweeps, aci_sweep_stats* stats) {
       emax = std::max(emax, epsb[b]);
     }
     S->prev = cur;
-    S->converged = !grew && emax <= p.tol;
     st.max_eps = emax;
+    st.last_precision = swept_prec;
+    if (swept_prec == PREC_FP64) {
+      S->converged = !grew && emax <= p.tol;
+    } else {
+      // precision ladder: a low-precision sweep never converges (its Pi
+      // carries errors above the tolerance); the next sweeps run in FP64 once
+      // a low-precision sweep kept the ranks or after low_max of them
+      S->converged = false;
+      ++S->low_done;
+      if (p.low_max >= 0 && (!grew || S->low_done >= p.low_max)) p.prec = PREC_FP64;
+    }
     if (S->converged && !S->fixed) break;
   }
   st.sweeps_done = S->sweeps;
@@ -903,7 +927,18 @@ int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_
   aci_session* S = nullptr;
   int rc = aci_session_create(ctx, inputs, n_inputs, dtype, op, tol, maxrank, &o, &S);
   if (rc < 0) return rc;
-  rc = aci_session_sweep(S, o.maxiter, nullptr);
+  if (S->plan->prec != PREC_FP64 && o.maxiter > 1) {
+    // precision ladder: the last allowed sweep is always FP64, so the
+    // returned cores, ranks and error estimates are FP64 results
+    rc = aci_session_sweep(S, o.maxiter - 1, nullptr);
+    if (rc >= 0 && !S->converged) {
+      S->plan->prec = PREC_FP64;
+      rc = aci_session_sweep(S, 1, nullptr);
+    }
+  } else {
+    if (S->plan->prec != PREC_FP64) S->plan->prec = PREC_FP64;
+    rc = aci_session_sweep(S, o.maxiter, nullptr);
+  }
   if (rc < 0) {
     aci_session_destroy(S);
     return rc;
@@ -929,10 +964,12 @@ static int ensure_step_ws(aci_ctx* ctx) {
 }
 
 int aci_env_contract(aci_ctx* ctx, int32_t dtype, int32_t side, int32_t count, const void* const* frames,
-                     const void* const* cores, void* const* outp, int32_t c, int32_t r0, int32_t d, int32_t r1) {
+                     const void* const* cores, void* const* outp, int32_t c, int32_t r0, int32_t d, int32_t r1,
+                     int32_t precision) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
   if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (precision < ACI_PREC_FP64 || precision > ACI_PREC_BF16X3) return set_err(ctx, ACI_E_DTYPE, "unknown precision");
   if (count < 1 || count > ACI_MAX_INPUTS || !frames || !cores || !outp) return set_err(ctx, ACI_E_INVALID, "bad count or null");
   if (c < 1 || r0 < 1 || d < 1 || r1 < 1) return set_err(ctx, ACI_E_INVALID, "bad dims");
   ContractArgs a{};
@@ -956,16 +993,18 @@ int aci_env_contract(aci_ctx* ctx, int32_t dtype, int32_t side, int32_t count, c
     }
   }
   if (side == 0) { mmax = c; nmax = d * r1; } else { mmax = r0 * d; nmax = c; }
-  HIPCHK(launch_contract(OP_NONE, a, mmax, nmax, ctx->stream));
+  HIPCHK(launch_contract(OP_NONE, precision, a, mmax, nmax, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return ACI_OK;
 }
 
 int aci_pi_eval(aci_ctx* ctx, int32_t dtype, int32_t op, int32_t n_inputs, const void* const* A,
-                const void* const* B, const int32_t* k, int32_t m, int32_t n, void* M, int32_t ldm) {
+                const void* const* B, const int32_t* k, int32_t m, int32_t n, void* M, int32_t ldm,
+                int32_t precision) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
   if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (precision < ACI_PREC_FP64 || precision > ACI_PREC_BF16X3) return set_err(ctx, ACI_E_DTYPE, "unknown precision");
   if (n_inputs < 1 || n_inputs > ACI_MAX_INPUTS || !A || !B || !k || !M) return set_err(ctx, ACI_E_INVALID, "bad arguments");
   if (op == ACI_OP_ABS2_MUL && n_inputs != 1) return set_err(ctx, ACI_E_INVALID, "ABS2_MUL takes one input");
   if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL) return set_err(ctx, ACI_E_INVALID, "op");
@@ -987,7 +1026,7 @@ int aci_pi_eval(aci_ctx* ctx, int32_t dtype, int32_t op, int32_t n_inputs, const
   g.M = dconst(m);
   g.N = dconst(n);
   g.ldc = dconst(ldm);
-  HIPCHK(launch_contract(op, a, m, n, ctx->stream));
+  HIPCHK(launch_contract(op, precision, a, m, n, ctx->stream));
   int flags = 0;
   HIPCHK(hipMemcpyAsync(&flags, ctx->step_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -1,16 +1,25 @@
-// Dense contractions of the local update on the FP64 matrix cores.
+// Dense contractions of the local update on the matrix cores.
 //
 // Environment contractions A = L_{l-1} X_l and B = X_{l+1} R_{l+2} and the
 // two-site tensors Pi^n = A^n B^n (Eq. pifromframes), with the elementwise f
 // of Eq. (localupdate) applied in the epilogue so that Pi = f(Pi^1..Pi^N) is
 // written once.  Each workgroup computes a 64x64 output tile; its four waves
-// each own a 32x32 quarter made of 2x2 blocks of v_mfma_f64_16x16x4f64.
-// Operand tiles of 64x16 (A, stored k-major) and 16x64 (B) are staged through
-// LDS so that every lane of an MFMA reads consecutive doubles.
+// each own a 32x32 quarter made of 2x2 blocks of 16x16 MFMA tiles.  Operands
+// are FP64 in HBM and the result is written in FP64 in every precision:
 //
-// v_mfma_f64_16x16x4f64 lane layout (measured on gfx950): lane l supplies
-// A[l%16][l/16] and B[l/16][l%16]; accumulator item v of lane l is
-// C[l/16 + 4v][l%16].
+// * FP64: v_mfma_f64_16x16x4f64; 64x16 (A, k-major) and 16x64 (B) tiles in
+//   LDS so that every lane of an MFMA reads consecutive doubles.
+// * FP32: operands rounded to FP32 while staged, v_mfma_f32_16x16x4f32,
+//   FP32 accumulation.
+// * BF16x3: each operand x is split while staged into hi = bf16(x) and
+//   lo = bf16(x - hi) (x first rounded to FP32); the product uses
+//   hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
+//   accumulation (about 16 significant bits per operand).
+//
+// Lane layouts (measured on gfx950), lane l, r = l % 16, g = l / 16:
+//   f64 16x16x4:   A[r][g], B[g][r];            acc item v = C[g + 4v][r]
+//   f32 16x16x4:   A[r][g], B[g][r];            acc item v = C[4g + v][r]
+//   bf16 16x16x32: A[r][8g + e], B[8g + e][r];  acc item v = C[4g + v][r]
 #include "kernels.h"
 
 namespace aci {
@@ -134,12 +143,195 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
   if (OP != OP_NONE && bad && args.err) atomicOr(args.err, ERR_NONFINITE);
 }
 
+// ---------------------------------------------------------------- FP32 / BF16x3
+constexpr int KL = 32;        // k per staged chunk
+constexpr int LDF = TM + 4;   // FP32 tiles, k-major rows of 64 (+pad)
+constexpr int LDH = KL + 8;   // bf16 tiles, 32 k per row/column (+pad; 16-byte rows)
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// Round-to-nearest-even FP32 -> bf16 bits (finite inputs; a non-finite
+// input stays non-finite, which the epilogue flags).
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  const unsigned int u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+template <int PREC>
+struct LpTiles;
+
+template <>
+struct LpTiles<PREC_FP32> {
+  float A[KL * LDF];   // [k][row]
+  float B[KL * LDF];   // [k][col]
+};
+
+template <>
+struct LpTiles<PREC_BF16X3> {
+  unsigned short Ah[TM * LDH], Al[TM * LDH];   // [row][k]
+  unsigned short Bh[TN * LDH], Bl[TN * LDH];   // [col][k]
+};
+
+template <int OP, int PREC>
+__global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
+  __shared__ LpTiles<PREC> sh;
+  const Group& g = args.g[blockIdx.z];
+  const int M = dget(g.M);
+  const int N = dget(g.N);
+  const int m0 = blockIdx.y * TM;
+  const int n0 = blockIdx.x * TN;
+  if (m0 >= M || n0 >= N) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  v4d res[2][2];
+  for (int t = 0; t < g.nterm; ++t) {
+    const Term& T = g.t[t];
+    const int K = dget(T.K);
+    const int lda = dget(T.lda);
+    const int ldb = dget(T.ldb);
+    v4f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < K; k0 += KL) {
+      // A chunk 64 x 32: thread -> row tid / 4, k (tid % 4) * 8 .. +7
+      // B chunk 32 x 64: thread -> k tid / 8, cols (tid % 8) * 8 .. +7
+      const int ar = tid >> 2, ak = (tid & 3) * 8;
+      const int bk = tid >> 3, bc = (tid & 7) * 8;
+      double av[8], bv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gr = m0 + ar, gk = k0 + ak + e;
+        av[e] = (gr < M && gk < K) ? T.A[(size_t)gr * lda + gk] : 0.0;
+        const int hk = k0 + bk, gc = n0 + bc + e;
+        bv[e] = (hk < K && gc < N) ? T.B[(size_t)hk * ldb + gc] : 0.0;
+      }
+      if (PREC == PREC_FP32) {
+        auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          S.A[(ak + e) * LDF + ar] = (float)av[e];
+          S.B[bk * LDF + bc + e] = (float)bv[e];
+        }
+      } else {
+        auto& S = reinterpret_cast<LpTiles<PREC_BF16X3>&>(sh);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float fa = (float)av[e];
+          const unsigned short ha = bf16_bits(fa);
+          S.Ah[ar * LDH + ak + e] = ha;
+          S.Al[ar * LDH + ak + e] = bf16_bits(fa - bf16_value(ha));
+          const float fb = (float)bv[e];
+          const unsigned short hb = bf16_bits(fb);
+          S.Bh[(bc + e) * LDH + bk] = hb;
+          S.Bl[(bc + e) * LDH + bk] = bf16_bits(fb - bf16_value(hb));
+        }
+      }
+      __syncthreads();
+      if (PREC == PREC_FP32) {
+        auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
+#pragma unroll
+        for (int ks = 0; ks < KL / 4; ++ks) {
+          const int kr = ks * 4 + lg;
+          float a[2], b[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) a[i] = S.A[kr * LDF + wm * 32 + i * 16 + lr];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) b[j] = S.B[kr * LDF + wn * 32 + j * 16 + lr];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+      } else {
+        auto& S = reinterpret_cast<LpTiles<PREC_BF16X3>&>(sh);
+        v8bf ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int row = wm * 32 + i * 16 + lr;
+          ah[i] = *reinterpret_cast<const v8bf*>(&S.Ah[row * LDH + 8 * lg]);
+          al[i] = *reinterpret_cast<const v8bf*>(&S.Al[row * LDH + 8 * lg]);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = wn * 32 + j * 16 + lr;
+          bh[j] = *reinterpret_cast<const v8bf*>(&S.Bh[col * LDH + 8 * lg]);
+          bl[j] = *reinterpret_cast<const v8bf*>(&S.Bl[col * LDH + 8 * lg]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const v4d x = v4d{(double)acc[i][j][0], (double)acc[i][j][1], (double)acc[i][j][2], (double)acc[i][j][3]};
+        if (OP == OP_ABS2_MUL) {
+          res[i][j] = (x * x) * x;
+        } else if (OP == OP_NONE || t == 0) {
+          res[i][j] = x;
+        } else {
+          res[i][j] = combine<OP>(res[i][j], x);
+        }
+      }
+  }
+
+  const int ldc = dget(g.ldc);
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 32 + i * 16 + 4 * lg + v;
+        const int col = n0 + wn * 32 + j * 16 + lr;
+        if (row < M && col < N) {
+          const double x = res[i][j][v];
+          if (OP != OP_NONE && !__builtin_isfinite(x)) bad = true;
+          g.C[(size_t)row * ldc + col] = x;
+        }
+      }
+  if (OP != OP_NONE && bad && args.err) atomicOr(args.err, ERR_NONFINITE);
+}
+
+template <int PREC>
+hipError_t launch_prec(int op, const ContractArgs& args, dim3 grid, dim3 block, hipStream_t s) {
+  switch (op) {
+    case OP_NONE: hipLaunchKernelGGL((contract_lp_kernel<OP_NONE, PREC>), grid, block, 0, s, args); break;
+    case OP_PRODUCT: hipLaunchKernelGGL((contract_lp_kernel<OP_PRODUCT, PREC>), grid, block, 0, s, args); break;
+    case OP_SUM: hipLaunchKernelGGL((contract_lp_kernel<OP_SUM, PREC>), grid, block, 0, s, args); break;
+    case OP_ABS2_MUL: hipLaunchKernelGGL((contract_lp_kernel<OP_ABS2_MUL, PREC>), grid, block, 0, s, args); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_contract(int op, const ContractArgs& args, int mmax, int nmax, hipStream_t s) {
+hipError_t launch_contract(int op, int prec, const ContractArgs& args, int mmax, int nmax, hipStream_t s) {
   if (mmax <= 0 || nmax <= 0 || args.ngroup <= 0) return hipSuccess;
   dim3 grid((nmax + TN - 1) / TN, (mmax + TM - 1) / TM, args.ngroup);
   dim3 block(256);
+  if (prec == PREC_FP32) return launch_prec<PREC_FP32>(op, args, grid, block, s);
+  if (prec == PREC_BF16X3) return launch_prec<PREC_BF16X3>(op, args, grid, block, s);
+  if (prec != PREC_FP64) return hipErrorInvalidValue;
   switch (op) {
     case OP_NONE: hipLaunchKernelGGL(contract_kernel<OP_NONE>, grid, block, 0, s, args); break;
     case OP_PRODUCT: hipLaunchKernelGGL(contract_kernel<OP_PRODUCT>, grid, block, 0, s, args); break;

@@ -34,7 +34,8 @@ struct ContractArgs {
 
 // op: OP_NONE (single term, plain GEMM), OP_PRODUCT, OP_SUM, OP_ABS2_MUL.
 // mmax/nmax bound the (possibly device-resident) output sizes of every group.
-hipError_t launch_contract(int op, const ContractArgs& args, int mmax, int nmax, hipStream_t s);
+// prec: PREC_FP64, PREC_FP32 or PREC_BF16X3 (operands and result FP64 in HBM).
+hipError_t launch_contract(int op, int prec, const ContractArgs& args, int mmax, int nmax, hipStream_t s);
 
 // ------------------------------------------------------------------- prrLU
 struct PrrluArgs {

@@ -14,11 +14,26 @@ def to_host(cores):
     return [c.detach().cpu().numpy() for c in cores]
 
 
-def gemm_bound(A, B):
-    """Elementwise forward error bound of a float64 product computed in any
-    summation order: K * 2^-52 * (|A| @ |B|), K the inner dimension."""
+def gemm_bound(A, B, precision="fp64"):
+    """Elementwise forward error bound of a product computed in any summation
+    order, from float64 operands:
+      fp64:   (K + 2) u64 |A||B|;
+      fp32:   operands rounded to fp32 (2 u32) and fp32 accumulation
+              ((K + 2) u32): (K + 4) u32 |A||B|;
+      bf16x3: x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi), so
+              |r| <= 2^-17 |x| (two bf16 roundings of 2^-9 each, plus the
+              fp32 rounding); the dropped lo*lo term and the r terms add at
+              most 2^-15 |a||b| per product, then fp32 accumulation.
+    K is the inner dimension, |A||B| = |A| @ |B|."""
     K = A.shape[1]
-    return (K + 2) * 2.0 ** -52 * (np.abs(A) @ np.abs(B))
+    AB = np.abs(A) @ np.abs(B)
+    if precision == "fp64":
+        return (K + 2) * 2.0 ** -52 * AB
+    if precision == "fp32":
+        return (K + 4) * 2.0 ** -24 * AB
+    if precision == "bf16x3":
+        return (2.0 ** -15 + (K + 4) * 2.0 ** -24) * AB
+    raise ValueError(precision)
 
 
 def compare_records(gpu_records, oracle_trace, label=""):

@@ -145,3 +145,59 @@ def test_session_launch_log_matches_sweep_stats():
     for i, kind in enumerate(("prrlu", "contract", "gather")):
         assert sum(r["us"] for r in log if r["kind"] == kind) == pytest.approx(1e3 * st["kernel_ms"][i], rel=1e-4)
     assert all(r["kernel"].startswith("prrlu_kernel<") for r in log if r["kind"] == "prrlu")
+
+
+# ------------------------------------------------------------ precision ladder
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mixed_precision_ladder_random_pair(precision):
+    """Low-precision sweeps, then FP64 sweeps (the last allowed sweep is
+    FP64): the converged result reconstructs the exact product like the FP64
+    run, within 1e-10 of the oracle's output."""
+    x1, x2 = W.random_pair()
+    ref = oracle.aci([x1, x2], "product", 1e-12, 64, seed=1003)
+    cores, info = aci.elementwise([to_dev(x1), to_dev(x2)], "product", 1e-12, 64, seed=1003,
+                                  precision=precision)
+    assert info.converged
+    y = W.tt_full([c.cpu().numpy() for c in cores])
+    assert rel_max_err(y, W.tt_full(ref.cores)) <= 1e-10
+    assert rel_max_err(y, W.tt_full(x1) * W.tt_full(x2)) <= 1e-10
+    assert info.ranks[1:-1] == ref.ranks
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mixed_precision_ladder_gaussians_at_1e8(precision):
+    """Product of two Gaussians (section 3.1) at tol 1e-8: the mixed-precision
+    run converges and both it and the oracle are within 10 tol of the closed
+    form; their outputs agree within 1e-7 relative."""
+    L = 12
+    gp, gm, h = W.gaussian_pair_full(L)
+    tp = W.tt_svd(gp, 2, 64, rtol=1e-15)
+    tm = W.tt_svd(gm, 2, 64, rtol=1e-15)
+    ref = oracle.aci([tp, tm], "product", 1e-8, 64, seed=11)
+    cores, info = aci.elementwise([to_dev(tp), to_dev(tm)], "product", 1e-8, 64, seed=11,
+                                  precision=precision)
+    assert info.converged
+    y = W.tt_full([c.cpu().numpy() for c in cores]).reshape(-1)
+    yr = W.tt_full(ref.cores).reshape(-1)
+    assert np.abs(y - h).max() <= 10 * 1e-8
+    assert np.abs(yr - h).max() <= 10 * 1e-8
+    assert rel_max_err(y, yr) <= 1e-7
+
+
+def test_session_ladder_switches_to_fp64():
+    x1, x2 = W.random_pair(L=10, chi=6, seeds=(1071, 1072))
+    s = aci.Session([to_dev(x1), to_dev(x2)], "product", 1e-10, 36, maxiter=10, seed=3,
+                    precision="fp32", low_precision_sweeps=2, fixed_sweeps=True)
+    try:
+        precs = [s.sweep(1)["last_precision"] for _ in range(4)]
+    finally:
+        s.close()
+    assert precs[0] == "fp32"
+    assert precs[2:] == ["fp64", "fp64"]
+    s = aci.Session([to_dev(x1), to_dev(x2)], "product", 1e-10, 36, maxiter=10, seed=3,
+                    precision="bf16x3", low_precision_sweeps=-1, fixed_sweeps=True)
+    try:
+        precs = [s.sweep(1)["last_precision"] for _ in range(3)]
+    finally:
+        s.close()
+    assert precs == ["bf16x3"] * 3

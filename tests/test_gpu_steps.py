@@ -24,36 +24,50 @@ def dev(x):
 # ------------------------------------------------------------ contractions
 @pytest.mark.parametrize("c,r0,d,r1", [(1, 1, 2, 1), (5, 3, 2, 7), (64, 64, 2, 64),
                                        (192, 128, 2, 128), (77, 129, 3, 65)])
-def test_env_contractions_match_products(c, r0, d, r1):
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_env_contractions_match_products(c, r0, d, r1, precision):
     rng = np.random.default_rng(c * 7 + r0)
     Ls = [rng.standard_normal((c, r0)) for _ in range(2)]
     Xs = [rng.standard_normal((r0, d, r1)) for _ in range(2)]
-    outs = aci.env_contract("left", [dev(x) for x in Ls], [dev(x) for x in Xs])
+    outs = aci.env_contract("left", [dev(x) for x in Ls], [dev(x) for x in Xs], precision=precision)
     for Lf, X, o in zip(Ls, Xs, outs):
         A = Lf
         B = X.reshape(r0, d * r1)
         ref = A @ B
-        assert np.all(np.abs(o.cpu().numpy() - ref) <= gemm_bound(A, B) + 1e-300)
+        assert np.all(np.abs(o.cpu().numpy() - ref) <= gemm_bound(A, B, precision) + 1e-300)
     Rs = [rng.standard_normal((r1, c)) for _ in range(2)]
-    outs = aci.env_contract("right", [dev(x) for x in Rs], [dev(x) for x in Xs])
+    outs = aci.env_contract("right", [dev(x) for x in Rs], [dev(x) for x in Xs], precision=precision)
     for R, X, o in zip(Rs, Xs, outs):
         A = X.reshape(r0 * d, r1)
         ref = A @ R
-        assert np.all(np.abs(o.cpu().numpy() - ref) <= gemm_bound(A, R) + 1e-300)
+        assert np.all(np.abs(o.cpu().numpy() - ref) <= gemm_bound(A, R, precision) + 1e-300)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_low_precision_products_are_not_fp64(precision):
+    """The low-precision paths really round: their error is far above FP64's
+    on a well-conditioned product (guards against a silent FP64 fallback)."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((128, 96))
+    B = rng.standard_normal((96, 128))
+    M = aci.pi_eval("product", [dev(A)], [dev(B)], precision=precision).cpu().numpy()
+    err = np.abs(M - A @ B).max() / np.abs(A @ B).max()
+    assert err > 1e-9
 
 
 @pytest.mark.parametrize("op,N", [("product", 2), ("sum", 2), ("product", 3), ("abs2_mul", 1),
                                   ("product", 1)])
 @pytest.mark.parametrize("m,n", [(2, 3), (64, 64), (130, 70), (384, 384)])
-def test_two_site_tensor_with_f(op, N, m, n):
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_two_site_tensor_with_f(op, N, m, n, precision):
     rng = np.random.default_rng(m + 31 * n + N)
     ks = [int(k) for k in rng.integers(1, 140, N)]
     A = [rng.standard_normal((m, k)) / np.sqrt(k) for k in ks]
     B = [rng.standard_normal((k, n)) for k in ks]
-    M = aci.pi_eval(op, [dev(a) for a in A], [dev(b) for b in B]).cpu().numpy()
+    M = aci.pi_eval(op, [dev(a) for a in A], [dev(b) for b in B], precision=precision).cpu().numpy()
     ref = apply_op(op, [a @ b for a, b in zip(A, B)])
     # first-order error bound of f applied to perturbed products
-    errs = [gemm_bound(a, b) for a, b in zip(A, B)]
+    errs = [gemm_bound(a, b, precision) for a, b in zip(A, B)]
     vals = [np.abs(a @ b) for a, b in zip(A, B)]
     if op == "sum":
         bound = sum(errs) + 4 * 2.0 ** -52 * sum(vals)

@@ -50,6 +50,7 @@ extern "C" {
 #define ACI_MAX_RANK 512        /* maxrank (output bond dimension cap) */
 #define ACI_MAX_INPUTS 4        /* N */
 #define ACI_MAX_MATRIX 1024     /* rows and columns of a matricised two-site tensor */
+#define ACI_MAX_BATCH 64        /* products of one batch */
 
 typedef enum { ACI_F64 = 0, ACI_C128 = 1 } aci_dtype;
 
@@ -98,6 +99,10 @@ typedef struct {
                             (aci_sweep_stats.kernel_ms) */
   int32_t low_precision_sweeps; /* ladder limit: 0 selects 4; < 0 never leaves
                             the low precision (sessions only, for timing) */
+  int32_t use_graph;     /* 1: capture a sweep's launches once into a hipGraph
+                            and replay it (ignored with profile or trace) */
+  int32_t tune;          /* batches: 1 = pick each product's LDU group count
+                            with aci_tune_prrlu (cached per context) */
 } aci_options;
 
 /* Result of aci_elementwise.  Output cores are written compactly, site after
@@ -244,6 +249,59 @@ int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, 
               double tol, int32_t maxrank, int32_t stop_rule,
               int32_t* rows, int32_t* cols, int32_t* rank, double* eps,
               void* Y, int32_t ldy);
+
+/* ---------------------------------------------------------------- batches
+ * Several independent elementwise operations (for instance the convective
+ * terms u_j d_j u_k of a Navier-Stokes right-hand side), each run as Alg. 1
+ * with the same op, tol, maxrank and options, advanced sweep by sweep
+ * together.  Product b has n_inputs[b] input TTs, taken in order from
+ * `inputs` (products may differ in L, d and ranks).  Each product runs on a
+ * stream of its own, created by the batch and ordered after the work
+ * enqueued on ctx's stream before aci_batch_create; its LDU launches are
+ * placed on XCD b % 8, and products sharing an XCD split its CUs (group
+ * count cap = CUs per XCD / products on that XCD, or the autotuned value
+ * with options.tune).  The batch owns all device memory it uses; input
+ * cores must stay valid until aci_batch_destroy.  options.init must be NULL
+ * (every product starts from the seeded default guess).  Errors name the
+ * product. */
+typedef struct aci_batch aci_batch;
+int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs,
+                     int32_t n_products, int32_t dtype, int32_t op, double tol,
+                     int32_t maxrank, const aci_options* opt, aci_batch** batch);
+/* Runs up to nsweeps sweeps of every product not yet converged (all of
+ * them with options.fixed_sweeps); stats sums kernel times, launches, flops
+ * and pivots over the products, max_eps is the largest over them, ranks are
+ * product 0's.  Returns ACI_OK once every product has converged. */
+int aci_batch_sweep(aci_batch* batch, int32_t nsweeps, aci_sweep_stats* stats);
+/* Output of product `product`, as aci_session_result. */
+int aci_batch_result(aci_batch* batch, int32_t product, void* out, int64_t out_capacity,
+                     aci_result* result);
+/* XCD and LDU group cap chosen for a product.  When some product's LDU
+ * cannot fit its share of an XCD (very large matrices), the batch sweeps
+ * the products one after another with cooperative LDU launches instead and
+ * reports xcd = -1. */
+int aci_batch_info(aci_batch* batch, int32_t product, int32_t* xcd, int32_t* max_groups);
+void aci_batch_destroy(aci_batch* batch);
+/* create + sweeps (the last allowed sweep in FP64, as aci_elementwise) +
+ * results + destroy.  outs[b] / out_capacity[b] / results[b] as in
+ * aci_elementwise.  Returns the worst status over the products. */
+int aci_elementwise_batched(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs,
+                            int32_t n_products, int32_t dtype, int32_t op, double tol,
+                            int32_t maxrank, const aci_options* opt, void* const* outs,
+                            const int64_t* out_capacity, aci_result* results);
+
+/* Autotuner of the LDU launch shape (Alg. 2 kernel): times the LDU of a
+ * seeded random m x n matrix (entries uniform on [-1, 1)) to rank
+ * min(maxrank, m, n) for group-count caps cap, cap/2, cap/4, ... (each
+ * distinct launch shape once; cap <= 0 selects one XCD's CUs), three runs
+ * each with the first discarded, and returns the fastest cap in
+ * *best_groups.  The choice is cached in the context per (m, n, maxrank,
+ * cap).  If candidates / us are given, up to `capacity` tried caps and
+ * their mean times (microseconds) are written and *count gets the number
+ * tried. */
+int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t cap,
+                   int32_t* best_groups, int32_t* candidates, float* us, int32_t capacity,
+                   int32_t* count);
 
 /* Frame update by gathering (Alg. 5, truncation step).  src is h x w with
  * leading dimension ld_src; idx (device) holds r indices, r read from the

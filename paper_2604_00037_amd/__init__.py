@@ -2,13 +2,15 @@
 elementwise operations on tensor trains (M. K. Ritter).
 
 ``elementwise`` runs the full sweep (Alg. 1) in the HIP library
-``libaci.so``; ``env_contract``, ``pi_eval``, ``prrlu`` and ``gather`` expose
-its single steps.  The library must be built (``python -m
+``libaci.so``; ``Session`` runs it sweep by sweep; ``elementwise_batched`` /
+``Batch`` advance several products together; ``env_contract``, ``pi_eval``,
+``prrlu`` and ``gather`` expose its single steps; ``tune_prrlu`` times the
+LDU launch shapes.  The library must be built (``python -m
 paper_2604_00037_amd.build``); nothing falls back to the CPU.
 """
 
-from .aci import (Context, Session, default_context, elementwise, env_contract, gather, pi_eval,
-                  prrlu)
+from .aci import (Batch, Context, Session, default_context, elementwise, elementwise_batched, env_contract,
+                  gather, pi_eval, prrlu, tune_prrlu)
 
-__all__ = ["Context", "Session", "default_context", "elementwise", "env_contract", "gather", "pi_eval",
-           "prrlu"]
+__all__ = ["Batch", "Context", "Session", "default_context", "elementwise", "elementwise_batched",
+           "env_contract", "gather", "pi_eval", "prrlu", "tune_prrlu"]

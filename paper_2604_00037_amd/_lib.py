@@ -24,7 +24,8 @@ EXPORTED = [
     "aci_ctx_create", "aci_ctx_destroy", "aci_last_error", "aci_elementwise",
     "aci_result_free", "aci_env_contract", "aci_pi_eval", "aci_prrlu", "aci_gather",
     "aci_session_create", "aci_session_sweep", "aci_session_result", "aci_session_launches",
-    "aci_session_destroy",
+    "aci_session_destroy", "aci_batch_create", "aci_batch_sweep", "aci_batch_result", "aci_batch_info",
+    "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu",
 ]
 
 
@@ -48,6 +49,8 @@ class AciOptions(C.Structure):
         ("fixed_sweeps", C.c_int32),
         ("profile", C.c_int32),
         ("low_precision_sweeps", C.c_int32),
+        ("use_graph", C.c_int32),
+        ("tune", C.c_int32),
     ]
 
 
@@ -146,6 +149,24 @@ def load(path=LIB_PATH):
     lib.aci_session_result.restype = C.c_int
     lib.aci_session_launches.argtypes = [vp, C.POINTER(AciLaunch), i32, C.POINTER(i32)]
     lib.aci_session_launches.restype = C.c_int
+    lib.aci_batch_create.argtypes = [vp, C.POINTER(AciTT), C.POINTER(i32), i32, i32, i32, C.c_double, i32,
+                                     C.POINTER(AciOptions), C.POINTER(vp)]
+    lib.aci_batch_create.restype = C.c_int
+    lib.aci_batch_sweep.argtypes = [vp, i32, C.POINTER(AciSweepStats)]
+    lib.aci_batch_sweep.restype = C.c_int
+    lib.aci_batch_result.argtypes = [vp, i32, vp, C.c_int64, C.POINTER(AciResult)]
+    lib.aci_batch_result.restype = C.c_int
+    lib.aci_batch_info.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32)]
+    lib.aci_batch_info.restype = C.c_int
+    lib.aci_batch_destroy.argtypes = [vp]
+    lib.aci_batch_destroy.restype = None
+    lib.aci_elementwise_batched.argtypes = [vp, C.POINTER(AciTT), C.POINTER(i32), i32, i32, i32, C.c_double,
+                                            i32, C.POINTER(AciOptions), C.POINTER(vp), C.POINTER(C.c_int64),
+                                            C.POINTER(AciResult)]
+    lib.aci_elementwise_batched.restype = C.c_int
+    lib.aci_tune_prrlu.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32),
+                                   C.POINTER(C.c_float), i32, C.POINTER(i32)]
+    lib.aci_tune_prrlu.restype = C.c_int
     lib.aci_session_destroy.argtypes = [vp]
     lib.aci_session_destroy.restype = None
     _lib = lib

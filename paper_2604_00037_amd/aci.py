@@ -94,9 +94,10 @@ class Info:
 
 
 def _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, profile,
-             low_precision_sweeps=0):
+             low_precision_sweeps=0, use_graph=False):
     opts = _lib.AciOptions()
     opts.low_precision_sweeps = int(low_precision_sweeps)
+    opts.use_graph = 1 if use_graph else 0
     opts.maxiter = maxiter
     opts.seed = seed
     opts.stop_rule = RULES[stop_rule]
@@ -202,7 +203,7 @@ class Session:
 
     def __init__(self, inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
                  stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False,
-                 profile=False, low_precision_sweeps=0, ctx=None):
+                 profile=False, low_precision_sweeps=0, use_graph=False, ctx=None):
         self.ctx = ctx or default_context()
         self.inputs = inputs            # the library reads these until close()
         self.maxrank = maxrank
@@ -210,7 +211,7 @@ class Session:
         self._keep = []
         tts = _inputs(inputs, self._keep)
         opts = _options(self._keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps,
-                        profile, low_precision_sweeps)
+                        profile, low_precision_sweeps, use_graph)
         self._init = init
         h = C.c_void_p()
         st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), F64, OPS[op], float(tol),
@@ -352,3 +353,113 @@ def gather(side, src, idx, ld_out=None, ctx=None):
                             C.c_void_p(out.data_ptr()), max(ld, 1))
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     return out
+
+
+def _stats_dict(stats, L):
+    return dict(sweeps_done=stats.sweeps_done, converged=bool(stats.converged),
+                kernel_ms=list(stats.kernel_ms), launches=list(stats.launches),
+                flops=list(stats.flops), pivots=stats.pivots,
+                ranks=[stats.ranks[i] for i in range(L + 1)], max_eps=stats.max_eps,
+                last_precision=[k for k, v in PRECISIONS.items() if v == stats.last_precision][0])
+
+
+def _batch_inputs(products, keep):
+    counts = [len(p) for p in products]
+    flat = [X for p in products for X in p]
+    return _inputs(flat, keep), (C.c_int32 * len(counts))(*counts)
+
+
+class Batch:
+    """Several elementwise operations advanced together (one stream per
+    product, LDUs spread over the XCDs); see aci_batch_create."""
+
+    def __init__(self, products, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0,
+                 stop_rule="exclusive", precision="fp64", fixed_sweeps=False, profile=False,
+                 low_precision_sweeps=0, use_graph=False, tune=False, ctx=None):
+        self.ctx = ctx or default_context()
+        self.products = products
+        self.maxrank = maxrank
+        self._keep = []
+        tts, counts = _batch_inputs(products, self._keep)
+        opts = _options(self._keep, maxiter, seed, None, stop_rule, precision, False, fixed_sweeps,
+                        profile, low_precision_sweeps, use_graph)
+        opts.tune = 1 if tune else 0
+        h = C.c_void_p()
+        st = self.ctx.lib.aci_batch_create(self.ctx.h, tts, counts, len(products), F64, OPS[op], float(tol),
+                                           int(maxrank), C.byref(opts), C.byref(h))
+        _check(self.ctx.lib, self.ctx.h, st, allow_warning=False)
+        self.h = h
+
+    def sweep(self, n=1):
+        stats = _lib.AciSweepStats()
+        st = self.ctx.lib.aci_batch_sweep(self.h, int(n), C.byref(stats))
+        _check(self.ctx.lib, self.ctx.h, st)
+        d = _stats_dict(stats, len(self.products[0][0]))
+        d["status"] = st
+        return d
+
+    def result(self, b):
+        inputs = self.products[b]
+        out, cap = _out_buffer(inputs, self.maxrank)
+        res = _lib.AciResult()
+        st = self.ctx.lib.aci_batch_result(self.h, int(b), C.c_void_p(out.data_ptr()), cap, C.byref(res))
+        try:
+            _check(self.ctx.lib, self.ctx.h, st)
+            return _unpack(res, out, [int(c.shape[1]) for c in inputs[0]], st, False)
+        finally:
+            self.ctx.lib.aci_result_free(C.byref(res))
+
+    def info(self, b):
+        x, g = C.c_int32(0), C.c_int32(0)
+        _check(self.ctx.lib, self.ctx.h, self.ctx.lib.aci_batch_info(self.h, int(b), C.byref(x), C.byref(g)))
+        return x.value, g.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.aci_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def elementwise_batched(products, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0,
+                        stop_rule="exclusive", precision="fp64", low_precision_sweeps=0,
+                        use_graph=False, tune=False, ctx=None):
+    """aci_elementwise_batched: returns [(cores, info)] per product."""
+    ctx = ctx or default_context()
+    lib = ctx.lib
+    keep = []
+    tts, counts = _batch_inputs(products, keep)
+    opts = _options(keep, maxiter, seed, None, stop_rule, precision, False, False, False,
+                    low_precision_sweeps, use_graph)
+    opts.tune = 1 if tune else 0
+    bufs = [_out_buffer(p, maxrank) for p in products]
+    outs = (C.c_void_p * len(products))(*[C.c_void_p(b.data_ptr()) for b, _ in bufs])
+    caps = (C.c_int64 * len(products))(*[c for _, c in bufs])
+    res = (_lib.AciResult * len(products))()
+    status = lib.aci_elementwise_batched(ctx.h, tts, counts, len(products), F64, OPS[op], float(tol),
+                                         int(maxrank), C.byref(opts), outs, caps, res)
+    try:
+        _check(lib, ctx.h, status)
+        return [_unpack(res[b], bufs[b][0], [int(c.shape[1]) for c in products[b][0]], status, False)
+                for b in range(len(products))]
+    finally:
+        for b in range(len(products)):
+            lib.aci_result_free(C.byref(res[b]))
+
+
+def tune_prrlu(m, n, maxrank, cap=0, ctx=None):
+    """aci_tune_prrlu: (best group cap, [(cap, mean us), ...])."""
+    ctx = ctx or default_context()
+    best = C.c_int32(0)
+    cand = (C.c_int32 * 16)()
+    us = (C.c_float * 16)()
+    cnt = C.c_int32(0)
+    st = ctx.lib.aci_tune_prrlu(ctx.h, int(m), int(n), int(maxrank), int(cap), C.byref(best), cand, us, 16,
+                                C.byref(cnt))
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return best.value, [(cand[i], us[i]) for i in range(cnt.value)]

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -34,7 +35,10 @@ struct aci_ctx {
   int* step_err = nullptr;     // [0] error flags, [1] abort word
   uint64_t* step_xbuf = nullptr;
   size_t step_xwords = 0;
+  std::map<uint64_t, int> tuned;   // autotuned LDU group caps by shape
 };
+
+static int ensure_step_ws(aci_ctx* ctx);
 
 namespace {
 
@@ -97,6 +101,9 @@ struct Plan {
   int prec = PREC_FP64;       // precision of the sweep being enqueued
   int low_max = 4;            // ladder: most low-precision sweeps (< 0: no limit)
   bool trace = false, fixed = false;
+  // placement of the LDU launches (batches): XCD, group cap, launch kind
+  int xcd = 0, max_groups = 0, cooperative = 1;
+  uint32_t* epoch = nullptr;  // device word: flag base of the next LDU launch
   double tol = 0.0;
   int d[ACI_MAX_SITES + 1];                         // d[l], l = 1..L
   int r[ACI_MAX_INPUTS][ACI_MAX_SITES + 1];         // r[n][l], l = 0..L
@@ -162,6 +169,7 @@ void layout(Plan& p, Arena& A, bool gen_init) {
   p.peps = A.take<double>(4);
   p.eps_bond = A.take<double>(L + 1);
   p.flags = A.take<int>(4);
+  p.epoch = A.take<uint32_t>(1);
   p.xbuf_words = prrlu_xbuf_words(p.ldm, p.ldm);
   p.xbuf = A.take<uint64_t>(p.xbuf_words);
   p.meta = A.take<int>((size_t)3 * 3 * (L - 1));
@@ -236,7 +244,11 @@ struct Enq {
     a.tol = p.tol;
     a.maxrank = p.maxrank;
     a.rule = p.rule;
-    a.flag_base = next_flag(ctx);
+    a.flag_base = 0;
+    a.epoch = p.epoch;
+    a.xcd = p.xcd;
+    a.max_groups = p.max_groups;
+    a.cooperative = p.cooperative;
     a.spin_limit = kSpinLimit;
     a.xbuf = p.xbuf;
     a.xbuf_words = p.xbuf_words;
@@ -258,7 +270,7 @@ struct Enq {
     a.ldy = ldy;
     a.err = p.flags;
     a.abort_word = p.flags + 1;
-    int rc = begin(CLS_PRRLU, prrlu_variant(mmax, nmax));
+    int rc = begin(CLS_PRRLU, prrlu_variant(mmax, nmax, p.max_groups));
     if (rc) return rc;
     hipError_t e = launch_prrlu(a, mmax, nmax, s);
     if (e != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("prrlu launch: ") + hipGetErrorString(e));
@@ -305,6 +317,10 @@ int enqueue_init(Enq& q) {
   ENQ(launch_fill_int(p.nI, 1, 1, s));
   ENQ(launch_fill_int(p.nJ + L + 1, 1, 1, s));
   ENQ(launch_fill_int(p.flags, 4, 0, s));
+  ENQ(launch_fill_int((int*)p.epoch, 1, 1, s));
+  // the LDU exchange words: flag 0 is never used, and the session's flags
+  // restart at 1, so memory left by an earlier session must not look valid
+  ENQ(launch_fill_int((int*)p.xbuf, 2 * p.xbuf_words, 0, s));
   for (int l = L; l >= 2; --l) {
     const int dl = p.d[l];
     const double* Msrc = (l == L) ? p.Yin[L] : p.G[l];
@@ -504,6 +520,17 @@ struct aci_session {
   bool converged = false;
   bool fixed = false;
   int low_done = 0;              // low-precision sweeps run so far
+  bool use_graph = false;        // replay each sweep from a captured hipGraph
+  hipStream_t cap_stream = nullptr;   // private stream the sweep is captured on
+  hipGraphExec_t gexec = nullptr;
+  int gprec = -1;                // precision the graph was captured with
+  int swept_prec = 0;            // precision of the sweep in flight
+  // pinned read-back of one sweep: ranks, eps, meta, flags
+  void* hbuf = nullptr;
+  int* h_cur = nullptr;
+  double* h_eps = nullptr;
+  int* h_meta = nullptr;
+  int* h_flags = nullptr;
   std::vector<int> prev;
   int init_ranks[ACI_MAX_SITES + 1];
   Prof prof;
@@ -513,6 +540,9 @@ struct aci_session {
 };
 
 namespace {
+
+// Entries of per-bond host arrays (with room for 2(L-1) updates' meta).
+int L_pad(int L) { return 2 * L + 2; }
 
 // Validation and static sizes shared by aci_elementwise and the sessions.
 int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op, double tol,
@@ -676,6 +706,9 @@ int aci_session_launches(aci_session* S, aci_launch* out, int32_t capacity, int3
 void aci_session_destroy(aci_session* S) {
   if (!S) return;
   if (S->ctx) (void)hipStreamSynchronize(S->ctx->stream);
+  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+  if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
+  if (S->hbuf) (void)hipHostFree(S->hbuf);
   if (S->ws) (void)hipFree(S->ws);
   for (hipEvent_t e : S->prof.pool) (void)hipEventDestroy(e);
   if (S->e0) (void)hipEventDestroy(S->e0);
@@ -683,8 +716,22 @@ void aci_session_destroy(aci_session* S) {
   delete S;
 }
 
+namespace {
+struct Placement {
+  int xcd = 0, max_groups = 0, cooperative = 1;
+};
+int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op, double tol,
+                   int32_t maxrank, const aci_options* opt, const Placement& pl, aci_session** out);
+}  // namespace
+
 int aci_session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
                        double tol, int32_t maxrank, const aci_options* opt, aci_session** out) {
+  return session_create(ctx, inputs, n_inputs, dtype, op, tol, maxrank, opt, Placement{}, out);
+}
+
+namespace {
+int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op, double tol,
+                   int32_t maxrank, const aci_options* opt, const Placement& pl, aci_session** out) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
   if (!out) return set_err(ctx, ACI_E_INVALID, "null session pointer");
@@ -703,6 +750,32 @@ int aci_session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int
   if (rc) return rc;
   S->fixed = p.fixed;
   S->prof.on = o.profile != 0;
+  // graphs need launches with static arguments: no events, no trace records
+  S->use_graph = o.use_graph != 0 && !S->prof.on && !p.trace;
+  p.xcd = pl.xcd;
+  p.max_groups = pl.max_groups;
+  if (S->use_graph) {
+    // captured launches are plain launches: every LDU must fit one XCD
+    const int mn = std::min(p.D * p.maxrank, (int)ACI_MAX_MATRIX);
+    const int cap = pl.max_groups > 0 ? pl.max_groups : prrlu_xcd_cus();
+    if (prrlu_groups(mn, mn, cap) > cap) S->use_graph = false;
+  }
+  p.cooperative = S->use_graph ? 0 : pl.cooperative;
+  {
+    const size_t nb = sizeof(int) * (L_pad(p.L)) * 5 + sizeof(double) * L_pad(p.L) + 64;
+    if (hipHostMalloc(&S->hbuf, nb, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(ctx, ACI_E_NOMEM, "pinned host allocation failed");
+    }
+    char* hb = (char*)S->hbuf;
+    S->h_eps = (double*)hb;
+    hb += sizeof(double) * L_pad(p.L);
+    S->h_cur = (int*)hb;
+    hb += sizeof(int) * L_pad(p.L);
+    S->h_meta = (int*)hb;
+    hb += sizeof(int) * 3 * L_pad(p.L);
+    S->h_flags = (int*)hb;
+  }
   const bool gen_init = (o.init == nullptr);
   Arena sz;
   layout(p, sz, gen_init);
@@ -746,92 +819,148 @@ int aci_session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int
   *out = S.release();
   return ACI_OK;
 }
+}  // namespace
+
+namespace {
+
+// Enqueues one sweep (or replays its graph) and the read-back of its ranks,
+// error estimates, per-update meta and flags into pinned host memory.
+int sweep_enqueue(aci_session* S) {
+  aci_ctx* ctx = S->ctx;
+  Plan& p = *S->plan;
+  const int L = p.L;
+  hipStream_t s = ctx->stream;
+  S->prof.clear();
+  S->swept_prec = p.prec;
+  HIPCHK(hipEventRecord(S->e0, s));
+  if (S->use_graph) {
+    if (!S->gexec || S->gprec != p.prec) {
+      if (S->gexec) {
+        HIPCHK(hipGraphExecDestroy(S->gexec));
+        S->gexec = nullptr;
+      }
+      // captured on a private stream (the context's may be the null
+      // stream, which cannot be captured), replayed on the context's
+      hipGraph_t g = nullptr;
+      if (!S->cap_stream) HIPCHK(hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(S->cap_stream, hipStreamCaptureModeRelaxed));
+      Enq q{ctx, p, S->cap_stream, S->rec, L - 1, &S->prof};
+      const int rc = enqueue_sweep(q);
+      const hipError_t ec = hipStreamEndCapture(S->cap_stream, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (ec != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("sweep capture: ") + hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&S->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+      S->gprec = p.prec;
+    }
+    HIPCHK(hipGraphLaunch(S->gexec, s));
+  } else {
+    Enq q{ctx, p, s, S->rec, L - 1, &S->prof};
+    const int rc = enqueue_sweep(q);
+    if (rc) return rc;
+    S->rec = q.rec;
+  }
+  HIPCHK(hipEventRecord(S->e1, s));
+  HIPCHK(hipMemcpyAsync(S->h_cur, p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(S->h_eps, p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(S->h_meta, p.meta + 3 * (L - 1), sizeof(int) * 3 * 2 * (L - 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(S->h_flags, p.flags, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+  return ACI_OK;
+}
+
+// After the stream has drained: errors, statistics, launch log, the
+// convergence test of Alg. 1 and the precision ladder.
+int sweep_finish(aci_session* S, aci_sweep_stats& st) {
+  aci_ctx* ctx = S->ctx;
+  Plan& p = *S->plan;
+  const int L = p.L;
+  ++S->sweeps;
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, S->e0, S->e1));
+  S->sweep_ms += ms;
+  const int fl = S->h_flags[0];
+  if (fl & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "a pivot exchange exceeded its spin limit");
+  if (fl & ERR_NONFINITE) return set_err(ctx, ACI_E_NUMERIC, "NaN or Inf in a two-site tensor");
+  if (fl & ERR_LIMIT) return set_err(ctx, ACI_E_LIMIT, "a pivot index fell outside its matrix");
+  const int* meta = S->h_meta;
+  for (size_t i = 0; i < S->prof.cls.size(); ++i) {
+    float kms = 0.f;
+    HIPCHK(hipEventElapsedTime(&kms, S->prof.pool[2 * i], S->prof.pool[2 * i + 1]));
+    const int c = S->prof.cls[i];
+    st.kernel_ms[c] += kms;
+    st.launches[c] += 1;
+    aci_launch rec{};
+    rec.kind = c;
+    rec.variant = S->prof.variant[i];
+    rec.part = S->prof.part[i];
+    rec.sweep = S->sweeps - 1;
+    rec.update = S->prof.slot[i] - (L - 1);
+    rec.us = 1e3f * kms;
+    if (rec.update >= 0 && rec.update < 2 * (L - 1) && c != CLS_GATHER) {
+      int kind, bond;
+      update_of(L, rec.update, kind, bond);
+      const int* mt = meta + 3 * rec.update;
+      rec.flops = update_flops(p, kind, bond, mt[0], mt[1], mt[2], c == CLS_PRRLU ? 0 : rec.part);
+    }
+    S->log.push_back(rec);
+  }
+  for (int u = 0; u < 2 * (L - 1); ++u) {
+    int kind, bond;
+    update_of(L, u, kind, bond);
+    account(p, kind, bond, meta[3 * u], meta[3 * u + 1], meta[3 * u + 2], st);
+  }
+  bool grew = false;
+  double emax = 0.0;
+  for (int b = 0; b < L - 1; ++b) {
+    grew = grew || S->h_cur[b] > S->prev[b];
+    emax = std::max(emax, S->h_eps[b]);
+  }
+  S->prev.assign(S->h_cur, S->h_cur + (L - 1));
+  st.max_eps = emax;
+  st.last_precision = S->swept_prec;
+  if (S->swept_prec == PREC_FP64) {
+    S->converged = !grew && emax <= p.tol;
+  } else {
+    // precision ladder: a low-precision sweep never converges (its Pi
+    // carries errors above the tolerance); the next sweeps run in FP64 once
+    // a low-precision sweep kept the ranks or after low_max of them
+    S->converged = false;
+    ++S->low_done;
+    if (p.low_max >= 0 && (!grew || S->low_done >= p.low_max)) p.prec = PREC_FP64;
+  }
+  return ACI_OK;
+}
+
+void stats_tail(aci_session* S, aci_sweep_stats& st) {
+  const int L = S->plan->L;
+  st.sweeps_done = S->sweeps;
+  st.converged = S->converged ? 1 : 0;
+  st.ranks[0] = st.ranks[L] = 1;
+  for (int b = 1; b < L; ++b) st.ranks[b] = S->prev[b - 1];
+}
+
+}  // namespace
 
 int aci_session_sweep(aci_session* S, int32_t nsweeps, aci_sweep_stats* stats) {
   if (!S || !S->ctx) return ACI_E_INVALID;
   aci_ctx* ctx = S->ctx;
   ctx->err.clear();
   if (nsweeps < 0) return set_err(ctx, ACI_E_INVALID, "nsweeps < 0");
-  Plan& p = *S->plan;
-  const int L = p.L;
-  hipStream_t s = ctx->stream;
   aci_sweep_stats st{};
-  std::vector<int> cur(L - 1), meta((size_t)3 * 2 * (L - 1));
-  std::vector<double> epsb(L - 1);
   S->log.clear();
   for (int it = 0; it < nsweeps; ++it) {
-    S->prof.clear();
-    const int swept_prec = p.prec;
-    Enq q{ctx, p, s, S->rec, L - 1, &S->prof};
-    HIPCHK(hipEventRecord(S->e0, s));
-    int rc = enqueue_sweep(q);
+    int rc = sweep_enqueue(S);
     if (rc) return rc;
-    HIPCHK(hipEventRecord(S->e1, s));
-    S->rec = q.rec;
-    int flags[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(cur.data(), p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(epsb.data(), p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(meta.data(), p.meta + 3 * (L - 1), sizeof(int) * meta.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(flags, p.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    ++S->sweeps;
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, S->e0, S->e1));
-    S->sweep_ms += ms;
-    if (flags[0] & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "a pivot exchange exceeded its spin limit");
-    if (flags[0] & ERR_NONFINITE) return set_err(ctx, ACI_E_NUMERIC, "NaN or Inf in a two-site tensor");
-    if (flags[0] & ERR_LIMIT) return set_err(ctx, ACI_E_LIMIT, "a pivot index fell outside its matrix");
-    for (size_t i = 0; i < S->prof.cls.size(); ++i) {
-      float kms = 0.f;
-      HIPCHK(hipEventElapsedTime(&kms, S->prof.pool[2 * i], S->prof.pool[2 * i + 1]));
-      const int c = S->prof.cls[i];
-      st.kernel_ms[c] += kms;
-      st.launches[c] += 1;
-      aci_launch rec{};
-      rec.kind = c;
-      rec.variant = S->prof.variant[i];
-      rec.part = S->prof.part[i];
-      rec.sweep = S->sweeps - 1;
-      rec.update = S->prof.slot[i] - (L - 1);
-      rec.us = 1e3f * kms;
-      if (rec.update >= 0 && rec.update < 2 * (L - 1) && c != CLS_GATHER) {
-        int kind, bond;
-        update_of(L, rec.update, kind, bond);
-        const int* mt = meta.data() + 3 * rec.update;
-        rec.flops = update_flops(p, kind, bond, mt[0], mt[1], mt[2], c == CLS_PRRLU ? 0 : rec.part);
-      }
-      S->log.push_back(rec);
-    }
-    for (int u = 0; u < 2 * (L - 1); ++u) {
-      int kind, bond;
-      update_of(L, u, kind, bond);
-      account(p, kind, bond, meta[3 * u], meta[3 * u + 1], meta[3 * u + 2], st);
-    }
-    bool grew = false;
-    double emax = 0.0;
-    for (int b = 0; b < L - 1; ++b) {
-      grew = grew || cur[b] > S->prev[b];
-      emax = std::max(emax, epsb[b]);
-    }
-    S->prev = cur;
-    st.max_eps = emax;
-    st.last_precision = swept_prec;
-    if (swept_prec == PREC_FP64) {
-      S->converged = !grew && emax <= p.tol;
-    } else {
-      // precision ladder: a low-precision sweep never converges (its Pi
-      // carries errors above the tolerance); the next sweeps run in FP64 once
-      // a low-precision sweep kept the ranks or after low_max of them
-      S->converged = false;
-      ++S->low_done;
-      if (p.low_max >= 0 && (!grew || S->low_done >= p.low_max)) p.prec = PREC_FP64;
-    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    rc = sweep_finish(S, st);
+    if (rc) return rc;
     if (S->converged && !S->fixed) break;
   }
-  st.sweeps_done = S->sweeps;
-  st.converged = S->converged ? 1 : 0;
-  st.ranks[0] = st.ranks[L] = 1;
-  for (int b = 1; b < L; ++b) st.ranks[b] = S->prev[b - 1];
+  stats_tail(S, st);
   if (stats) *stats = st;
   return S->converged ? ACI_OK : ACI_W_NOT_CONVERGED;
 }
@@ -948,6 +1077,330 @@ int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_
   return rc;
 }
 
+// ------------------------------------------------------------ batches
+struct aci_batch {
+  aci_ctx* parent = nullptr;
+  bool serial = false;   // products swept one after another (cooperative LDUs)
+  std::vector<hipStream_t> streams;
+  std::vector<aci_ctx*> ctxs;
+  std::vector<aci_session*> sess;
+  std::vector<int> groups;
+  hipEvent_t ready = nullptr;
+};
+
+void aci_batch_destroy(aci_batch* B) {
+  if (!B) return;
+  for (aci_session* S : B->sess) aci_session_destroy(S);
+  for (aci_ctx* c : B->ctxs) aci_ctx_destroy(c);
+  for (hipStream_t st : B->streams) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  if (B->ready) (void)hipEventDestroy(B->ready);
+  delete B;
+}
+
+int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs, int32_t n_products,
+                     int32_t dtype, int32_t op, double tol, int32_t maxrank, const aci_options* opt,
+                     aci_batch** out) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!out || !inputs || !n_inputs) return set_err(ctx, ACI_E_INVALID, "null argument");
+  *out = nullptr;
+  if (n_products < 1 || n_products > ACI_MAX_BATCH) return set_err(ctx, ACI_E_LIMIT, "n_products out of range");
+  aci_options o{};
+  o.maxiter = 20;
+  if (opt) o = *opt;
+  if (o.init) return set_err(ctx, ACI_E_INVALID, "a batch takes the default initial guess (options.init must be NULL)");
+  std::unique_ptr<aci_batch, void (*)(aci_batch*)> B(new (std::nothrow) aci_batch(), aci_batch_destroy);
+  if (!B) return set_err(ctx, ACI_E_NOMEM, "host allocation");
+  B->parent = ctx;
+  HIPCHK(hipEventCreateWithFlags(&B->ready, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(B->ready, ctx->stream));
+  // Placement: the products' sweeps overlap on their own streams, so their
+  // LDU launches spin side by side.  Each launches exactly its P groups,
+  // dealt round robin over the 8 XCDs (ceil(P/8) per XCD); with P capped at
+  // 8 * floor(CUs per XCD / products) every XCD can hold all the groups of
+  // all products at once, one per CU, so no launch waits for CUs held by a
+  // spinning one.  If some LDU needs more groups than that, the products are
+  // swept one after another with cooperative launches instead.
+  const int cus = prrlu_xcd_cus();
+  const int share = 8 * (cus / n_products);
+  {
+    int off0 = 0;
+    for (int b = 0; b < n_products; ++b) {
+      if (n_inputs[b] < 1 || n_inputs[b] > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
+      int dmax = 1;
+      for (int n = 0; n < n_inputs[b]; ++n)
+        for (int l = 0; l < inputs[off0 + n].L && inputs[off0 + n].d; ++l) dmax = std::max(dmax, (int)inputs[off0 + n].d[l]);
+      const int mn = std::min(dmax * std::max(1, maxrank), (int)ACI_MAX_MATRIX);
+      if (share < 1 || prrlu_groups(mn, mn, share) > share) B->serial = true;
+      off0 += n_inputs[b];
+    }
+  }
+  int off = 0;
+  for (int b = 0; b < n_products; ++b) {
+    if (n_inputs[b] < 1 || n_inputs[b] > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
+    int cap = B->serial ? 0 : share;
+    if (o.tune && !B->serial) {
+      int dmax = 1;
+      for (int n = 0; n < n_inputs[b]; ++n)
+        for (int l = 0; l < inputs[off + n].L && inputs[off + n].d; ++l) dmax = std::max(dmax, (int)inputs[off + n].d[l]);
+      const int mn = std::min(dmax * std::max(1, maxrank), (int)ACI_MAX_MATRIX);
+      int best = cap;
+      const int rc = aci_tune_prrlu(ctx, mn, mn, std::min(maxrank, mn), cap, &best, nullptr, nullptr, 0, nullptr);
+      if (rc < 0) return rc;
+      cap = best;
+    }
+    hipStream_t st = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    B->streams.push_back(st);
+    HIPCHK(hipStreamWaitEvent(st, B->ready, 0));
+    aci_ctx* c = nullptr;
+    int rc = aci_ctx_create(&c, st);
+    if (rc) return set_err(ctx, rc, "context creation");
+    B->ctxs.push_back(c);
+    Placement pl;
+    pl.xcd = B->serial ? 0 : -1;
+    pl.max_groups = cap;
+    pl.cooperative = B->serial ? 1 : 0;   // plain launches: LDUs of different products overlap
+    aci_session* S = nullptr;
+    rc = session_create(c, inputs + off, n_inputs[b], dtype, op, tol, maxrank, &o, pl, &S);
+    if (rc < 0) return set_err(ctx, rc, std::string("product ") + std::to_string(b) + ": " + c->err);
+    B->sess.push_back(S);
+    B->groups.push_back(cap);
+    off += n_inputs[b];
+  }
+  *out = B.release();
+  return ACI_OK;
+}
+
+int aci_batch_sweep(aci_batch* B, int32_t nsweeps, aci_sweep_stats* stats) {
+  if (!B || !B->parent) return ACI_E_INVALID;
+  aci_ctx* ctx = B->parent;
+  ctx->err.clear();
+  if (nsweeps < 0) return set_err(ctx, ACI_E_INVALID, "nsweeps < 0");
+  aci_sweep_stats st{};
+  double emax = 0.0;
+  for (aci_session* S : B->sess) S->log.clear();
+  const int n = (int)B->sess.size();
+  std::vector<char> act(n);
+  for (int it = 0; it < nsweeps; ++it) {
+    bool any = false;
+    for (int b = 0; b < n; ++b) {
+      aci_session* S = B->sess[b];
+      act[b] = !(S->converged && !S->fixed);
+      any = any || act[b];
+    }
+    if (!any) break;
+    // enqueue every product's sweep on its own stream, then drain them (in
+    // serial mode each product is drained before the next starts)
+    if (!B->serial)
+      for (int b = 0; b < n; ++b)
+        if (act[b]) {
+          const int rc = sweep_enqueue(B->sess[b]);
+          if (rc) return set_err(ctx, rc, std::string("product ") + std::to_string(b) + ": " + B->ctxs[b]->err);
+        }
+    emax = 0.0;
+    for (int b = 0; b < n; ++b)
+      if (act[b]) {
+        if (B->serial) {
+          const int rc = sweep_enqueue(B->sess[b]);
+          if (rc) return set_err(ctx, rc, std::string("product ") + std::to_string(b) + ": " + B->ctxs[b]->err);
+        }
+        HIPCHK(hipStreamSynchronize(B->streams[b]));
+        aci_sweep_stats one{};
+        const int rc = sweep_finish(B->sess[b], one);
+        if (rc) return set_err(ctx, rc, std::string("product ") + std::to_string(b) + ": " + B->ctxs[b]->err);
+        for (int c = 0; c < 3; ++c) {
+          st.kernel_ms[c] += one.kernel_ms[c];
+          st.launches[c] += one.launches[c];
+          st.flops[c] += one.flops[c];
+        }
+        st.pivots += one.pivots;
+        st.last_precision = std::max(st.last_precision, one.last_precision);
+      }
+    for (int b = 0; b < n; ++b) {
+      const aci_session* S = B->sess[b];
+      double e = 0.0;
+      for (int k = 0; k < S->plan->L - 1; ++k) e = std::max(e, S->h_eps[k]);
+      emax = std::max(emax, e);
+    }
+  }
+  bool all = true;
+  int sweeps = 0;
+  for (aci_session* S : B->sess) {
+    all = all && S->converged;
+    sweeps = std::max(sweeps, S->sweeps);
+  }
+  stats_tail(B->sess[0], st);
+  st.sweeps_done = sweeps;
+  st.converged = all ? 1 : 0;
+  st.max_eps = emax;
+  if (stats) *stats = st;
+  return all ? ACI_OK : ACI_W_NOT_CONVERGED;
+}
+
+int aci_batch_result(aci_batch* B, int32_t product, void* out, int64_t out_capacity, aci_result* result) {
+  if (!B || !B->parent) return ACI_E_INVALID;
+  if (product < 0 || product >= (int)B->sess.size()) return set_err(B->parent, ACI_E_INVALID, "product out of range");
+  const int rc = aci_session_result(B->sess[product], out, out_capacity, result);
+  if (rc < 0) return set_err(B->parent, rc, B->ctxs[product]->err);
+  return rc;
+}
+
+int aci_batch_info(aci_batch* B, int32_t product, int32_t* xcd, int32_t* max_groups) {
+  if (!B || product < 0 || product >= (int)B->sess.size()) return ACI_E_INVALID;
+  // -1: groups spread over all XCDs (overlapping products); 0: serial batch
+  if (xcd) *xcd = B->sess[product]->plan->xcd;
+  if (max_groups) *max_groups = B->groups[product];
+  return ACI_OK;
+}
+
+int aci_elementwise_batched(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs, int32_t n_products,
+                            int32_t dtype, int32_t op, double tol, int32_t maxrank, const aci_options* opt,
+                            void* const* outs, const int64_t* out_capacity, aci_result* results) {
+  if (!ctx) return ACI_E_INVALID;
+  if (!outs || !out_capacity || !results) return set_err(ctx, ACI_E_INVALID, "null argument");
+  for (int b = 0; b < n_products; ++b) std::memset(&results[b], 0, sizeof(aci_result));
+  aci_options o{};
+  o.maxiter = 20;
+  if (opt) o = *opt;
+  if (o.maxiter <= 0) o.maxiter = 20;
+  aci_batch* B = nullptr;
+  int rc = aci_batch_create(ctx, inputs, n_inputs, n_products, dtype, op, tol, maxrank, &o, &B);
+  if (rc < 0) return rc;
+  if (o.precision != ACI_PREC_FP64 && o.maxiter > 1) {
+    rc = aci_batch_sweep(B, o.maxiter - 1, nullptr);
+    if (rc >= 0) {
+      // the last allowed sweep is FP64 for every product not yet converged
+      for (aci_session* S : B->sess) S->plan->prec = PREC_FP64;
+      rc = aci_batch_sweep(B, 1, nullptr);
+    }
+  } else {
+    for (aci_session* S : B->sess) S->plan->prec = PREC_FP64;
+    rc = aci_batch_sweep(B, o.maxiter, nullptr);
+  }
+  int worst = rc;
+  for (int b = 0; b < n_products && rc >= 0; ++b) {
+    const int r = aci_batch_result(B, b, outs[b], out_capacity[b], &results[b]);
+    if (r < 0) {
+      rc = r;
+      break;
+    }
+    worst = std::max(worst, r);
+  }
+  aci_batch_destroy(B);
+  return rc < 0 ? rc : worst;
+}
+
+// ------------------------------------------------------------ autotuner
+int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t cap, int32_t* best_groups,
+                   int32_t* candidates, float* us, int32_t capacity, int32_t* count) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!best_groups) return set_err(ctx, ACI_E_INVALID, "null argument");
+  if (m < 1 || n < 1 || m > ACI_MAX_MATRIX || n > ACI_MAX_MATRIX || maxrank < 1) return set_err(ctx, ACI_E_LIMIT, "shape out of range");
+  if (cap < 1) cap = prrlu_xcd_cus();
+  const uint64_t key = ((uint64_t)m << 40) | ((uint64_t)n << 24) | ((uint64_t)maxrank << 8) | (uint64_t)std::min(cap, 255);
+  auto hit = ctx->tuned.find(key);
+  if (hit != ctx->tuned.end() && !candidates && !us) {
+    *best_groups = hit->second;
+    return ACI_OK;
+  }
+  // candidate caps: cap, then halving; each distinct P (group count) once
+  std::vector<int> cand;
+  for (int c = cap; c >= 1; c /= 2) {
+    const int v = prrlu_variant(m, n, c);
+    bool dup = false;
+    for (int x : cand) dup = dup || prrlu_variant(m, n, x) == v;
+    if (!dup) cand.push_back(c);
+  }
+  int rc = ensure_step_ws(ctx);
+  if (rc) return rc;
+  const size_t bytes = ((size_t)m * n + 8) * sizeof(double) + ((size_t)2 * ACI_MAX_MATRIX + 16) * sizeof(int);
+  void* ws = nullptr;
+  if (hipMalloc(&ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(ctx, ACI_E_NOMEM, "tuning workspace");
+  }
+  double* M = (double*)ws;
+  double* ep = M + (size_t)m * n;
+  int* rows = (int*)(ep + 8);
+  int* cols = rows + ACI_MAX_MATRIX;
+  int* rk = cols + ACI_MAX_MATRIX;
+  std::vector<double> h((size_t)m * n);
+  SplitMix64 rng{0x5eedull + (uint64_t)m * 7919u + (uint64_t)n};
+  for (double& x : h) x = rng.uniform();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = cand.empty() ? 1 : cand[0];
+  float best_us = 1e30f;
+  int k = 0;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(ws);
+  };
+  if (hipMemcpy(M, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return set_err(ctx, ACI_E_HIP, "tuning setup");
+  }
+  for (int c : cand) {
+    float tot = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      PrrluArgs a{};
+      a.M = M;
+      a.m = dconst(m);
+      a.n = dconst(n);
+      a.ldm = dconst(n);
+      a.tol = 0.0;
+      a.maxrank = std::min(maxrank, std::min(m, n));
+      a.rule = RULE_EXCLUSIVE;
+      a.flag_base = next_flag(ctx);
+      a.spin_limit = kSpinLimit;
+      a.xbuf = ctx->step_xbuf;
+      a.xbuf_words = ctx->step_xwords;
+      a.rows = rows;
+      a.cols = cols;
+      a.rank = rk;
+      a.eps = ep;
+      a.err = ctx->step_err;
+      a.abort_word = ctx->step_err + 1;
+      a.max_groups = c;
+      a.cooperative = 1;
+      hipError_t e = hipEventRecord(e0, ctx->stream);
+      if (e == hipSuccess) e = launch_fill_int(ctx->step_err, 2, 0, ctx->stream);
+      if (e == hipSuccess) e = launch_prrlu(a, m, n, ctx->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        cleanup();
+        return set_err(ctx, ACI_E_HIP, std::string("tuning run: ") + hipGetErrorString(e));
+      }
+      if (rep > 0) tot += ms;   // the first run warms up
+    }
+    const float t = 1e3f * tot / 2.f;
+    if (candidates && k < capacity) candidates[k] = c;
+    if (us && k < capacity) us[k] = t;
+    ++k;
+    if (t < best_us) {
+      best_us = t;
+      best = c;
+    }
+  }
+  int fl[2] = {0, 0};
+  (void)hipMemcpy(fl, ctx->step_err, sizeof(fl), hipMemcpyDeviceToHost);
+  cleanup();
+  if (fl[0] & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "a pivot exchange exceeded its spin limit");
+  if (count) *count = k;
+  ctx->tuned[key] = best;
+  *best_groups = best;
+  return ACI_OK;
+}
+
 // ------------------------------------------------------------ single steps
 static int ensure_step_ws(aci_ctx* ctx) {
   if (!ctx->step_err) {
@@ -1057,6 +1510,7 @@ int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, 
   a.maxrank = maxrank;
   a.rule = stop_rule;
   a.flag_base = next_flag(ctx);
+  a.cooperative = 1;
   a.spin_limit = kSpinLimit;
   a.xbuf = ctx->step_xbuf;
   a.xbuf_words = ctx->step_xwords;

@@ -63,15 +63,28 @@ struct PrrluArgs {
   int* meta2;       // out: optional second copy (trace)
   int* err;
   int* abort_word;
+  // placement and launch (host side unless noted)
+  int xcd;            // XCD whose CUs run the groups (0..7); -1: exactly P
+                      // workgroups dealt over all XCDs (plain launches only)
+  int max_groups;     // cap on P (0: one XCD's CUs)
+  int cooperative;    // 1: hipLaunchCooperativeKernel; 0: plain launch (graph capture)
+  uint32_t* epoch;    // device word holding flag_base (nullptr: use flag_base);
+                      // the kernel advances it for the next launch
 };
 
-// Chooses the workgroup shape for mmax x nmax, launches cooperatively.
+// Chooses the workgroup shape for mmax x nmax and launches.
 hipError_t launch_prrlu(const PrrluArgs& a, int mmax, int nmax, hipStream_t s);
 // Exchange-buffer words needed for matrices up to mmax x nmax.
 size_t prrlu_xbuf_words(int mmax, int nmax);
 // Instance launch_prrlu picks for these bounds: 10000*solo + 100*RS + CS, or
 // -1 if the bounds are out of range.
-int prrlu_variant(int mmax, int nmax);
+int prrlu_variant(int mmax, int nmax, int max_groups = 0);
+// CUs of one XCD (the most groups one LDU launch places on an XCD)
+int prrlu_xcd_cus();
+// Cooperating groups (P) launch_prrlu uses for these bounds and group cap.
+int prrlu_groups(int mmax, int nmax, int max_groups);
+// flag_base advance per launch (steps and the XCD check stay below it)
+constexpr uint32_t kFlagStride = 2048;
 
 // ----------------------------------------------------------------- gathers
 struct GatherItem {

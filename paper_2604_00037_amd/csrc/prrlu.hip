@@ -168,8 +168,11 @@ constexpr uint32_t kXccFlagOffset = 1536;
 
 template <int RS, int CS, bool SOLO>
 __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
-  if (blockIdx.x % a.stride) return;
+  if ((int)(blockIdx.x % a.stride) != (a.stride == 8 ? a.xcd : 0)) return;
   const int w = blockIdx.x / a.stride;
+  // flags of this launch: step k uses fbase + k
+  const uint32_t fbase = a.epoch ? __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : a.flag_base;
   const int P = a.P;
   const int m = dget(a.m), n = dget(a.n), ldm = dget(a.ldm);
   const int kmax = m < n ? m : n;
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
     // which XCD each group runs on, exchanged once at agent scope through
     // word 0 of the parity-1 slots (overwritten by step 1 only after every
     // group has passed step 0, hence this exchange)
-    const uint32_t xf = a.flag_base + kXccFlagOffset;
+    const uint32_t xf = fbase + kXccFlagOffset;
     uint64_t* slots1 = a.xbuf + (size_t)P * a.xwords;
     if (threadIdx.x == 0) xw_put(slots1 + (size_t)w * per, (uint32_t)hw_xcc_id(), xf, false);
     bool ok = true;
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
 #pragma unroll
       for (int b = 0; b < CS; ++b) u[b] = srow[lane + 64 * b];
     } else {
-      const uint32_t flag = a.flag_base + (uint32_t)k;
+      const uint32_t flag = fbase + (uint32_t)k;
       uint64_t* slot_base = a.xbuf + (size_t)par * P * a.xwords;
       uint64_t* mine = slot_base + (size_t)w * per;
       if (wv == 0 && lane < 3) {
@@ -528,6 +531,13 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
       }
   }
   if (w == 0 && threadIdx.x == 0) {
+    if (a.epoch) {
+      // every group read the epoch before its first candidate, and group 0
+      // has seen all of them, so the next launch's flags can be published
+      uint32_t next = fbase + kFlagStride;
+      if (next < kFlagStride) next = 1;
+      __hip_atomic_store(a.epoch, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     *a.rank = final_rank;
     *a.eps = eps;
     if (a.rank2) *a.rank2 = final_rank;
@@ -594,30 +604,49 @@ struct Shape {
 };
 constexpr Shape kShapes[] = {{1, 16}, {2, 16}, {4, 16}, {6, 8}, {8, 8}, {12, 4}, {16, 4}};
 
+hipError_t do_launch(const void* fn, dim3 grid, size_t lds, PrrluArgs& args, hipStream_t s) {
+  hipError_t e;
+  if (args.cooperative) {
+    void* kp[] = {&args};
+    e = hipLaunchCooperativeKernel(fn, grid, dim3(NT), kp, (unsigned)lds, s);
+  } else {
+    // plain launch (stream capture): at most one XCD's worth of groups, one
+    // per CU, so all of them become resident once the CUs are free
+    void* kp[] = {&args};
+    e = hipLaunchKernel(fn, grid, dim3(NT), kp, lds, s);
+  }
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
 template <int RS, int CS>
 hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
   PrrluArgs args = a;
-  dim3 block(NT);
+  // xcd < 0 ("spread"): exactly P workgroups, dealt round robin over the
+  // XCDs, for launches that overlap with other spinning launches: a launch
+  // of 8P workgroups would also need CUs on the other XCDs for its idle
+  // workgroups, and two such launches can each wait for the other's CUs
+  const bool spread = a.xcd < 0;
   if (a.P == 1) {
-    args.stride = 1;
-    void* kp[] = {&args};
+    // one group: 8 workgroups of which the one on the requested XCD runs
+    args.stride = (a.cooperative || spread) ? 1 : 8;
     const size_t lds = (size_t)(kCandWords + 128 * CS) * 4;
-    hipError_t e = hipLaunchCooperativeKernel((const void*)prrlu_kernel<RS, CS, true>, dim3(1), block, kp,
-                                              (unsigned)lds, s);
-    if (e != hipSuccess) (void)hipGetLastError();
-    return e;
+    return do_launch((const void*)prrlu_kernel<RS, CS, true>, dim3(args.stride), lds, args, s);
   }
   const void* fn = (const void*)prrlu_kernel<RS, CS, false>;
   const size_t lds = group_lds((size_t)(kCandWords + 128 * CS) * 4);
+  if (spread) {
+    args.stride = 1;
+    return do_launch(fn, dim3(args.P), lds, args, s);
+  }
   static int per_cu = resident_per_cu(fn, lds);
   // Workgroups are dealt to the 8 XCDs round robin, so launching 8x the
-  // groups and keeping every 8th puts the cooperating groups on one XCD,
-  // which lets the exchange stay in that XCD's L2.  Only when they all fit.
+  // groups and keeping every 8th (offset by the XCD index) puts the
+  // cooperating groups on one XCD, which lets the exchange stay in that
+  // XCD's L2.  Only when they all fit.
   args.stride = (a.P <= per_cu * cus_per_xcd()) ? 8 : 1;
-  void* kp[] = {&args};
-  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(args.P * args.stride), block, kp, (unsigned)lds, s);
-  if (e != hipSuccess) (void)hipGetLastError();
-  return e;
+  if (!a.cooperative && args.stride != 8) return hipErrorInvalidValue;
+  return do_launch(fn, dim3(args.P * args.stride), lds, args, s);
 }
 
 const Shape* pick_shape(int nmax) {
@@ -630,19 +659,30 @@ const Shape* pick_shape(int nmax) {
 // one XCD (one group per CU), unless one group can hold all rows.  More groups spread the elimination over more
 // CUs; past one XCD the exchange has to go through device-scope memory, which
 // costs more than the shorter update saves.
-int pick_rs(const Shape& sh, int mmax) {
+int pick_rs(const Shape& sh, int mmax, int max_groups) {
   // one workgroup when the rows fit in its registers: the exchange then
   // stays in LDS, which beats any split of so few rows over several CUs
   int rs = 1;
   while (rs < sh.rs_max && WAVES * rs < mmax) rs *= 2;
   if (WAVES * rs >= mmax) return rs;
-  const int target_p = cus_per_xcd();
+  int target_p = cus_per_xcd();
+  if (max_groups > 0 && max_groups < target_p) target_p = max_groups;
   rs = 1;
   while (rs < sh.rs_max && (mmax + WAVES * rs - 1) / (WAVES * rs) > target_p) rs *= 2;
   return rs;
 }
 
 }  // namespace
+
+int prrlu_xcd_cus() { return cus_per_xcd(); }
+
+int prrlu_groups(int mmax, int nmax, int max_groups) {
+  if (mmax < 1 || nmax < 1 || mmax > ACI_MAX_MATRIX || nmax > ACI_MAX_MATRIX) return -1;
+  const Shape* sh = pick_shape(nmax);
+  if (!sh) return -1;
+  const int rs = pick_rs(*sh, mmax, max_groups);
+  return (mmax + WAVES * rs - 1) / (WAVES * rs);
+}
 
 size_t prrlu_xbuf_words(int mmax, int nmax) {
   // every launch uses at most 64 groups of at most 4 + 2n words per parity
@@ -652,11 +692,11 @@ size_t prrlu_xbuf_words(int mmax, int nmax) {
   return (size_t)2 * 64 * (4 + 2 * 64 * sh->cs);
 }
 
-int prrlu_variant(int mmax, int nmax) {
+int prrlu_variant(int mmax, int nmax, int max_groups) {
   if (mmax < 1 || nmax < 1 || mmax > ACI_MAX_MATRIX || nmax > ACI_MAX_MATRIX) return -1;
   const Shape* sh = pick_shape(nmax);
   if (!sh) return -1;
-  const int rs = pick_rs(*sh, mmax);
+  const int rs = pick_rs(*sh, mmax, max_groups);
   const int P = (mmax + WAVES * rs - 1) / (WAVES * rs);
   return (P == 1 ? 10000 : 0) + 100 * rs + sh->cs;
 }
@@ -666,8 +706,9 @@ hipError_t launch_prrlu(const PrrluArgs& a0, int mmax, int nmax, hipStream_t s) 
   const Shape* sh = pick_shape(nmax);
   if (!sh) return hipErrorInvalidValue;
   PrrluArgs a = a0;
-  const int rs = pick_rs(*sh, mmax);
+  const int rs = pick_rs(*sh, mmax, a.max_groups);
   a.P = (mmax + WAVES * rs - 1) / (WAVES * rs);
+  if (a.xcd > 7 || (a.xcd < 0 && a.cooperative)) return hipErrorInvalidValue;
   if (a.P > 64) return hipErrorInvalidValue;
   a.xwords = 4 + 2 * 64 * sh->cs;
   if ((size_t)2 * a.P * a.xwords > a.xbuf_words) return hipErrorInvalidValue;

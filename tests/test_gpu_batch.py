@@ -1,0 +1,148 @@
+"""Batches (several products advanced together, one stream per product, LDUs
+placed per XCD) and hipGraph replay of sweeps, through the C ABI.
+
+The kernels of a batch are the same as those of a single run and every
+result element is produced by the same operations whatever the launch
+placement, so batched outputs must equal separate runs bit for bit; separate
+runs are in turn checked against the oracle (test_gpu_aci.py and below)."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import rel_max_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+aci = pytest.importorskip("paper_2604_00037_amd")
+
+
+def products_small():
+    out = []
+    for b, (chi, s) in enumerate([(4, 2101), (6, 2103), (5, 2105), (3, 2107)]):
+        x1, x2 = W.random_pair(L=10, chi=chi, seeds=(s, s + 1))
+        out.append([x1, x2])
+    return out
+
+
+def assert_same(a, b):
+    assert len(a) == len(b)
+    for p, q in zip(a, b):
+        assert p.shape == q.shape
+        assert torch.equal(p, q)
+
+
+def test_batch_equals_separate_runs_and_oracle():
+    prods = products_small()
+    dev = [[to_dev(x) for x in p] for p in prods]
+    res = aci.elementwise_batched(dev, "product", 1e-12, 40, seed=9)
+    for b, (p, (cores, info)) in enumerate(zip(prods, res)):
+        sc, si = aci.elementwise(dev[b], "product", 1e-12, 40, seed=9)
+        assert info.ranks == si.ranks and info.sweeps == si.sweeps and info.converged == si.converged
+        assert_same(cores, sc)
+        ref = oracle.aci(p, "product", 1e-12, 40, seed=9)
+        assert info.ranks[1:-1] == ref.ranks
+        y = W.tt_full([c.cpu().numpy() for c in cores])
+        assert rel_max_err(y, W.tt_full(ref.cores)) <= 1e-10
+
+
+def test_batch_of_ten_shares_xcds_and_differs_in_length():
+    """Ten overlapping products with a common group cap; one product has a
+    different number of sites; the larger products need several
+    cooperating groups per LDU."""
+    prods = []
+    for b in range(10):
+        L = 12 if b != 3 else 9
+        chi = 10 if b % 2 == 0 else 7
+        x1, x2 = W.random_pair(L=L, chi=chi, seeds=(2200 + 2 * b, 2201 + 2 * b))
+        prods.append([x1, x2])
+    dev = [[to_dev(x) for x in p] for p in prods]
+    B = aci.Batch(dev, "product", 1e-11, 100, maxiter=12, seed=4)
+    try:
+        B.sweep(12)
+        got = [B.result(b) for b in range(10)]
+        place = [B.info(b) for b in range(10)]
+    finally:
+        B.close()
+    # overlapping products: groups spread over the XCDs, one cap for all,
+    # small enough that every XCD holds all of them (ceil(cap/8) each)
+    assert all(x == -1 for x, _ in place)
+    caps = {g for _, g in place}
+    assert len(caps) == 1
+    cap = caps.pop()
+    assert cap >= 8 and 10 * (-(-cap // 8)) <= 32
+    for b in range(10):
+        sc, si = aci.elementwise(dev[b], "product", 1e-11, 100, maxiter=12, seed=4)
+        cores, info = got[b]
+        assert info.ranks == si.ranks and info.converged == si.converged
+        assert_same(cores, sc)
+        if b in (0, 3):
+            f = W.tt_full(prods[b][0]) * W.tt_full(prods[b][1])
+            assert rel_max_err(W.tt_full([c.cpu().numpy() for c in cores]), f) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_session_graph_replays_match_eager(precision):
+    """Every replay of a captured sweep, with eager work and synchronisation
+    in between, gives the eager sweep's state bit for bit."""
+    x1, x2 = W.random_pair(L=12, chi=9, seeds=(2301, 2302))
+    d = [to_dev(x1), to_dev(x2)]
+    kw = dict(maxiter=6, seed=5, fixed_sweeps=True, precision=precision, low_precision_sweeps=2)
+    g = aci.Session(d, "product", 1e-11, 81, use_graph=True, **kw)
+    e = aci.Session(d, "product", 1e-11, 81, use_graph=False, **kw)
+    try:
+        for it in range(6):
+            sg = g.sweep(1)
+            se = e.sweep(1)
+            assert sg["ranks"] == se["ranks"] and sg["last_precision"] == se["last_precision"]
+            cg, ig = g.result()
+            ce, ie = e.result()
+            assert ig.eps == ie.eps
+            assert_same(cg, ce)
+            # eager work of the program between replays
+            t = torch.randn(1000, device="cuda")
+            assert torch.isfinite((t * t).sum())
+            torch.cuda.synchronize()
+    finally:
+        g.close()
+        e.close()
+
+
+def test_batch_graph_and_mixed_precision_match_separate_runs():
+    prods = products_small()
+    dev = [[to_dev(x) for x in p] for p in prods]
+    res = aci.elementwise_batched(dev, "product", 1e-12, 40, seed=9, precision="fp32", use_graph=True)
+    for b, (cores, info) in enumerate(res):
+        sc, si = aci.elementwise(dev[b], "product", 1e-12, 40, seed=9, precision="fp32")
+        assert info.ranks == si.ranks and info.converged and si.converged
+        assert_same(cores, sc)
+        f = W.tt_full(prods[b][0]) * W.tt_full(prods[b][1])
+        assert rel_max_err(W.tt_full([c.cpu().numpy() for c in cores]), f) <= 1e-10
+
+
+def test_tune_prrlu_picks_a_measured_candidate():
+    best, tried = aci.tune_prrlu(384, 384, 192, 32)
+    assert tried and all(us > 0 for _, us in tried)
+    caps = [c for c, _ in tried]
+    assert best in caps
+    assert min(tried, key=lambda t: t[1])[0] == best
+    again, _ = aci.tune_prrlu(384, 384, 192, 32)
+    assert again == best
+
+
+def test_tuned_batch_equals_separate_runs():
+    prods = products_small()[:2]
+    dev = [[to_dev(x) for x in p] for p in prods]
+    res = aci.elementwise_batched(dev, "product", 1e-12, 40, seed=9, tune=True)
+    for b, (cores, info) in enumerate(res):
+        sc, si = aci.elementwise(dev[b], "product", 1e-12, 40, seed=9)
+        assert_same(cores, sc)
+
+
+def test_batch_rejects_explicit_init_and_bad_sizes():
+    prods = products_small()[:1]
+    dev = [[to_dev(x) for x in p] for p in prods]
+    with pytest.raises(Exception, match="LIMIT"):
+        aci.elementwise_batched(dev * 65, "product", 1e-12, 40)

@@ -252,6 +252,54 @@ def time_mode(aci, inputs, precision, steps, warmup):
             "ranks": st["ranks"]}
 
 
+def time_batched(aci, steps, warmup, device):
+    """The nine convective products u_j * d_j u_k (three velocity components
+    of the same random Fourier kind, spectral derivatives, uneven ranks
+    64..256), tol 1e-8, output rank cap 256: sweeps of the whole set per
+    second with the products overlapping (one batch), against the same
+    sessions run one after another."""
+    import torch
+    import workloads as W
+    t = time.perf_counter()
+    u, du = W.velocity_set(R=10, kmax=KMAX, device=device)
+    log(f"velocity set generated in {time.perf_counter() - t:.1f} s")
+    products = []
+    for j in range(3):
+        for k in range(3):
+            products.append([[torch.from_numpy(c).to(device) for c in x] for x in (u[j], du[j][k])])
+    ranks_in = sorted({max(c.shape[2] for c in x) for p in products for x in p})
+    total = steps + warmup
+    kw = dict(maxiter=total, seed=INIT_SEED, fixed_sweeps=True)
+    B = aci.Batch(products, "product", TOL, 256, use_graph=True, **kw)
+    B.sweep(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = B.sweep(steps)
+    torch.cuda.synchronize()
+    batched = time.perf_counter() - t0
+    caps = sorted({B.info(b)[1] for b in range(len(products))})
+    B.close()
+    seq = 0.0
+    for p in products:
+        S = aci.Session(p, "product", TOL, 256, use_graph=True, **kw)
+        S.sweep(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.sweep(steps)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t0
+        S.close()
+    log(f"batched: {steps} sweeps of 9 products in {batched:.3f} s; one after another {seq:.3f} s")
+    return {"workload": "u_j * d_j u_k, j,k = 1..3: 9 products of 3D Fourier velocity fields (|k|<=32) and "
+                        "their spectral derivatives, 1024^3 grid, L=30 d=2, input ranks "
+                        f"{ranks_in}, tol {TOL}, rank cap 256, FP64",
+            "products": len(products), "sweeps_per_s": steps / batched,
+            "product_sweeps_per_s": len(products) * steps / batched,
+            "sequential_product_sweeps_per_s": len(products) * steps / seq,
+            "speedup_vs_sequential": seq / batched, "ldu_group_caps": caps,
+            "max_eps": st["max_eps"], "pivots_per_sweep": st["pivots"] / steps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +308,7 @@ def main():
     ap.add_argument("--bits", type=int, default=10, help="quantics bits per axis (L = 3 * bits)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16x3 contraction modes")
+    ap.add_argument("--no-batched", action="store_true", help="skip the nine-product batch")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print a summary of a rocprofv3 run of this script (needs --bench-json) and exit")
     ap.add_argument("--bench-json", metavar="FILE", help="output of the profiled run")
@@ -362,6 +411,8 @@ def main():
     if not args.no_mixed:
         for prec in ("fp32", "bf16x3"):
             out["modes"][prec] = time_mode(aci, inputs, prec, args.steps, args.warmup)
+    if not args.no_batched:
+        out["batched"] = time_batched(aci, max(2, args.steps // 3), 1, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u, v)
         out["speedup_vs_cpu_oracle"] = out["value"] / out["cpu_baseline"]["value"]

@@ -17,6 +17,9 @@ the algorithms of Appendix B of the paper in their order:
 * ``splitmix64``      -- the counter-based generator of the default Y_init
 * ``reference``       -- exact Kronecker-delta product and SVD rounding,
                          an independent route to the Hadamard product
+* ``proposal``        -- extension: row features, the small scoring network
+                         (forward, gradients, Adam) and the seeded rook
+                         search with its acceptance test
 
 Parity status of each function is stated in its docstring.
 """
@@ -26,9 +29,10 @@ from .ci import cross_interpolate, local_update, left_frame, right_frame
 from .aci import aci, ACIResult, apply_op, default_init_ranks
 from .splitmix import splitmix64_stream, default_init
 from . import reference
+from . import proposal
 
 __all__ = [
     "prrlu", "PrrLU", "cross_interpolate", "local_update", "left_frame",
     "right_frame", "aci", "ACIResult", "apply_op", "default_init_ranks",
-    "splitmix64_stream", "default_init", "reference",
+    "splitmix64_stream", "default_init", "reference", "proposal",
 ]

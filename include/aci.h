@@ -51,6 +51,10 @@ extern "C" {
 #define ACI_MAX_INPUTS 4        /* N */
 #define ACI_MAX_MATRIX 1024     /* rows and columns of a matricised two-site tensor */
 #define ACI_MAX_BATCH 64        /* products of one batch */
+#define ACI_MAX_MLP_BATCH 4096  /* samples of one training step of the scoring network */
+#define ACI_MLP_FEATURES 7
+#define ACI_MLP_HIDDEN 64
+#define ACI_MLP_PARAMS (7 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
 
 typedef enum { ACI_F64 = 0, ACI_C128 = 1 } aci_dtype;
 
@@ -302,6 +306,60 @@ int aci_elementwise_batched(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n
 int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t cap,
                    int32_t* best_groups, int32_t* candidates, float* us, int32_t capacity,
                    int32_t* count);
+
+/* ------------------------------------------------------- learned proposal
+ * An extension of the method (not in the paper): a small network scores the
+ * rows of the two-site matrix, a rook search seeded by the scores proposes
+ * pivots, and the proposal is accepted only if the dense residual
+ * max |M - L Up| is within tol; otherwise the full search of Alg. 2 decides.
+ * All pointers are device pointers; every call returns after its work is
+ * done.  Definitions (features, rounding, search order) are those of the
+ * CPU reference in the test suite and are repeated at each call.
+ *
+ * Row features, X (m x 7 float32, row-major): f0, f1 = row 2-norm of the
+ * left environment env[t] (m x env_w[t], leading dim env_ld[t]) over the
+ * largest row norm (0 if absent or all zero); f2 = 1 for the n_prev rows in
+ * prev_rows (pivot rows of the previous update of the same bond); f3..f6 =
+ * |M[i, c_t]| / max over the four columns c_t = floor((2t + 1) n / 8). */
+int aci_proposal_features(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ldm,
+                          const void* const* env, const int32_t* env_w, const int32_t* env_ld,
+                          int32_t n_env, const int32_t* prev_rows, int32_t n_prev, float* X);
+/* Network 7 -> 64 -> 64 -> 1 (ReLU), parameters: ACI_MLP_PARAMS float32 in
+ * the order W1 (7 x 64, row-major), b1, W2 (64 x 64), b2, w3, b3.  Each
+ * layer rounds inputs and weights to float16, accumulates the exact products
+ * in float32 in index order and adds the float32 bias.  scores: count
+ * logits for X (count x 7). */
+int aci_mlp_forward(aci_ctx* ctx, const float* params, const float* X, int32_t count, float* scores);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias corrections for
+ * step >= 1) on the mean binary cross entropy of logits vs labels y (0/1),
+ * count <= ACI_MAX_MLP_BATCH samples, in one workgroup with gradients summed
+ * in sample order.  params, adam_m, adam_v (ACI_MLP_PARAMS each) are
+ * updated in place; grads (optional, device) receives the gradient; *loss
+ * (optional, host) the mean loss before the step. */
+int aci_mlp_train_step(aci_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
+                       const float* X, const float* y, int32_t count, float lr, float* grads,
+                       float* loss);
+/* Rook search with lazy residuals on M (m x n, ldm), at most maxrank pivots,
+ * each step started at the best-scored free row (scores may be NULL: the
+ * smallest free row) and at most max_iter row/column scan pairs long; stop
+ * rule as the exclusive rule of Alg. 2.  Out (device): rows, cols (maxrank
+ * each), *rank, *eps (|pivot| that stopped the search, 0 if exhausted), L
+ * (m x maxrank, ldl >= maxrank: residual columns over the pivot), Up
+ * (maxrank x n, ldu >= n: residual rows), *scans (optional). */
+int aci_rook_lu(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ldm, double tol,
+                int32_t maxrank, const float* scores, int32_t max_iter, int32_t* rows,
+                int32_t* cols, int32_t* rank, double* eps, void* L, int32_t ldl, void* Up,
+                int32_t ldu, int32_t* scans);
+/* Acceptance test: *eps = max |M - L Up| (FP64 matrix-core product), and
+ * *accepted = (*eps <= tol); rank read from the device. */
+int aci_rook_check(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ldm, const void* L,
+                   int32_t ldl, const void* Up, int32_t ldu, const int32_t* rank, double tol,
+                   double* eps, int32_t* accepted);
+/* Right factor of an accepted search (Alg. 3, right-interpolative form):
+ * Y = T^{-1} Up with T = Up[:, cols] upper triangular, by back substitution
+ * (Y[:, cols] = identity).  Y: rank x n, leading dim ldy. */
+int aci_rook_right_factor(aci_ctx* ctx, const void* Up, int32_t ldu, const int32_t* cols,
+                          const int32_t* rank, int32_t n, void* Y, int32_t ldy);
 
 /* Frame update by gathering (Alg. 5, truncation step).  src is h x w with
  * leading dimension ld_src; idx (device) holds r indices, r read from the

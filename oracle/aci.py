@@ -115,10 +115,23 @@ def _pi_tensors(inputs, Lf, Rf, l):
     return out
 
 
+def _left_envs(inputs, Lf, l):
+    """A^n = L^n_{l-1} X^n_l as (c_L d) x r_l matrices (rows a*d + s)."""
+    out = []
+    for n, X in enumerate(inputs):
+        Xl = X[l - 1]
+        r0, d, r1 = Xl.shape
+        out.append((Lf[n][l - 1] @ Xl.reshape(r0, d * r1)).reshape(-1, r1))
+    return out
+
+
 def aci(inputs, op, tol, maxrank, maxiter=20, init=None, seed=0,
-        rule="exclusive", log_gaps=False):
+        rule="exclusive", log_gaps=False, record=None):
     """Approximate f(x^1, ..., x^N) as a TT (Alg. 1).  ``inputs`` is a list
-    of N TTs (lists of cores).  Returns an ``ACIResult``."""
+    of N TTs (lists of cores).  Returns an ``ACIResult``.  If ``record`` is
+    a list, every local update appends its two-site matrix M, the left
+    environments A^n and its pivots (training data of the learned
+    proposal)."""
     N = len(inputs)
     if N < 1:
         raise ValueError("need at least one input")
@@ -179,6 +192,9 @@ def aci(inputs, op, tol, maxrank, maxiter=20, init=None, seed=0,
             Pis = _pi_tensors(inputs, Lf, Rf, l)
             Pi = apply_op(op, Pis)
             _, _, M, lu = local_update(Pi, tol, maxrank, "right", rule, log_gaps)
+            if record is not None:
+                record.append(dict(sweep=it, dir="LR", bond=l, M=M.copy(), A=_left_envs(inputs, Lf, l),
+                                   rows=lu.rows.copy(), cols=lu.cols.copy(), rank=lu.rank, eps=lu.eps))
             d = dims[l - 1]
             cR = Pi.shape[3]
             I[l] = [I[l - 1][int(p) // d] + (int(p) % d,) for p in lu.rows]
@@ -194,6 +210,9 @@ def aci(inputs, op, tol, maxrank, maxiter=20, init=None, seed=0,
             Pis = _pi_tensors(inputs, Lf, Rf, l)
             Pi = apply_op(op, Pis)
             Yl, Yr, M, lu = local_update(Pi, tol, maxrank, "right", rule, log_gaps)
+            if record is not None:
+                record.append(dict(sweep=it, dir="RL", bond=l, M=M.copy(), A=_left_envs(inputs, Lf, l),
+                                   rows=lu.rows.copy(), cols=lu.cols.copy(), rank=lu.rank, eps=lu.eps))
             # The output factors are those of Alg. 3 with P^{-1} in the right
             # factor: B = U_JJ^{-1} U becomes Y_{l+1}; only at bond 1 is the
             # left factor M[:, J] kept (reading R6).

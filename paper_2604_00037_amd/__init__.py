@@ -10,7 +10,9 @@ paper_2604_00037_amd.build``); nothing falls back to the CPU.
 """
 
 from .aci import (Batch, Context, Session, default_context, elementwise, elementwise_batched, env_contract,
-                  gather, pi_eval, prrlu, tune_prrlu)
+                  gather, mlp_forward, mlp_train_step, pi_eval, proposal_features, prrlu, rook_check,
+                  rook_lu, rook_right_factor, tune_prrlu)
 
 __all__ = ["Batch", "Context", "Session", "default_context", "elementwise", "elementwise_batched",
-           "env_contract", "gather", "pi_eval", "prrlu", "tune_prrlu"]
+           "env_contract", "gather", "mlp_forward", "mlp_train_step", "pi_eval", "proposal_features",
+           "prrlu", "rook_check", "rook_lu", "rook_right_factor", "tune_prrlu"]

@@ -26,7 +26,10 @@ EXPORTED = [
     "aci_session_create", "aci_session_sweep", "aci_session_result", "aci_session_launches",
     "aci_session_destroy", "aci_batch_create", "aci_batch_sweep", "aci_batch_result", "aci_batch_info",
     "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu",
+    "aci_proposal_features", "aci_mlp_forward", "aci_mlp_train_step", "aci_rook_lu", "aci_rook_check",
+    "aci_rook_right_factor",
 ]
+MLP_PARAMS = 7 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
 
 class AciTT(C.Structure):
@@ -167,6 +170,20 @@ def load(path=LIB_PATH):
     lib.aci_tune_prrlu.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32),
                                    C.POINTER(C.c_float), i32, C.POINTER(i32)]
     lib.aci_tune_prrlu.restype = C.c_int
+    f32p = C.POINTER(C.c_float)
+    i32p = C.POINTER(i32)
+    lib.aci_proposal_features.argtypes = [vp, vp, i32, i32, i32, C.POINTER(vp), i32p, i32p, i32, vp, i32, vp]
+    lib.aci_proposal_features.restype = C.c_int
+    lib.aci_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
+    lib.aci_mlp_forward.restype = C.c_int
+    lib.aci_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, C.c_float, vp, f32p]
+    lib.aci_mlp_train_step.restype = C.c_int
+    lib.aci_rook_lu.argtypes = [vp, vp, i32, i32, i32, C.c_double, i32, vp, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp]
+    lib.aci_rook_lu.restype = C.c_int
+    lib.aci_rook_check.argtypes = [vp, vp, i32, i32, i32, vp, i32, vp, i32, vp, C.c_double, vp, vp]
+    lib.aci_rook_check.restype = C.c_int
+    lib.aci_rook_right_factor.argtypes = [vp, vp, i32, vp, vp, i32, vp, i32]
+    lib.aci_rook_right_factor.restype = C.c_int
     lib.aci_session_destroy.argtypes = [vp]
     lib.aci_session_destroy.restype = None
     _lib = lib

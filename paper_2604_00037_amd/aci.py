@@ -463,3 +463,89 @@ def tune_prrlu(m, n, maxrank, cap=0, ctx=None):
                                 C.byref(cnt))
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     return best.value, [(cand[i], us[i]) for i in range(cnt.value)]
+
+
+# ------------------------------------------------------------ learned proposal
+def _p(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def proposal_features(M, env, prev_rows=None, ctx=None):
+    """Row features (m x 7 float32) of the two-site matrix M (device, m x n)
+    from the left environments env (list of <= 2 device matrices with m rows)
+    and the previous pivot rows (device int32 tensor or None)."""
+    ctx = ctx or default_context()
+    _dev_tensor(M, "M")
+    m, n = M.shape
+    X = torch.empty((m, 7), dtype=torch.float32, device=M.device)
+    envp = (C.c_void_p * 2)(*[_p(e) for e in env] + [None] * (2 - len(env)))
+    ew = (C.c_int32 * 2)(*[int(e.shape[1]) for e in env] + [0] * (2 - len(env)))
+    el = (C.c_int32 * 2)(*[int(e.stride(0)) for e in env] + [0] * (2 - len(env)))
+    npv = 0 if prev_rows is None else int(prev_rows.numel())
+    st = ctx.lib.aci_proposal_features(ctx.h, _p(M), m, n, int(M.stride(0)), envp, ew, el, len(env),
+                                       _p(prev_rows) if npv else None, npv, _p(X))
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return X
+
+
+def mlp_forward(params, X, ctx=None):
+    ctx = ctx or default_context()
+    out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    st = ctx.lib.aci_mlp_forward(ctx.h, _p(params), _p(X), int(X.shape[0]), _p(out))
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return out
+
+
+def mlp_train_step(params, adam_m, adam_v, step, X, y, lr=1e-3, want_grads=False, ctx=None):
+    """One Adam step in place; returns (mean loss before the step, grads or None)."""
+    ctx = ctx or default_context()
+    g = torch.empty_like(params) if want_grads else None
+    loss = C.c_float(0.0)
+    st = ctx.lib.aci_mlp_train_step(ctx.h, _p(params), _p(adam_m), _p(adam_v), int(step), _p(X), _p(y),
+                                    int(X.shape[0]), float(lr), _p(g), C.byref(loss))
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return loss.value, g
+
+
+def rook_lu(M, tol, maxrank, scores=None, max_iter=8, ctx=None):
+    """Rook search: dict(rows, cols, rank, eps, L (m x rank), Up (rank x n), scans)."""
+    ctx = ctx or default_context()
+    _dev_tensor(M, "M")
+    m, n = M.shape
+    dev = M.device
+    rows = torch.zeros(maxrank, dtype=torch.int32, device=dev)
+    cols = torch.zeros(maxrank, dtype=torch.int32, device=dev)
+    ib = torch.zeros(4, dtype=torch.int32, device=dev)
+    eps = torch.zeros(1, dtype=torch.float64, device=dev)
+    L = torch.zeros((m, maxrank), dtype=torch.float64, device=dev)
+    Up = torch.zeros((maxrank, n), dtype=torch.float64, device=dev)
+    st = ctx.lib.aci_rook_lu(ctx.h, _p(M), m, n, int(M.stride(0)), float(tol), int(maxrank), _p(scores),
+                             int(max_iter), _p(rows), _p(cols), C.c_void_p(ib.data_ptr()), _p(eps), _p(L),
+                             maxrank, _p(Up), n, C.c_void_p(ib.data_ptr() + 4))
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    r = int(ib[0].item())
+    return dict(rows=rows[:r].cpu().numpy(), cols=cols[:r].cpu().numpy(), rank=r, eps=float(eps.item()),
+                L=L[:, :r], Up=Up[:r], scans=int(ib[1].item()), _L=L, _Up=Up, _rows=rows, _cols=cols,
+                _rank=ib[:1])
+
+
+def rook_check(M, rk, tol, ctx=None):
+    """(accepted, eps) of a rook_lu result against M."""
+    ctx = ctx or default_context()
+    m, n = M.shape
+    eps = torch.zeros(1, dtype=torch.float64, device=M.device)
+    acc = torch.zeros(1, dtype=torch.int32, device=M.device)
+    st = ctx.lib.aci_rook_check(ctx.h, _p(M), m, n, int(M.stride(0)), _p(rk["_L"]), int(rk["_L"].shape[1]),
+                                _p(rk["_Up"]), n, _p(rk["_rank"]), float(tol), _p(eps), _p(acc))
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return bool(acc.item()), float(eps.item())
+
+
+def rook_right_factor(rk, ctx=None):
+    ctx = ctx or default_context()
+    Up = rk["_Up"]
+    n = Up.shape[1]
+    Y = torch.zeros_like(Up)
+    st = ctx.lib.aci_rook_right_factor(ctx.h, _p(Up), n, _p(rk["_cols"]), _p(rk["_rank"]), n, _p(Y), n)
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return Y[:rk["rank"]]

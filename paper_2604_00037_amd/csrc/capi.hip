@@ -36,6 +36,10 @@ struct aci_ctx {
   uint64_t* step_xbuf = nullptr;
   size_t step_xwords = 0;
   std::map<uint64_t, int> tuned;   // autotuned LDU group caps by shape
+  float* mlp_scratch = nullptr;    // training scratch of the scoring network
+  size_t mlp_scratch_n = 0;
+  double* check_c = nullptr;       // L Up of the residual check
+  size_t check_c_n = 0;
 };
 
 static int ensure_step_ws(aci_ctx* ctx);
@@ -674,6 +678,8 @@ int aci_ctx_create(aci_ctx** out, void* stream) {
 
 void aci_ctx_destroy(aci_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
+  if (ctx->check_c) (void)hipFree(ctx->check_c);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->step_err) (void)hipFree(ctx->step_err);
   if (ctx->step_xbuf) (void)hipFree(ctx->step_xbuf);
@@ -1292,6 +1298,187 @@ int aci_elementwise_batched(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n
   }
   aci_batch_destroy(B);
   return rc < 0 ? rc : worst;
+}
+
+// ------------------------------------------------------------ learned proposal
+extern "C++" {
+namespace {
+template <typename T>
+int grow(aci_ctx* ctx, T*& buf, size_t& have, size_t need, const char* what) {
+  if (have >= need) return ACI_OK;
+  if (buf) (void)hipFree(buf);
+  buf = nullptr;
+  have = 0;
+  if (hipMalloc(&buf, need * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(ctx, ACI_E_NOMEM, what);
+  }
+  have = need;
+  return ACI_OK;
+}
+}  // namespace
+}  // extern "C++"
+
+int aci_proposal_features(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ldm, const void* const* env,
+                          const int32_t* env_w, const int32_t* env_ld, int32_t n_env, const int32_t* prev_rows,
+                          int32_t n_prev, float* X) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!M || !X || m < 1 || n < 1 || ldm < n || n_env < 0 || n_env > 2 || n_prev < 0 || (n_prev > 0 && !prev_rows))
+    return set_err(ctx, ACI_E_INVALID, "bad arguments");
+  if (m > ACI_MAX_MATRIX || n > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "matrix too large");
+  int rc = ensure_step_ws(ctx);
+  if (rc) return rc;
+  FeatureArgs a{};
+  a.M = (const double*)M;
+  a.m = dconst(m);
+  a.n = dconst(n);
+  a.ldm = dconst(ldm);
+  a.n_env = n_env;
+  for (int t = 0; t < n_env; ++t) {
+    if (!env || !env[t] || !env_w || !env_ld || env_w[t] < 1 || env_ld[t] < env_w[t])
+      return set_err(ctx, ACI_E_INVALID, "bad environment");
+    a.env[t] = (const double*)env[t];
+    a.env_w[t] = dconst(env_w[t]);
+    a.env_ld[t] = dconst(env_ld[t]);
+  }
+  a.prev_rows = prev_rows;
+  HIPCHK(hipMemcpyAsync(ctx->step_err + 2, &n_prev, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+  a.prev_rank = ctx->step_err + 2;
+  a.X = X;
+  HIPCHK(launch_features(a, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ACI_OK;
+}
+
+int aci_mlp_forward(aci_ctx* ctx, const float* params, const float* X, int32_t count, float* scores) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!params || !X || !scores || count < 0) return set_err(ctx, ACI_E_INVALID, "bad arguments");
+  HIPCHK(launch_mlp_forward(params, X, count, scores, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ACI_OK;
+}
+
+int aci_mlp_train_step(aci_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step, const float* X,
+                       const float* y, int32_t count, float lr, float* grads, float* loss) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!params || !adam_m || !adam_v || !X || !y || count < 1 || step < 1) return set_err(ctx, ACI_E_INVALID, "bad arguments");
+  if (count > ACI_MAX_MLP_BATCH) return set_err(ctx, ACI_E_LIMIT, "minibatch too large");
+  int rc = grow(ctx, ctx->mlp_scratch, ctx->mlp_scratch_n, (size_t)(6 * MLP_HIDDEN + 1) * count + 64, "network scratch");
+  if (rc) return rc;
+  rc = ensure_step_ws(ctx);
+  if (rc) return rc;
+  const double b1 = 0.9, b2 = 0.999;
+  TrainArgs a{};
+  a.params = params;
+  a.adam_m = adam_m;
+  a.adam_v = adam_v;
+  a.X = X;
+  a.y = y;
+  a.count = count;
+  a.lr = lr;
+  a.beta1 = (float)b1;
+  a.beta2 = (float)b2;
+  a.one_minus_beta1 = (float)(1.0 - b1);
+  a.one_minus_beta2 = (float)(1.0 - b2);
+  a.c1 = (float)(1.0 - std::pow(b1, (double)step));
+  a.c2 = (float)(1.0 - std::pow(b2, (double)step));
+  a.eps = 1e-8f;
+  a.scratch = ctx->mlp_scratch;
+  a.grads = grads;
+  float* dloss = (float*)(ctx->step_err + 3);
+  a.loss = dloss;
+  HIPCHK(launch_mlp_train(a, ctx->stream));
+  float lh = 0.f;
+  HIPCHK(hipMemcpyAsync(&lh, dloss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (loss) *loss = lh;
+  return ACI_OK;
+}
+
+int aci_rook_lu(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ldm, double tol, int32_t maxrank,
+                const float* scores, int32_t max_iter, int32_t* rows, int32_t* cols, int32_t* rank, double* eps,
+                void* L, int32_t ldl, void* Up, int32_t ldu, int32_t* scans) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!M || !rows || !cols || !rank || !eps || !L || !Up || m < 1 || n < 1 || ldm < n || maxrank < 1 ||
+      ldl < maxrank || ldu < n || max_iter < 1 || !(tol >= 0.0))
+    return set_err(ctx, ACI_E_INVALID, "bad arguments");
+  if (m > ACI_MAX_MATRIX || n > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "matrix too large");
+  RookArgs a{};
+  a.M = (const double*)M;
+  a.m = dconst(m);
+  a.n = dconst(n);
+  a.ldm = dconst(ldm);
+  a.tol = tol;
+  a.maxrank = maxrank;
+  a.max_iter = max_iter;
+  a.scores = scores;
+  a.L = (double*)L;
+  a.ldl = ldl;
+  a.Up = (double*)Up;
+  a.ldu = ldu;
+  a.rows = rows;
+  a.cols = cols;
+  a.rank = rank;
+  a.eps = eps;
+  a.scans = scans;
+  HIPCHK(launch_rook(a, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ACI_OK;
+}
+
+int aci_rook_check(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ldm, const void* L, int32_t ldl,
+                   const void* Up, int32_t ldu, const int32_t* rank, double tol, double* eps, int32_t* accepted) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!M || !L || !Up || !rank || !eps || !accepted || m < 1 || n < 1 || ldm < n || ldu < n || ldl < 1)
+    return set_err(ctx, ACI_E_INVALID, "bad arguments");
+  int rc = grow(ctx, ctx->check_c, ctx->check_c_n, (size_t)m * n, "check workspace");
+  if (rc) return rc;
+  ContractArgs c{};
+  c.ngroup = 1;
+  Group& g = c.g[0];
+  g.nterm = 1;
+  g.t[0] = Term{(const double*)L, (const double*)Up, Dim{rank, 1, 0}, dconst(ldl), dconst(ldu)};
+  g.C = ctx->check_c;
+  g.M = dconst(m);
+  g.N = dconst(n);
+  g.ldc = dconst(n);
+  HIPCHK(launch_contract(OP_NONE, PREC_FP64, c, m, n, ctx->stream));
+  CheckArgs a{};
+  a.M = (const double*)M;
+  a.m = dconst(m);
+  a.n = dconst(n);
+  a.ldm = dconst(ldm);
+  a.C = ctx->check_c;
+  a.ldc = n;
+  a.tol = tol;
+  a.eps = eps;
+  a.accepted = accepted;
+  HIPCHK(launch_check(a, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ACI_OK;
+}
+
+int aci_rook_right_factor(aci_ctx* ctx, const void* Up, int32_t ldu, const int32_t* cols, const int32_t* rank,
+                          int32_t n, void* Y, int32_t ldy) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!Up || !cols || !rank || !Y || n < 1 || ldu < n || ldy < n) return set_err(ctx, ACI_E_INVALID, "bad arguments");
+  SolveArgs a{};
+  a.Up = (const double*)Up;
+  a.ldu = ldu;
+  a.cols = cols;
+  a.rank = rank;
+  a.n = dconst(n);
+  a.Y = (double*)Y;
+  a.ldy = ldy;
+  HIPCHK(launch_rook_solve(a, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ACI_OK;
 }
 
 // ------------------------------------------------------------ autotuner

@@ -86,6 +86,81 @@ int prrlu_groups(int mmax, int nmax, int max_groups);
 // flag_base advance per launch (steps and the XCD check stay below it)
 constexpr uint32_t kFlagStride = 2048;
 
+// ------------------------------------------------------ learned proposal
+constexpr int MLP_FEATURES = 7;
+constexpr int MLP_HIDDEN = 64;
+// flat parameter array: W1 (7 x 64), b1, W2 (64 x 64), b2, w3, b3
+constexpr int MLP_PARAMS =
+    MLP_FEATURES * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1;
+
+struct FeatureArgs {
+  const double* M;
+  Dim m, n, ldm;
+  const double* env[2];   // left environments A^n (rows a*d + s), row-major
+  Dim env_w[2], env_ld[2];
+  int n_env;
+  const int* prev_rows;   // pivot rows of the previous update of this bond
+  const int* prev_rank;   // their number (device), may be null
+  float* X;               // m x 7 out
+};
+
+struct TrainArgs {
+  float* params;
+  float* adam_m;
+  float* adam_v;
+  const float* X;         // count x 7
+  const float* y;         // count labels (0 / 1)
+  int count;
+  float lr, beta1, beta2, one_minus_beta1, one_minus_beta2, c1, c2, eps;
+  float* scratch;         // (6 * 64 + 1) * count floats
+  float* grads;           // optional MLP_PARAMS out
+  float* loss;            // optional mean loss out
+};
+
+struct RookArgs {
+  const double* M;
+  Dim m, n, ldm;
+  double tol;
+  int maxrank;
+  int max_iter;
+  const float* scores;    // m, may be null
+  double* L;              // m x maxrank, row-major, leading dim ldl
+  int ldl;
+  double* Up;             // maxrank x n, leading dim ldu
+  int ldu;
+  int *rows, *cols, *rank;
+  double* eps;
+  int* scans;             // optional
+};
+
+struct CheckArgs {
+  const double* M;
+  Dim m, n, ldm;
+  const double* C;        // L Up
+  int ldc;
+  double tol;
+  double* eps;
+  int* accepted;
+};
+
+struct SolveArgs {
+  const double* Up;
+  int ldu;
+  const int* cols;
+  const int* rank;
+  Dim n;
+  double* Y;
+  int ldy;
+  const int* skip;        // optional: return at once when *skip != 0
+};
+
+hipError_t launch_features(const FeatureArgs& a, hipStream_t s);
+hipError_t launch_mlp_forward(const float* params, const float* X, int count, float* out, hipStream_t s);
+hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t s);
+hipError_t launch_rook(const RookArgs& a, hipStream_t s);
+hipError_t launch_check(const CheckArgs& a, hipStream_t s);
+hipError_t launch_rook_solve(const SolveArgs& a, hipStream_t s);
+
 // ----------------------------------------------------------------- gathers
 struct GatherItem {
   const double* src;

@@ -1,0 +1,182 @@
+"""Learned pivot proposal on the GPU against the oracle: row features, the
+scoring network (forward bit for bit, one Adam step and its gradients), the
+seeded rook search (bit for bit), its acceptance test and right factor; and
+what a network trained on the GPU gains: fewer rook scans per pivot on
+held-out fields than the search without scores or with an untrained
+network."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import proposal as P
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+aci = pytest.importorskip("paper_2604_00037_amd")
+
+
+def dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def flat(net):
+    return np.concatenate([p.reshape(-1) for p in net.params()]).astype(np.float32)
+
+
+def unflat(v):
+    sizes = [(7, 64), (64,), (64, 64), (64,), (64,), (1,)]
+    out, off = [], 0
+    for s in sizes:
+        c = int(np.prod(s))
+        out.append(np.array(v[off:off + c], dtype=np.float32).reshape(s))
+        off += c
+    return P.MLP(*out)
+
+
+def test_features_match_oracle():
+    rng = np.random.default_rng(1)
+    M = rng.standard_normal((50, 40))
+    A = [rng.standard_normal((50, 13)), rng.standard_normal((50, 9))]
+    prev = np.array([3, 7, 49], dtype=np.int32)
+    X = aci.proposal_features(dev(M), [dev(a) for a in A], dev(prev)).cpu().numpy()
+    ref = P.row_features(M, A, prev)
+    np.testing.assert_allclose(X, ref, rtol=1e-6, atol=1e-7)
+    X1 = aci.proposal_features(dev(M), [dev(A[0])]).cpu().numpy()
+    np.testing.assert_allclose(X1, P.row_features(M, A[:1], []), rtol=1e-6, atol=1e-7)
+
+
+def test_network_forward_bitwise():
+    net = P.mlp_init(31)
+    X = np.random.default_rng(2).uniform(0, 1, (300, 7)).astype(np.float32)
+    z = aci.mlp_forward(dev(flat(net)), dev(X)).cpu().numpy()
+    zr, _ = P.mlp_forward(net, X)
+    assert np.array_equal(z, zr.astype(np.float32))
+
+
+def test_training_step_matches_oracle():
+    net = P.mlp_init(37)
+    rng = np.random.default_rng(3)
+    X = rng.uniform(0, 1, (200, 7)).astype(np.float32)
+    y = (rng.uniform(0, 1, 200) < 0.4).astype(np.float32)
+    p = dev(flat(net))
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    st = {}
+    for step in range(1, 6):
+        gref, lref = P.mlp_grads(net, X, y)
+        loss, g = aci.mlp_train_step(p, m, v, step, dev(X), dev(y), lr=1e-2, want_grads=True)
+        np.testing.assert_allclose(g.cpu().numpy(), np.concatenate([a.reshape(-1) for a in gref]),
+                                   rtol=1e-5, atol=1e-9)
+        assert abs(loss - lref) <= 1e-5 * (1 + abs(lref))
+        P.adam_step(net, gref, st, lr=1e-2)
+        np.testing.assert_allclose(p.cpu().numpy(), flat(net), rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("m,n,maxrank,tol,seeded", [(30, 20, 20, 0.0, False), (30, 20, 20, 0.0, True),
+                                                    (64, 80, 12, 0.0, True), (17, 33, 40, 1e-3, True),
+                                                    (129, 70, 70, 0.0, False)])
+def test_rook_search_bitwise(m, n, maxrank, tol, seeded):
+    rng = np.random.default_rng(m * 7 + n)
+    M = rng.standard_normal((m, n))
+    if tol > 0:
+        M = rng.standard_normal((m, 5)) @ rng.standard_normal((5, n)) + 1e-4 * M
+    scores = rng.standard_normal(m).astype(np.float32) if seeded else None
+    rk = aci.rook_lu(dev(M), tol, maxrank, scores=None if scores is None else dev(scores), max_iter=8)
+    ref = P.rook_lu(M, tol, maxrank, scores=scores, max_iter=8)
+    assert rk["rank"] == ref.rank
+    assert np.array_equal(rk["rows"], ref.rows) and np.array_equal(rk["cols"], ref.cols)
+    assert rk["scans"] == ref.scans
+    assert rk["eps"] == ref.eps_rook
+    assert np.array_equal(rk["L"].cpu().numpy(), ref.L)
+    assert np.array_equal(rk["Up"].cpu().numpy(), ref.Up)
+    ok, eps = aci.rook_check(dev(M), rk, max(tol, 1e-300))
+    ok_ref, eps_ref = P.rook_accept(M, ref, max(tol, 1e-300))
+    assert ok == ok_ref
+    assert abs(eps - eps_ref) <= 1e-12 * np.abs(M).max() * m
+    Y = aci.rook_right_factor(rk).cpu().numpy()
+    Yr = P.rook_right_factor(ref)
+    np.testing.assert_allclose(Y, Yr, rtol=1e-12, atol=1e-12)
+    assert np.array_equal(Y[:, ref.cols], np.eye(ref.rank))
+
+
+# ------------------------------------------------------------ what it gains
+def _field(R, kmax, s, chi):
+    g = W.fourier3d_full(R, kmax, s)
+    q = np.ascontiguousarray(W.grid_to_quantics(g, R, 3)).reshape(-1)
+    return W.tt_svd(q, 2, chi, rtol=1e-12)
+
+
+def _records(seeds):
+    """Local updates of plain FP64 ACI (the oracle) on products of two 3D
+    random Fourier fields (R = 4 bits per axis, |k| <= 4, rank 24), tol 1e-8,
+    rank cap 64: two-site matrices, left environments and pivots."""
+    recs = []
+    for s in seeds:
+        rec = []
+        oracle.aci([_field(4, 4, s, 24), _field(4, 4, s + 1000, 24)], "product", 1e-8, 64, maxiter=3,
+                   seed=s, record=rec)
+        prev = {}
+        for r in rec:
+            key = (r["bond"], r["dir"])
+            r["prev"] = prev.get(key, np.zeros(0, np.int32)).astype(np.int32)
+            prev[key] = r["rows"]
+        recs += rec
+    return recs
+
+
+def _gpu_features(r):
+    prev = dev(r["prev"]) if len(r["prev"]) else None
+    return aci.proposal_features(dev(r["M"]), [dev(a) for a in r["A"]], prev)
+
+
+def test_trained_network_reduces_rook_scans():
+    train, test = _records(range(1, 7)), _records(range(101, 104))
+    # labels: the first half of each update's pivot rows (the early pivots
+    # are where a good start row saves the most scans)
+    Xs, ys = [], []
+    for r in train:
+        X = _gpu_features(r)
+        y = np.zeros(r["M"].shape[0], np.float32)
+        y[r["rows"][:max(1, len(r["rows"]) // 2)]] = 1
+        Xs.append(X)
+        ys.append(torch.from_numpy(y).cuda())
+    X = torch.cat(Xs)
+    y = torch.cat(ys)
+    p0 = flat(P.mlp_init(7))
+    p = dev(p0)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    rng = np.random.default_rng(0)
+    losses = []
+    for step in range(1, 301):
+        idx = torch.from_numpy(rng.choice(X.shape[0], 512, replace=False)).cuda()
+        loss, _ = aci.mlp_train_step(p, m, v, step, X[idx].contiguous(), y[idx].contiguous(), lr=3e-3)
+        losses.append(loss)
+    assert np.mean(losses[-20:]) < 0.8 * np.mean(losses[:20])
+    untrained = dev(p0)
+
+    def scans(params):
+        tot, piv, acc = 0, 0, 0
+        for r in test:
+            Md = dev(r["M"])
+            sc = None if params is None else aci.mlp_forward(params, _gpu_features(r))
+            rk = aci.rook_lu(Md, 1e-8, 64, scores=sc)
+            ok, _ = aci.rook_check(Md, rk, 1e-8)
+            tot += rk["scans"]
+            piv += rk["rank"]
+            acc += ok
+        return tot / piv, acc
+
+    s_none, a_none = scans(None)
+    s_untr, a_untr = scans(untrained)
+    s_trained, a_trained = scans(p)
+    print(f"rook scans per pivot: trained {s_trained:.3f}, untrained {s_untr:.3f}, no scores {s_none:.3f}; "
+          f"accepted {a_trained}/{a_untr}/{a_none} of {len(test)}")
+    assert s_trained < s_none and s_trained < s_untr
+    assert a_trained >= a_none

@@ -107,6 +107,12 @@ typedef struct {
                             and replay it (ignored with profile or trace) */
   int32_t tune;          /* batches: 1 = pick each product's LDU group count
                             with aci_tune_prrlu (cached per context) */
+  const float* proposal; /* learned pivot proposal (extension): device array of
+                            ACI_MLP_PARAMS network parameters, or NULL.  Every
+                            local update then scores the rows, runs the seeded
+                            rook search and keeps it if max |M - L Up| <= tol;
+                            otherwise the LDU of Alg. 2 runs as usual */
+  int32_t proposal_scans; /* rook scan-pair limit per pivot; 0 selects 8 */
 } aci_options;
 
 /* Result of aci_elementwise.  Output cores are written compactly, site after
@@ -153,6 +159,8 @@ typedef struct {
   int32_t ranks[ACI_MAX_SITES + 1];  /* right-to-left ranks after the last sweep */
   double max_eps;                    /* largest right-to-left error estimate */
   int32_t last_precision;            /* aci_precision of the last sweep run */
+  int32_t proposals_tried;           /* local updates with a learned proposal */
+  int32_t proposals_accepted;        /* of which the rook result was kept */
 } aci_sweep_stats;
 
 /* One kernel launch of a profiled aci_session_sweep call (options.profile).

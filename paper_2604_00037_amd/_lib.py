@@ -54,6 +54,8 @@ class AciOptions(C.Structure):
         ("low_precision_sweeps", C.c_int32),
         ("use_graph", C.c_int32),
         ("tune", C.c_int32),
+        ("proposal", C.c_void_p),
+        ("proposal_scans", C.c_int32),
     ]
 
 
@@ -88,6 +90,8 @@ class AciSweepStats(C.Structure):
         ("ranks", C.c_int32 * (MAX_SITES + 1)),
         ("max_eps", C.c_double),
         ("last_precision", C.c_int32),
+        ("proposals_tried", C.c_int32),
+        ("proposals_accepted", C.c_int32),
     ]
 
 

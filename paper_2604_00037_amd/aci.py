@@ -28,11 +28,12 @@ def _check(lib, ctx, status, allow_warning=True):
     raise _lib.HipError(f"{name}: {msg}")
 
 
-def _dev_tensor(t, name):
+def _dev_tensor(t, name, dtype=None):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a device tensor")
-    if t.dtype != torch.float64:
-        raise TypeError(f"{name} must be float64")
+    want = dtype if dtype is not None else torch.float64
+    if t.dtype != want:
+        raise TypeError(f"{name} must be {str(want).replace('torch.', '')}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t
@@ -94,10 +95,17 @@ class Info:
 
 
 def _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, profile,
-             low_precision_sweeps=0, use_graph=False):
+             low_precision_sweeps=0, use_graph=False, proposal=None, proposal_scans=0):
     opts = _lib.AciOptions()
     opts.low_precision_sweeps = int(low_precision_sweeps)
     opts.use_graph = 1 if use_graph else 0
+    if proposal is not None:
+        _dev_tensor(proposal, "proposal", torch.float32)
+        if proposal.numel() != _lib.MLP_PARAMS:
+            raise ValueError(f"proposal must be {_lib.MLP_PARAMS} float32 network parameters")
+        keep.append(proposal)
+        opts.proposal = C.c_void_p(proposal.data_ptr())
+    opts.proposal_scans = int(proposal_scans)
     opts.maxiter = maxiter
     opts.seed = seed
     opts.stop_rule = RULES[stop_rule]
@@ -163,7 +171,7 @@ def _unpack(res, out, dims, status, trace):
 
 def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
                 stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False,
-                low_precision_sweeps=0, ctx=None):
+                low_precision_sweeps=0, proposal=None, proposal_scans=0, ctx=None):
     """Alg. 1: returns (cores, info) with cores a list of device tensors of
     shape (r_{l-1}, d_l, r_l) approximating op(inputs) elementwise."""
     ctx = ctx or default_context()
@@ -171,7 +179,7 @@ def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed
     keep = []
     tts = _inputs(inputs, keep)
     opts = _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, False,
-                    low_precision_sweeps)
+                    low_precision_sweeps, False, proposal, proposal_scans)
     out, cap = _out_buffer(inputs, maxrank)
     res = _lib.AciResult()
     status = lib.aci_elementwise(ctx.h, tts, len(inputs), F64, OPS[op], float(tol), int(maxrank),
@@ -186,6 +194,10 @@ def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed
 def kernel_name(kind, variant):
     """Kernel instance behind a launch-log entry, spelled as in the device
     profiler's kernel names."""
+    if kind == 0 and variant >= 20000:
+        return {20001: "features_kernel", 20002: "mlp_forward_kernel", 20003: "rook_kernel",
+                20004: "contract_kernel<-1>", 20005: "check_kernel", 20006: "commit_kernel",
+                20007: "copy_rows_kernel", 20008: "rook_solve_kernel"}[variant]
     if kind == 0:
         solo, rest = divmod(variant, 10000)
         rs, cs = divmod(rest, 100)
@@ -203,7 +215,8 @@ class Session:
 
     def __init__(self, inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
                  stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False,
-                 profile=False, low_precision_sweeps=0, use_graph=False, ctx=None):
+                 profile=False, low_precision_sweeps=0, use_graph=False, proposal=None, proposal_scans=0,
+                 ctx=None):
         self.ctx = ctx or default_context()
         self.inputs = inputs            # the library reads these until close()
         self.maxrank = maxrank
@@ -211,7 +224,7 @@ class Session:
         self._keep = []
         tts = _inputs(inputs, self._keep)
         opts = _options(self._keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps,
-                        profile, low_precision_sweeps, use_graph)
+                        profile, low_precision_sweeps, use_graph, proposal, proposal_scans)
         self._init = init
         h = C.c_void_p()
         st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), F64, OPS[op], float(tol),
@@ -228,7 +241,8 @@ class Session:
                     kernel_ms=list(stats.kernel_ms), launches=list(stats.launches),
                     flops=list(stats.flops), pivots=stats.pivots,
                     ranks=[stats.ranks[i] for i in range(L + 1)], max_eps=stats.max_eps,
-                    last_precision=[k for k, v in PRECISIONS.items() if v == stats.last_precision][0])
+                    last_precision=[k for k, v in PRECISIONS.items() if v == stats.last_precision][0],
+                    proposals_tried=stats.proposals_tried, proposals_accepted=stats.proposals_accepted)
 
     def launches(self):
         """Launch log of the last ``sweep`` call (needs ``profile=True``): one

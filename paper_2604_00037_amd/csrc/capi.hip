@@ -108,6 +108,13 @@ struct Plan {
   // placement of the LDU launches (batches): XCD, group cap, launch kind
   int xcd = 0, max_groups = 0, cooperative = 1;
   uint32_t* epoch = nullptr;  // device word: flag base of the next LDU launch
+  // learned proposal (options.proposal): network, scan limit and buffers
+  const float* mlp = nullptr;
+  int rook_iter = 8;
+  float *feat = nullptr, *scores = nullptr;
+  double *rkL = nullptr, *rkUp = nullptr, *rkC = nullptr, *rkeps = nullptr, *chkeps = nullptr;
+  int *rkrows = nullptr, *rkcols = nullptr, *rkrank = nullptr, *acc = nullptr, *acc_count = nullptr;
+  int *prevr = nullptr, *prevk = nullptr;   // previous pivot rows per (direction, bond)
   double tol = 0.0;
   int d[ACI_MAX_SITES + 1];                         // d[l], l = 1..L
   int r[ACI_MAX_INPUTS][ACI_MAX_SITES + 1];         // r[n][l], l = 0..L
@@ -177,6 +184,23 @@ void layout(Plan& p, Arena& A, bool gen_init) {
   p.xbuf_words = prrlu_xbuf_words(p.ldm, p.ldm);
   p.xbuf = A.take<uint64_t>(p.xbuf_words);
   p.meta = A.take<int>((size_t)3 * 3 * (L - 1));
+  if (p.mlp) {
+    const size_t rows = (size_t)p.D * p.maxrank;
+    p.feat = A.take<float>(rows * MLP_FEATURES);
+    p.scores = A.take<float>(rows);
+    p.rkL = A.take<double>(rows * p.maxrank);
+    p.rkUp = A.take<double>((size_t)p.maxrank * p.ldm);
+    p.rkC = A.take<double>(rows * p.ldm);
+    p.rkeps = A.take<double>(1);
+    p.chkeps = A.take<double>(1);
+    p.rkrows = A.take<int>(p.maxrank);
+    p.rkcols = A.take<int>(p.maxrank);
+    p.rkrank = A.take<int>(1);
+    p.acc = A.take<int>(2);
+    p.acc_count = A.take<int>(1);
+    p.prevr = A.take<int>((size_t)2 * (L + 1) * p.maxrank);
+    p.prevk = A.take<int>((size_t)2 * (L + 1));
+  }
   if (p.trace) {
     p.tr_meta = A.take<int>((size_t)3 * p.n_rec);
     p.tr_eps = A.take<double>(p.n_rec);
@@ -239,8 +263,9 @@ struct Enq {
   bool tracing() const { return p.trace && rec < p.n_rec; }
 
   int prrlu(const double* M, Dim m, Dim n, Dim ldm, int mmax, int nmax, int* rank2, double* eps2,
-            double* Y, Dim ldy) {
+            double* Y, Dim ldy, const int* skip = nullptr) {
     PrrluArgs a{};
+    a.skip = skip;
     a.M = M;
     a.m = m;
     a.n = n;
@@ -278,6 +303,106 @@ struct Enq {
     if (rc) return rc;
     hipError_t e = launch_prrlu(a, mmax, nmax, s);
     if (e != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("prrlu launch: ") + hipGetErrorString(e));
+    return end();
+  }
+  // Learned proposal for the two-site matrix in p.Mbuf at bond l (dir 0
+  // left to right, 1 right to left): features, scores, seeded rook search,
+  // dense residual check, and on acceptance the pivots, rank and error in
+  // the places the LDU would write them.  p.acc[0] then tells the LDU to
+  // skip, p.acc[1] the right-factor solve.
+  int propose(int l, int dir, Dim m, Dim n, int mrows, int ncols_max, int* rank2, double* eps2) {
+    FeatureArgs fa{};
+    fa.M = p.Mbuf;
+    fa.m = m;
+    fa.n = n;
+    fa.ldm = dconst(p.ldm);
+    fa.n_env = p.N < 2 ? p.N : 2;
+    for (int t = 0; t < fa.n_env; ++t) {
+      fa.env[t] = p.Ac[t][l];
+      fa.env_w[t] = dconst(p.r[t][l]);
+      fa.env_ld[t] = dconst(p.r[t][l]);
+    }
+    fa.prev_rows = p.prevr + (size_t)(dir * (p.L + 1) + l) * p.maxrank;
+    fa.prev_rank = p.prevk + dir * (p.L + 1) + l;
+    fa.X = p.feat;
+    if (int rc = stepf(20001, [&] { return launch_features(fa, s); })) return rc;
+    if (int rc = stepf(20002, [&] { return launch_mlp_forward(p.mlp, p.feat, mrows, p.scores, s); })) return rc;
+    RookArgs ra{};
+    ra.M = p.Mbuf;
+    ra.m = m;
+    ra.n = n;
+    ra.ldm = dconst(p.ldm);
+    ra.tol = p.tol;
+    ra.maxrank = p.maxrank;
+    ra.max_iter = p.rook_iter;
+    ra.scores = p.scores;
+    ra.L = p.rkL;
+    ra.ldl = p.maxrank;
+    ra.Up = p.rkUp;
+    ra.ldu = p.ldm;
+    ra.rows = p.rkrows;
+    ra.cols = p.rkcols;
+    ra.rank = p.rkrank;
+    ra.eps = p.rkeps;
+    if (int rc = stepf(20003, [&] { return launch_rook(ra, s); })) return rc;
+    ContractArgs c{};
+    c.ngroup = 1;
+    Group& g = c.g[0];
+    g.nterm = 1;
+    g.t[0] = Term{p.rkL, p.rkUp, Dim{p.rkrank, 1, 0}, dconst(p.maxrank), dconst(p.ldm)};
+    g.C = p.rkC;
+    g.M = m;
+    g.N = n;
+    g.ldc = dconst(p.ldm);
+    if (int rc = stepf(20004, [&] { return launch_contract(OP_NONE, PREC_FP64, c, mrows, ncols_max, s); })) return rc;
+    CheckArgs ca{};
+    ca.M = p.Mbuf;
+    ca.m = m;
+    ca.n = n;
+    ca.ldm = dconst(p.ldm);
+    ca.C = p.rkC;
+    ca.ldc = p.ldm;
+    ca.tol = p.tol;
+    ca.eps = p.chkeps;
+    ca.accepted = p.acc;
+    ca.count = p.acc_count;
+    if (int rc = stepf(20005, [&] { return launch_check(ca, s); })) return rc;
+    CommitArgs cm{};
+    cm.accepted = p.acc;
+    cm.src_rows = p.rkrows;
+    cm.src_cols = p.rkcols;
+    cm.src_rank = p.rkrank;
+    cm.src_eps = p.chkeps;
+    cm.rows = const_cast<int*>(rows());
+    cm.cols = const_cast<int*>(cols());
+    cm.rank = p.prank;
+    cm.rank2 = rank2;
+    cm.eps = tracing() ? p.tr_eps + rec : p.peps;
+    cm.eps2 = eps2;
+    cm.meta = p.meta + (size_t)3 * slot;
+    cm.meta2 = tracing() ? p.tr_meta + (size_t)3 * rec : nullptr;
+    cm.m = m;
+    cm.n = n;
+    cm.maxrank = p.maxrank;
+    return stepf(20006, [&] { return launch_commit(cm, s); });
+  }
+  // keep this update's pivot rows for the next update of the same bond
+  int keep_rows(int l, int dir) {
+    CopyRowsArgs a{};
+    a.src = rows();
+    a.rank = p.prank;
+    a.dst = p.prevr + (size_t)(dir * (p.L + 1) + l) * p.maxrank;
+    a.dst_rank = p.prevk + dir * (p.L + 1) + l;
+    a.maxrank = p.maxrank;
+    return stepf(20007, [&] { return launch_copy_rows(a, s); });
+  }
+  // a profiled launch of the proposal pipeline (class prrLU, instance code)
+  template <typename F>
+  int stepf(int variant, F&& launch) {
+    int rc = begin(CLS_PRRLU, variant);
+    if (rc) return rc;
+    const hipError_t e = launch();
+    if (e != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("proposal launch: ") + hipGetErrorString(e));
     return end();
   }
   // pointers the prrLU of the current record wrote its pivots to
@@ -322,6 +447,7 @@ int enqueue_init(Enq& q) {
   ENQ(launch_fill_int(p.nJ + L + 1, 1, 1, s));
   ENQ(launch_fill_int(p.flags, 4, 0, s));
   ENQ(launch_fill_int((int*)p.epoch, 1, 1, s));
+  if (p.mlp) ENQ(launch_fill_int(p.prevk, 2 * (L + 1), 0, s));
   // the LDU exchange words: flag 0 is never used, and the session's flags
   // restart at 1, so memory left by an earlier session must not look valid
   ENQ(launch_fill_int((int*)p.xbuf, 2 * p.xbuf_words, 0, s));
@@ -416,6 +542,7 @@ int enqueue_sweep(Enq& q) {
   hipStream_t s = q.s;
   const int L = p.L;
   q.slot = L - 1;
+  if (p.mlp) ENQ(launch_fill_int(p.acc_count, 1, 0, s));
   // ---- left to right
   for (int l = 1; l <= L - 1; ++l) {
     ContractArgs c{};
@@ -436,9 +563,17 @@ int enqueue_sweep(Enq& q) {
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const int mmax = p.d[l] * p.capI[l - 1], nmax2 = p.d[l + 1] * p.capJ[l + 2];
+    const int* skip = nullptr;
+    if (p.mlp) {
+      rc = q.propose(l, 0, ddev(p.nI + l - 1, p.d[l]), ddev(p.nJ + l + 2, p.d[l + 1]), mmax, nmax2, p.nI + l,
+                     nullptr);
+      if (rc) return rc;
+      skip = p.acc;
+    }
     rc = q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ddev(p.nJ + l + 2, p.d[l + 1]), dconst(p.ldm),
-                 mmax, nmax2, p.nI + l, nullptr, nullptr, dconst(0));
+                 mmax, nmax2, p.nI + l, nullptr, nullptr, dconst(0), skip);
     if (rc) return rc;
+    if (p.mlp && (rc = q.keep_rows(l, 0))) return rc;
     // L^n_l = A^n_l[I_l, :]  (Alg. 5, Leftframe)
     GatherArgs g{};
     g.count = p.N;
@@ -474,9 +609,31 @@ int enqueue_sweep(Enq& q) {
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const Dim ncols = ddev(p.nJ + l + 2, p.d[l + 1]);
+    const int* skip = nullptr;
+    if (p.mlp) {
+      rc = q.propose(l, 1, ddev(p.nI + l - 1, p.d[l]), ncols, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2],
+                     p.nJ + l + 1, p.eps_bond + (l - 1));
+      if (rc) return rc;
+      skip = p.acc;
+    }
     rc = q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ncols, dconst(p.ldm), p.d[l] * p.capI[l - 1],
-                 p.d[l + 1] * p.capJ[l + 2], p.nJ + l + 1, p.eps_bond + (l - 1), p.Ycore[l + 1], ncols);
+                 p.d[l + 1] * p.capJ[l + 2], p.nJ + l + 1, p.eps_bond + (l - 1), p.Ycore[l + 1], ncols, skip);
     if (rc) return rc;
+    if (p.mlp) {
+      // an accepted proposal's right factor (the LDU forms it otherwise)
+      SolveArgs sa{};
+      sa.Up = p.rkUp;
+      sa.ldu = p.ldm;
+      sa.cols = p.rkcols;
+      sa.rank = p.rkrank;
+      sa.n = ncols;
+      sa.Y = p.Ycore[l + 1];
+      sa.ldy = ncols;
+      sa.skip = p.acc + 1;
+      rc = q.stepf(20008, [&] { return launch_rook_solve(sa, s); });
+      if (rc) return rc;
+      if ((rc = q.keep_rows(l, 1))) return rc;
+    }
     // R^n_{l+1} = B^n_l[:, J_{l+1}]  (Alg. 5, Rightframe)
     GatherArgs g{};
     g.count = p.N;
@@ -574,6 +731,8 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
   p.trace = o.trace != 0;
   p.fixed = o.fixed_sweeps != 0;
   p.prec_req = o.precision;
+  p.mlp = o.proposal;
+  p.rook_iter = o.proposal_scans > 0 ? o.proposal_scans : 8;
   p.prec = o.precision;
   p.low_max = o.low_precision_sweeps == 0 ? 4 : o.low_precision_sweeps;
   for (int n = 0; n < n_inputs; ++n) {
@@ -875,6 +1034,7 @@ int sweep_enqueue(aci_session* S) {
   HIPCHK(hipMemcpyAsync(S->h_eps, p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(S->h_meta, p.meta + 3 * (L - 1), sizeof(int) * 3 * 2 * (L - 1), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(S->h_flags, p.flags, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+  if (p.mlp) HIPCHK(hipMemcpyAsync(S->h_flags + 2, p.acc_count, sizeof(int), hipMemcpyDeviceToHost, s));
   return ACI_OK;
 }
 
@@ -906,7 +1066,7 @@ int sweep_finish(aci_session* S, aci_sweep_stats& st) {
     rec.sweep = S->sweeps - 1;
     rec.update = S->prof.slot[i] - (L - 1);
     rec.us = 1e3f * kms;
-    if (rec.update >= 0 && rec.update < 2 * (L - 1) && c != CLS_GATHER) {
+    if (rec.update >= 0 && rec.update < 2 * (L - 1) && c != CLS_GATHER && rec.variant < 20000) {
       int kind, bond;
       update_of(L, rec.update, kind, bond);
       const int* mt = meta + 3 * rec.update;
@@ -928,6 +1088,10 @@ int sweep_finish(aci_session* S, aci_sweep_stats& st) {
   S->prev.assign(S->h_cur, S->h_cur + (L - 1));
   st.max_eps = emax;
   st.last_precision = S->swept_prec;
+  if (p.mlp) {
+    st.proposals_tried += 2 * (L - 1);
+    st.proposals_accepted += S->h_flags[2];
+  }
   if (S->swept_prec == PREC_FP64) {
     S->converged = !grew && emax <= p.tol;
   } else {
@@ -1432,6 +1596,8 @@ int aci_rook_lu(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ldm, 
 
 int aci_rook_check(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ldm, const void* L, int32_t ldl,
                    const void* Up, int32_t ldu, const int32_t* rank, double tol, double* eps, int32_t* accepted) {
+  // the kernel writes the flag and its negation: stage them in the step workspace
+  int32_t* flags2 = nullptr;
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
   if (!M || !L || !Up || !rank || !eps || !accepted || m < 1 || n < 1 || ldm < n || ldu < n || ldl < 1)
@@ -1457,8 +1623,12 @@ int aci_rook_check(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ld
   a.ldc = n;
   a.tol = tol;
   a.eps = eps;
-  a.accepted = accepted;
+  rc = ensure_step_ws(ctx);
+  if (rc) return rc;
+  flags2 = ctx->step_err + 2;
+  a.accepted = flags2;
   HIPCHK(launch_check(a, ctx->stream));
+  HIPCHK(hipMemcpyAsync(accepted, flags2, sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return ACI_OK;
 }
@@ -1475,7 +1645,7 @@ int aci_rook_right_factor(aci_ctx* ctx, const void* Up, int32_t ldu, const int32
   a.rank = rank;
   a.n = dconst(n);
   a.Y = (double*)Y;
-  a.ldy = ldy;
+  a.ldy = dconst(ldy);
   HIPCHK(launch_rook_solve(a, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return ACI_OK;

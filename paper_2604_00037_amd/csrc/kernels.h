@@ -70,6 +70,7 @@ struct PrrluArgs {
   int cooperative;    // 1: hipLaunchCooperativeKernel; 0: plain launch (graph capture)
   uint32_t* epoch;    // device word holding flag_base (nullptr: use flag_base);
                       // the kernel advances it for the next launch
+  const int* skip;    // optional: the launch does nothing when *skip != 0
 };
 
 // Chooses the workgroup shape for mmax x nmax and launches.
@@ -140,7 +141,29 @@ struct CheckArgs {
   int ldc;
   double tol;
   double* eps;
-  int* accepted;
+  int* accepted;          // [0] = eps <= tol, [1] = its negation
+  int* count;             // optional: incremented when accepted
+};
+
+// Copies an accepted proposal into the outputs of the LDU it replaces.
+struct CommitArgs {
+  const int* accepted;
+  const int *src_rows, *src_cols, *src_rank;
+  const double* src_eps;
+  int *rows, *cols, *rank, *rank2;
+  double *eps, *eps2;
+  int *meta, *meta2;
+  Dim m, n;
+  int maxrank;
+};
+
+// dst[0 .. *rank) = src, *dst_rank = *rank
+struct CopyRowsArgs {
+  const int* src;
+  const int* rank;
+  int* dst;
+  int* dst_rank;
+  int maxrank;
 };
 
 struct SolveArgs {
@@ -150,7 +173,7 @@ struct SolveArgs {
   const int* rank;
   Dim n;
   double* Y;
-  int ldy;
+  Dim ldy;
   const int* skip;        // optional: return at once when *skip != 0
 };
 
@@ -160,6 +183,8 @@ hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t s);
 hipError_t launch_rook(const RookArgs& a, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
 hipError_t launch_rook_solve(const SolveArgs& a, hipStream_t s);
+hipError_t launch_commit(const CommitArgs& a, hipStream_t s);
+hipError_t launch_copy_rows(const CopyRowsArgs& a, hipStream_t s);
 
 // ----------------------------------------------------------------- gathers
 struct GatherItem {

@@ -413,9 +413,44 @@ __global__ __launch_bounds__(NT) void check_kernel(CheckArgs a) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    const int ok = red[0] <= a.tol ? 1 : 0;
     *a.eps = red[0];
-    *a.accepted = red[0] <= a.tol ? 1 : 0;
+    a.accepted[0] = ok;
+    a.accepted[1] = 1 - ok;
+    if (ok && a.count) atomicAdd(a.count, 1);
   }
+}
+
+__global__ void commit_kernel(CommitArgs a) {
+  if (!*a.accepted) return;
+  const int r = *a.src_rank;
+  for (int k = threadIdx.x; k < r && k < a.maxrank; k += blockDim.x) {
+    a.rows[k] = a.src_rows[k];
+    a.cols[k] = a.src_cols[k];
+  }
+  if (threadIdx.x == 0) {
+    const double e = *a.src_eps;
+    *a.rank = r;
+    *a.eps = e;
+    if (a.rank2) *a.rank2 = r;
+    if (a.eps2) *a.eps2 = e;
+    if (a.meta) {
+      a.meta[0] = r;
+      a.meta[1] = dget(a.m);
+      a.meta[2] = dget(a.n);
+    }
+    if (a.meta2) {
+      a.meta2[0] = r;
+      a.meta2[1] = dget(a.m);
+      a.meta2[2] = dget(a.n);
+    }
+  }
+}
+
+__global__ void copy_rows_kernel(CopyRowsArgs a) {
+  const int r = *a.rank;
+  for (int k = threadIdx.x; k < r && k < a.maxrank; k += blockDim.x) a.dst[k] = a.src[k];
+  if (threadIdx.x == 0) *a.dst_rank = r < a.maxrank ? r : a.maxrank;
 }
 
 // ------------------------------------------------------- right factor
@@ -425,12 +460,13 @@ __global__ __launch_bounds__(NT) void rook_solve_kernel(SolveArgs a) {
   if (a.skip && *a.skip) return;
   const int r = *a.rank;
   const int n = dget(a.n);
+  const int ldy = dget(a.ldy);
   for (int t = r - 1; t >= 0; --t) {
     const double d = a.Up[(size_t)t * a.ldu + a.cols[t]];
     for (int j = threadIdx.x; j < n; j += NT) {
       double acc = a.Up[(size_t)t * a.ldu + j];
-      for (int s = t + 1; s < r; ++s) acc = acc - a.Up[(size_t)t * a.ldu + a.cols[s]] * a.Y[(size_t)s * a.ldy + j];
-      a.Y[(size_t)t * a.ldy + j] = d != 0.0 ? acc / d : 0.0;
+      for (int s = t + 1; s < r; ++s) acc = acc - a.Up[(size_t)t * a.ldu + a.cols[s]] * a.Y[(size_t)s * ldy + j];
+      a.Y[(size_t)t * ldy + j] = d != 0.0 ? acc / d : 0.0;
     }
     __syncthreads();
   }
@@ -469,6 +505,16 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t s) {
 
 hipError_t launch_rook_solve(const SolveArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(rook_solve_kernel, dim3(1), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit(const CommitArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(commit_kernel, dim3(1), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const CopyRowsArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(1), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 

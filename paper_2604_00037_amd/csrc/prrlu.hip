@@ -169,6 +169,9 @@ constexpr uint32_t kXccFlagOffset = 1536;
 template <int RS, int CS, bool SOLO>
 __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
   if ((int)(blockIdx.x % a.stride) != (a.stride == 8 ? a.xcd : 0)) return;
+  // a proposal already supplied this factorisation (every group reads the
+  // same word, so the whole launch leaves together; the epoch is untouched)
+  if (a.skip && *a.skip) return;
   const int w = blockIdx.x / a.stride;
   // flags of this launch: step k uses fbase + k
   const uint32_t fbase = a.epoch ? __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)

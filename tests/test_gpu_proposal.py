@@ -180,3 +180,81 @@ def test_trained_network_reduces_rook_scans():
           f"accepted {a_trained}/{a_untr}/{a_none} of {len(test)}")
     assert s_trained < s_none and s_trained < s_untr
     assert a_trained >= a_none
+
+
+# ------------------------------------------------------------ inside the sweep
+from helpers import rel_max_err, to_dev  # noqa: E402
+
+
+def test_sweep_with_proposal_reconstructs_exactly_and_accepts():
+    """Exact-rank products at tol 1e-12: the rook proposals (untrained
+    network) are accepted at least sometimes, and the result still
+    reconstructs the product like the plain sweep."""
+    x1, x2 = W.random_pair(L=10, chi=5, seeds=(4101, 4102))
+    params = dev(flat(P.mlp_init(41)))
+    s = aci.Session([to_dev(x1), to_dev(x2)], "product", 1e-12, 30, maxiter=8, seed=2, proposal=params)
+    try:
+        st = s.sweep(8)
+        cores, info = s.result()
+    finally:
+        s.close()
+    assert info.converged
+    assert st["proposals_tried"] > 0 and st["proposals_accepted"] > 0
+    f = W.tt_full(x1) * W.tt_full(x2)
+    assert rel_max_err(W.tt_full([c.cpu().numpy() for c in cores]), f) <= 1e-10
+
+
+def test_rejected_proposals_leave_the_sweep_unchanged():
+    """Rank cap 1 on random inputs: no two-site matrix has rank 1, so no
+    rank-1 rook result reaches the tolerance 1e-300, every proposal is
+    rejected and the LDU's output is reproduced bit for bit (also when the
+    sweep replays a captured graph)."""
+    x1, x2 = W.random_pair(L=10, chi=6, seeds=(4111, 4112))
+    d = [to_dev(x1), to_dev(x2)]
+    params = dev(flat(P.mlp_init(43)))
+    plain, pi = aci.elementwise(d, "product", 1e-300, 1, maxiter=4, seed=3, fixed_sweeps=True)
+    for use_graph in (False, True):
+        s = aci.Session(d, "product", 1e-300, 1, maxiter=4, seed=3, proposal=params, use_graph=use_graph,
+                        fixed_sweeps=True)
+        try:
+            st = s.sweep(4)
+            cores, info = s.result()
+        finally:
+            s.close()
+        assert st["proposals_accepted"] == 0 and st["proposals_tried"] > 0
+        assert info.ranks == pi.ranks and info.eps == pi.eps
+        for a, b in zip(cores, plain):
+            assert torch.equal(a, b)
+
+
+def test_sweep_with_trained_proposal_on_held_out_fields():
+    """Network trained on the GPU (as above) used inside the sweeps of a
+    held-out 3D Fourier product: converged, within 10 tol of the exact
+    product at samples, and most proposals accepted."""
+    train = _records(range(1, 5))
+    Xs, ys = [], []
+    for r in train:
+        Xs.append(_gpu_features(r))
+        y = np.zeros(r["M"].shape[0], np.float32)
+        y[r["rows"][:max(1, len(r["rows"]) // 2)]] = 1
+        ys.append(torch.from_numpy(y).cuda())
+    X, y = torch.cat(Xs), torch.cat(ys)
+    p = dev(flat(P.mlp_init(7)))
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    rng = np.random.default_rng(1)
+    for step in range(1, 201):
+        idx = torch.from_numpy(rng.choice(X.shape[0], 512, replace=False)).cuda()
+        aci.mlp_train_step(p, m, v, step, X[idx].contiguous(), y[idx].contiguous(), lr=3e-3)
+    g1, g2 = _field(4, 4, 151, 24), _field(4, 4, 1151, 24)
+    s = aci.Session([to_dev(g1), to_dev(g2)], "product", 1e-8, 64, maxiter=6, seed=5, proposal=p)
+    try:
+        st = s.sweep(6)
+        cores, info = s.result()
+    finally:
+        s.close()
+    assert info.converged
+    assert st["proposals_accepted"] >= 0.5 * st["proposals_tried"]
+    f = W.tt_full(g1) * W.tt_full(g2)
+    y = W.tt_full([c.cpu().numpy() for c in cores])
+    assert np.abs(y - f).max() <= 10 * 1e-8 * max(1.0, np.abs(f).max())
+    print(f"accepted {st['proposals_accepted']} of {st['proposals_tried']} proposals in the last sweeps")

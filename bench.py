@@ -300,6 +300,77 @@ def time_batched(aci, steps, warmup, device):
             "max_eps": st["max_eps"], "pivots_per_sweep": st["pivots"] / steps}
 
 
+def time_proposal(aci, device, steps=300):
+    """Learned pivot proposal: a scoring network trained on the GPU from the
+    pivots of plain FP64 ACI (the oracle) on products of 3D Fourier fields
+    (4 bits per axis, |k| <= 4, rank 24, training seeds 1..6), then used in
+    the sweeps of a held-out product of the same kind at 5 bits per axis
+    (L = 15, rank 48), tol 1e-8, rank cap 128: sweeps to convergence and
+    wall time with and without proposals, and how many were accepted."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads as W
+    from oracle import proposal as P
+
+    def field(R, kmax, s, chi):
+        g = W.fourier3d_full(R, kmax, s)
+        q = np.ascontiguousarray(W.grid_to_quantics(g, R, 3)).reshape(-1)
+        return W.tt_svd(q, 2, chi, rtol=1e-12)
+
+    t = time.perf_counter()
+    Xs, ys = [], []
+    for sd in range(1, 7):
+        rec = []
+        oracle.aci([field(4, 4, sd, 24), field(4, 4, sd + 1000, 24)], "product", TOL, 64, maxiter=3, seed=sd,
+                   record=rec)
+        prev = {}
+        for r in rec:
+            key = (r["bond"], r["dir"])
+            pr = prev.get(key, np.zeros(0, np.int32)).astype(np.int32)
+            prev[key] = r["rows"]
+            M = torch.from_numpy(r["M"]).to(device)
+            X = aci.proposal_features(M, [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in r["A"]],
+                                      torch.from_numpy(pr).to(device) if len(pr) else None)
+            y = np.zeros(r["M"].shape[0], np.float32)
+            y[r["rows"][:max(1, len(r["rows"]) // 2)]] = 1
+            Xs.append(X)
+            ys.append(torch.from_numpy(y).to(device))
+    X, y = torch.cat(Xs), torch.cat(ys)
+    p = torch.from_numpy(np.concatenate([q.reshape(-1) for q in P.mlp_init(7).params()])).to(device)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    rng = np.random.default_rng(0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for step in range(1, steps + 1):
+        idx = torch.from_numpy(rng.choice(X.shape[0], 512, replace=False)).to(device)
+        loss, _ = aci.mlp_train_step(p, m, v, step, X[idx].contiguous(), y[idx].contiguous(), lr=3e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    log(f"proposal: {X.shape[0]} training rows from oracle runs, {steps} Adam steps in {train_s:.2f} s, "
+        f"loss {loss:.3f}")
+    g1, g2 = field(5, 4, 151, 48), field(5, 4, 1151, 48)
+    d = [[torch.from_numpy(c).to(device) for c in g] for g in (g1, g2)]
+    out = {"workload": "u*v of two random 3D Fourier fields (|k|<=4) on a 32^3 grid, L=15 d=2, TT rank 48, "
+                       f"tol {TOL}, rank cap 128, FP64; network trained on 16^3 fields",
+           "training_rows": int(X.shape[0]), "training_s": train_s}
+    for name, prop in (("plain", None), ("proposal", p)):
+        S = aci.Session(d, "product", TOL, 128, maxiter=20, seed=INIT_SEED, proposal=prop, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.sweep(20)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        S.close()
+        out[name] = {"sweeps": st["sweeps_done"], "converged": st["converged"], "seconds": el,
+                     "sweeps_per_s": st["sweeps_done"] / el, "max_eps": st["max_eps"],
+                     "proposals_tried": st["proposals_tried"], "proposals_accepted": st["proposals_accepted"]}
+        log(f"proposal mode {name}: {st['sweeps_done']} sweeps in {el:.3f} s, converged {st['converged']}, "
+            f"accepted {st['proposals_accepted']}/{st['proposals_tried']}")
+    log(f"proposal section took {time.perf_counter() - t:.1f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +380,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16x3 contraction modes")
     ap.add_argument("--no-batched", action="store_true", help="skip the nine-product batch")
+    ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print a summary of a rocprofv3 run of this script (needs --bench-json) and exit")
     ap.add_argument("--bench-json", metavar="FILE", help="output of the profiled run")
@@ -413,6 +485,8 @@ def main():
             out["modes"][prec] = time_mode(aci, inputs, prec, args.steps, args.warmup)
     if not args.no_batched:
         out["batched"] = time_batched(aci, max(2, args.steps // 3), 1, dev)
+    if not args.no_proposal:
+        out["proposal"] = time_proposal(aci, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u, v)
         out["speedup_vs_cpu_oracle"] = out["value"] / out["cpu_baseline"]["value"]

@@ -2,7 +2,7 @@
 
 Device memory and streams come from PyTorch (HIP build); every step of the
 computation runs in the library's HIP kernels.  All tensors passed in must be
-contiguous float64 tensors on the current HIP device.
+contiguous float64 (or complex128) tensors on the current HIP device.
 """
 
 from __future__ import annotations
@@ -18,6 +18,12 @@ OPS = {"product": 0, "sum": 1, "abs2_mul": 2}
 RULES = {"exclusive": 0, "literal": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 F64 = 0
+C128 = 1
+
+
+def _code(t):
+    """aci_dtype of a tensor."""
+    return C128 if t.dtype == torch.complex128 else F64
 
 
 def _check(lib, ctx, status, allow_warning=True):
@@ -31,9 +37,9 @@ def _check(lib, ctx, status, allow_warning=True):
 def _dev_tensor(t, name, dtype=None):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a device tensor")
-    want = dtype if dtype is not None else torch.float64
-    if t.dtype != want:
-        raise TypeError(f"{name} must be {str(want).replace('torch.', '')}")
+    want = (dtype,) if dtype is not None else (torch.float64, torch.complex128)
+    if t.dtype not in want:
+        raise TypeError(f"{name} must be " + " or ".join(str(w).replace("torch.", "") for w in want))
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t
@@ -125,11 +131,14 @@ def _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweep
 def _inputs(inputs, keep):
     if len(inputs) < 1:
         raise ValueError("need at least one input TT")
+    dt = inputs[0][0].dtype
     for n, X in enumerate(inputs):
         for l, c in enumerate(X):
             _dev_tensor(c, f"inputs[{n}][{l}]")
             if c.dim() != 3:
                 raise ValueError("cores must be 3-dimensional")
+            if c.dtype != dt:
+                raise TypeError("all input cores must share one dtype")
     return (_lib.AciTT * len(inputs))(*[_tt_struct(X, keep) for X in inputs])
 
 
@@ -140,7 +149,7 @@ def _out_buffer(inputs, maxrank):
     # limit is rejected by the library itself)
     mr = min(int(maxrank), 512)
     cap = L * dmax * mr * mr
-    return torch.empty(cap, dtype=torch.float64, device=inputs[0][0].device), cap
+    return torch.empty(cap, dtype=inputs[0][0].dtype, device=inputs[0][0].device), cap
 
 
 def _unpack(res, out, dims, status, trace):
@@ -182,7 +191,7 @@ def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed
                     low_precision_sweeps, False, proposal, proposal_scans)
     out, cap = _out_buffer(inputs, maxrank)
     res = _lib.AciResult()
-    status = lib.aci_elementwise(ctx.h, tts, len(inputs), F64, OPS[op], float(tol), int(maxrank),
+    status = lib.aci_elementwise(ctx.h, tts, len(inputs), _code(inputs[0][0]), OPS[op], float(tol), int(maxrank),
                                  C.byref(opts), C.c_void_p(out.data_ptr()), cap, C.byref(res))
     try:
         _check(lib, ctx.h, status)
@@ -227,7 +236,7 @@ class Session:
                         profile, low_precision_sweeps, use_graph, proposal, proposal_scans)
         self._init = init
         h = C.c_void_p()
-        st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), F64, OPS[op], float(tol),
+        st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), _code(inputs[0][0]), OPS[op], float(tol),
                                              int(maxrank), C.byref(opts), C.byref(h))
         _check(self.ctx.lib, self.ctx.h, st, allow_warning=False)
         self.h = h
@@ -294,14 +303,14 @@ def env_contract(side, frames, cores, precision="fp64", ctx=None):
     r0, d, r1 = (int(s) for s in cores[0].shape)
     if side == "left":
         c = int(frames[0].shape[0])
-        outs = [torch.empty(c, d * r1, dtype=torch.float64, device=cores[0].device) for _ in range(n)]
+        outs = [torch.empty(c, d * r1, dtype=cores[0].dtype, device=cores[0].device) for _ in range(n)]
     else:
         c = int(frames[0].shape[1])
-        outs = [torch.empty(r0 * d, c, dtype=torch.float64, device=cores[0].device) for _ in range(n)]
+        outs = [torch.empty(r0 * d, c, dtype=cores[0].dtype, device=cores[0].device) for _ in range(n)]
     fp = (C.c_void_p * n)(*[f.data_ptr() for f in frames])
     cp = (C.c_void_p * n)(*[x.data_ptr() for x in cores])
     op_ = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
-    st = ctx.lib.aci_env_contract(ctx.h, F64, 0 if side == "left" else 1, n, fp, cp, op_, c, r0, d, r1,
+    st = ctx.lib.aci_env_contract(ctx.h, _code(cores[0]), 0 if side == "left" else 1, n, fp, cp, op_, c, r0, d, r1,
                                   PRECISIONS[precision])
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     return outs
@@ -316,11 +325,11 @@ def pi_eval(op, A, B, precision="fp64", ctx=None):
         _dev_tensor(b, "B")
     m = int(A[0].shape[0])
     ncol = int(B[0].shape[1])
-    M = torch.empty(m, ncol, dtype=torch.float64, device=A[0].device)
+    M = torch.empty(m, ncol, dtype=A[0].dtype, device=A[0].device)
     ap = (C.c_void_p * n)(*[a.data_ptr() for a in A])
     bp = (C.c_void_p * n)(*[b.data_ptr() for b in B])
     ks = (C.c_int32 * n)(*[int(a.shape[1]) for a in A])
-    st = ctx.lib.aci_pi_eval(ctx.h, F64, OPS[op], n, ap, bp, ks, m, ncol, C.c_void_p(M.data_ptr()), ncol,
+    st = ctx.lib.aci_pi_eval(ctx.h, _code(A[0]), OPS[op], n, ap, bp, ks, m, ncol, C.c_void_p(M.data_ptr()), ncol,
                              PRECISIONS[precision])
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     return M
@@ -337,8 +346,8 @@ def prrlu(M, tol, maxrank, stop_rule="exclusive", want_y=False, ctx=None):
     cols = torch.full((kcap,), -1, dtype=torch.int32, device=dev)
     rank = torch.zeros(1, dtype=torch.int32, device=dev)
     eps = torch.zeros(1, dtype=torch.float64, device=dev)
-    Y = torch.zeros(kcap, n, dtype=torch.float64, device=dev) if want_y else None
-    st = ctx.lib.aci_prrlu(ctx.h, F64, C.c_void_p(M.data_ptr()), m, n, n, float(tol), int(maxrank),
+    Y = torch.zeros(kcap, n, dtype=M.dtype, device=dev) if want_y else None
+    st = ctx.lib.aci_prrlu(ctx.h, _code(M), C.c_void_p(M.data_ptr()), m, n, n, float(tol), int(maxrank),
                            RULES[stop_rule], C.c_void_p(rows.data_ptr()), C.c_void_p(cols.data_ptr()),
                            C.c_void_p(rank.data_ptr()), C.c_void_p(eps.data_ptr()),
                            C.c_void_p(Y.data_ptr() if Y is not None else 0), n)
@@ -357,12 +366,12 @@ def gather(side, src, idx, ld_out=None, ctx=None):
     r = int(idx_t.numel())
     rank = torch.tensor([r], dtype=torch.int32, device=src.device)
     if side == "rows":
-        out = torch.zeros(r, w, dtype=torch.float64, device=src.device)
+        out = torch.zeros(r, w, dtype=src.dtype, device=src.device)
         ld = w
     else:
-        out = torch.zeros(h, r, dtype=torch.float64, device=src.device)
+        out = torch.zeros(h, r, dtype=src.dtype, device=src.device)
         ld = r
-    st = ctx.lib.aci_gather(ctx.h, F64, 0 if side == "rows" else 1, C.c_void_p(src.data_ptr()), h, w, w,
+    st = ctx.lib.aci_gather(ctx.h, _code(src), 0 if side == "rows" else 1, C.c_void_p(src.data_ptr()), h, w, w,
                             C.c_void_p(idx_t.data_ptr()), C.c_void_p(rank.data_ptr()),
                             C.c_void_p(out.data_ptr()), max(ld, 1))
     _check(ctx.lib, ctx.h, st, allow_warning=False)
@@ -399,7 +408,8 @@ class Batch:
                         profile, low_precision_sweeps, use_graph)
         opts.tune = 1 if tune else 0
         h = C.c_void_p()
-        st = self.ctx.lib.aci_batch_create(self.ctx.h, tts, counts, len(products), F64, OPS[op], float(tol),
+        st = self.ctx.lib.aci_batch_create(self.ctx.h, tts, counts, len(products), _code(products[0][0][0]), OPS[op],
+                                           float(tol),
                                            int(maxrank), C.byref(opts), C.byref(h))
         _check(self.ctx.lib, self.ctx.h, st, allow_warning=False)
         self.h = h
@@ -455,7 +465,8 @@ def elementwise_batched(products, op="product", tol=1e-12, maxrank=64, *, maxite
     outs = (C.c_void_p * len(products))(*[C.c_void_p(b.data_ptr()) for b, _ in bufs])
     caps = (C.c_int64 * len(products))(*[c for _, c in bufs])
     res = (_lib.AciResult * len(products))()
-    status = lib.aci_elementwise_batched(ctx.h, tts, counts, len(products), F64, OPS[op], float(tol),
+    status = lib.aci_elementwise_batched(ctx.h, tts, counts, len(products), _code(products[0][0][0]), OPS[op],
+                                         float(tol),
                                          int(maxrank), C.byref(opts), outs, caps, res)
     try:
         _check(lib, ctx.h, status)
@@ -489,7 +500,7 @@ def proposal_features(M, env, prev_rows=None, ctx=None):
     from the left environments env (list of <= 2 device matrices with m rows)
     and the previous pivot rows (device int32 tensor or None)."""
     ctx = ctx or default_context()
-    _dev_tensor(M, "M")
+    _dev_tensor(M, "M", torch.float64)
     m, n = M.shape
     X = torch.empty((m, 7), dtype=torch.float32, device=M.device)
     envp = (C.c_void_p * 2)(*[_p(e) for e in env] + [None] * (2 - len(env)))
@@ -524,7 +535,7 @@ def mlp_train_step(params, adam_m, adam_v, step, X, y, lr=1e-3, want_grads=False
 def rook_lu(M, tol, maxrank, scores=None, max_iter=8, ctx=None):
     """Rook search: dict(rows, cols, rank, eps, L (m x rank), Up (rank x n), scans)."""
     ctx = ctx or default_context()
-    _dev_tensor(M, "M")
+    _dev_tensor(M, "M", torch.float64)
     m, n = M.shape
     dev = M.device
     rows = torch.zeros(maxrank, dtype=torch.int32, device=dev)

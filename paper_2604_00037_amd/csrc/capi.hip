@@ -101,6 +101,7 @@ struct SplitMix64 {
 
 struct Plan {
   int L = 0, N = 0, op = 0, maxrank = 0, maxiter = 20, rule = 0;
+  int cplx = 0, ew = 1;       // complex entries; doubles per entry
   int prec_req = PREC_FP64;   // requested contraction precision
   int prec = PREC_FP64;       // precision of the sweep being enqueued
   int low_max = 4;            // ladder: most low-precision sweeps (< 0: no limit)
@@ -156,22 +157,22 @@ struct Plan {
 void layout(Plan& p, Arena& A, bool gen_init) {
   const int L = p.L;
   for (int n = 0; n < p.N; ++n) {
-    for (int l = 0; l < L; ++l) p.Lf[n][l] = A.take<double>((size_t)p.capI[l] * p.r[n][l]);
-    for (int l = 2; l <= L + 1; ++l) p.Rf[n][l] = A.take<double>((size_t)p.r[n][l - 1] * p.ldR);
+    for (int l = 0; l < L; ++l) p.Lf[n][l] = A.take<double>((size_t)p.ew * p.capI[l] * p.r[n][l]);
+    for (int l = 2; l <= L + 1; ++l) p.Rf[n][l] = A.take<double>((size_t)p.ew * p.r[n][l - 1] * p.ldR);
     for (int l = 1; l < L; ++l) {
-      p.Ac[n][l] = A.take<double>((size_t)p.capI[l - 1] * p.d[l] * p.r[n][l]);
-      p.Bc[n][l] = A.take<double>((size_t)p.r[n][l] * p.d[l + 1] * p.capJ[l + 2]);
+      p.Ac[n][l] = A.take<double>((size_t)p.ew * p.capI[l - 1] * p.d[l] * p.r[n][l]);
+      p.Bc[n][l] = A.take<double>((size_t)p.ew * p.r[n][l] * p.d[l + 1] * p.capJ[l + 2]);
     }
   }
-  p.Mbuf = A.take<double>((size_t)p.ldm * p.ldm);
+  p.Mbuf = A.take<double>((size_t)p.ew * p.ldm * p.ldm);
   int rho_max = 1;
   for (int l = 0; l <= L; ++l) rho_max = std::max(rho_max, p.rho[l]);
   for (int l = 1; l <= L; ++l) {
-    p.G[l] = A.take<double>((size_t)p.rho[l - 1] * p.d[l] * p.rho[l]);
-    p.Gin[l] = gen_init ? A.take<double>((size_t)p.rho[l - 1] * p.d[l] * p.rho[l]) : nullptr;
-    p.Ycore[l] = A.take<double>((size_t)p.maxrank * p.d[l] * p.maxrank);
+    p.G[l] = A.take<double>((size_t)p.ew * p.rho[l - 1] * p.d[l] * p.rho[l]);
+    p.Gin[l] = gen_init ? A.take<double>((size_t)p.ew * p.rho[l - 1] * p.d[l] * p.rho[l]) : nullptr;
+    p.Ycore[l] = A.take<double>((size_t)p.ew * p.maxrank * p.d[l] * p.maxrank);
   }
-  p.Atmp = A.take<double>((size_t)rho_max * p.ldR);
+  p.Atmp = A.take<double>((size_t)p.ew * rho_max * p.ldR);
   p.nI = A.take<int>(L + 2);
   p.nJ = A.take<int>(L + 3);
   p.prow = A.take<int>(p.maxrank + 1);
@@ -181,7 +182,7 @@ void layout(Plan& p, Arena& A, bool gen_init) {
   p.eps_bond = A.take<double>(L + 1);
   p.flags = A.take<int>(4);
   p.epoch = A.take<uint32_t>(1);
-  p.xbuf_words = prrlu_xbuf_words(p.ldm, p.ldm);
+  p.xbuf_words = prrlu_xbuf_words(p.ldm, p.ldm, p.cplx);
   p.xbuf = A.take<uint64_t>(p.xbuf_words);
   p.meta = A.take<int>((size_t)3 * 3 * (L - 1));
   if (p.mlp) {
@@ -266,6 +267,7 @@ struct Enq {
             double* Y, Dim ldy, const int* skip = nullptr) {
     PrrluArgs a{};
     a.skip = skip;
+    a.cplx = p.cplx;
     a.M = M;
     a.m = m;
     a.n = n;
@@ -299,7 +301,7 @@ struct Enq {
     a.ldy = ldy;
     a.err = p.flags;
     a.abort_word = p.flags + 1;
-    int rc = begin(CLS_PRRLU, prrlu_variant(mmax, nmax, p.max_groups));
+    int rc = begin(CLS_PRRLU, prrlu_variant(mmax, nmax, p.max_groups, p.cplx));
     if (rc) return rc;
     hipError_t e = launch_prrlu(a, mmax, nmax, s);
     if (e != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("prrlu launch: ") + hipGetErrorString(e));
@@ -440,6 +442,9 @@ int enqueue_init(Enq& q) {
   hipStream_t s = q.s;
   const int L = p.L;
   for (int n = 0; n < p.N; ++n) {
+    // the boundary frames are [1] (complex: 1 + 0i)
+    ENQ(launch_fill(p.Lf[n][0], p.ew, 0.0, s));
+    ENQ(launch_fill(p.Rf[n][L + 1], p.ew, 0.0, s));
     ENQ(launch_fill(p.Lf[n][0], 1, 1.0, s));
     ENQ(launch_fill(p.Rf[n][L + 1], 1, 1.0, s));
   }
@@ -463,6 +468,7 @@ int enqueue_init(Enq& q) {
     if (l > 2) {
       // G_{l-1} = Y_init_{l-1} * M[:, J_l]
       GatherArgs g{};
+    g.esz = p.ew;
       g.count = 1;
       g.side = 1;
       g.idx = cols;
@@ -471,6 +477,7 @@ int enqueue_init(Enq& q) {
       g.it[0] = GatherItem{Msrc, p.Atmp, ncols, dconst(p.ldR), dconst(p.rho[l - 1]), ncols};
       ENQP(q, CLS_GATHER, launch_gather(g, p.maxrank, p.rho[l - 1], s));
       ContractArgs c{};
+    c.cplx = p.cplx;
       c.ngroup = 1;
       c.err = nullptr;
       Group& gr = c.g[0];
@@ -485,6 +492,7 @@ int enqueue_init(Enq& q) {
     }
     // B^n_{l-1} = X^n_l R^n_{l+1};  R^n_l = B^n_{l-1}[:, J_l]  (Alg. 5, Rightframe)
     ContractArgs c{};
+    c.cplx = p.cplx;
     c.ngroup = p.N;
     int mmax = 0;
     for (int n = 0; n < p.N; ++n) {
@@ -499,6 +507,7 @@ int enqueue_init(Enq& q) {
     }
     ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, PREC_FP64), 1, launch_contract(OP_NONE, PREC_FP64, c, mmax, p.capJ[l + 1], s));
     GatherArgs g{};
+    g.esz = p.ew;
     g.count = p.N;
     g.side = 1;
     g.idx = cols;
@@ -520,6 +529,8 @@ int enqueue_pi(Enq& q, int l) {
   aci_ctx* ctx = q.ctx;
   Plan& p = q.p;
   ContractArgs c{};
+  c.cplx = p.cplx;
+    c.cplx = p.cplx;
   c.ngroup = 1;
   c.err = p.flags;
   Group& gr = c.g[0];
@@ -546,6 +557,7 @@ int enqueue_sweep(Enq& q) {
   // ---- left to right
   for (int l = 1; l <= L - 1; ++l) {
     ContractArgs c{};
+    c.cplx = p.cplx;
     c.ngroup = p.N;
     int nmax = 0;
     for (int n = 0; n < p.N; ++n) {
@@ -576,6 +588,7 @@ int enqueue_sweep(Enq& q) {
     if (p.mlp && (rc = q.keep_rows(l, 0))) return rc;
     // L^n_l = A^n_l[I_l, :]  (Alg. 5, Leftframe)
     GatherArgs g{};
+    g.esz = p.ew;
     g.count = p.N;
     g.side = 0;
     g.idx = q.rows();
@@ -593,6 +606,7 @@ int enqueue_sweep(Enq& q) {
   // ---- right to left
   for (int l = L - 1; l >= 1; --l) {
     ContractArgs c{};
+    c.cplx = p.cplx;
     c.ngroup = p.N;
     int mmax = 0;
     for (int n = 0; n < p.N; ++n) {
@@ -636,6 +650,7 @@ int enqueue_sweep(Enq& q) {
     }
     // R^n_{l+1} = B^n_l[:, J_{l+1}]  (Alg. 5, Rightframe)
     GatherArgs g{};
+    g.esz = p.ew;
     g.count = p.N;
     g.side = 1;
     g.idx = q.cols();
@@ -710,7 +725,7 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
                  int32_t maxrank, const aci_options& o, Plan& p) {
   if (!inputs) return set_err(ctx, ACI_E_INVALID, "null inputs");
   if (n_inputs < 1 || n_inputs > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
-  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64 cores are supported by this build");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
   if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL) return set_err(ctx, ACI_E_INVALID, "unknown op");
   if (op == ACI_OP_ABS2_MUL && n_inputs != 1) return set_err(ctx, ACI_E_INVALID, "ABS2_MUL takes one input");
   if (!(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "tol must be >= 0");
@@ -731,7 +746,10 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
   p.trace = o.trace != 0;
   p.fixed = o.fixed_sweeps != 0;
   p.prec_req = o.precision;
+  p.cplx = dtype == ACI_C128 ? 1 : 0;
+  p.ew = p.cplx ? 2 : 1;
   p.mlp = o.proposal;
+  if (p.mlp && p.cplx) return set_err(ctx, ACI_E_DTYPE, "the learned proposal takes real matrices only");
   p.rook_iter = o.proposal_scans > 0 ? o.proposal_scans : 8;
   p.prec = o.precision;
   p.low_max = o.low_precision_sweeps == 0 ? 4 : o.low_precision_sweeps;
@@ -959,7 +977,8 @@ int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t
     SplitMix64 rng{o.seed};
     std::vector<double> h;
     for (int l = 1; l <= L; ++l) {
-      const size_t cnt = (size_t)p.rho[l - 1] * p.d[l] * p.rho[l];
+      // complex entries take two consecutive draws (re, im)
+      const size_t cnt = (size_t)p.ew * p.rho[l - 1] * p.d[l] * p.rho[l];
       h.resize(cnt);
       for (size_t i = 0; i < cnt; ++i) h[i] = rng.uniform();
       HIPCHK(hipMemcpyAsync(p.Gin[l], h.data(), cnt * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1168,7 +1187,8 @@ int aci_session_result(aci_session* S, void* out, int64_t out_capacity, aci_resu
   for (int l = 1; l <= L; ++l) {
     const int64_t cnt = (int64_t)result->ranks[l - 1] * p.d[l] * result->ranks[l];
     result->core_offset[l - 1] = off;
-    HIPCHK(hipMemcpyAsync((double*)out + off, p.Ycore[l], cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync((double*)out + off * p.ew, p.Ycore[l], cnt * p.ew * sizeof(double), hipMemcpyDeviceToDevice,
+                          s));
     off += cnt;
   }
   result->out_elems = off;
@@ -1763,7 +1783,7 @@ static int ensure_step_ws(aci_ctx* ctx) {
   if (!ctx->step_err) {
     if (hipMalloc(&ctx->step_err, 4 * sizeof(int)) != hipSuccess) return set_err(ctx, ACI_E_NOMEM, "step workspace");
   }
-  const size_t words = prrlu_xbuf_words(ACI_MAX_MATRIX, ACI_MAX_MATRIX);
+  const size_t words = prrlu_xbuf_words(ACI_MAX_MATRIX, ACI_MAX_MATRIX, 1);
   if (ctx->step_xwords < words) {
     if (ctx->step_xbuf) (void)hipFree(ctx->step_xbuf);
     ctx->step_xbuf = nullptr;
@@ -1778,11 +1798,12 @@ int aci_env_contract(aci_ctx* ctx, int32_t dtype, int32_t side, int32_t count, c
                      int32_t precision) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
-  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
   if (precision < ACI_PREC_FP64 || precision > ACI_PREC_BF16X3) return set_err(ctx, ACI_E_DTYPE, "unknown precision");
   if (count < 1 || count > ACI_MAX_INPUTS || !frames || !cores || !outp) return set_err(ctx, ACI_E_INVALID, "bad count or null");
   if (c < 1 || r0 < 1 || d < 1 || r1 < 1) return set_err(ctx, ACI_E_INVALID, "bad dims");
   ContractArgs a{};
+  a.cplx = dtype == ACI_C128 ? 1 : 0;
   a.ngroup = count;
   int mmax, nmax;
   for (int i = 0; i < count; ++i) {
@@ -1813,13 +1834,14 @@ int aci_pi_eval(aci_ctx* ctx, int32_t dtype, int32_t op, int32_t n_inputs, const
                 int32_t precision) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
-  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
   if (precision < ACI_PREC_FP64 || precision > ACI_PREC_BF16X3) return set_err(ctx, ACI_E_DTYPE, "unknown precision");
   if (n_inputs < 1 || n_inputs > ACI_MAX_INPUTS || !A || !B || !k || !M) return set_err(ctx, ACI_E_INVALID, "bad arguments");
   if (op == ACI_OP_ABS2_MUL && n_inputs != 1) return set_err(ctx, ACI_E_INVALID, "ABS2_MUL takes one input");
   if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL) return set_err(ctx, ACI_E_INVALID, "op");
   if (m < 1 || n < 1 || ldm < n) return set_err(ctx, ACI_E_INVALID, "bad dims");
   ContractArgs a{};
+  a.cplx = dtype == ACI_C128 ? 1 : 0;
   a.ngroup = 1;
   a.err = ctx->step_err;
   int rc = ensure_step_ws(ctx);
@@ -1849,7 +1871,7 @@ int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, 
               void* Y, int32_t ldy) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
-  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
   if (!M || !rows || !cols || !rank || !eps) return set_err(ctx, ACI_E_INVALID, "null pointer");
   if (m < 1 || n < 1 || ldm < n || maxrank < 1 || !(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "bad dims or tolerance");
   if (m > ACI_MAX_MATRIX || n > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "matrix above ACI_MAX_MATRIX");
@@ -1860,6 +1882,7 @@ int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, 
   HIPCHK(launch_fill_int(ctx->step_err, 2, 0, ctx->stream));
   PrrluArgs a{};
   a.M = (const double*)M;
+  a.cplx = dtype == ACI_C128 ? 1 : 0;
   a.m = dconst(m);
   a.n = dconst(n);
   a.ldm = dconst(ldm);
@@ -1891,10 +1914,11 @@ int aci_gather(aci_ctx* ctx, int32_t dtype, int32_t side, const void* src, int32
                const int32_t* idx, const int32_t* rank, void* out, int32_t ld_out) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
-  if (dtype != ACI_F64) return set_err(ctx, ACI_E_DTYPE, "only ACI_F64");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
   if (!src || !idx || !rank || !out) return set_err(ctx, ACI_E_INVALID, "null pointer");
   if (h < 1 || w < 1 || ld_src < w || ld_out < 1 || (side != 0 && side != 1)) return set_err(ctx, ACI_E_INVALID, "bad dims");
   GatherArgs a{};
+  a.esz = dtype == ACI_C128 ? 2 : 1;
   a.count = 1;
   a.side = side;
   a.idx = idx;

@@ -16,6 +16,15 @@
 //   hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
 //   accumulation (about 16 significant bits per operand).
 //
+// Complex operands (interleaved re, im) use the same kernels on real views:
+// A (m x K complex) is read as the real m x 2K matrix [re im re im ...], and
+// B (K x N complex) is expanded while staged into the real 2K x 2N matrix
+// with b[2t][2j] = re, b[2t][2j+1] = im, b[2t+1][2j] = -im,
+// b[2t+1][2j+1] = re of B[t][j], so the real product is C interleaved (the
+// same 8 mkn real flops as a complex GEMM).  An f that couples re and im
+// (products of several terms, |z|^2 z) pairs each accumulator value with the
+// one of the neighbouring lane, which holds the other part of the element.
+//
 // Lane layouts (measured on gfx950), lane l, r = l % 16, g = l / 16:
 //   f64 16x16x4:   A[r][g], B[g][r];            acc item v = C[g + 4v][r]
 //   f32 16x16x4:   A[r][g], B[g][r];            acc item v = C[4g + v][r]
@@ -38,13 +47,41 @@ __device__ __forceinline__ v4d combine(v4d r, v4d a) {
   return r + a;  // OP_SUM
 }
 
+// Operand B entry (k, c) of the real view: the element itself, or for
+// complex B the expanded 2K x 2N entry described above.
+template <bool CPLX>
+__device__ __forceinline__ double b_entry(const double* B, int ldb, int k, int c) {
+  if (!CPLX) return B[(size_t)k * ldb + c];
+  const double* e = B + 2 * ((size_t)(k >> 1) * ldb + (c >> 1));
+  const int s = k & 1, h = c & 1;
+  return s == 0 ? (h == 0 ? e[0] : e[1]) : (h == 0 ? -e[1] : e[0]);
+}
+
+// f applied to one accumulator value of a complex result, given the value
+// the neighbouring lane holds for the same element (even lane: real part).
 template <int OP>
+__device__ __forceinline__ double cplx_combine(double res, double res_o, double acc, double acc_o, bool even) {
+  const double rr = even ? res : res_o, ri = even ? res_o : res;
+  const double ar = even ? acc : acc_o, ai = even ? acc_o : acc;
+  if (OP == OP_PRODUCT) return even ? rr * ar - ri * ai : rr * ai + ri * ar;
+  return res + acc;
+}
+template <bool CPLX>
+__device__ __forceinline__ double abs2_mul(double x, double x_o, bool even) {
+  if (!CPLX) return (x * x) * x;
+  const double re = even ? x : x_o, im = even ? x_o : x;
+  const double a = re * re + im * im;
+  return a * x;
+}
+
+template <int OP, bool CPLX>
 __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
   __shared__ double sA[KC * LDA_S];
   __shared__ double sB[KC * LDB_S];
+  constexpr int W = CPLX ? 2 : 1;
   const Group& g = args.g[blockIdx.z];
   const int M = dget(g.M);
-  const int N = dget(g.N);
+  const int N = W * dget(g.N);
   const int m0 = blockIdx.y * TM;
   const int n0 = blockIdx.x * TN;
   if (m0 >= M || n0 >= N) return;
@@ -54,11 +91,12 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, lk = lane >> 4;
 
+  const bool even = (lr & 1) == 0;
   v4d res[2][2];
   for (int t = 0; t < g.nterm; ++t) {
     const Term& T = g.t[t];
-    const int K = dget(T.K);
-    const int lda = dget(T.lda);
+    const int K = W * dget(T.K);
+    const int lda = W * dget(T.lda);
     const int ldb = dget(T.ldb);
     v4d acc[2][2];
 #pragma unroll
@@ -89,7 +127,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
         for (int e = 0; e < 4; ++e) {
           const int gc = n0 + cq + e;
           double v = 0.0;
-          if (gk < K && gc < N) v = T.B[(size_t)gk * ldb + gc];
+          if (gk < K && gc < N) v = b_entry<CPLX>(T.B, ldb, gk, gc);
           sB[kk * LDB_S + cq + e] = v;
         }
       }
@@ -115,16 +153,28 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         if (OP == OP_ABS2_MUL) {
-          res[i][j] = (acc[i][j] * acc[i][j]) * acc[i][j];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double x = acc[i][j][v];
+            const double xo = CPLX ? __shfl_xor(x, 1) : x;
+            res[i][j][v] = abs2_mul<CPLX>(x, xo, even);
+          }
         } else if (OP == OP_NONE || t == 0) {
           res[i][j] = acc[i][j];
+        } else if (CPLX && OP == OP_PRODUCT) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double r0 = res[i][j][v], a0 = acc[i][j][v];
+            const double ro = __shfl_xor(r0, 1), ao = __shfl_xor(a0, 1);
+            res[i][j][v] = cplx_combine<OP>(r0, ro, a0, ao, even);
+          }
         } else {
           res[i][j] = combine<OP>(res[i][j], acc[i][j]);
         }
       }
   }
 
-  const int ldc = dget(g.ldc);
+  const int ldc = W * dget(g.ldc);
   bool bad = false;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -173,12 +223,13 @@ struct LpTiles<PREC_BF16X3> {
   unsigned short Bh[TN * LDH], Bl[TN * LDH];   // [col][k]
 };
 
-template <int OP, int PREC>
+template <int OP, int PREC, bool CPLX>
 __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
   __shared__ LpTiles<PREC> sh;
+  constexpr int W = CPLX ? 2 : 1;
   const Group& g = args.g[blockIdx.z];
   const int M = dget(g.M);
-  const int N = dget(g.N);
+  const int N = W * dget(g.N);
   const int m0 = blockIdx.y * TM;
   const int n0 = blockIdx.x * TN;
   if (m0 >= M || n0 >= N) return;
@@ -187,12 +238,13 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, lg = lane >> 4;
+  const bool even = (lr & 1) == 0;
 
   v4d res[2][2];
   for (int t = 0; t < g.nterm; ++t) {
     const Term& T = g.t[t];
-    const int K = dget(T.K);
-    const int lda = dget(T.lda);
+    const int K = W * dget(T.K);
+    const int lda = W * dget(T.lda);
     const int ldb = dget(T.ldb);
     v4f acc[2][2];
 #pragma unroll
@@ -211,7 +263,7 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
         const int gr = m0 + ar, gk = k0 + ak + e;
         av[e] = (gr < M && gk < K) ? T.A[(size_t)gr * lda + gk] : 0.0;
         const int hk = k0 + bk, gc = n0 + bc + e;
-        bv[e] = (hk < K && gc < N) ? T.B[(size_t)hk * ldb + gc] : 0.0;
+        bv[e] = (hk < K && gc < N) ? b_entry<CPLX>(T.B, ldb, hk, gc) : 0.0;
       }
       if (PREC == PREC_FP32) {
         auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
@@ -283,16 +335,28 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
       for (int j = 0; j < 2; ++j) {
         const v4d x = v4d{(double)acc[i][j][0], (double)acc[i][j][1], (double)acc[i][j][2], (double)acc[i][j][3]};
         if (OP == OP_ABS2_MUL) {
-          res[i][j] = (x * x) * x;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double xv = x[v];
+            const double xo = CPLX ? __shfl_xor(xv, 1) : xv;
+            res[i][j][v] = abs2_mul<CPLX>(xv, xo, even);
+          }
         } else if (OP == OP_NONE || t == 0) {
           res[i][j] = x;
+        } else if (CPLX && OP == OP_PRODUCT) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double r0 = res[i][j][v], a0 = x[v];
+            const double ro = __shfl_xor(r0, 1), ao = __shfl_xor(a0, 1);
+            res[i][j][v] = cplx_combine<OP>(r0, ro, a0, ao, even);
+          }
         } else {
           res[i][j] = combine<OP>(res[i][j], x);
         }
       }
   }
 
-  const int ldc = dget(g.ldc);
+  const int ldc = W * dget(g.ldc);
   bool bad = false;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -311,13 +375,25 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
   if (OP != OP_NONE && bad && args.err) atomicOr(args.err, ERR_NONFINITE);
 }
 
-template <int PREC>
+template <int PREC, bool CPLX>
 hipError_t launch_prec(int op, const ContractArgs& args, dim3 grid, dim3 block, hipStream_t s) {
   switch (op) {
-    case OP_NONE: hipLaunchKernelGGL((contract_lp_kernel<OP_NONE, PREC>), grid, block, 0, s, args); break;
-    case OP_PRODUCT: hipLaunchKernelGGL((contract_lp_kernel<OP_PRODUCT, PREC>), grid, block, 0, s, args); break;
-    case OP_SUM: hipLaunchKernelGGL((contract_lp_kernel<OP_SUM, PREC>), grid, block, 0, s, args); break;
-    case OP_ABS2_MUL: hipLaunchKernelGGL((contract_lp_kernel<OP_ABS2_MUL, PREC>), grid, block, 0, s, args); break;
+    case OP_NONE: hipLaunchKernelGGL((contract_lp_kernel<OP_NONE, PREC, CPLX>), grid, block, 0, s, args); break;
+    case OP_PRODUCT: hipLaunchKernelGGL((contract_lp_kernel<OP_PRODUCT, PREC, CPLX>), grid, block, 0, s, args); break;
+    case OP_SUM: hipLaunchKernelGGL((contract_lp_kernel<OP_SUM, PREC, CPLX>), grid, block, 0, s, args); break;
+    case OP_ABS2_MUL: hipLaunchKernelGGL((contract_lp_kernel<OP_ABS2_MUL, PREC, CPLX>), grid, block, 0, s, args); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <bool CPLX>
+hipError_t launch_fp64(int op, const ContractArgs& args, dim3 grid, dim3 block, hipStream_t s) {
+  switch (op) {
+    case OP_NONE: hipLaunchKernelGGL((contract_kernel<OP_NONE, CPLX>), grid, block, 0, s, args); break;
+    case OP_PRODUCT: hipLaunchKernelGGL((contract_kernel<OP_PRODUCT, CPLX>), grid, block, 0, s, args); break;
+    case OP_SUM: hipLaunchKernelGGL((contract_kernel<OP_SUM, CPLX>), grid, block, 0, s, args); break;
+    case OP_ABS2_MUL: hipLaunchKernelGGL((contract_kernel<OP_ABS2_MUL, CPLX>), grid, block, 0, s, args); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -327,19 +403,16 @@ hipError_t launch_prec(int op, const ContractArgs& args, dim3 grid, dim3 block, 
 
 hipError_t launch_contract(int op, int prec, const ContractArgs& args, int mmax, int nmax, hipStream_t s) {
   if (mmax <= 0 || nmax <= 0 || args.ngroup <= 0) return hipSuccess;
-  dim3 grid((nmax + TN - 1) / TN, (mmax + TM - 1) / TM, args.ngroup);
+  const bool cplx = args.cplx != 0;
+  const int nreal = cplx ? 2 * nmax : nmax;
+  dim3 grid((nreal + TN - 1) / TN, (mmax + TM - 1) / TM, args.ngroup);
   dim3 block(256);
-  if (prec == PREC_FP32) return launch_prec<PREC_FP32>(op, args, grid, block, s);
-  if (prec == PREC_BF16X3) return launch_prec<PREC_BF16X3>(op, args, grid, block, s);
+  if (prec == PREC_FP32) return cplx ? launch_prec<PREC_FP32, true>(op, args, grid, block, s)
+                                     : launch_prec<PREC_FP32, false>(op, args, grid, block, s);
+  if (prec == PREC_BF16X3) return cplx ? launch_prec<PREC_BF16X3, true>(op, args, grid, block, s)
+                                       : launch_prec<PREC_BF16X3, false>(op, args, grid, block, s);
   if (prec != PREC_FP64) return hipErrorInvalidValue;
-  switch (op) {
-    case OP_NONE: hipLaunchKernelGGL(contract_kernel<OP_NONE>, grid, block, 0, s, args); break;
-    case OP_PRODUCT: hipLaunchKernelGGL(contract_kernel<OP_PRODUCT>, grid, block, 0, s, args); break;
-    case OP_SUM: hipLaunchKernelGGL(contract_kernel<OP_SUM>, grid, block, 0, s, args); break;
-    case OP_ABS2_MUL: hipLaunchKernelGGL(contract_kernel<OP_ABS2_MUL>, grid, block, 0, s, args); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return cplx ? launch_fp64<true>(op, args, grid, block, s) : launch_fp64<false>(op, args, grid, block, s);
 }
 
 }  // namespace aci

@@ -13,9 +13,11 @@ namespace {
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
   const GatherItem& it = a.it[blockIdx.z];
   const int r = *a.rank;
+  // elements of esz doubles (2: complex, interleaved re, im)
+  const int es = a.esz > 1 ? a.esz : 1;
   const int ext = dget(it.extent);
-  const int lds = dget(it.ld_src);
-  const int ldd = dget(it.ld_dst);
+  const int lds = dget(it.ld_src) * es;
+  const int ldd = dget(it.ld_dst) * es;
   const int nsrc = dget(it.src_n);
   if (a.side == 0) {
     // one row per (k), threads along the row
@@ -26,7 +28,7 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
       if (threadIdx.x == 0 && a.err) atomicOr(a.err, ERR_LIMIT);
       return;
     }
-    for (int c = blockIdx.y * 256 + threadIdx.x; c < ext; c += gridDim.y * 256)
+    for (int c = blockIdx.y * 256 + threadIdx.x; c < ext * es; c += gridDim.y * 256)
       it.dst[(size_t)k * ldd + c] = it.src[(size_t)src_row * lds + c];
   } else {
     // threads along k (destination row is contiguous in k)
@@ -38,7 +40,7 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
       return;
     }
     for (int h = blockIdx.y; h < ext; h += gridDim.y)
-      it.dst[(size_t)h * ldd + k] = it.src[(size_t)h * lds + sc];
+      for (int e = 0; e < es; ++e) it.dst[(size_t)h * ldd + (size_t)k * es + e] = it.src[(size_t)h * lds + (size_t)sc * es + e];
   }
 }
 

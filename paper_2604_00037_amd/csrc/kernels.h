@@ -30,6 +30,8 @@ struct ContractArgs {
   Group g[ACI_MAX_INPUTS];
   int ngroup;
   int* err;  // ERR_NONFINITE is or-ed in when an output is NaN/Inf (may be null)
+  int cplx;  // 1: operands and result are complex (interleaved re, im); dims
+             // and leading dimensions count complex elements
 };
 
 // op: OP_NONE (single term, plain GEMM), OP_PRODUCT, OP_SUM, OP_ABS2_MUL.
@@ -71,19 +73,21 @@ struct PrrluArgs {
   uint32_t* epoch;    // device word holding flag_base (nullptr: use flag_base);
                       // the kernel advances it for the next launch
   const int* skip;    // optional: the launch does nothing when *skip != 0
+  int cplx;           // 1: complex entries (interleaved re, im): M, Y and the
+                      // leading dimensions count complex elements
 };
 
 // Chooses the workgroup shape for mmax x nmax and launches.
 hipError_t launch_prrlu(const PrrluArgs& a, int mmax, int nmax, hipStream_t s);
 // Exchange-buffer words needed for matrices up to mmax x nmax.
-size_t prrlu_xbuf_words(int mmax, int nmax);
-// Instance launch_prrlu picks for these bounds: 10000*solo + 100*RS + CS, or
-// -1 if the bounds are out of range.
-int prrlu_variant(int mmax, int nmax, int max_groups = 0);
+size_t prrlu_xbuf_words(int mmax, int nmax, int cplx = 0);
+// Instance launch_prrlu picks for these bounds: 100000*cplx + 10000*solo +
+// 100*RS + CS, or -1 if the bounds are out of range.
+int prrlu_variant(int mmax, int nmax, int max_groups = 0, int cplx = 0);
 // CUs of one XCD (the most groups one LDU launch places on an XCD)
 int prrlu_xcd_cus();
 // Cooperating groups (P) launch_prrlu uses for these bounds and group cap.
-int prrlu_groups(int mmax, int nmax, int max_groups);
+int prrlu_groups(int mmax, int nmax, int max_groups, int cplx = 0);
 // flag_base advance per launch (steps and the XCD check stay below it)
 constexpr uint32_t kFlagStride = 2048;
 
@@ -202,6 +206,7 @@ struct GatherArgs {
   const int* idx;
   const int* rank;   // number of gathered rows/columns (device)
   int* err;          // ERR_LIMIT is or-ed in for an index out of range (may be null)
+  int esz;           // doubles per element (1 real, 2 complex; 0 counts as 1)
 };
 hipError_t launch_gather(const GatherArgs& a, int rmax, int extent_max, hipStream_t s);
 

@@ -166,7 +166,21 @@ constexpr int kCandWords = 256;
 // a step index no pivot step uses (steps stay below ACI_MAX_MATRIX)
 constexpr uint32_t kXccFlagOffset = 1536;
 
-template <int RS, int CS, bool SOLO>
+// Squared magnitude of a complex entry (two roundings, no fused multiply-add:
+// the key of the complex pivot search).
+__device__ __forceinline__ double cabs2(double re, double im) {
+  const double a = re * re;
+  const double b = im * im;
+  return a + b;
+}
+
+// Complex entries (CX) are held as two register arrays, real and imaginary
+// parts; the search key is re^2 + im^2 and the pivot magnitude its square
+// root; the elimination spells the complex arithmetic out as
+//   l = s_q conj(pi) / |pi|^2,  s_j -= l u_j  (re: (l.re u.re - l.im u.im),
+//   im: (l.re u.im + l.im u.re)),
+// every product and sum rounded on its own.
+template <int RS, int CS, bool SOLO, bool CX>
 __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
   if ((int)(blockIdx.x % a.stride) != (a.stride == 8 ? a.xcd : 0)) return;
   // a proposal already supplied this factorisation (every group reads the
@@ -176,6 +190,7 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
   // flags of this launch: step k uses fbase + k
   const uint32_t fbase = a.epoch ? __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                  : a.flag_base;
+  constexpr int EW = CX ? 2 : 1;   // doubles per entry
   const int P = a.P;
   const int m = dget(a.m), n = dget(a.n), ldm = dget(a.ldm);
   const int kmax = m < n ? m : n;
@@ -184,8 +199,9 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
   const bool needY = a.Y != nullptr;
   const int ldy = needY ? dget(a.ldy) : 0;
   // slot of group g in the exchange buffer: words [g per, g per + 3) hold the
-  // candidate (key lo, key hi, index), then 2n words its row (lo, hi)
-  const int per = 3 + 2 * n;
+  // candidate (key lo, key hi, index), then 2 EW n words its row (lo, hi of
+  // each double)
+  const int per = 3 + 2 * EW * n;
 
   __shared__ double red_k[2][WAVES];
   __shared__ int red_i[2][WAVES];
@@ -194,6 +210,7 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
   uint32_t* xrow = xs + kCandWords;
 
   double s[RS][CS];
+  double si[CX ? RS : 1][CX ? CS : 1];
   // row slot r of this wave holds global row w + P (wv + 4 r).  Row states
   // are wave-uniform bit sets: alive rows take part in the pivot search and
   // the Schur update, B rows (right-to-left updates only) in the
@@ -205,7 +222,7 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
 #pragma unroll
   for (int b = 0; b < CS; ++b) cv[b] = (lane + 64 * b) < n;
 
-  // rm[r]: largest |entry| of row slot r in this lane (-1 when the row is not
+  // rm[r]: largest key of row slot r in this lane (-1 when the row is not
   // alive).  Entries of columns >= n and of eliminated columns are zero.
   double rm[RS];
 #pragma unroll
@@ -217,10 +234,14 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
 #pragma unroll
     for (int b = 0; b < CS; ++b) {
       const int j = lane + 64 * b;
-      double v = 0.0;
-      if (i < m && cv[b]) v = a.M[(size_t)i * ldm + j];
+      double v = 0.0, vi = 0.0;
+      if (i < m && cv[b]) {
+        v = a.M[EW * ((size_t)i * ldm + j)];
+        if constexpr (CX) vi = a.M[2 * ((size_t)i * ldm + j) + 1];
+      }
       s[r][b] = v;
-      if (i < m) rm[r] = fmax(rm[r], fabs(v));
+      if constexpr (CX) si[r][b] = vi;
+      if (i < m) rm[r] = fmax(rm[r], CX ? cabs2(v, vi) : fabs(v));
     }
   }
 
@@ -280,8 +301,10 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
       if (!found && __ballot(rm[r] == bk) != 0) {
         if (rm[r] == bk) {
 #pragma unroll
-          for (int b = CS - 1; b >= 0; --b)
-            if (fabs(s[r][b]) == bk) bi = ((row0 + rstride * r) << 16) | (lane + 64 * b);
+          for (int b = CS - 1; b >= 0; --b) {
+            const double kb = CX ? cabs2(s[r][b], si[CX ? r : 0][CX ? b : 0]) : fabs(s[r][b]);
+            if (kb == bk) bi = ((row0 + rstride * r) << 16) | (lane + 64 * b);
+          }
         }
         found = true;
       }
@@ -305,10 +328,11 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
       break;
     }
 
-    // ---- global winner (v, p, q) and pivot row u
+    // ---- global winner (key, p, q) and pivot row u (+ ui)
     double v;
     int widx;
     double u[CS];
+    double ui[CX ? CS : 1];
     if (SOLO) {
       double* srow = reinterpret_cast<double*>(xrow);
       v = ck;
@@ -321,13 +345,19 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
           for (int r = 0; r < RS; ++r)
             if (r == r0) {
 #pragma unroll
-              for (int b = 0; b < CS; ++b) srow[lane + 64 * b] = s[r][b];
+              for (int b = 0; b < CS; ++b) {
+                srow[EW * (lane + 64 * b)] = s[r][b];
+                if constexpr (CX) srow[2 * (lane + 64 * b) + 1] = si[r][b];
+              }
             }
         }
       }
       __syncthreads();
 #pragma unroll
-      for (int b = 0; b < CS; ++b) u[b] = srow[lane + 64 * b];
+      for (int b = 0; b < CS; ++b) {
+        u[b] = srow[EW * (lane + 64 * b)];
+        if constexpr (CX) ui[b] = srow[2 * (lane + 64 * b) + 1];
+      }
     } else {
       const uint32_t flag = fbase + (uint32_t)k;
       uint64_t* slot_base = a.xbuf + (size_t)par * P * a.xwords;
@@ -347,8 +377,12 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
               for (int b = 0; b < CS; ++b)
                 if (cv[b]) {
                   const int j = lane + 64 * b;
-                  xw_put(mine + 3 + 2 * j, lo32(s[r][b]), flag, same_xcd);
-                  xw_put(mine + 4 + 2 * j, hi32(s[r][b]), flag, same_xcd);
+                  xw_put(mine + 3 + 2 * EW * j, lo32(s[r][b]), flag, same_xcd);
+                  xw_put(mine + 4 + 2 * EW * j, hi32(s[r][b]), flag, same_xcd);
+                  if constexpr (CX) {
+                    xw_put(mine + 5 + 4 * j, lo32(si[r][b]), flag, same_xcd);
+                    xw_put(mine + 6 + 4 * j, hi32(si[r][b]), flag, same_xcd);
+                  }
                 }
             }
         }
@@ -393,23 +427,29 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
       }
       // round trip 2: the winner's row (already published with its candidate)
       const int wg = (widx >> 16) % P;
-      ok = poll_words<(128 * CS + NT - 1) / NT>(slot_base + (size_t)wg * per + 3, 2 * n, flag, a.abort_word,
-                                                a.spin_limit, xrow);
+      ok = poll_words<(128 * EW * CS + NT - 1) / NT>(slot_base + (size_t)wg * per + 3, 2 * EW * n, flag,
+                                                     a.abort_word, a.spin_limit, xrow);
       if (!ok) failed = true;
       __syncthreads();
 #pragma unroll
       for (int b = 0; b < CS; ++b) {
         const int j = lane + 64 * b;
-        u[b] = cv[b] ? join64(xrow[2 * j], xrow[2 * j + 1]) : 0.0;
+        u[b] = cv[b] ? join64(xrow[2 * EW * j], xrow[2 * EW * j + 1]) : 0.0;
+        if constexpr (CX) ui[b] = cv[b] ? join64(xrow[4 * j + 2], xrow[4 * j + 3]) : 0.0;
       }
       if (failed) {
         v = 0.0;
         widx = 0;
 #pragma unroll
-        for (int b = 0; b < CS; ++b) u[b] = 0.0;
+        for (int b = 0; b < CS; ++b) {
+          u[b] = 0.0;
+          if constexpr (CX) ui[b] = 0.0;
+        }
         if (threadIdx.x == 0 && a.err) atomicOr(a.err, ERR_TIMEOUT);
       }
     }
+    // pivot magnitude: the key itself (real) or its square root (complex)
+    if constexpr (CX) v = sqrt(v);
 
     const int p = widx >> 16;
     const int q = widx & 0xffff;
@@ -426,11 +466,13 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
       break;
     }
     const double piv = lane_pick<CS>(u, qb, ql);
+    double pivi = 0.0;
+    if constexpr (CX) pivi = lane_pick<CS>(ui, qb, ql);
     if (w == 0 && threadIdx.x == 0) {
       a.rows[k] = p;
       a.cols[k] = q;
     }
-    if (piv == 0.0) {
+    if (piv == 0.0 && pivi == 0.0) {
       // all-zero matrix (only possible at k == 0): one pivot at the tie-break
       // cell, B = unit row e_q, error 0
 #pragma unroll
@@ -439,21 +481,25 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
           brows |= 1u << r;
           pstep[r] = 0;
 #pragma unroll
-          for (int b = 0; b < CS; ++b) s[r][b] = (lane + 64 * b == q) ? 1.0 : 0.0;
+          for (int b = 0; b < CS; ++b) {
+            s[r][b] = (lane + 64 * b == q) ? 1.0 : 0.0;
+            if constexpr (CX) si[r][b] = 0.0;
+          }
         }
       eps = 0.0;
       final_rank = 1;
       break;
     }
+    const double den = CX ? cabs2(piv, pivi) : 0.0;
 
     // ---- elimination, fused with the next step's local maxima
     // slot of the pivot row in this wave (-1: another wave or group owns it)
     const int rp = ((p - row0) % rstride == 0 && p >= row0) ? (p - row0) / rstride : -1;
     // multipliers s_iq / pivot of the rows: one vector division with lane r
     // dividing row r's entry (correctly rounded, like a scalar division)
-    double quo;
+    double quo, quoi = 0.0;
     {
-      double num = 0.0;
+      double num = 0.0, numi = 0.0;
 #pragma unroll
       for (int c = 0; c < CS; ++c)
         if (c == qb) {
@@ -461,9 +507,21 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
           for (int r = 0; r < RS; ++r) {
             const double sq = readlane_f64(s[r][c], ql);
             num = lane == r ? sq : num;
+            if constexpr (CX) {
+              const double sqi = readlane_f64(si[r][c], ql);
+              numi = lane == r ? sqi : numi;
+            }
           }
         }
-      quo = num / piv;
+      if constexpr (CX) {
+        // (num + i numi) conj(pivot) / |pivot|^2
+        const double a1 = num * piv, a2 = numi * pivi;
+        const double b1 = numi * piv, b2 = num * pivi;
+        quo = (a1 + a2) / den;
+        quoi = (b1 - b2) / den;
+      } else {
+        quo = num / piv;
+      }
     }
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
@@ -475,22 +533,45 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
             brows |= 1u << r;
             pstep[r] = k;
 #pragma unroll
-            for (int b = 0; b < CS; ++b) s[r][b] = s[r][b] / piv;
+            for (int b = 0; b < CS; ++b) {
+              if constexpr (CX) {
+                const double sr = s[r][b], sm = si[r][b];
+                const double a1 = sr * piv, a2 = sm * pivi, b1 = sm * piv, b2 = sr * pivi;
+                s[r][b] = (a1 + a2) / den;
+                si[r][b] = (b1 - b2) / den;
+              } else {
+                s[r][b] = s[r][b] / piv;
+              }
+            }
           }
         } else {
           const double c = readlane_f64(quo, r);
+          double cim = 0.0;
+          if constexpr (CX) cim = readlane_f64(quoi, r);
 #pragma unroll
           for (int b = 0; b < CS; ++b) {
-            const double t = c * u[b];
-            s[r][b] = s[r][b] - t;
+            if constexpr (CX) {
+              const double t1 = c * u[b], t2 = cim * ui[b];
+              const double tr = t1 - t2;
+              const double t3 = c * ui[b], t4 = cim * u[b];
+              const double tim = t3 + t4;
+              s[r][b] = s[r][b] - tr;
+              si[r][b] = si[r][b] - tim;
+            } else {
+              const double t = c * u[b];
+              s[r][b] = s[r][b] - t;
+            }
           }
           // eliminated column q: exactly zero from now on
 #pragma unroll
           for (int b = 0; b < CS; ++b)
-            if (b == qb) s[r][b] = lane == ql ? 0.0 : s[r][b];
+            if (b == qb) {
+              s[r][b] = lane == ql ? 0.0 : s[r][b];
+              if constexpr (CX) si[r][b] = lane == ql ? 0.0 : si[r][b];
+            }
           double mx = 0.0;
 #pragma unroll
-          for (int b = 0; b < CS; ++b) mx = fmax(mx, fabs(s[r][b]));
+          for (int b = 0; b < CS; ++b) mx = fmax(mx, CX ? cabs2(s[r][b], si[CX ? r : 0][CX ? b : 0]) : fabs(s[r][b]));
           rm[r] = mx;
         }
       }
@@ -501,15 +582,37 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
       // rows of B chosen at earlier steps: reduce them against the new pivot
       // row normalised by the pivot (Gauss-Jordan), so that B[:, J] = I
 #pragma unroll
-      for (int b = 0; b < CS; ++b) u[b] = u[b] / piv;
+      for (int b = 0; b < CS; ++b) {
+        if constexpr (CX) {
+          const double ur = u[b], um = ui[b];
+          const double a1 = ur * piv, a2 = um * pivi, b1 = um * piv, b2 = ur * pivi;
+          u[b] = (a1 + a2) / den;
+          ui[b] = (b1 - b2) / den;
+        } else {
+          u[b] = u[b] / piv;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < RS; ++r) {
         if (((brows >> r) & 1u) && r != rp) {
           const double c = lane_pick<CS>(s[r], qb, ql);
+          if constexpr (CX) {
+            const double cim = lane_pick<CS>(si[r], qb, ql);
 #pragma unroll
-          for (int b = 0; b < CS; ++b) {
-            const double t = c * u[b];
-            s[r][b] = s[r][b] - t;
+            for (int b = 0; b < CS; ++b) {
+              const double t1 = c * u[b], t2 = cim * ui[b];
+              const double tr = t1 - t2;
+              const double t3 = c * ui[b], t4 = cim * u[b];
+              const double tim = t3 + t4;
+              s[r][b] = s[r][b] - tr;
+              si[r][b] = si[r][b] - tim;
+            }
+          } else {
+#pragma unroll
+            for (int b = 0; b < CS; ++b) {
+              const double t = c * u[b];
+              s[r][b] = s[r][b] - t;
+            }
           }
         }
       }
@@ -530,7 +633,11 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
       if (((brows >> r) & 1u) && pstep[r] >= 0 && pstep[r] < final_rank) {
 #pragma unroll
         for (int b = 0; b < CS; ++b)
-          if (cv[b]) a.Y[(size_t)pstep[r] * ldy + lane + 64 * b] = s[r][b];
+          if (cv[b]) {
+            const size_t o = (size_t)pstep[r] * ldy + lane + 64 * b;
+            a.Y[EW * o] = s[r][b];
+            if constexpr (CX) a.Y[2 * o + 1] = si[r][b];
+          }
       }
   }
   if (w == 0 && threadIdx.x == 0) {
@@ -622,9 +729,10 @@ hipError_t do_launch(const void* fn, dim3 grid, size_t lds, PrrluArgs& args, hip
   return e;
 }
 
-template <int RS, int CS>
+template <int RS, int CS, bool CX>
 hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
   PrrluArgs args = a;
+  constexpr int EW = CX ? 2 : 1;
   // xcd < 0 ("spread"): exactly P workgroups, dealt round robin over the
   // XCDs, for launches that overlap with other spinning launches: a launch
   // of 8P workgroups would also need CUs on the other XCDs for its idle
@@ -633,11 +741,11 @@ hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
   if (a.P == 1) {
     // one group: 8 workgroups of which the one on the requested XCD runs
     args.stride = (a.cooperative || spread) ? 1 : 8;
-    const size_t lds = (size_t)(kCandWords + 128 * CS) * 4;
-    return do_launch((const void*)prrlu_kernel<RS, CS, true>, dim3(args.stride), lds, args, s);
+    const size_t lds = (size_t)(kCandWords + 128 * EW * CS) * 4;
+    return do_launch((const void*)prrlu_kernel<RS, CS, true, CX>, dim3(args.stride), lds, args, s);
   }
-  const void* fn = (const void*)prrlu_kernel<RS, CS, false>;
-  const size_t lds = group_lds((size_t)(kCandWords + 128 * CS) * 4);
+  const void* fn = (const void*)prrlu_kernel<RS, CS, false, CX>;
+  const size_t lds = group_lds((size_t)(kCandWords + 128 * EW * CS) * 4);
   if (spread) {
     args.stride = 1;
     return do_launch(fn, dim3(args.P), lds, args, s);
@@ -652,16 +760,25 @@ hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
   return do_launch(fn, dim3(args.P * args.stride), lds, args, s);
 }
 
-const Shape* pick_shape(int nmax) {
+// Register shapes of complex matrices (two doubles per entry).
+constexpr Shape kShapesC[] = {{1, 8}, {2, 8}, {4, 8}, {8, 4}, {16, 4}};
+
+const Shape* pick_shape(int nmax, bool cx = false) {
+  if (cx) {
+    for (const Shape& sh : kShapesC)
+      if (64 * sh.cs >= nmax) return &sh;
+    return nullptr;
+  }
   for (const Shape& sh : kShapes)
     if (64 * sh.cs >= nmax) return &sh;
   return nullptr;
 }
 
 // Rows per group: the fewest register slots that keep the group count within
-// one XCD (one group per CU), unless one group can hold all rows.  More groups spread the elimination over more
-// CUs; past one XCD the exchange has to go through device-scope memory, which
-// costs more than the shorter update saves.
+// one XCD (one group per CU), unless one group can hold all rows.  More
+// groups spread the elimination over more CUs; past one XCD the exchange has
+// to go through device-scope memory, which costs more than the shorter
+// update saves.
 int pick_rs(const Shape& sh, int mmax, int max_groups) {
   // one workgroup when the rows fit in its registers: the exchange then
   // stays in LDS, which beats any split of so few rows over several CUs
@@ -675,78 +792,109 @@ int pick_rs(const Shape& sh, int mmax, int max_groups) {
   return rs;
 }
 
+template <bool CX>
+hipError_t launch_instance(const PrrluArgs& a, int cs, int rs, hipStream_t s) {
+  if (CX) {
+    switch (cs * 32 + rs) {
+      case 1 * 32 + 1: return launch_shape<1, 1, true>(a, s);
+      case 1 * 32 + 2: return launch_shape<2, 1, true>(a, s);
+      case 1 * 32 + 4: return launch_shape<4, 1, true>(a, s);
+      case 1 * 32 + 8: return launch_shape<8, 1, true>(a, s);
+      case 2 * 32 + 1: return launch_shape<1, 2, true>(a, s);
+      case 2 * 32 + 2: return launch_shape<2, 2, true>(a, s);
+      case 2 * 32 + 4: return launch_shape<4, 2, true>(a, s);
+      case 2 * 32 + 8: return launch_shape<8, 2, true>(a, s);
+      case 4 * 32 + 1: return launch_shape<1, 4, true>(a, s);
+      case 4 * 32 + 2: return launch_shape<2, 4, true>(a, s);
+      case 4 * 32 + 4: return launch_shape<4, 4, true>(a, s);
+      case 4 * 32 + 8: return launch_shape<8, 4, true>(a, s);
+      case 8 * 32 + 1: return launch_shape<1, 8, true>(a, s);
+      case 8 * 32 + 2: return launch_shape<2, 8, true>(a, s);
+      case 8 * 32 + 4: return launch_shape<4, 8, true>(a, s);
+      case 16 * 32 + 1: return launch_shape<1, 16, true>(a, s);
+      case 16 * 32 + 2: return launch_shape<2, 16, true>(a, s);
+      case 16 * 32 + 4: return launch_shape<4, 16, true>(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (cs * 32 + rs) {
+    case 1 * 32 + 1: return launch_shape<1, 1, false>(a, s);
+    case 1 * 32 + 2: return launch_shape<2, 1, false>(a, s);
+    case 1 * 32 + 4: return launch_shape<4, 1, false>(a, s);
+    case 1 * 32 + 8: return launch_shape<8, 1, false>(a, s);
+    case 1 * 32 + 16: return launch_shape<16, 1, false>(a, s);
+    case 2 * 32 + 1: return launch_shape<1, 2, false>(a, s);
+    case 2 * 32 + 2: return launch_shape<2, 2, false>(a, s);
+    case 2 * 32 + 4: return launch_shape<4, 2, false>(a, s);
+    case 2 * 32 + 8: return launch_shape<8, 2, false>(a, s);
+    case 2 * 32 + 16: return launch_shape<16, 2, false>(a, s);
+    case 4 * 32 + 1: return launch_shape<1, 4, false>(a, s);
+    case 4 * 32 + 2: return launch_shape<2, 4, false>(a, s);
+    case 4 * 32 + 4: return launch_shape<4, 4, false>(a, s);
+    case 4 * 32 + 8: return launch_shape<8, 4, false>(a, s);
+    case 4 * 32 + 16: return launch_shape<16, 4, false>(a, s);
+    case 6 * 32 + 1: return launch_shape<1, 6, false>(a, s);
+    case 6 * 32 + 2: return launch_shape<2, 6, false>(a, s);
+    case 6 * 32 + 4: return launch_shape<4, 6, false>(a, s);
+    case 6 * 32 + 8: return launch_shape<8, 6, false>(a, s);
+    case 8 * 32 + 1: return launch_shape<1, 8, false>(a, s);
+    case 8 * 32 + 2: return launch_shape<2, 8, false>(a, s);
+    case 8 * 32 + 4: return launch_shape<4, 8, false>(a, s);
+    case 8 * 32 + 8: return launch_shape<8, 8, false>(a, s);
+    case 12 * 32 + 1: return launch_shape<1, 12, false>(a, s);
+    case 12 * 32 + 2: return launch_shape<2, 12, false>(a, s);
+    case 12 * 32 + 4: return launch_shape<4, 12, false>(a, s);
+    case 16 * 32 + 1: return launch_shape<1, 16, false>(a, s);
+    case 16 * 32 + 2: return launch_shape<2, 16, false>(a, s);
+    case 16 * 32 + 4: return launch_shape<4, 16, false>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 int prrlu_xcd_cus() { return cus_per_xcd(); }
 
-int prrlu_groups(int mmax, int nmax, int max_groups) {
+int prrlu_groups(int mmax, int nmax, int max_groups, int cplx) {
   if (mmax < 1 || nmax < 1 || mmax > ACI_MAX_MATRIX || nmax > ACI_MAX_MATRIX) return -1;
-  const Shape* sh = pick_shape(nmax);
+  const Shape* sh = pick_shape(nmax, cplx != 0);
   if (!sh) return -1;
   const int rs = pick_rs(*sh, mmax, max_groups);
   return (mmax + WAVES * rs - 1) / (WAVES * rs);
 }
 
-size_t prrlu_xbuf_words(int mmax, int nmax) {
-  // every launch uses at most 64 groups of at most 4 + 2n words per parity
+size_t prrlu_xbuf_words(int mmax, int nmax, int cplx) {
+  // every launch uses at most 64 groups of at most 4 + 2 EW n words per parity
   (void)mmax;
-  const Shape* sh = pick_shape(nmax < 1 ? 1 : nmax);
-  if (!sh) sh = &kShapes[sizeof(kShapes) / sizeof(kShapes[0]) - 1];
-  return (size_t)2 * 64 * (4 + 2 * 64 * sh->cs);
+  const int ew = cplx ? 2 : 1;
+  const Shape* sh = pick_shape(nmax < 1 ? 1 : nmax, cplx != 0);
+  if (!sh) sh = cplx ? &kShapesC[sizeof(kShapesC) / sizeof(kShapesC[0]) - 1]
+                     : &kShapes[sizeof(kShapes) / sizeof(kShapes[0]) - 1];
+  return (size_t)2 * 64 * (4 + 2 * ew * 64 * sh->cs);
 }
 
-int prrlu_variant(int mmax, int nmax, int max_groups) {
+int prrlu_variant(int mmax, int nmax, int max_groups, int cplx) {
   if (mmax < 1 || nmax < 1 || mmax > ACI_MAX_MATRIX || nmax > ACI_MAX_MATRIX) return -1;
-  const Shape* sh = pick_shape(nmax);
+  const Shape* sh = pick_shape(nmax, cplx != 0);
   if (!sh) return -1;
   const int rs = pick_rs(*sh, mmax, max_groups);
   const int P = (mmax + WAVES * rs - 1) / (WAVES * rs);
-  return (P == 1 ? 10000 : 0) + 100 * rs + sh->cs;
+  return (cplx ? 100000 : 0) + (P == 1 ? 10000 : 0) + 100 * rs + sh->cs;
 }
 
 hipError_t launch_prrlu(const PrrluArgs& a0, int mmax, int nmax, hipStream_t s) {
   if (mmax < 1 || nmax < 1 || mmax > ACI_MAX_MATRIX || nmax > ACI_MAX_MATRIX) return hipErrorInvalidValue;
-  const Shape* sh = pick_shape(nmax);
+  const bool cx = a0.cplx != 0;
+  const Shape* sh = pick_shape(nmax, cx);
   if (!sh) return hipErrorInvalidValue;
   PrrluArgs a = a0;
   const int rs = pick_rs(*sh, mmax, a.max_groups);
   a.P = (mmax + WAVES * rs - 1) / (WAVES * rs);
   if (a.xcd > 7 || (a.xcd < 0 && a.cooperative)) return hipErrorInvalidValue;
   if (a.P > 64) return hipErrorInvalidValue;
-  a.xwords = 4 + 2 * 64 * sh->cs;
+  a.xwords = 4 + 2 * (cx ? 2 : 1) * 64 * sh->cs;
   if ((size_t)2 * a.P * a.xwords > a.xbuf_words) return hipErrorInvalidValue;
-  switch (sh->cs * 32 + rs) {
-    case 1 * 32 + 1: return launch_shape<1, 1>(a, s);
-    case 1 * 32 + 2: return launch_shape<2, 1>(a, s);
-    case 1 * 32 + 4: return launch_shape<4, 1>(a, s);
-    case 1 * 32 + 8: return launch_shape<8, 1>(a, s);
-    case 1 * 32 + 16: return launch_shape<16, 1>(a, s);
-    case 2 * 32 + 1: return launch_shape<1, 2>(a, s);
-    case 2 * 32 + 2: return launch_shape<2, 2>(a, s);
-    case 2 * 32 + 4: return launch_shape<4, 2>(a, s);
-    case 2 * 32 + 8: return launch_shape<8, 2>(a, s);
-    case 2 * 32 + 16: return launch_shape<16, 2>(a, s);
-    case 4 * 32 + 1: return launch_shape<1, 4>(a, s);
-    case 4 * 32 + 2: return launch_shape<2, 4>(a, s);
-    case 4 * 32 + 4: return launch_shape<4, 4>(a, s);
-    case 4 * 32 + 8: return launch_shape<8, 4>(a, s);
-    case 4 * 32 + 16: return launch_shape<16, 4>(a, s);
-    case 6 * 32 + 1: return launch_shape<1, 6>(a, s);
-    case 6 * 32 + 2: return launch_shape<2, 6>(a, s);
-    case 6 * 32 + 4: return launch_shape<4, 6>(a, s);
-    case 6 * 32 + 8: return launch_shape<8, 6>(a, s);
-    case 8 * 32 + 1: return launch_shape<1, 8>(a, s);
-    case 8 * 32 + 2: return launch_shape<2, 8>(a, s);
-    case 8 * 32 + 4: return launch_shape<4, 8>(a, s);
-    case 8 * 32 + 8: return launch_shape<8, 8>(a, s);
-    case 12 * 32 + 1: return launch_shape<1, 12>(a, s);
-    case 12 * 32 + 2: return launch_shape<2, 12>(a, s);
-    case 12 * 32 + 4: return launch_shape<4, 12>(a, s);
-    case 16 * 32 + 1: return launch_shape<1, 16>(a, s);
-    case 16 * 32 + 2: return launch_shape<2, 16>(a, s);
-    case 16 * 32 + 4: return launch_shape<4, 16>(a, s);
-    default: return hipErrorInvalidValue;
-  }
+  return cx ? launch_instance<true>(a, sh->cs, rs, s) : launch_instance<false>(a, sh->cs, rs, s);
 }
 
 }  // namespace aci

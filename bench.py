@@ -300,6 +300,49 @@ def time_batched(aci, steps, warmup, device):
             "max_eps": st["max_eps"], "pivots_per_sweep": st["pivots"] / steps}
 
 
+def time_c5(aci, device, steps=2, warmup=1):
+    """Gross-Pitaevskii nonlinear term |psi|^2 psi: a complex field of 32
+    Gaussian vortex modes, each carrying a speckle of 16 random plane waves
+    (|k| <= 256 per axis), on the (2^14)^2 grid (2D quantics, L=28, d=2),
+    compressed to TT rank 512; ACI rank cap 512, tol 1e-8.  Sweeps/s with
+    complex128 contractions (FP64 matrix cores) and with complex64
+    contractions (FP32 matrix cores); the LDU stays complex128 in both."""
+    import torch
+    import workloads as W
+    t = time.perf_counter()
+    psi = W.gp_field(R=14, chi=512, seed=5001, device=device, waves=16, kmax=256)
+    torch.cuda.synchronize()
+    log(f"GP field compressed in {time.perf_counter() - t:.1f} s; ranks {max(c.shape[2] for c in psi)}")
+    cores = [[torch.from_numpy(c).to(device) for c in psi]]
+    out = {"workload": "|psi|^2 psi of a GP vortex field, 32 Gaussian modes x 16 plane waves (|k|<=256), "
+                       "(2^14)^2 grid, 2D quantics L=28 d=2, "
+                       f"TT rank {max(c.shape[2] for c in psi)}, ACI rank cap 512, tol 1e-8, complex"}
+    for prec, peak in (("fp64", PEAK_MFMA["fp64"]), ("fp32", PEAK_MFMA["fp32"])):
+        S = aci.Session(cores, "abs2_mul", 1e-8, 512, maxiter=steps + warmup, seed=INIT_SEED,
+                        fixed_sweeps=True, profile=True, precision=prec, low_precision_sweeps=-1)
+        S.sweep(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.sweep(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        S.close()
+        con_tf = st["flops"][1] / (st["kernel_ms"][1] * 1e-3) / 1e12 if st["kernel_ms"][1] else 0.0
+        out["complex128" if prec == "fp64" else "complex64"] = {
+            "sweeps_per_s": steps / el, "ms_per_sweep": 1e3 * el / steps,
+            "contraction_tflops": con_tf, "contraction_frac": con_tf / peak,
+            "contraction_ms_per_sweep": st["kernel_ms"][1] / steps,
+            "prrlu_ms_per_sweep": st["kernel_ms"][0] / steps,
+            "prrlu_us_per_pivot": 1e3 * st["kernel_ms"][0] / max(1, st["pivots"]),
+            "pivots_per_sweep": st["pivots"] / steps, "max_eps": st["max_eps"], "max_rank": max(st["ranks"])}
+        log(f"GP {prec} contractions: {steps} sweeps in {el:.3f} s; contractions {con_tf:.2f} TFLOP/s "
+            f"({con_tf / peak:.1%} of peak); LDU {out['complex128' if prec == 'fp64' else 'complex64']['prrlu_us_per_pivot']:.2f} "
+            f"us/pivot; max eps {st['max_eps']:.3e}")
+    del cores
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_proposal(aci, device, steps=300):
     """Learned pivot proposal: a scoring network trained on the GPU from the
     pivots of plain FP64 ACI (the oracle) on products of 3D Fourier fields
@@ -381,6 +424,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / BF16x3 contraction modes")
     ap.add_argument("--no-batched", action="store_true", help="skip the nine-product batch")
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--no-gp", action="store_true", help="skip the complex |psi|^2 psi workload")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print a summary of a rocprofv3 run of this script (needs --bench-json) and exit")
     ap.add_argument("--bench-json", metavar="FILE", help="output of the profiled run")
@@ -487,6 +531,8 @@ def main():
         out["batched"] = time_batched(aci, max(2, args.steps // 3), 1, dev)
     if not args.no_proposal:
         out["proposal"] = time_proposal(aci, dev)
+    if not args.no_gp:
+        out["gp"] = time_c5(aci, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u, v)
         out["speedup_vs_cpu_oracle"] = out["value"] / out["cpu_baseline"]["value"]

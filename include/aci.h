@@ -165,12 +165,13 @@ typedef struct {
 
 /* One kernel launch of a profiled aci_session_sweep call (options.profile).
  * kind: 0 LDU with full pivoting, 1 contraction, 2 frame gather.
- * variant: kind 0: 10000*solo + 100*RS + CS, the instance
- *          prrlu_kernel<RS, CS, solo> (RS row slots per wave, CS column
- *          slots per lane, solo = one workgroup); kind 1:
+ * variant: kind 0: 100000*complex + 10000*solo + 100*RS + CS, the instance
+ *          prrlu_kernel<RS, CS, solo, complex> (RS row slots per wave, CS
+ *          column slots per lane, solo = one workgroup), or 20001..20008 for
+ *          the learned-proposal kernels; kind 1: 1000*complex +
  *          100*precision + op + 1 with op the fused epilogue (-1 none, else
- *          aci_op): instance contract_kernel<op> (FP64) or
- *          contract_lp_kernel<op, precision>; kind 2: 0.
+ *          aci_op): instance contract_kernel<op, complex> (FP64) or
+ *          contract_lp_kernel<op, precision, complex>; kind 2: 0.
  * part: kind 1 only: 1 environment product, 2 two-site tensor (with f).
  * update: local update within its sweep, 0..2(L-1)-1 (left-to-right first).
  * flops: algorithmic flops of this launch, counted as in aci_sweep_stats. */

@@ -203,18 +203,21 @@ def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed
 def kernel_name(kind, variant):
     """Kernel instance behind a launch-log entry, spelled as in the device
     profiler's kernel names."""
-    if kind == 0 and variant >= 20000:
+    b = {0: "false", 1: "true"}
+    if kind == 0 and 20000 <= variant < 30000:
         return {20001: "features_kernel", 20002: "mlp_forward_kernel", 20003: "rook_kernel",
-                20004: "contract_kernel<-1>", 20005: "check_kernel", 20006: "commit_kernel",
+                20004: "contract_kernel<-1, false>", 20005: "check_kernel", 20006: "commit_kernel",
                 20007: "copy_rows_kernel", 20008: "rook_solve_kernel"}[variant]
     if kind == 0:
-        solo, rest = divmod(variant, 10000)
+        cx, rest = divmod(variant, 100000)
+        solo, rest = divmod(rest, 10000)
         rs, cs = divmod(rest, 100)
-        return f"prrlu_kernel<{rs}, {cs}, {'true' if solo else 'false'}>"
+        return f"prrlu_kernel<{rs}, {cs}, {b[solo]}, {b[cx]}>"
     if kind == 1:
-        prec, op = divmod(variant, 100)
+        cx, rest = divmod(variant, 1000)
+        prec, op = divmod(rest, 100)
         op -= 1
-        return f"contract_kernel<{op}>" if prec == 0 else f"contract_lp_kernel<{op}, {prec}>"
+        return f"contract_kernel<{op}, {b[cx]}>" if prec == 0 else f"contract_lp_kernel<{op}, {prec}, {b[cx]}>"
     return "gather_kernel"
 
 

@@ -211,7 +211,7 @@ void layout(Plan& p, Arena& A, bool gen_init) {
 }
 
 // Launch-log instance code of a contraction (see aci_launch).
-int contract_variant(int op, int prec) { return 100 * prec + op + 1; }
+int contract_variant(int op, int prec, int cplx) { return 1000 * cplx + 100 * prec + op + 1; }
 
 // Kernel classes of the profile (see aci_sweep_stats).
 enum { CLS_PRRLU = 0, CLS_CONTRACT = 1, CLS_GATHER = 2, NCLS = 3 };
@@ -487,7 +487,7 @@ int enqueue_init(Enq& q) {
       gr.M = dconst(p.rho[l - 2] * p.d[l - 1]);
       gr.N = ddev(p.nJ + l);
       gr.ldc = ddev(p.nJ + l);
-      ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, PREC_FP64), 1,
+      ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, PREC_FP64, p.cplx), 1,
             launch_contract(OP_NONE, PREC_FP64, c, p.rho[l - 2] * p.d[l - 1], p.maxrank, s));
     }
     // B^n_{l-1} = X^n_l R^n_{l+1};  R^n_l = B^n_{l-1}[:, J_l]  (Alg. 5, Rightframe)
@@ -505,7 +505,7 @@ int enqueue_init(Enq& q) {
       gr.ldc = ddev(p.nJ + l + 1);
       mmax = std::max(mmax, p.r[n][l - 1] * dl);
     }
-    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, PREC_FP64), 1, launch_contract(OP_NONE, PREC_FP64, c, mmax, p.capJ[l + 1], s));
+    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, PREC_FP64, p.cplx), 1, launch_contract(OP_NONE, PREC_FP64, c, mmax, p.capJ[l + 1], s));
     GatherArgs g{};
     g.esz = p.ew;
     g.count = p.N;
@@ -542,7 +542,7 @@ int enqueue_pi(Enq& q, int l) {
   gr.M = ddev(p.nI + l - 1, p.d[l]);
   gr.N = ddev(p.nJ + l + 2, p.d[l + 1]);
   gr.ldc = dconst(p.ldm);
-  ENQPV(q, CLS_CONTRACT, contract_variant(p.op, p.prec), 2,
+  ENQPV(q, CLS_CONTRACT, contract_variant(p.op, p.prec, p.cplx), 2,
         launch_contract(p.op, p.prec, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], q.s));
   return ACI_OK;
 }
@@ -571,7 +571,7 @@ int enqueue_sweep(Enq& q) {
       gr.ldc = dconst(w);
       nmax = std::max(nmax, w);
     }
-    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec), 1, launch_contract(OP_NONE, p.prec, c, p.capI[l - 1], nmax, s));
+    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec, p.cplx), 1, launch_contract(OP_NONE, p.prec, c, p.capI[l - 1], nmax, s));
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const int mmax = p.d[l] * p.capI[l - 1], nmax2 = p.d[l + 1] * p.capJ[l + 2];
@@ -619,7 +619,7 @@ int enqueue_sweep(Enq& q) {
       gr.ldc = ddev(p.nJ + l + 2);
       mmax = std::max(mmax, p.r[n][l] * p.d[l + 1]);
     }
-    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec), 1, launch_contract(OP_NONE, p.prec, c, mmax, p.capJ[l + 2], s));
+    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec, p.cplx), 1, launch_contract(OP_NONE, p.prec, c, mmax, p.capJ[l + 2], s));
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const Dim ncols = ddev(p.nJ + l + 2, p.d[l + 1]);
@@ -804,11 +804,13 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
 // part 0 the LDU (plus the pivot-matrix solve right to left), 1 the fresh
 // environment product, 2 the two-site tensors.
 double update_flops(const Plan& p, int kind, int bond, int r, int m, int n, int part) {
+  // complex entries: a complex multiply-add is 8 real flops, 4x the real count
+  const double cx = p.cplx ? 4.0 : 1.0;
   double f = 0.0;
   if (part == 0) {
     for (int k = 0; k < r; ++k) f += 2.0 * (double)(m - k - 1) * (double)(n - k - 1);
     if (kind == 2 && n > r) f += (double)r * (r - 1) * (double)(n - r);
-    return f;
+    return cx * f;
   }
   const int l = bond;
   const double cL = (double)m / p.d[l], cR = (double)n / p.d[l + 1];
@@ -819,7 +821,7 @@ double update_flops(const Plan& p, int kind, int bond, int r, int m, int n, int 
     else
       f += 2.0 * (double)m * p.r[q][l] * (double)n;
   }
-  return f;
+  return cx * f;
 }
 
 void account(const Plan& p, int kind, int bond, int r, int m, int n, aci_sweep_stats& st) {
@@ -941,7 +943,8 @@ int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t
     // captured launches are plain launches: every LDU must fit one XCD
     const int mn = std::min(p.D * p.maxrank, (int)ACI_MAX_MATRIX);
     const int cap = pl.max_groups > 0 ? pl.max_groups : prrlu_xcd_cus();
-    if (prrlu_groups(mn, mn, cap) > cap) S->use_graph = false;
+    const int g = prrlu_groups(mn, mn, cap, p.cplx);
+    if (g < 0 || g > cap) S->use_graph = false;
   }
   p.cooperative = S->use_graph ? 0 : pl.cooperative;
   {
@@ -1324,7 +1327,8 @@ int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs
       for (int n = 0; n < n_inputs[b]; ++n)
         for (int l = 0; l < inputs[off0 + n].L && inputs[off0 + n].d; ++l) dmax = std::max(dmax, (int)inputs[off0 + n].d[l]);
       const int mn = std::min(dmax * std::max(1, maxrank), (int)ACI_MAX_MATRIX);
-      if (share < 1 || prrlu_groups(mn, mn, share) > share) B->serial = true;
+      const int g = prrlu_groups(mn, mn, share, dtype == ACI_C128);
+      if (share < 1 || g < 0 || g > share) B->serial = true;
       off0 += n_inputs[b];
     }
   }

@@ -160,9 +160,11 @@ __device__ __forceinline__ bool poll_words(const uint64_t* src, int cnt, uint32_
   return ok;
 }
 
-// LDS of a cooperative launch: candidate words at [0, kCandWords), the
-// winner's row after them.
-constexpr int kCandWords = 256;
+// Most workgroups one factorisation may use (one per CU).
+constexpr int kMaxGroups = 128;
+// LDS of a cooperative launch: candidate words at [0, kCandWords) (three per
+// group), the winner's row after them.
+constexpr int kCandWords = 3 * kMaxGroups;
 // a step index no pivot step uses (steps stay below ACI_MAX_MATRIX)
 constexpr uint32_t kXccFlagOffset = 1536;
 
@@ -275,7 +277,7 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
     }
     if (!ok) failed = true;
     __syncthreads();
-    same_xcd = __ballot(lane < P && xs[lane] != xs[0]) == 0;
+    same_xcd = __ballot((lane < P && xs[lane] != xs[0]) || (lane + 64 < P && xs[lane + 64] != xs[0])) == 0;
   }
 
   int k = 0;
@@ -387,11 +389,11 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
             }
         }
       }
-      // round trip 1: the P candidates (thread t < 3P reads one word)
+      // round trip 1: the P candidates (thread t reads words t, t + NT, ...)
       bool ok = true;
-      if (threadIdx.x < 3 * P) {
-        const int g = threadIdx.x / 3;
-        const uint64_t* src = slot_base + (size_t)g * per + (threadIdx.x - 3 * g);
+      for (int t = threadIdx.x; ok && t < 3 * P; t += NT) {
+        const int g = t / 3;
+        const uint64_t* src = slot_base + (size_t)g * per + (t - 3 * g);
         uint64_t raw = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t spins = 0;
         while ((uint32_t)(raw >> 32) != flag) {
@@ -405,15 +407,21 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
           }
           raw = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        xs[threadIdx.x] = (uint32_t)raw;
+        xs[t] = (uint32_t)raw;
       }
       if (!ok) failed = true;
       __syncthreads();
+      // lane l folds the candidates of groups l, l + 64 (same order as the
+      // wave reduction: larger key, then smaller index)
       double tk = -1.0;
       int ti = INT_MAX;
-      if (lane < P) {
-        tk = join64(xs[3 * lane], xs[3 * lane + 1]);
-        ti = (int)xs[3 * lane + 2];
+      for (int g = lane; g < P; g += 64) {
+        const double gk = join64(xs[3 * g], xs[3 * g + 1]);
+        const int gi = (int)xs[3 * g + 2];
+        if (gk > tk || (gk == tk && gi < ti)) {
+          tk = gk;
+          ti = gi;
+        }
       }
       wave_argmax(tk, ti);
       v = tk;
@@ -761,7 +769,9 @@ hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
 }
 
 // Register shapes of complex matrices (two doubles per entry).
-constexpr Shape kShapesC[] = {{1, 8}, {2, 8}, {4, 8}, {8, 4}, {16, 4}};
+// Columns up to 1024 take 16 slots of two doubles: two rows per wave fill the
+// registers, so a 1024-row matrix spreads over 128 groups.
+constexpr Shape kShapesC[] = {{1, 8}, {2, 8}, {4, 8}, {8, 4}, {16, 2}};
 
 const Shape* pick_shape(int nmax, bool cx = false) {
   if (cx) {
@@ -813,7 +823,6 @@ hipError_t launch_instance(const PrrluArgs& a, int cs, int rs, hipStream_t s) {
       case 8 * 32 + 4: return launch_shape<4, 8, true>(a, s);
       case 16 * 32 + 1: return launch_shape<1, 16, true>(a, s);
       case 16 * 32 + 2: return launch_shape<2, 16, true>(a, s);
-      case 16 * 32 + 4: return launch_shape<4, 16, true>(a, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -864,13 +873,13 @@ int prrlu_groups(int mmax, int nmax, int max_groups, int cplx) {
 }
 
 size_t prrlu_xbuf_words(int mmax, int nmax, int cplx) {
-  // every launch uses at most 64 groups of at most 4 + 2 EW n words per parity
+  // every launch uses at most kMaxGroups groups of at most 4 + 2 EW n words per parity
   (void)mmax;
   const int ew = cplx ? 2 : 1;
   const Shape* sh = pick_shape(nmax < 1 ? 1 : nmax, cplx != 0);
   if (!sh) sh = cplx ? &kShapesC[sizeof(kShapesC) / sizeof(kShapesC[0]) - 1]
                      : &kShapes[sizeof(kShapes) / sizeof(kShapes[0]) - 1];
-  return (size_t)2 * 64 * (4 + 2 * ew * 64 * sh->cs);
+  return (size_t)2 * kMaxGroups * (4 + 2 * ew * 64 * sh->cs);
 }
 
 int prrlu_variant(int mmax, int nmax, int max_groups, int cplx) {
@@ -891,7 +900,7 @@ hipError_t launch_prrlu(const PrrluArgs& a0, int mmax, int nmax, hipStream_t s) 
   const int rs = pick_rs(*sh, mmax, a.max_groups);
   a.P = (mmax + WAVES * rs - 1) / (WAVES * rs);
   if (a.xcd > 7 || (a.xcd < 0 && a.cooperative)) return hipErrorInvalidValue;
-  if (a.P > 64) return hipErrorInvalidValue;
+  if (a.P > kMaxGroups) return hipErrorInvalidValue;
   a.xwords = 4 + 2 * (cx ? 2 : 1) * 64 * sh->cs;
   if ((size_t)2 * a.P * a.xwords > a.xbuf_words) return hipErrorInvalidValue;
   return cx ? launch_instance<true>(a, sh->cs, rs, s) : launch_instance<false>(a, sh->cs, rs, s);

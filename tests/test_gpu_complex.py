@@ -68,7 +68,8 @@ def test_complex_environment_contraction():
 
 
 @pytest.mark.parametrize("m,n,maxrank,tol", [(7, 9, 9, 0.0), (64, 64, 64, 0.0), (300, 200, 120, 0.0),
-                                             (100, 130, 100, 1e-6), (513, 400, 64, 0.0)])
+                                             (100, 130, 100, 1e-6), (513, 400, 64, 0.0),
+                                             (600, 1000, 200, 0.0), (1024, 1024, 512, 0.0)])
 def test_complex_ldu_pivots_bitwise(m, n, maxrank, tol):
     rng = np.random.default_rng(m * 3 + n)
     M = crandn(rng, (m, n))

@@ -185,14 +185,53 @@ def gp_vortex_params(seed, modes=32):
     return a, centres, widths, signs
 
 
-def gp_vortex_full(R, seed, modes=32, device=None, width_scale=1.0):
+def gp_wave_params(seed, modes=32, waves=8, kmax=48):
+    """Random plane-wave content of each mode: integer wavevectors with
+    components in [-kmax, kmax] and complex normal amplitudes."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    k = rng.integers(-kmax, kmax + 1, (modes, waves, 2))
+    b = (rng.standard_normal((modes, waves)) + 1j * rng.standard_normal((modes, waves))) / np.sqrt(2.0 * waves)
+    return k, b
+
+
+def gp_vortex_full(R, seed, modes=32, device=None, width_scale=1.0, waves=0, kmax=48):
     """psi(x, y) = sum_m a_m ((x-x_m) + i s_m (y-y_m))/w_m
-    exp(-((x-x_m)^2 + (y-y_m)^2)/(2 w_m^2)) on the (2^R)^2 grid of [0,1)^2,
-    normalised to max |psi| = 1 over the grid."""
+    exp(-((x-x_m)^2 + (y-y_m)^2)/(2 w_m^2)) S_m(x, y) on the (2^R)^2 grid of
+    [0,1)^2, normalised to max |psi| = 1 over the grid.  S_m = 1 when
+    ``waves`` is 0; otherwise S_m = sum_j b_mj exp(2 pi i k_mj . (x, y)) is a
+    random superposition of ``waves`` plane waves (|k_j| <= kmax per axis),
+    which fills every mode with phase singularities (a speckle of vortices)
+    and raises the quantics ranks.  Every term is separable in x and y, so
+    the waves > 0 field is assembled as one product X Y^T of n x (2 modes
+    waves) factors."""
     a, c, w, s = gp_vortex_params(seed, modes)
     w = w * width_scale
     n = 2 ** R
     xp, dev = _backend(device)
+    if waves > 0:
+        k, b = gp_wave_params(seed, modes, waves, kmax)
+        x = np.arange(n, dtype=np.float64) / n
+        X = np.empty((n, modes, waves, 2), dtype=np.complex128)
+        Y = np.empty((n, modes, waves, 2), dtype=np.complex128)
+        for m in range(modes):
+            dx, dy = x - c[m, 0], x - c[m, 1]
+            gx = np.exp(-dx * dx / (2 * w[m] ** 2))
+            gy = np.exp(-dy * dy / (2 * w[m] ** 2))
+            ex = np.exp(2j * np.pi * np.outer(x, k[m, :, 0]))     # n x waves
+            ey = np.exp(2j * np.pi * np.outer(x, k[m, :, 1]))
+            coef = a[m] * b[m] / w[m]
+            X[:, m, :, 0] = (dx * gx)[:, None] * ex * coef
+            Y[:, m, :, 0] = gy[:, None] * ey
+            X[:, m, :, 1] = gx[:, None] * ex * (1j * s[m]) * coef
+            Y[:, m, :, 1] = (dy * gy)[:, None] * ey
+        X = X.reshape(n, -1)
+        Y = Y.reshape(n, -1)
+        if dev is None:
+            psi = X @ Y.T
+            return psi / np.abs(psi).max()
+        torch = xp
+        psi = torch.from_numpy(X).to(dev) @ torch.from_numpy(np.ascontiguousarray(Y.T)).to(dev)
+        return psi / psi.abs().max()
     if dev is None:
         x = np.arange(n, dtype=np.float64) / n
         psi = np.zeros((n, n), dtype=np.complex128)

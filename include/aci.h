@@ -113,6 +113,15 @@ typedef struct {
                             rook search and keeps it if max |M - L Up| <= tol;
                             otherwise the LDU of Alg. 2 runs as usual */
   int32_t proposal_scans; /* rook scan-pair limit per pivot; 0 selects 8 */
+  int32_t batch_mode;    /* batches: 0 = joint when possible, else overlapped;
+                            1 = joint (error if not possible): the products
+                            advance update by update together and the LDUs of
+                            one update run as one launch, each product's
+                            groups on one XCD; needs at most 12 products of
+                            one length and no proposal; 2 = overlapped: every
+                            product sweeps on its own stream, LDU groups
+                            spread over the XCDs; 3 = one product after
+                            another */
 } aci_options;
 
 /* Result of aci_elementwise.  Output cores are written compactly, site after
@@ -268,15 +277,28 @@ int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, 
  * terms u_j d_j u_k of a Navier-Stokes right-hand side), each run as Alg. 1
  * with the same op, tol, maxrank and options, advanced sweep by sweep
  * together.  Product b has n_inputs[b] input TTs, taken in order from
- * `inputs` (products may differ in L, d and ranks).  Each product runs on a
- * stream of its own, created by the batch and ordered after the work
- * enqueued on ctx's stream before aci_batch_create; its LDU launches are
- * placed on XCD b % 8, and products sharing an XCD split its CUs (group
- * count cap = CUs per XCD / products on that XCD, or the autotuned value
- * with options.tune).  The batch owns all device memory it uses; input
- * cores must stay valid until aci_batch_destroy.  options.init must be NULL
- * (every product starts from the seeded default guess).  Errors name the
- * product. */
+ * `inputs` (products may differ in L, d and ranks).  Each product's
+ * contractions and gathers run on a stream of its own, created by the batch
+ * and ordered after the work enqueued on ctx's stream before
+ * aci_batch_create.  options.batch_mode picks how the LDUs (Alg. 2) of the
+ * products share the GPU:
+ *   joint (default when possible): the products advance update by update
+ *     together; after every product's two-site tensor of update u is ready,
+ *     one launch factorises all of them, each product's cooperating
+ *     workgroups on a single XCD (products dealt largest first to the least
+ *     loaded XCD), then every product continues with its gathers.  Needs at
+ *     most 12 products of one length L, no learned proposal, and LDUs that
+ *     fit one XCD's CUs each.  With options.use_graph the whole joint sweep
+ *     (all streams) is captured once into one hipGraph.
+ *   overlapped: every product sweeps on its own stream; its LDU launches
+ *     use exactly their P workgroups dealt over all XCDs, P capped at
+ *     8 * floor(CUs per XCD / products) (or the autotuned value with
+ *     options.tune) so that all of them fit at once.
+ *   serial: one product after another with cooperative LDU launches (also
+ *     the fallback of overlapped when some LDU cannot fit its share).
+ * The batch owns all device memory it uses; input cores must stay valid
+ * until aci_batch_destroy.  options.init must be NULL (every product starts
+ * from the seeded default guess).  Errors name the product. */
 typedef struct aci_batch aci_batch;
 int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs,
                      int32_t n_products, int32_t dtype, int32_t op, double tol,
@@ -289,10 +311,9 @@ int aci_batch_sweep(aci_batch* batch, int32_t nsweeps, aci_sweep_stats* stats);
 /* Output of product `product`, as aci_session_result. */
 int aci_batch_result(aci_batch* batch, int32_t product, void* out, int64_t out_capacity,
                      aci_result* result);
-/* XCD and LDU group cap chosen for a product.  When some product's LDU
- * cannot fit its share of an XCD (very large matrices), the batch sweeps
- * the products one after another with cooperative LDU launches instead and
- * reports xcd = -1. */
+/* Placement of a product's LDUs: xcd = -2 in joint mode (XCD chosen per
+ * launch by the placement, max_groups = 0), -1 in overlapped mode (groups
+ * dealt over all XCDs, max_groups = the cap), 0 in serial mode. */
 int aci_batch_info(aci_batch* batch, int32_t product, int32_t* xcd, int32_t* max_groups);
 void aci_batch_destroy(aci_batch* batch);
 /* create + sweeps (the last allowed sweep in FP64, as aci_elementwise) +

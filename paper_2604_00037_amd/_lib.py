@@ -56,6 +56,7 @@ class AciOptions(C.Structure):
         ("tune", C.c_int32),
         ("proposal", C.c_void_p),
         ("proposal_scans", C.c_int32),
+        ("batch_mode", C.c_int32),
     ]
 
 

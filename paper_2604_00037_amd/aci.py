@@ -204,6 +204,10 @@ def kernel_name(kind, variant):
     """Kernel instance behind a launch-log entry, spelled as in the device
     profiler's kernel names."""
     b = {0: "false", 1: "true"}
+    if kind == 0 and variant >= 200000:
+        cx, rest = divmod(variant - 200000, 100000)
+        rs, cs = divmod(rest, 100)
+        return f"prrlu_batch_kernel<{rs}, {cs}, {b[cx]}>"
     if kind == 0 and 20000 <= variant < 30000:
         return {20001: "features_kernel", 20002: "mlp_forward_kernel", 20003: "rook_kernel",
                 20004: "contract_kernel<-1, false>", 20005: "check_kernel", 20006: "commit_kernel",
@@ -395,13 +399,18 @@ def _batch_inputs(products, keep):
     return _inputs(flat, keep), (C.c_int32 * len(counts))(*counts)
 
 
+BATCH_MODES = {"auto": 0, "joint": 1, "overlapped": 2, "serial": 3}
+
+
 class Batch:
-    """Several elementwise operations advanced together (one stream per
-    product, LDUs spread over the XCDs); see aci_batch_create."""
+    """Several elementwise operations advanced together; see aci_batch_create.
+    ``mode``: "joint" (update by update, one LDU launch per update with every
+    product on its own XCD), "overlapped" (one stream per product, LDUs spread
+    over the XCDs), "serial", or "auto" (joint when possible)."""
 
     def __init__(self, products, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0,
                  stop_rule="exclusive", precision="fp64", fixed_sweeps=False, profile=False,
-                 low_precision_sweeps=0, use_graph=False, tune=False, ctx=None):
+                 low_precision_sweeps=0, use_graph=False, tune=False, mode="auto", ctx=None):
         self.ctx = ctx or default_context()
         self.products = products
         self.maxrank = maxrank
@@ -410,6 +419,7 @@ class Batch:
         opts = _options(self._keep, maxiter, seed, None, stop_rule, precision, False, fixed_sweeps,
                         profile, low_precision_sweeps, use_graph)
         opts.tune = 1 if tune else 0
+        opts.batch_mode = BATCH_MODES[mode]
         h = C.c_void_p()
         st = self.ctx.lib.aci_batch_create(self.ctx.h, tts, counts, len(products), _code(products[0][0][0]), OPS[op],
                                            float(tol),
@@ -455,7 +465,7 @@ class Batch:
 
 def elementwise_batched(products, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0,
                         stop_rule="exclusive", precision="fp64", low_precision_sweeps=0,
-                        use_graph=False, tune=False, ctx=None):
+                        use_graph=False, tune=False, mode="auto", ctx=None):
     """aci_elementwise_batched: returns [(cores, info)] per product."""
     ctx = ctx or default_context()
     lib = ctx.lib
@@ -464,6 +474,7 @@ def elementwise_batched(products, op="product", tol=1e-12, maxrank=64, *, maxite
     opts = _options(keep, maxiter, seed, None, stop_rule, precision, False, False, False,
                     low_precision_sweeps, use_graph)
     opts.tune = 1 if tune else 0
+    opts.batch_mode = BATCH_MODES[mode]
     bufs = [_out_buffer(p, maxrank) for p in products]
     outs = (C.c_void_p * len(products))(*[C.c_void_p(b.data_ptr()) for b, _ in bufs])
     caps = (C.c_int64 * len(products))(*[c for _, c in bufs])

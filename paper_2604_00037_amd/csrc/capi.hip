@@ -238,6 +238,12 @@ struct Enq {
   int rec = 0;          // prrLU calls so far (trace record index)
   int slot = 0;         // meta slot: init calls 0..L-2, sweep calls L-1 ..
   Prof* prof = nullptr;
+  // deferred LDU: prrlu() only records its arguments (a batch launches the
+  // LDUs of all its products together)
+  bool defer = false;
+  bool has_pend = false;
+  PrrluArgs pend{};
+  int pend_mmax = 0, pend_nmax = 0;
 
   int begin(int c, int variant = 0, int part = 0) {
     if (!prof || !prof->on) return ACI_OK;
@@ -301,6 +307,13 @@ struct Enq {
     a.ldy = ldy;
     a.err = p.flags;
     a.abort_word = p.flags + 1;
+    if (defer) {
+      pend = a;
+      pend_mmax = mmax;
+      pend_nmax = nmax;
+      has_pend = true;
+      return ACI_OK;
+    }
     int rc = begin(CLS_PRRLU, prrlu_variant(mmax, nmax, p.max_groups, p.cplx));
     if (rc) return rc;
     hipError_t e = launch_prrlu(a, mmax, nmax, s);
@@ -547,44 +560,50 @@ int enqueue_pi(Enq& q, int l) {
   return ACI_OK;
 }
 
-int enqueue_sweep(Enq& q) {
+// Local update u of a sweep (u < L-1: left to right at bond u+1, otherwise
+// right to left at bond 2(L-1)-u).  Stage 0 enqueues the environment and
+// two-site contractions, the proposal and the LDU (only recorded when q.defer);
+// stage 1 what depends on the LDU's pivots.
+int enqueue_update(Enq& q, int u, int stage) {
   aci_ctx* ctx = q.ctx;
   Plan& p = q.p;
   hipStream_t s = q.s;
   const int L = p.L;
-  q.slot = L - 1;
-  if (p.mlp) ENQ(launch_fill_int(p.acc_count, 1, 0, s));
-  // ---- left to right
-  for (int l = 1; l <= L - 1; ++l) {
-    ContractArgs c{};
-    c.cplx = p.cplx;
-    c.ngroup = p.N;
-    int nmax = 0;
-    for (int n = 0; n < p.N; ++n) {
-      Group& gr = c.g[n];
-      gr.nterm = 1;
-      const int w = p.d[l] * p.r[n][l];
-      gr.t[0] = Term{p.Lf[n][l - 1], p.X[n][l], dconst(p.r[n][l - 1]), dconst(p.r[n][l - 1]), dconst(w)};
-      gr.C = p.Ac[n][l];
-      gr.M = ddev(p.nI + l - 1);
-      gr.N = dconst(w);
-      gr.ldc = dconst(w);
-      nmax = std::max(nmax, w);
-    }
-    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec, p.cplx), 1, launch_contract(OP_NONE, p.prec, c, p.capI[l - 1], nmax, s));
-    int rc = enqueue_pi(q, l);
-    if (rc) return rc;
-    const int mmax = p.d[l] * p.capI[l - 1], nmax2 = p.d[l + 1] * p.capJ[l + 2];
-    const int* skip = nullptr;
-    if (p.mlp) {
-      rc = q.propose(l, 0, ddev(p.nI + l - 1, p.d[l]), ddev(p.nJ + l + 2, p.d[l + 1]), mmax, nmax2, p.nI + l,
-                     nullptr);
+  if (u < L - 1) {
+    // ---- left to right
+    const int l = u + 1;
+    if (stage == 0) {
+      ContractArgs c{};
+      c.cplx = p.cplx;
+      c.ngroup = p.N;
+      int nmax = 0;
+      for (int n = 0; n < p.N; ++n) {
+        Group& gr = c.g[n];
+        gr.nterm = 1;
+        const int w = p.d[l] * p.r[n][l];
+        gr.t[0] = Term{p.Lf[n][l - 1], p.X[n][l], dconst(p.r[n][l - 1]), dconst(p.r[n][l - 1]), dconst(w)};
+        gr.C = p.Ac[n][l];
+        gr.M = ddev(p.nI + l - 1);
+        gr.N = dconst(w);
+        gr.ldc = dconst(w);
+        nmax = std::max(nmax, w);
+      }
+      ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec, p.cplx), 1,
+            launch_contract(OP_NONE, p.prec, c, p.capI[l - 1], nmax, s));
+      int rc = enqueue_pi(q, l);
       if (rc) return rc;
-      skip = p.acc;
+      const int mmax = p.d[l] * p.capI[l - 1], nmax2 = p.d[l + 1] * p.capJ[l + 2];
+      const int* skip = nullptr;
+      if (p.mlp) {
+        rc = q.propose(l, 0, ddev(p.nI + l - 1, p.d[l]), ddev(p.nJ + l + 2, p.d[l + 1]), mmax, nmax2, p.nI + l,
+                       nullptr);
+        if (rc) return rc;
+        skip = p.acc;
+      }
+      return q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ddev(p.nJ + l + 2, p.d[l + 1]), dconst(p.ldm),
+                     mmax, nmax2, p.nI + l, nullptr, nullptr, dconst(0), skip);
     }
-    rc = q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ddev(p.nJ + l + 2, p.d[l + 1]), dconst(p.ldm),
-                 mmax, nmax2, p.nI + l, nullptr, nullptr, dconst(0), skip);
-    if (rc) return rc;
+    int rc = 0;
     if (p.mlp && (rc = q.keep_rows(l, 0))) return rc;
     // L^n_l = A^n_l[I_l, :]  (Alg. 5, Leftframe)
     GatherArgs g{};
@@ -602,9 +621,12 @@ int enqueue_sweep(Enq& q) {
     }
     ENQP(q, CLS_GATHER, launch_gather(g, p.capI[l], emax, s));
     q.next_record();
+    return ACI_OK;
   }
   // ---- right to left
-  for (int l = L - 1; l >= 1; --l) {
+  const int l = 2 * (L - 1) - u;
+  const Dim ncols = ddev(p.nJ + l + 2, p.d[l + 1]);
+  if (stage == 0) {
     ContractArgs c{};
     c.cplx = p.cplx;
     c.ngroup = p.N;
@@ -619,10 +641,10 @@ int enqueue_sweep(Enq& q) {
       gr.ldc = ddev(p.nJ + l + 2);
       mmax = std::max(mmax, p.r[n][l] * p.d[l + 1]);
     }
-    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec, p.cplx), 1, launch_contract(OP_NONE, p.prec, c, mmax, p.capJ[l + 2], s));
+    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec, p.cplx), 1,
+          launch_contract(OP_NONE, p.prec, c, mmax, p.capJ[l + 2], s));
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
-    const Dim ncols = ddev(p.nJ + l + 2, p.d[l + 1]);
     const int* skip = nullptr;
     if (p.mlp) {
       rc = q.propose(l, 1, ddev(p.nI + l - 1, p.d[l]), ncols, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2],
@@ -630,46 +652,58 @@ int enqueue_sweep(Enq& q) {
       if (rc) return rc;
       skip = p.acc;
     }
-    rc = q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ncols, dconst(p.ldm), p.d[l] * p.capI[l - 1],
-                 p.d[l + 1] * p.capJ[l + 2], p.nJ + l + 1, p.eps_bond + (l - 1), p.Ycore[l + 1], ncols, skip);
-    if (rc) return rc;
-    if (p.mlp) {
-      // an accepted proposal's right factor (the LDU forms it otherwise)
-      SolveArgs sa{};
-      sa.Up = p.rkUp;
-      sa.ldu = p.ldm;
-      sa.cols = p.rkcols;
-      sa.rank = p.rkrank;
-      sa.n = ncols;
-      sa.Y = p.Ycore[l + 1];
-      sa.ldy = ncols;
-      sa.skip = p.acc + 1;
-      rc = q.stepf(20008, [&] { return launch_rook_solve(sa, s); });
-      if (rc) return rc;
-      if ((rc = q.keep_rows(l, 1))) return rc;
-    }
-    // R^n_{l+1} = B^n_l[:, J_{l+1}]  (Alg. 5, Rightframe)
-    GatherArgs g{};
-    g.esz = p.ew;
-    g.count = p.N;
-    g.side = 1;
-    g.idx = q.cols();
-    g.rank = p.nJ + l + 1;
-    g.err = p.flags;
-    int emax = 0;
-    for (int n = 0; n < p.N; ++n) {
-      g.it[n] = GatherItem{p.Bc[n][l], p.Rf[n][l + 1], ncols, dconst(p.ldR), dconst(p.r[n][l]), ncols};
-      emax = std::max(emax, p.r[n][l]);
-    }
-    if (l == 1) {
-      // Y_1 = M[:, J_2] (the left factor of the last update, Alg. 3)
-      g.it[p.N] = GatherItem{p.Mbuf, p.Ycore[1], dconst(p.ldm), ddev(p.nJ + 2), dconst(p.d[1]), ncols};
-      g.count = p.N + 1;
-      emax = std::max(emax, p.d[1]);
-    }
-    ENQP(q, CLS_GATHER, launch_gather(g, p.capJ[l + 1], emax, s));
-    q.next_record();
+    return q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ncols, dconst(p.ldm), p.d[l] * p.capI[l - 1],
+                   p.d[l + 1] * p.capJ[l + 2], p.nJ + l + 1, p.eps_bond + (l - 1), p.Ycore[l + 1], ncols, skip);
   }
+  int rc = 0;
+  if (p.mlp) {
+    // an accepted proposal's right factor (the LDU forms it otherwise)
+    SolveArgs sa{};
+    sa.Up = p.rkUp;
+    sa.ldu = p.ldm;
+    sa.cols = p.rkcols;
+    sa.rank = p.rkrank;
+    sa.n = ncols;
+    sa.Y = p.Ycore[l + 1];
+    sa.ldy = ncols;
+    sa.skip = p.acc + 1;
+    rc = q.stepf(20008, [&] { return launch_rook_solve(sa, s); });
+    if (rc) return rc;
+    if ((rc = q.keep_rows(l, 1))) return rc;
+  }
+  // R^n_{l+1} = B^n_l[:, J_{l+1}]  (Alg. 5, Rightframe)
+  GatherArgs g{};
+  g.esz = p.ew;
+  g.count = p.N;
+  g.side = 1;
+  g.idx = q.cols();
+  g.rank = p.nJ + l + 1;
+  g.err = p.flags;
+  int emax = 0;
+  for (int n = 0; n < p.N; ++n) {
+    g.it[n] = GatherItem{p.Bc[n][l], p.Rf[n][l + 1], ncols, dconst(p.ldR), dconst(p.r[n][l]), ncols};
+    emax = std::max(emax, p.r[n][l]);
+  }
+  if (l == 1) {
+    // Y_1 = M[:, J_2] (the left factor of the last update, Alg. 3)
+    g.it[p.N] = GatherItem{p.Mbuf, p.Ycore[1], dconst(p.ldm), ddev(p.nJ + 2), dconst(p.d[1]), ncols};
+    g.count = p.N + 1;
+    emax = std::max(emax, p.d[1]);
+  }
+  ENQP(q, CLS_GATHER, launch_gather(g, p.capJ[l + 1], emax, s));
+  q.next_record();
+  return ACI_OK;
+}
+
+// One sweep of Alg. 1: 2(L-1) local updates, left to right then right to left.
+int enqueue_sweep(Enq& q) {
+  aci_ctx* ctx = q.ctx;
+  Plan& p = q.p;
+  q.slot = p.L - 1;
+  if (p.mlp) ENQ(launch_fill_int(p.acc_count, 1, 0, q.s));
+  for (int u = 0; u < 2 * (p.L - 1); ++u)
+    for (int stage = 0; stage < 2; ++stage)
+      if (int rc = enqueue_update(q, u, stage)) return rc;
   return ACI_OK;
 }
 
@@ -1012,6 +1046,21 @@ namespace {
 
 // Enqueues one sweep (or replays its graph) and the read-back of its ranks,
 // error estimates, per-update meta and flags into pinned host memory.
+// End of a sweep on stream s: the end event and the read-back of ranks, eps,
+// meta and flags into pinned host memory.
+int sweep_readback(aci_session* S, hipStream_t s) {
+  aci_ctx* ctx = S->ctx;
+  Plan& p = *S->plan;
+  const int L = p.L;
+  HIPCHK(hipEventRecord(S->e1, s));
+  HIPCHK(hipMemcpyAsync(S->h_cur, p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(S->h_eps, p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(S->h_meta, p.meta + 3 * (L - 1), sizeof(int) * 3 * 2 * (L - 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(S->h_flags, p.flags, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+  if (p.mlp) HIPCHK(hipMemcpyAsync(S->h_flags + 2, p.acc_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  return ACI_OK;
+}
+
 int sweep_enqueue(aci_session* S) {
   aci_ctx* ctx = S->ctx;
   Plan& p = *S->plan;
@@ -1051,13 +1100,7 @@ int sweep_enqueue(aci_session* S) {
     if (rc) return rc;
     S->rec = q.rec;
   }
-  HIPCHK(hipEventRecord(S->e1, s));
-  HIPCHK(hipMemcpyAsync(S->h_cur, p.nJ + 2, sizeof(int) * (L - 1), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(S->h_eps, p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(S->h_meta, p.meta + 3 * (L - 1), sizeof(int) * 3 * 2 * (L - 1), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(S->h_flags, p.flags, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
-  if (p.mlp) HIPCHK(hipMemcpyAsync(S->h_flags + 2, p.acc_count, sizeof(int), hipMemcpyDeviceToHost, s));
-  return ACI_OK;
+  return sweep_readback(S, s);
 }
 
 // After the stream has drained: errors, statistics, launch log, the
@@ -1274,11 +1317,20 @@ int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_
 struct aci_batch {
   aci_ctx* parent = nullptr;
   bool serial = false;   // products swept one after another (cooperative LDUs)
+  // joint: the products advance update by update together, and the LDUs of
+  // one local update run as one launch with every product on its own XCD
+  bool joint = false;
+  bool jgraph = false;   // joint sweeps captured once into a hipGraph
   std::vector<hipStream_t> streams;
   std::vector<aci_ctx*> ctxs;
   std::vector<aci_session*> sess;
   std::vector<int> groups;
   hipEvent_t ready = nullptr;
+  hipStream_t jstream = nullptr;     // the joint LDU launches
+  hipEvent_t jdone = nullptr, jfork = nullptr;
+  std::vector<hipEvent_t> pre;       // per product: update stage 0 enqueued
+  hipGraphExec_t jexec = nullptr;
+  std::vector<int> jkey;             // products and precisions jexec was captured for
 };
 
 void aci_batch_destroy(aci_batch* B) {
@@ -1290,8 +1342,135 @@ void aci_batch_destroy(aci_batch* B) {
     (void)hipStreamDestroy(st);
   }
   if (B->ready) (void)hipEventDestroy(B->ready);
+  if (B->jexec) (void)hipGraphExecDestroy(B->jexec);
+  if (B->jstream) {
+    (void)hipStreamSynchronize(B->jstream);
+    (void)hipStreamDestroy(B->jstream);
+  }
+  if (B->jdone) (void)hipEventDestroy(B->jdone);
+  if (B->jfork) (void)hipEventDestroy(B->jfork);
+  for (hipEvent_t e : B->pre) (void)hipEventDestroy(e);
   delete B;
 }
+
+extern "C++" {
+namespace {
+
+// The 2(L-1) local updates of one sweep of the active products `ids`, in
+// lockstep: per update, every product's contractions on its own stream, then
+// one batched LDU launch on the joint stream, then every product's gathers.
+// With `timed`, each product's start event is recorded first (not inside a
+// graph capture).
+int joint_enqueue(aci_batch* B, const std::vector<int>& ids, bool timed) {
+  aci_ctx* ctx = B->parent;
+  const int L = B->sess[ids[0]]->plan->L;
+  std::vector<Enq> qs;
+  qs.reserve(ids.size());
+  for (int b : ids) {
+    aci_session* S = B->sess[b];
+    S->prof.clear();
+    S->swept_prec = S->plan->prec;
+    if (timed) HIPCHK(hipEventRecord(S->e0, B->streams[b]));
+    qs.push_back(Enq{B->ctxs[b], *S->plan, B->streams[b], S->rec, L - 1, &S->prof});
+    qs.back().defer = true;
+  }
+  const int cnt = (int)ids.size();
+  std::vector<PrrluArgs> args(cnt);
+  std::vector<int> mm(cnt);
+  auto fail = [&](int i, int rc) {
+    return set_err(ctx, rc, std::string("product ") + std::to_string(ids[i]) + ": " + B->ctxs[ids[i]]->err);
+  };
+  for (int u = 0; u < 2 * (L - 1); ++u) {
+    int nmax = 1;
+    for (int i = 0; i < cnt; ++i) {
+      Enq& q = qs[i];
+      q.has_pend = false;
+      if (int rc = enqueue_update(q, u, 0)) return fail(i, rc);
+      if (!q.has_pend) return set_err(ctx, ACI_E_INVALID, "joint batch: update without an LDU");
+      args[i] = q.pend;
+      mm[i] = q.pend_mmax;
+      nmax = std::max(nmax, q.pend_nmax);
+      HIPCHK(hipEventRecord(B->pre[ids[i]], B->streams[ids[i]]));
+      HIPCHK(hipStreamWaitEvent(B->jstream, B->pre[ids[i]], 0));
+    }
+    // the batched LDU, logged as a launch of the first active product
+    Enq& q0 = qs[0];
+    const hipStream_t own = q0.s;
+    q0.s = B->jstream;
+    if (int rc = q0.begin(CLS_PRRLU, prrlu_batch_variant(mm.data(), cnt, nmax, q0.p.cplx))) return fail(0, rc);
+    const hipError_t e = launch_prrlu_batch(args.data(), mm.data(), cnt, nmax, B->jstream);
+    if (e != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("batched prrlu launch: ") + hipGetErrorString(e));
+    if (int rc = q0.end()) return fail(0, rc);
+    q0.s = own;
+    HIPCHK(hipEventRecord(B->jdone, B->jstream));
+    for (int i = 0; i < cnt; ++i) {
+      HIPCHK(hipStreamWaitEvent(B->streams[ids[i]], B->jdone, 0));
+      if (int rc = enqueue_update(qs[i], u, 1)) return fail(i, rc);
+    }
+  }
+  for (int i = 0; i < cnt; ++i) B->sess[ids[i]]->rec = qs[i].rec;
+  return ACI_OK;
+}
+
+// One joint sweep of the active products, replayed from a captured graph
+// when the batch uses graphs, followed by every product's read-back.
+int joint_sweep(aci_batch* B, const std::vector<int>& ids) {
+  aci_ctx* ctx = B->parent;
+  if (!B->jgraph) {
+    if (int rc = joint_enqueue(B, ids, true)) return rc;
+  } else {
+    std::vector<int> key(B->sess.size(), -1);
+    for (int b : ids) key[b] = B->sess[b]->plan->prec;
+    if (!B->jexec || key != B->jkey) {
+      if (B->jexec) {
+        HIPCHK(hipGraphExecDestroy(B->jexec));
+        B->jexec = nullptr;
+      }
+      // every product stream joins the capture through the fork event and
+      // is joined back before it ends
+      HIPCHK(hipStreamBeginCapture(B->jstream, hipStreamCaptureModeRelaxed));
+      int rc = ACI_OK;
+      hipError_t ec = hipEventRecord(B->jfork, B->jstream);
+      for (int b : ids)
+        if (ec == hipSuccess) ec = hipStreamWaitEvent(B->streams[b], B->jfork, 0);
+      if (ec == hipSuccess) rc = joint_enqueue(B, ids, false);
+      for (int b : ids)
+        if (ec == hipSuccess && rc == ACI_OK) {
+          ec = hipEventRecord(B->pre[b], B->streams[b]);
+          if (ec == hipSuccess) ec = hipStreamWaitEvent(B->jstream, B->pre[b], 0);
+        }
+      hipGraph_t g = nullptr;
+      const hipError_t ee = hipStreamEndCapture(B->jstream, &g);
+      if (rc || ec != hipSuccess || ee != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc) return rc;
+        return set_err(ctx, ACI_E_HIP, std::string("joint sweep capture: ") +
+                                           hipGetErrorString(ec != hipSuccess ? ec : ee));
+      }
+      const hipError_t ei = hipGraphInstantiate(&B->jexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+      B->jkey = key;
+    }
+    for (int b : ids) {
+      aci_session* S = B->sess[b];
+      S->prof.clear();
+      S->swept_prec = S->plan->prec;
+      HIPCHK(hipEventRecord(S->e0, B->jstream));
+    }
+    HIPCHK(hipGraphLaunch(B->jexec, B->jstream));
+    HIPCHK(hipEventRecord(B->jdone, B->jstream));
+    for (int b : ids) HIPCHK(hipStreamWaitEvent(B->streams[b], B->jdone, 0));
+  }
+  for (int b : ids) {
+    if (int rc = sweep_readback(B->sess[b], B->streams[b]))
+      return set_err(ctx, rc, std::string("product ") + std::to_string(b) + ": " + B->ctxs[b]->err);
+  }
+  return ACI_OK;
+}
+
+}  // namespace
+}  // extern "C++"
 
 int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs, int32_t n_products,
                      int32_t dtype, int32_t op, double tol, int32_t maxrank, const aci_options* opt,
@@ -1305,6 +1484,7 @@ int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs
   o.maxiter = 20;
   if (opt) o = *opt;
   if (o.init) return set_err(ctx, ACI_E_INVALID, "a batch takes the default initial guess (options.init must be NULL)");
+  if (o.batch_mode < 0 || o.batch_mode > 3) return set_err(ctx, ACI_E_INVALID, "batch_mode must be 0..3");
   std::unique_ptr<aci_batch, void (*)(aci_batch*)> B(new (std::nothrow) aci_batch(), aci_batch_destroy);
   if (!B) return set_err(ctx, ACI_E_NOMEM, "host allocation");
   B->parent = ctx;
@@ -1317,26 +1497,53 @@ int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs
   // all products at once, one per CU, so no launch waits for CUs held by a
   // spinning one.  If some LDU needs more groups than that, the products are
   // swept one after another with cooperative launches instead.
+  //
+  // Joint mode (the default when it fits): the products advance update by
+  // update together and the LDUs of one update form one launch in which
+  // every product's groups sit on a single XCD, so every exchange stays in
+  // an L2 and no two spinning launches ever wait for each other's CUs.  It
+  // needs products of one length, no learned proposal, at most
+  // kBatchMaxProducts products, and LDUs that fit one XCD share each at their
+  // largest sizes.
   const int cus = prrlu_xcd_cus();
   const int share = 8 * (cus / n_products);
   {
     int off0 = 0;
+    bool same_len = true;
+    std::vector<int> mm;
+    int nmx = 1;
     for (int b = 0; b < n_products; ++b) {
       if (n_inputs[b] < 1 || n_inputs[b] > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
       int dmax = 1;
       for (int n = 0; n < n_inputs[b]; ++n)
         for (int l = 0; l < inputs[off0 + n].L && inputs[off0 + n].d; ++l) dmax = std::max(dmax, (int)inputs[off0 + n].d[l]);
+      same_len = same_len && inputs[off0].L == inputs[0].L;
       const int mn = std::min(dmax * std::max(1, maxrank), (int)ACI_MAX_MATRIX);
+      mm.push_back(mn);
+      nmx = std::max(nmx, mn);
       const int g = prrlu_groups(mn, mn, share, dtype == ACI_C128);
       if (share < 1 || g < 0 || g > share) B->serial = true;
       off0 += n_inputs[b];
     }
+    const bool joint_ok = n_products <= kBatchMaxProducts && !o.proposal && same_len &&
+                          prrlu_batch_variant(mm.data(), n_products, nmx, dtype == ACI_C128) >= 0;
+    if (o.batch_mode == 1 && !joint_ok)
+      return set_err(ctx, ACI_E_LIMIT, "joint batch needs at most 12 products of one length, no proposal, and LDUs "
+                                       "that fit one XCD share each");
+    B->joint = joint_ok && o.batch_mode <= 1;
+    if (o.batch_mode == 3) B->serial = true;
+    if (B->joint) {
+      B->serial = false;
+      B->jgraph = o.use_graph && !o.profile && !o.trace;
+    }
   }
+  aci_options os = o;
+  if (B->joint) os.use_graph = 0;   // the batch captures the joint sweep itself
   int off = 0;
   for (int b = 0; b < n_products; ++b) {
     if (n_inputs[b] < 1 || n_inputs[b] > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
-    int cap = B->serial ? 0 : share;
-    if (o.tune && !B->serial) {
+    int cap = (B->serial || B->joint) ? 0 : share;
+    if (o.tune && !B->serial && !B->joint) {
       int dmax = 1;
       for (int n = 0; n < n_inputs[b]; ++n)
         for (int l = 0; l < inputs[off + n].L && inputs[off + n].d; ++l) dmax = std::max(dmax, (int)inputs[off + n].d[l]);
@@ -1355,15 +1562,27 @@ int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs
     if (rc) return set_err(ctx, rc, "context creation");
     B->ctxs.push_back(c);
     Placement pl;
-    pl.xcd = B->serial ? 0 : -1;
+    pl.xcd = (B->serial || B->joint) ? 0 : -1;
     pl.max_groups = cap;
-    pl.cooperative = B->serial ? 1 : 0;   // plain launches: LDUs of different products overlap
+    pl.cooperative = (B->serial || B->joint) ? 1 : 0;   // plain launches: LDUs of different products overlap
     aci_session* S = nullptr;
-    rc = session_create(c, inputs + off, n_inputs[b], dtype, op, tol, maxrank, &o, pl, &S);
+    rc = session_create(c, inputs + off, n_inputs[b], dtype, op, tol, maxrank, &os, pl, &S);
     if (rc < 0) return set_err(ctx, rc, std::string("product ") + std::to_string(b) + ": " + c->err);
+    // cooperative initialisation LDUs of different products never overlap
+    if (pl.cooperative) HIPCHK(hipStreamSynchronize(st));
     B->sess.push_back(S);
     B->groups.push_back(cap);
     off += n_inputs[b];
+  }
+  if (B->joint) {
+    HIPCHK(hipStreamCreateWithFlags(&B->jstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&B->jdone, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&B->jfork, hipEventDisableTiming));
+    for (int b = 0; b < n_products; ++b) {
+      hipEvent_t e = nullptr;
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      B->pre.push_back(e);
+    }
   }
   *out = B.release();
   return ACI_OK;
@@ -1389,12 +1608,18 @@ int aci_batch_sweep(aci_batch* B, int32_t nsweeps, aci_sweep_stats* stats) {
     if (!any) break;
     // enqueue every product's sweep on its own stream, then drain them (in
     // serial mode each product is drained before the next starts)
-    if (!B->serial)
+    if (B->joint) {
+      std::vector<int> ids;
+      for (int b = 0; b < n; ++b)
+        if (act[b]) ids.push_back(b);
+      if (const int rc = joint_sweep(B, ids)) return rc;
+    } else if (!B->serial) {
       for (int b = 0; b < n; ++b)
         if (act[b]) {
           const int rc = sweep_enqueue(B->sess[b]);
           if (rc) return set_err(ctx, rc, std::string("product ") + std::to_string(b) + ": " + B->ctxs[b]->err);
         }
+    }
     emax = 0.0;
     for (int b = 0; b < n; ++b)
       if (act[b]) {
@@ -1445,8 +1670,9 @@ int aci_batch_result(aci_batch* B, int32_t product, void* out, int64_t out_capac
 
 int aci_batch_info(aci_batch* B, int32_t product, int32_t* xcd, int32_t* max_groups) {
   if (!B || product < 0 || product >= (int)B->sess.size()) return ACI_E_INVALID;
-  // -1: groups spread over all XCDs (overlapping products); 0: serial batch
-  if (xcd) *xcd = B->sess[product]->plan->xcd;
+  // -2: joint launches; -1: groups spread over all XCDs (overlapping
+  // products); 0: serial batch
+  if (xcd) *xcd = B->joint ? -2 : B->sess[product]->plan->xcd;
   if (max_groups) *max_groups = B->groups[product];
   return ACI_OK;
 }

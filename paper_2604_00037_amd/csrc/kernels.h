@@ -91,6 +91,25 @@ int prrlu_groups(int mmax, int nmax, int max_groups, int cplx = 0);
 // flag_base advance per launch (steps and the XCD check stay below it)
 constexpr uint32_t kFlagStride = 2048;
 
+// Factorisations of several products in one launch, each product's groups
+// on one XCD.  prod[x][s] is the product slot s of XCD x works for (-1:
+// idle), group[x][s] its group index there.
+constexpr int kBatchMaxProducts = 12;
+constexpr int kBatchSlots = 32;
+struct PrrluBatchArgs {
+  PrrluArgs a[kBatchMaxProducts];
+  int8_t prod[8][kBatchSlots];
+  uint8_t group[8][kBatchSlots];
+};
+static_assert(sizeof(PrrluBatchArgs) <= 4096, "batched LDU arguments exceed 4 KiB");
+// Placement and launch of count <= kBatchMaxProducts factorisations of
+// matrices up to mmax[i] x nmax (one dtype).  Returns hipErrorInvalidValue
+// when the products do not fit one XCD share each.
+hipError_t launch_prrlu_batch(const PrrluArgs* a, const int* mmax, int count, int nmax, hipStream_t s);
+// Instance code of that launch (200000 + 100000*cplx + 100*RS + CS), or -1
+// when the products do not fit.
+int prrlu_batch_variant(const int* mmax, int count, int nmax, int cplx);
+
 // ------------------------------------------------------ learned proposal
 constexpr int MLP_FEATURES = 7;
 constexpr int MLP_HIDDEN = 64;

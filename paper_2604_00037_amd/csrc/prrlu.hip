@@ -21,6 +21,7 @@
 // dies (left-to-right updates) or becomes the next row of B, normalised by the
 // pivot.  Rows of B are kept reduced against every later pivot row
 // (Gauss-Jordan), which gives U_JJ^{-1} U with B[:, J] = identity.
+#include <algorithm>
 #include <climits>
 
 #include "kernels.h"
@@ -182,13 +183,11 @@ __device__ __forceinline__ double cabs2(double re, double im) {
 //   l = s_q conj(pi) / |pi|^2,  s_j -= l u_j  (re: (l.re u.re - l.im u.im),
 //   im: (l.re u.im + l.im u.re)),
 // every product and sum rounded on its own.
+//
+// The factorisation itself, run by group w (0 <= w < a.P) of the
+// cooperating groups.
 template <int RS, int CS, bool SOLO, bool CX>
-__global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
-  if ((int)(blockIdx.x % a.stride) != (a.stride == 8 ? a.xcd : 0)) return;
-  // a proposal already supplied this factorisation (every group reads the
-  // same word, so the whole launch leaves together; the epoch is untouched)
-  if (a.skip && *a.skip) return;
-  const int w = blockIdx.x / a.stride;
+__device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   // flags of this launch: step k uses fbase + k
   const uint32_t fbase = a.epoch ? __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                  : a.flag_base;
@@ -673,6 +672,30 @@ __global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
   }
 }
 
+template <int RS, int CS, bool SOLO, bool CX>
+__global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
+  if ((int)(blockIdx.x % a.stride) != (a.stride == 8 ? a.xcd : 0)) return;
+  // a proposal already supplied this factorisation (every group reads the
+  // same word, so the whole launch leaves together; the epoch is untouched)
+  if (a.skip && *a.skip) return;
+  prrlu_body<RS, CS, SOLO, CX>(a, blockIdx.x / a.stride);
+}
+
+// Several products' factorisations in one launch.  Workgroup b runs on XCD
+// b % 8 (the dispatcher deals workgroups round robin over the XCDs); slot
+// b / 8 of that XCD belongs to the product and group the placement names, or
+// is idle.  Every product's groups share one XCD, so its exchange stays in
+// that XCD's L2.
+template <int RS, int CS, bool CX>
+__global__ __launch_bounds__(NT) void prrlu_batch_kernel(PrrluBatchArgs bt) {
+  const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int prod = bt.prod[x][slot];
+  if (prod < 0) return;
+  const PrrluArgs& a = bt.a[prod];
+  if (a.skip && *a.skip) return;
+  prrlu_body<RS, CS, false, CX>(a, bt.group[x][slot]);
+}
+
 // Resident workgroups per CU of one kernel instance.
 int resident_per_cu(const void* fn, size_t lds) {
   int nb = 0;
@@ -891,6 +914,121 @@ int prrlu_variant(int mmax, int nmax, int max_groups, int cplx) {
   return (cplx ? 100000 : 0) + (P == 1 ? 10000 : 0) + 100 * rs + sh->cs;
 }
 
+// Batch placement: the fewest row slots per wave for which every product's
+// groups (one per CU) fit on one XCD, products dealt largest first to the
+// least loaded XCD.
+static bool batch_place(const int* mmax, int count, const Shape& sh, int& rs, int* P, PrrluBatchArgs* out) {
+  const int cap = std::min(cus_per_xcd(), kBatchSlots);
+  if (count < 1 || count > kBatchMaxProducts) return false;
+  for (rs = 1; rs <= sh.rs_max; rs *= 2) {
+    bool ok = true;
+    int order[kBatchMaxProducts];
+    for (int b = 0; b < count; ++b) {
+      P[b] = (std::max(mmax[b], 1) + WAVES * rs - 1) / (WAVES * rs);
+      ok = ok && P[b] <= cap;
+      order[b] = b;
+    }
+    if (!ok) continue;
+    std::stable_sort(order, order + count, [&](int x, int y) { return P[x] > P[y]; });
+    int load[8] = {0, 0, 0, 0, 0, 0, 0, 0}, xcd_of[kBatchMaxProducts], start[kBatchMaxProducts];
+    for (int i = 0; i < count && ok; ++i) {
+      const int b = order[i];
+      int x = 0;
+      for (int y = 1; y < 8; ++y)
+        if (load[y] < load[x]) x = y;
+      if (load[x] + P[b] > cap) ok = false;
+      xcd_of[b] = x;
+      start[b] = load[x];
+      load[x] += P[b];
+    }
+    if (!ok) continue;
+    if (out) {
+      for (int x = 0; x < 8; ++x)
+        for (int t = 0; t < kBatchSlots; ++t) {
+          out->prod[x][t] = -1;
+          out->group[x][t] = 0;
+        }
+      for (int b = 0; b < count; ++b)
+        for (int g = 0; g < P[b]; ++g) {
+          out->prod[xcd_of[b]][start[b] + g] = (int8_t)b;
+          out->group[xcd_of[b]][start[b] + g] = (uint8_t)g;
+        }
+    }
+    return true;
+  }
+  return false;
+}
+
+template <int RS, int CS, bool CX>
+hipError_t launch_batch_shape(const PrrluBatchArgs& bt, int slots, hipStream_t s) {
+  constexpr int EW = CX ? 2 : 1;
+  const void* fn = (const void*)prrlu_batch_kernel<RS, CS, CX>;
+  const size_t lds = group_lds((size_t)(kCandWords + 128 * EW * CS) * 4);
+  PrrluBatchArgs args = bt;
+  void* kp[] = {&args};
+  const hipError_t e = hipLaunchKernel(fn, dim3(8 * slots), dim3(NT), kp, lds, s);
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
+template <bool CX>
+hipError_t launch_batch_instance(const PrrluBatchArgs& bt, int slots, int cs, int rs, hipStream_t s) {
+  if (CX) {
+    switch (cs * 32 + rs) {
+      case 1 * 32 + 1: return launch_batch_shape<1, 1, true>(bt, slots, s);
+      case 1 * 32 + 2: return launch_batch_shape<2, 1, true>(bt, slots, s);
+      case 1 * 32 + 4: return launch_batch_shape<4, 1, true>(bt, slots, s);
+      case 1 * 32 + 8: return launch_batch_shape<8, 1, true>(bt, slots, s);
+      case 2 * 32 + 1: return launch_batch_shape<1, 2, true>(bt, slots, s);
+      case 2 * 32 + 2: return launch_batch_shape<2, 2, true>(bt, slots, s);
+      case 2 * 32 + 4: return launch_batch_shape<4, 2, true>(bt, slots, s);
+      case 2 * 32 + 8: return launch_batch_shape<8, 2, true>(bt, slots, s);
+      case 4 * 32 + 1: return launch_batch_shape<1, 4, true>(bt, slots, s);
+      case 4 * 32 + 2: return launch_batch_shape<2, 4, true>(bt, slots, s);
+      case 4 * 32 + 4: return launch_batch_shape<4, 4, true>(bt, slots, s);
+      case 4 * 32 + 8: return launch_batch_shape<8, 4, true>(bt, slots, s);
+      case 8 * 32 + 1: return launch_batch_shape<1, 8, true>(bt, slots, s);
+      case 8 * 32 + 2: return launch_batch_shape<2, 8, true>(bt, slots, s);
+      case 8 * 32 + 4: return launch_batch_shape<4, 8, true>(bt, slots, s);
+      case 16 * 32 + 1: return launch_batch_shape<1, 16, true>(bt, slots, s);
+      case 16 * 32 + 2: return launch_batch_shape<2, 16, true>(bt, slots, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (cs * 32 + rs) {
+    case 1 * 32 + 1: return launch_batch_shape<1, 1, false>(bt, slots, s);
+    case 1 * 32 + 2: return launch_batch_shape<2, 1, false>(bt, slots, s);
+    case 1 * 32 + 4: return launch_batch_shape<4, 1, false>(bt, slots, s);
+    case 1 * 32 + 8: return launch_batch_shape<8, 1, false>(bt, slots, s);
+    case 1 * 32 + 16: return launch_batch_shape<16, 1, false>(bt, slots, s);
+    case 2 * 32 + 1: return launch_batch_shape<1, 2, false>(bt, slots, s);
+    case 2 * 32 + 2: return launch_batch_shape<2, 2, false>(bt, slots, s);
+    case 2 * 32 + 4: return launch_batch_shape<4, 2, false>(bt, slots, s);
+    case 2 * 32 + 8: return launch_batch_shape<8, 2, false>(bt, slots, s);
+    case 2 * 32 + 16: return launch_batch_shape<16, 2, false>(bt, slots, s);
+    case 4 * 32 + 1: return launch_batch_shape<1, 4, false>(bt, slots, s);
+    case 4 * 32 + 2: return launch_batch_shape<2, 4, false>(bt, slots, s);
+    case 4 * 32 + 4: return launch_batch_shape<4, 4, false>(bt, slots, s);
+    case 4 * 32 + 8: return launch_batch_shape<8, 4, false>(bt, slots, s);
+    case 4 * 32 + 16: return launch_batch_shape<16, 4, false>(bt, slots, s);
+    case 6 * 32 + 1: return launch_batch_shape<1, 6, false>(bt, slots, s);
+    case 6 * 32 + 2: return launch_batch_shape<2, 6, false>(bt, slots, s);
+    case 6 * 32 + 4: return launch_batch_shape<4, 6, false>(bt, slots, s);
+    case 6 * 32 + 8: return launch_batch_shape<8, 6, false>(bt, slots, s);
+    case 8 * 32 + 1: return launch_batch_shape<1, 8, false>(bt, slots, s);
+    case 8 * 32 + 2: return launch_batch_shape<2, 8, false>(bt, slots, s);
+    case 8 * 32 + 4: return launch_batch_shape<4, 8, false>(bt, slots, s);
+    case 8 * 32 + 8: return launch_batch_shape<8, 8, false>(bt, slots, s);
+    case 12 * 32 + 1: return launch_batch_shape<1, 12, false>(bt, slots, s);
+    case 12 * 32 + 2: return launch_batch_shape<2, 12, false>(bt, slots, s);
+    case 12 * 32 + 4: return launch_batch_shape<4, 12, false>(bt, slots, s);
+    case 16 * 32 + 1: return launch_batch_shape<1, 16, false>(bt, slots, s);
+    case 16 * 32 + 2: return launch_batch_shape<2, 16, false>(bt, slots, s);
+    case 16 * 32 + 4: return launch_batch_shape<4, 16, false>(bt, slots, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_prrlu(const PrrluArgs& a0, int mmax, int nmax, hipStream_t s) {
   if (mmax < 1 || nmax < 1 || mmax > ACI_MAX_MATRIX || nmax > ACI_MAX_MATRIX) return hipErrorInvalidValue;
   const bool cx = a0.cplx != 0;
@@ -904,6 +1042,43 @@ hipError_t launch_prrlu(const PrrluArgs& a0, int mmax, int nmax, hipStream_t s) 
   a.xwords = 4 + 2 * (cx ? 2 : 1) * 64 * sh->cs;
   if ((size_t)2 * a.P * a.xwords > a.xbuf_words) return hipErrorInvalidValue;
   return cx ? launch_instance<true>(a, sh->cs, rs, s) : launch_instance<false>(a, sh->cs, rs, s);
+}
+
+int prrlu_batch_variant(const int* mmax, int count, int nmax, int cplx) {
+  if (count < 1 || count > kBatchMaxProducts || nmax < 1 || nmax > ACI_MAX_MATRIX) return -1;
+  for (int b = 0; b < count; ++b)
+    if (mmax[b] < 1 || mmax[b] > ACI_MAX_MATRIX) return -1;
+  const Shape* sh = pick_shape(nmax, cplx != 0);
+  if (!sh) return -1;
+  int rs = 0, P[kBatchMaxProducts];
+  if (!batch_place(mmax, count, *sh, rs, P, nullptr)) return -1;
+  return 200000 + (cplx ? 100000 : 0) + 100 * rs + sh->cs;
+}
+
+hipError_t launch_prrlu_batch(const PrrluArgs* a, const int* mmax, int count, int nmax, hipStream_t s) {
+  if (count < 1 || count > kBatchMaxProducts || nmax < 1 || nmax > ACI_MAX_MATRIX) return hipErrorInvalidValue;
+  const bool cx = a[0].cplx != 0;
+  for (int b = 0; b < count; ++b)
+    if (mmax[b] < 1 || mmax[b] > ACI_MAX_MATRIX || (a[b].cplx != 0) != cx) return hipErrorInvalidValue;
+  const Shape* sh = pick_shape(nmax, cx);
+  if (!sh) return hipErrorInvalidValue;
+  PrrluBatchArgs bt{};
+  int rs = 0, P[kBatchMaxProducts];
+  if (!batch_place(mmax, count, *sh, rs, P, &bt)) return hipErrorInvalidValue;
+  const int xwords = 4 + 2 * (cx ? 2 : 1) * 64 * sh->cs;
+  int slots = 0;
+  for (int x = 0; x < 8; ++x)
+    for (int t = 0; t < kBatchSlots; ++t)
+      if (bt.prod[x][t] >= 0) slots = std::max(slots, t + 1);
+  for (int b = 0; b < count; ++b) {
+    bt.a[b] = a[b];
+    bt.a[b].P = P[b];
+    bt.a[b].stride = 1;
+    bt.a[b].xwords = xwords;
+    if ((size_t)2 * P[b] * xwords > a[b].xbuf_words) return hipErrorInvalidValue;
+  }
+  return cx ? launch_batch_instance<true>(bt, slots, sh->cs, rs, s)
+            : launch_batch_instance<false>(bt, slots, sh->cs, rs, s);
 }
 
 }  // namespace aci

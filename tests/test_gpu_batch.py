@@ -1,5 +1,7 @@
-"""Batches (several products advanced together, one stream per product, LDUs
-placed per XCD) and hipGraph replay of sweeps, through the C ABI.
+"""Batches (several products advanced together: joint mode with one LDU
+launch per local update and every product on its own XCD, overlapped mode
+with one stream per product, serial mode) and hipGraph replay of sweeps,
+through the C ABI.
 
 The kernels of a batch are the same as those of a single run and every
 result element is produced by the same operations whatever the launch
@@ -135,7 +137,7 @@ def test_tune_prrlu_picks_a_measured_candidate():
 def test_tuned_batch_equals_separate_runs():
     prods = products_small()[:2]
     dev = [[to_dev(x) for x in p] for p in prods]
-    res = aci.elementwise_batched(dev, "product", 1e-12, 40, seed=9, tune=True)
+    res = aci.elementwise_batched(dev, "product", 1e-12, 40, seed=9, tune=True, mode="overlapped")
     for b, (cores, info) in enumerate(res):
         sc, si = aci.elementwise(dev[b], "product", 1e-12, 40, seed=9)
         assert_same(cores, sc)
@@ -146,3 +148,109 @@ def test_batch_rejects_explicit_init_and_bad_sizes():
     dev = [[to_dev(x) for x in p] for p in prods]
     with pytest.raises(Exception, match="LIMIT"):
         aci.elementwise_batched(dev * 65, "product", 1e-12, 40)
+
+
+def nine_products():
+    prods = []
+    for b in range(9):
+        x1, x2 = W.random_pair(L=12, chi=10 - (b % 3), seeds=(2400 + 2 * b, 2401 + 2 * b))
+        prods.append([x1, x2])
+    return prods
+
+
+def separate_fixed(dev, sweeps, **kw):
+    out = []
+    for d in dev:
+        S = aci.Session(d, "product", 1e-11, 64, maxiter=sweeps, seed=4, fixed_sweeps=True, **kw)
+        S.sweep(sweeps)
+        out.append(S.result())
+        S.close()
+    return out
+
+
+@pytest.mark.parametrize("mode,xcd", [("joint", -2), ("overlapped", -1), ("serial", 0)])
+def test_batch_modes_equal_separate_runs(mode, xcd):
+    """Nine products of one length whose two-site matrices reach 128 x 128
+    (rank cap 64): in joint mode each LDU needs 16 cooperating groups and two
+    products share an XCD.  Every placement gives the separate runs' outputs
+    bit for bit."""
+    prods = nine_products()
+    dev = [[to_dev(x) for x in p] for p in prods]
+    B = aci.Batch(dev, "product", 1e-11, 64, maxiter=5, seed=4, fixed_sweeps=True, mode=mode)
+    try:
+        st = B.sweep(5)
+        got = [B.result(b) for b in range(9)]
+        place = [B.info(b) for b in range(9)]
+    finally:
+        B.close()
+    assert all(x == xcd for x, _ in place)
+    assert st["sweeps_done"] == 5
+    ref = separate_fixed(dev, 5)
+    for b in range(9):
+        cores, info = got[b]
+        sc, si = ref[b]
+        assert info.ranks == si.ranks and info.eps == si.eps
+        assert_same(cores, sc)
+
+
+def test_joint_batch_profiled_launches():
+    """The launch log of a joint batch holds one batched LDU launch per local
+    update (logged with the first product) and no single-product LDU."""
+    prods = nine_products()[:3]
+    dev = [[to_dev(x) for x in p] for p in prods]
+    B = aci.Batch(dev, "product", 1e-11, 64, maxiter=2, seed=4, fixed_sweeps=True, mode="joint", profile=True)
+    try:
+        st = B.sweep(2)
+    finally:
+        B.close()
+    L = 12
+    assert st["launches"][0] == 2 * 2 * (L - 1)
+
+
+def test_joint_graph_replays_match_eager():
+    """Replays of the captured joint sweep, with eager work and
+    synchronisation in between, track the eager joint batch bit for bit."""
+    prods = nine_products()[:4]
+    dev = [[to_dev(x) for x in p] for p in prods]
+    kw = dict(maxiter=4, seed=4, fixed_sweeps=True, mode="joint")
+    G = aci.Batch(dev, "product", 1e-11, 64, use_graph=True, **kw)
+    E = aci.Batch(dev, "product", 1e-11, 64, use_graph=False, **kw)
+    try:
+        for it in range(4):
+            sg = G.sweep(1)
+            se = E.sweep(1)
+            assert sg["ranks"] == se["ranks"] and sg["max_eps"] == se["max_eps"]
+            for b in range(4):
+                cg, ig = G.result(b)
+                ce, ie = E.result(b)
+                assert ig.eps == ie.eps
+                assert_same(cg, ce)
+            t = torch.randn(1000, device="cuda")
+            assert torch.isfinite((t * t).sum())
+            torch.cuda.synchronize()
+    finally:
+        G.close()
+        E.close()
+
+
+def test_joint_batch_complex_matches_separate_runs():
+    fields = [W.gp_field(R=5, chi=32, seed=s, width_scale=2.0) for s in (5001, 5002)]
+    dev = [[to_dev(f)] for f in fields]
+    res = aci.elementwise_batched(dev, "abs2_mul", 1e-8, 64, seed=6, mode="joint")
+    for b, (cores, info) in enumerate(res):
+        sc, si = aci.elementwise(dev[b], "abs2_mul", 1e-8, 64, seed=6)
+        assert info.ranks == si.ranks and info.converged == si.converged
+        assert_same(cores, sc)
+
+
+def test_joint_mode_rejected_when_impossible():
+    x1, x2 = W.random_pair(L=10, chi=4, seeds=(2501, 2502))
+    y1, y2 = W.random_pair(L=9, chi=4, seeds=(2503, 2504))
+    dev = [[to_dev(x1), to_dev(x2)], [to_dev(y1), to_dev(y2)]]
+    with pytest.raises(Exception, match="LIMIT"):
+        aci.Batch(dev, "product", 1e-12, 40, mode="joint")
+    B = aci.Batch(dev, "product", 1e-12, 40)      # auto: overlapped
+    try:
+        assert all(B.info(b)[0] == -1 for b in range(2))
+    finally:
+        B.close()

@@ -104,6 +104,22 @@ def roofline(launches):
             "share_of_kernel_time": e["us"] / sum(v["us"] for v in by.values())}
 
 
+def kernel_stats_table(directory):
+    """Markdown rows of the library's kernels in run_kernel_stats.csv."""
+    import csv
+    out = ["| kernel | calls | total ms | mean us | min us | max us |", "|---|---|---|---|---|---|"]
+    with open(os.path.join(directory, "run_kernel_stats.csv")) as f:
+        for row in csv.DictReader(f):
+            if "aci::" not in row["Name"]:
+                continue
+            nm = row["Name"].replace("void aci::(anonymous namespace)::", "").replace("aci::(anonymous namespace)::", "")
+            nm = nm.split("(")[0]
+            out.append(f"| `{nm}` | {row['Calls']} | {float(row['TotalDurationNs']) / 1e6:.3f} | "
+                       f"{float(row['AverageNs']) / 1e3:.1f} | {float(row['MinNs']) / 1e3:.1f} | "
+                       f"{float(row['MaxNs']) / 1e3:.1f} |")
+    return out
+
+
 def summarize_rocprof(directory, bench_json):
     """Markdown summary of a rocprofv3 --kernel-trace --stats run of this
     script: the per-kernel statistics of the library's kernels over the whole
@@ -115,16 +131,7 @@ def summarize_rocprof(directory, bench_json):
         line = [x for x in f.read().splitlines() if x.startswith("{")][-1]
     b = json.loads(line)
     roof = b["roofline"]
-    out = ["| kernel | calls | total ms | mean us | min us | max us |", "|---|---|---|---|---|---|"]
-    with open(os.path.join(directory, "run_kernel_stats.csv")) as f:
-        for row in csv.DictReader(f):
-            if "aci::" not in row["Name"]:
-                continue
-            nm = row["Name"].replace("void aci::(anonymous namespace)::", "").replace("aci::(anonymous namespace)::", "")
-            nm = nm.split("(")[0]
-            out.append(f"| `{nm}` | {row['Calls']} | {float(row['TotalDurationNs']) / 1e6:.3f} | "
-                       f"{float(row['AverageNs']) / 1e3:.1f} | {float(row['MinNs']) / 1e3:.1f} | "
-                       f"{float(row['MaxNs']) / 1e3:.1f} |")
+    out = kernel_stats_table(directory)
     durs = []
     with open(os.path.join(directory, "run_kernel_trace.csv")) as f:
         for row in csv.DictReader(f):
@@ -434,6 +441,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the nine-product batch")
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-gp", action="store_true", help="skip the complex |psi|^2 psi workload")
+    ap.add_argument("--only", choices=["gp", "batched"],
+                    help="run just one section and print its JSON (for profiling that workload)")
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="table of the library kernels of a rocprofv3 --stats run")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print a summary of a rocprofv3 run of this script (needs --bench-json) and exit")
     ap.add_argument("--bench-json", metavar="FILE", help="output of the profiled run")
@@ -449,6 +460,9 @@ def main():
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.bench_json))
         return
+    if args.summarize_stats:
+        print("\n".join(kernel_stats_table(args.summarize_stats)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the sweep of a single product does not shard "
               "across GPUs (run it with --gpus 1)", file=sys.stderr)
@@ -459,6 +473,12 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.only == "gp":
+        print(json.dumps(time_c5(aci, dev)), flush=True)
+        return
+    if args.only == "batched":
+        print(json.dumps(time_batched(aci, max(2, args.steps // 3), 1, dev)), flush=True)
+        return
     u, v = make_inputs(args.bits, dev)
     inputs = [[torch.from_numpy(c).to(dev) for c in x] for x in (u, v)]
     L = len(u)

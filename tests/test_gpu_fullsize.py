@@ -59,10 +59,15 @@ def test_fourier_product_full_size_sampled():
     assert err <= 4 * (L - 1) * st["max_eps"] + 1e-12 * scale
 
 
+@pytest.fixture(scope="module")
+def gp_psi():
+    return W.gp_field(R=14, chi=512, seed=5001, device=torch.device("cuda:0"), waves=16, kmax=256)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_gross_pitaevskii_full_size_sampled(precision):
+def test_gross_pitaevskii_full_size_sampled(precision, gp_psi):
     dev = torch.device("cuda:0")
-    psi = W.gp_field(R=14, chi=512, seed=5001, device=dev, waves=16, kmax=256)
+    psi = gp_psi
     L = len(psi)
     assert L == 28 and max(c.shape[2] for c in psi) == 512
     S = aci.Session([cores_on(psi, dev)], "abs2_mul", 1e-8, 512, maxiter=3, seed=2003, fixed_sweeps=True,

@@ -192,6 +192,9 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   const uint32_t fbase = a.epoch ? __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                  : a.flag_base;
   constexpr int EW = CX ? 2 : 1;   // doubles per entry
+  // only complex rows of 1024 columns (two rows per wave) need more than 64
+  // groups; every other shape keeps P <= 64, one candidate per lane
+  constexpr bool WIDE = CX && CS == 16;
   const int P = a.P;
   const int m = dget(a.m), n = dget(a.n), ldm = dget(a.ldm);
   const int kmax = m < n ? m : n;
@@ -388,9 +391,13 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
             }
         }
       }
-      // round trip 1: the P candidates (thread t reads words t, t + NT, ...)
+      // round trip 1: the P candidates (thread t reads word t, and t + NT
+      // when more than 85 groups cooperate)
       bool ok = true;
-      for (int t = threadIdx.x; ok && t < 3 * P; t += NT) {
+#pragma unroll
+      for (int i = 0; i < WIDE + 1; ++i) {
+        const int t = threadIdx.x + NT * i;
+        if (!ok || t >= 3 * P) continue;
         const int g = t / 3;
         const uint64_t* src = slot_base + (size_t)g * per + (t - 3 * g);
         uint64_t raw = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -410,16 +417,23 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
       }
       if (!ok) failed = true;
       __syncthreads();
-      // lane l folds the candidates of groups l, l + 64 (same order as the
-      // wave reduction: larger key, then smaller index)
+      // lane l takes the candidate of group l (and folds in group l + 64 in
+      // the order of the wave reduction: larger key, then smaller index)
       double tk = -1.0;
       int ti = INT_MAX;
-      for (int g = lane; g < P; g += 64) {
-        const double gk = join64(xs[3 * g], xs[3 * g + 1]);
-        const int gi = (int)xs[3 * g + 2];
-        if (gk > tk || (gk == tk && gi < ti)) {
-          tk = gk;
-          ti = gi;
+      if (lane < P) {
+        tk = join64(xs[3 * lane], xs[3 * lane + 1]);
+        ti = (int)xs[3 * lane + 2];
+      }
+      if constexpr (WIDE) {
+        const int g = lane + 64;
+        if (g < P) {
+          const double gk = join64(xs[3 * g], xs[3 * g + 1]);
+          const int gi = (int)xs[3 * g + 2];
+          if (gk > tk || (gk == tk && gi < ti)) {
+            tk = gk;
+            ti = gi;
+          }
         }
       }
       wave_argmax(tk, ti);
@@ -1038,7 +1052,7 @@ hipError_t launch_prrlu(const PrrluArgs& a0, int mmax, int nmax, hipStream_t s) 
   const int rs = pick_rs(*sh, mmax, a.max_groups);
   a.P = (mmax + WAVES * rs - 1) / (WAVES * rs);
   if (a.xcd > 7 || (a.xcd < 0 && a.cooperative)) return hipErrorInvalidValue;
-  if (a.P > kMaxGroups) return hipErrorInvalidValue;
+  if (a.P > ((cx && sh->cs == 16) ? kMaxGroups : 64)) return hipErrorInvalidValue;
   a.xwords = 4 + 2 * (cx ? 2 : 1) * 64 * sh->cs;
   if ((size_t)2 * a.P * a.xwords > a.xbuf_words) return hipErrorInvalidValue;
   return cx ? launch_instance<true>(a, sh->cs, rs, s) : launch_instance<false>(a, sh->cs, rs, s);

@@ -342,9 +342,16 @@ def time_c5(aci, device, steps=2, warmup=1):
         st = S.sweep(steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        # kernel-level figure: the launches of at least 1 GFLOP (the two-site
+        # products and environments at rank 512)
+        big = [r for r in S.launches() if r["kind"] == "contract" and r["flops"] >= 1e9]
+        big_tf = sum(r["flops"] for r in big) / (sum(r["us"] for r in big) * 1e-6) / 1e12 if big else 0.0
         S.close()
         con_tf = st["flops"][1] / (st["kernel_ms"][1] * 1e-3) / 1e12 if st["kernel_ms"][1] else 0.0
         out["complex128" if prec == "fp64" else "complex64"] = {
+            "large_contraction_launches": len(big), "large_contraction_tflops": big_tf,
+            "large_contraction_frac": big_tf / peak,
+            "large_contraction_avg_us": sum(r["us"] for r in big) / len(big) if big else None,
             "sweeps_per_s": steps / el, "ms_per_sweep": 1e3 * el / steps,
             "contraction_tflops": con_tf, "contraction_frac": con_tf / peak,
             "contraction_ms_per_sweep": st["kernel_ms"][1] / steps,
@@ -352,7 +359,7 @@ def time_c5(aci, device, steps=2, warmup=1):
             "prrlu_us_per_pivot": 1e3 * st["kernel_ms"][0] / max(1, st["pivots"]),
             "pivots_per_sweep": st["pivots"] / steps, "max_eps": st["max_eps"], "max_rank": max(st["ranks"])}
         log(f"GP {prec} contractions: {steps} sweeps in {el:.3f} s; contractions {con_tf:.2f} TFLOP/s "
-            f"({con_tf / peak:.1%} of peak); LDU {out['complex128' if prec == 'fp64' else 'complex64']['prrlu_us_per_pivot']:.2f} "
+            f"({con_tf / peak:.1%} of peak; launches >= 1 GFLOP {big_tf:.2f} TFLOP/s, {big_tf / peak:.1%}); LDU {out['complex128' if prec == 'fp64' else 'complex64']['prrlu_us_per_pivot']:.2f} "
             f"us/pivot; max eps {st['max_eps']:.3e}")
     del cores
     torch.cuda.empty_cache()

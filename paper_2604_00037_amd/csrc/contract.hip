@@ -37,24 +37,65 @@ namespace {
 
 constexpr int TM = 64;
 constexpr int TN = 64;
-constexpr int KC = 16;
+constexpr int KC = 32;        // k per staged chunk (every precision)
 constexpr int LDA_S = TM + 2;
 constexpr int LDB_S = TN + 2;
+
+// One staged chunk (64 x 32 of A, 32 x 64 of B in the real view) is loaded
+// by the 256 threads into registers, eight values of each operand per
+// thread, while the previous chunk is multiplied from LDS.
+//   A value e of thread t: row t / 4, k 8 (t % 4) + e.
+//   B value e, real:    k t / 8,               column 8 (t % 8) + e.
+//   B value e, complex: k 2 (t / 16) + e / 4,  column 4 (t % 16) + e % 4;
+// complex B is read once per element (two neighbouring elements per thread)
+// and expanded in registers into its 2 x 2 real block.
+__device__ __forceinline__ int a_row(int t) { return t >> 2; }
+__device__ __forceinline__ int a_k(int t, int e) { return ((t & 3) << 3) + e; }
+template <bool CPLX>
+__device__ __forceinline__ int b_k(int t, int e) { return CPLX ? 2 * (t >> 4) + (e >> 2) : t >> 3; }
+template <bool CPLX>
+__device__ __forceinline__ int b_col(int t, int e) { return CPLX ? ((t & 15) << 2) + (e & 3) : ((t & 7) << 3) + e; }
+
+template <bool CPLX>
+__device__ __forceinline__ void load_chunk(const Term& T, int M, int N, int K, int lda, int ldb, int m0, int n0,
+                                           int k0, int t, double (&av)[8], double (&bv)[8]) {
+  const int gr = m0 + a_row(t);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int gk = k0 + a_k(t, e);
+    av[e] = (gr < M && gk < K) ? T.A[(size_t)gr * lda + gk] : 0.0;
+  }
+  if (!CPLX) {
+    const int gk = k0 + b_k<false>(t, 0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int gc = n0 + b_col<false>(t, e);
+      bv[e] = (gk < K && gc < N) ? T.B[(size_t)gk * ldb + gc] : 0.0;
+    }
+  } else {
+    // complex row (k0 + 2 (t / 16)) / 2, columns (n0 + 4 (t % 16)) / 2 + q
+    const int ct = (k0 >> 1) + (t >> 4);
+    const int cj = (n0 >> 1) + ((t & 15) << 1);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      double re = 0.0, im = 0.0;
+      if (2 * ct < K && 2 * (cj + q) < N) {
+        const double* e = T.B + 2 * ((size_t)ct * ldb + cj + q);
+        re = e[0];
+        im = e[1];
+      }
+      bv[2 * q] = re;         // real row 2ct:     (re, im)
+      bv[2 * q + 1] = im;
+      bv[4 + 2 * q] = -im;    // real row 2ct + 1: (-im, re)
+      bv[4 + 2 * q + 1] = re;
+    }
+  }
+}
 
 template <int OP>
 __device__ __forceinline__ v4d combine(v4d r, v4d a) {
   if (OP == OP_PRODUCT) return r * a;
   return r + a;  // OP_SUM
-}
-
-// Operand B entry (k, c) of the real view: the element itself, or for
-// complex B the expanded 2K x 2N entry described above.
-template <bool CPLX>
-__device__ __forceinline__ double b_entry(const double* B, int ldb, int k, int c) {
-  if (!CPLX) return B[(size_t)k * ldb + c];
-  const double* e = B + 2 * ((size_t)(k >> 1) * ldb + (c >> 1));
-  const int s = k & 1, h = c & 1;
-  return s == 0 ? (h == 0 ? e[0] : e[1]) : (h == 0 ? -e[1] : e[0]);
 }
 
 // f applied to one accumulator value of a complex result, given the value
@@ -104,34 +145,17 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
+    double av[8], bv[8];
+    load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av, bv);
     for (int k0 = 0; k0 < K; k0 += KC) {
-      // A tile: 64 rows x 16 k, thread -> row tid/4, k (tid%4)*4 .. +3
-      {
-        const int r = tid >> 2;
-        const int kq = (tid & 3) * 4;
-        const int gr = m0 + r;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int gk = k0 + kq + e;
-          double v = 0.0;
-          if (gr < M && gk < K) v = T.A[(size_t)gr * lda + gk];
-          sA[(kq + e) * LDA_S + r] = v;
-        }
-      }
-      // B tile: 16 k x 64 cols, thread -> k tid/16, cols (tid%16)*4 .. +3
-      {
-        const int kk = tid >> 4;
-        const int cq = (tid & 15) * 4;
-        const int gk = k0 + kk;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int gc = n0 + cq + e;
-          double v = 0.0;
-          if (gk < K && gc < N) v = b_entry<CPLX>(T.B, ldb, gk, gc);
-          sB[kk * LDB_S + cq + e] = v;
-        }
+      for (int e = 0; e < 8; ++e) {
+        sA[a_k(tid, e) * LDA_S + a_row(tid)] = av[e];
+        sB[b_k<CPLX>(tid, e) * LDB_S + b_col<CPLX>(tid, e)] = bv[e];
       }
       __syncthreads();
+      // the next chunk's loads are in flight while this one is multiplied
+      if (k0 + KC < K) load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KC, tid, av, bv);
 #pragma unroll
       for (int ks = 0; ks < KC / 4; ++ks) {
         const int kr = ks * 4 + lk;
@@ -194,7 +218,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
 }
 
 // ---------------------------------------------------------------- FP32 / BF16x3
-constexpr int KL = 32;        // k per staged chunk
+constexpr int KL = KC;        // k per staged chunk
 constexpr int LDF = TM + 4;   // FP32 tiles, k-major rows of 64 (+pad)
 constexpr int LDH = KL + 8;   // bf16 tiles, 32 k per row/column (+pad; 16-byte rows)
 
@@ -252,41 +276,36 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
+    double av[8], bv[8];
+    load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av, bv);
     for (int k0 = 0; k0 < K; k0 += KL) {
-      // A chunk 64 x 32: thread -> row tid / 4, k (tid % 4) * 8 .. +7
-      // B chunk 32 x 64: thread -> k tid / 8, cols (tid % 8) * 8 .. +7
-      const int ar = tid >> 2, ak = (tid & 3) * 8;
-      const int bk = tid >> 3, bc = (tid & 7) * 8;
-      double av[8], bv[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gr = m0 + ar, gk = k0 + ak + e;
-        av[e] = (gr < M && gk < K) ? T.A[(size_t)gr * lda + gk] : 0.0;
-        const int hk = k0 + bk, gc = n0 + bc + e;
-        bv[e] = (hk < K && gc < N) ? b_entry<CPLX>(T.B, ldb, hk, gc) : 0.0;
-      }
+      const int ar = a_row(tid);
       if (PREC == PREC_FP32) {
         auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          S.A[(ak + e) * LDF + ar] = (float)av[e];
-          S.B[bk * LDF + bc + e] = (float)bv[e];
+          S.A[a_k(tid, e) * LDF + ar] = (float)av[e];
+          S.B[b_k<CPLX>(tid, e) * LDF + b_col<CPLX>(tid, e)] = (float)bv[e];
         }
       } else {
         auto& S = reinterpret_cast<LpTiles<PREC_BF16X3>&>(sh);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
+          const int ak = a_k(tid, e);
           const float fa = (float)av[e];
           const unsigned short ha = bf16_bits(fa);
-          S.Ah[ar * LDH + ak + e] = ha;
-          S.Al[ar * LDH + ak + e] = bf16_bits(fa - bf16_value(ha));
+          S.Ah[ar * LDH + ak] = ha;
+          S.Al[ar * LDH + ak] = bf16_bits(fa - bf16_value(ha));
+          const int bk = b_k<CPLX>(tid, e), bc = b_col<CPLX>(tid, e);
           const float fb = (float)bv[e];
           const unsigned short hb = bf16_bits(fb);
-          S.Bh[(bc + e) * LDH + bk] = hb;
-          S.Bl[(bc + e) * LDH + bk] = bf16_bits(fb - bf16_value(hb));
+          S.Bh[bc * LDH + bk] = hb;
+          S.Bl[bc * LDH + bk] = bf16_bits(fb - bf16_value(hb));
         }
       }
       __syncthreads();
+      // the next chunk's loads are in flight while this one is multiplied
+      if (k0 + KL < K) load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL, tid, av, bv);
       if (PREC == PREC_FP32) {
         auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
 #pragma unroll

@@ -218,9 +218,10 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
 }
 
 // ---------------------------------------------------------------- FP32 / BF16x3
-constexpr int KL = KC;        // k per staged chunk
+constexpr int KL = 2 * KC;    // k per staged chunk: two load chunks (the
+                              // low-precision products are cheaper per k)
 constexpr int LDF = TM + 4;   // FP32 tiles, k-major rows of 64 (+pad)
-constexpr int LDH = KL + 8;   // bf16 tiles, 32 k per row/column (+pad; 16-byte rows)
+constexpr int LDH = KL + 8;   // bf16 tiles, 64 k per row/column (+pad; 16-byte rows)
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
@@ -276,36 +277,44 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    double av[8], bv[8];
-    load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av, bv);
+    double av[2][8], bv[2][8];
+    load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av[0], bv[0]);
+    load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, KC, tid, av[1], bv[1]);
     for (int k0 = 0; k0 < K; k0 += KL) {
       const int ar = a_row(tid);
-      if (PREC == PREC_FP32) {
-        auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          S.A[a_k(tid, e) * LDF + ar] = (float)av[e];
-          S.B[b_k<CPLX>(tid, e) * LDF + b_col<CPLX>(tid, e)] = (float)bv[e];
-        }
-      } else {
-        auto& S = reinterpret_cast<LpTiles<PREC_BF16X3>&>(sh);
+      for (int h = 0; h < 2; ++h) {
+        const int kh = KC * h;
+        if (PREC == PREC_FP32) {
+          auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int ak = a_k(tid, e);
-          const float fa = (float)av[e];
-          const unsigned short ha = bf16_bits(fa);
-          S.Ah[ar * LDH + ak] = ha;
-          S.Al[ar * LDH + ak] = bf16_bits(fa - bf16_value(ha));
-          const int bk = b_k<CPLX>(tid, e), bc = b_col<CPLX>(tid, e);
-          const float fb = (float)bv[e];
-          const unsigned short hb = bf16_bits(fb);
-          S.Bh[bc * LDH + bk] = hb;
-          S.Bl[bc * LDH + bk] = bf16_bits(fb - bf16_value(hb));
+          for (int e = 0; e < 8; ++e) {
+            S.A[(kh + a_k(tid, e)) * LDF + ar] = (float)av[h][e];
+            S.B[(kh + b_k<CPLX>(tid, e)) * LDF + b_col<CPLX>(tid, e)] = (float)bv[h][e];
+          }
+        } else {
+          auto& S = reinterpret_cast<LpTiles<PREC_BF16X3>&>(sh);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int ak = kh + a_k(tid, e);
+            const float fa = (float)av[h][e];
+            const unsigned short ha = bf16_bits(fa);
+            S.Ah[ar * LDH + ak] = ha;
+            S.Al[ar * LDH + ak] = bf16_bits(fa - bf16_value(ha));
+            const int bk = kh + b_k<CPLX>(tid, e), bc = b_col<CPLX>(tid, e);
+            const float fb = (float)bv[h][e];
+            const unsigned short hb = bf16_bits(fb);
+            S.Bh[bc * LDH + bk] = hb;
+            S.Bl[bc * LDH + bk] = bf16_bits(fb - bf16_value(hb));
+          }
         }
       }
       __syncthreads();
       // the next chunk's loads are in flight while this one is multiplied
-      if (k0 + KL < K) load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL, tid, av, bv);
+      if (k0 + KL < K) {
+        load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL, tid, av[0], bv[0]);
+        load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL + KC, tid, av[1], bv[1]);
+      }
       if (PREC == PREC_FP32) {
         auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
 #pragma unroll
@@ -324,27 +333,30 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
         }
       } else {
         auto& S = reinterpret_cast<LpTiles<PREC_BF16X3>&>(sh);
-        v8bf ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int row = wm * 32 + i * 16 + lr;
-          ah[i] = *reinterpret_cast<const v8bf*>(&S.Ah[row * LDH + 8 * lg]);
-          al[i] = *reinterpret_cast<const v8bf*>(&S.Al[row * LDH + 8 * lg]);
-        }
+        for (int ks = 0; ks < KL / 32; ++ks) {
+          v8bf ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int col = wn * 32 + j * 16 + lr;
-          bh[j] = *reinterpret_cast<const v8bf*>(&S.Bh[col * LDH + 8 * lg]);
-          bl[j] = *reinterpret_cast<const v8bf*>(&S.Bl[col * LDH + 8 * lg]);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < 2; ++i) {
+            const int row = wm * 32 + i * 16 + lr;
+            ah[i] = *reinterpret_cast<const v8bf*>(&S.Ah[row * LDH + 32 * ks + 8 * lg]);
+            al[i] = *reinterpret_cast<const v8bf*>(&S.Al[row * LDH + 32 * ks + 8 * lg]);
+          }
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            const int col = wn * 32 + j * 16 + lr;
+            bh[j] = *reinterpret_cast<const v8bf*>(&S.Bh[col * LDH + 32 * ks + 8 * lg]);
+            bl[j] = *reinterpret_cast<const v8bf*>(&S.Bl[col * LDH + 32 * ks + 8 * lg]);
           }
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        }
       }
       __syncthreads();
     }

@@ -148,6 +148,18 @@ typedef struct {
   double* rec_eps;                      /* host, n_records */
   int32_t* rec_rows;                    /* host, n_records x record_stride */
   int32_t* rec_cols;                    /* host, n_records x record_stride */
+  /* Nested index sets after the last sweep (Alg. 1, the pivots of its
+   * right-to-left half): for bond l = 1..L-1, I_l holds ranks[l]
+   * multi-indices of l digits (sigma_1..sigma_l, each < d), row-major at
+   * I_idx + I_off[l-1]; J_{l+1} holds ranks[l] multi-indices of L-l digits
+   * (sigma_{l+1}..sigma_L) at J_idx + J_off[l-1].  I_l is built from the
+   * row pivots of the right-to-left update at bond l through the I_{l-1} of
+   * the left-to-right half; J_{l+1} from its column pivots through J_{l+2}.
+   * Host memory, released by aci_result_free. */
+  int64_t I_off[ACI_MAX_SITES];
+  int64_t J_off[ACI_MAX_SITES];
+  uint8_t* I_idx;
+  uint8_t* J_idx;
 } aci_result;
 
 /* Per-call statistics of aci_session_sweep.  Kernel classes: 0 = LDU with
@@ -223,6 +235,18 @@ void aci_session_destroy(aci_session* session);
 /* Context: owns the device workspace, bound to the current device and to
  * `stream` (a hipStream_t; NULL = the null stream). */
 int aci_ctx_create(aci_ctx** ctx, void* stream);
+/* The same, with the library's device memory (session and batch workspaces,
+ * step and tuning buffers) taken from the caller's allocator instead of
+ * hipMalloc, for callers whose memory pool should own it (for instance a
+ * framework's caching allocator).  alloc(bytes, user) returns device memory
+ * of the current device, aligned to at least 256 bytes, or NULL (the call
+ * then fails with ACI_E_NOMEM); release(ptr, user) gives it back.  The
+ * library synchronises every stream that used a buffer before releasing
+ * it.  Batches created on this context use the same allocator.  Pinned host
+ * buffers still come from hipHostMalloc.  ACI_E_INVALID if alloc or release
+ * is NULL. */
+int aci_ctx_create_with_allocator(aci_ctx** ctx, void* stream, void* (*alloc)(size_t bytes, void* user),
+                                  void (*release)(void* ptr, void* user), void* user);
 void aci_ctx_destroy(aci_ctx* ctx);
 const char* aci_last_error(const aci_ctx* ctx);
 

@@ -21,7 +21,7 @@ STATUS_NAMES = {
 }
 
 EXPORTED = [
-    "aci_ctx_create", "aci_ctx_destroy", "aci_last_error", "aci_elementwise",
+    "aci_ctx_create", "aci_ctx_create_with_allocator", "aci_ctx_destroy", "aci_last_error", "aci_elementwise",
     "aci_result_free", "aci_env_contract", "aci_pi_eval", "aci_prrlu", "aci_gather",
     "aci_session_create", "aci_session_sweep", "aci_session_result", "aci_session_launches",
     "aci_session_destroy", "aci_batch_create", "aci_batch_sweep", "aci_batch_result", "aci_batch_info",
@@ -77,6 +77,10 @@ class AciResult(C.Structure):
         ("rec_eps", C.POINTER(C.c_double)),
         ("rec_rows", C.POINTER(C.c_int32)),
         ("rec_cols", C.POINTER(C.c_int32)),
+        ("I_off", C.c_int64 * MAX_SITES),
+        ("J_off", C.c_int64 * MAX_SITES),
+        ("I_idx", C.POINTER(C.c_uint8)),
+        ("J_idx", C.POINTER(C.c_uint8)),
     ]
 
 
@@ -115,6 +119,11 @@ class HipError(RuntimeError):
 _lib = None
 
 
+# device allocator callbacks of aci_ctx_create_with_allocator
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 def load(path=LIB_PATH):
     """Load the library once; raise if it has not been built."""
     global _lib
@@ -129,6 +138,8 @@ def load(path=LIB_PATH):
     i32 = C.c_int32
     lib.aci_ctx_create.argtypes = [C.POINTER(vp), vp]
     lib.aci_ctx_create.restype = C.c_int
+    lib.aci_ctx_create_with_allocator.argtypes = [C.POINTER(vp), vp, ALLOC_FN, RELEASE_FN, vp]
+    lib.aci_ctx_create_with_allocator.restype = C.c_int
     lib.aci_ctx_destroy.argtypes = [vp]
     lib.aci_ctx_destroy.restype = None
     lib.aci_last_error.argtypes = [vp]

@@ -46,15 +46,38 @@ def _dev_tensor(t, name, dtype=None):
 
 
 class Context:
-    """Owns an ``aci_ctx`` bound to the current device and torch stream."""
+    """Owns an ``aci_ctx`` bound to the current device and torch stream.
+    ``allocator="torch"`` gives the library's device memory to torch's
+    caching allocator (aci_ctx_create_with_allocator) instead of hipMalloc."""
 
-    def __init__(self, stream=None):
+    def __init__(self, stream=None, allocator=None):
         self.lib = _lib.load()
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = C.c_void_p()
-        _check(self.lib, None, self.lib.aci_ctx_create(C.byref(h), C.c_void_p(stream.cuda_stream)))
+        if allocator is None:
+            st = self.lib.aci_ctx_create(C.byref(h), C.c_void_p(stream.cuda_stream))
+        elif allocator == "torch":
+            device = torch.cuda.current_device()
+
+            def alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+                except RuntimeError:
+                    return None
+
+            def release(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            # the callbacks must outlive the context
+            self._alloc = _lib.ALLOC_FN(alloc)
+            self._release = _lib.RELEASE_FN(release)
+            st = self.lib.aci_ctx_create_with_allocator(C.byref(h), C.c_void_p(stream.cuda_stream), self._alloc,
+                                                        self._release, None)
+        else:
+            raise ValueError("allocator must be None or 'torch'")
+        _check(self.lib, None, st)
         self.h = h
 
     def close(self):
@@ -98,6 +121,8 @@ class Info:
     init_ranks: list
     sweep_ms: float
     records: list = field(default_factory=list)
+    I: list = field(default_factory=list)    # I_0..I_L as lists of tuples (I_0, I_L empty)
+    J: list = field(default_factory=list)    # J_1..J_{L+1} at index 1..L+1 (J_1, J_{L+1} empty)
 
 
 def _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, profile,
@@ -171,10 +196,16 @@ def _unpack(res, out, dims, status, trace):
                 m=meta[4], n=meta[5], eps=res.rec_eps[r],
                 rows=[res.rec_rows[stride * r + i] for i in range(rank)],
                 cols=[res.rec_cols[stride * r + i] for i in range(rank)]))
+    I = [[()]] + [[] for _ in range(L)]
+    J = [[] for _ in range(L + 1)] + [[()]]
+    for l in range(1, L):
+        oi, oj, w = res.I_off[l - 1], res.J_off[l - 1], L - l
+        I[l] = [tuple(res.I_idx[oi + k * l + t] for t in range(l)) for k in range(ranks[l])]
+        J[l + 1] = [tuple(res.J_idx[oj + k * w + t] for t in range(w)) for k in range(ranks[l])]
     info = Info(status=status, sweeps=res.sweeps, converged=bool(res.converged),
                 ranks=ranks, eps=[res.eps[i] for i in range(L - 1)],
                 init_ranks=[res.init_ranks[i] for i in range(L + 1)],
-                sweep_ms=res.sweep_ms, records=records)
+                sweep_ms=res.sweep_ms, records=records, I=I, J=J)
     return cores, info
 
 

@@ -40,9 +40,38 @@ struct aci_ctx {
   size_t mlp_scratch_n = 0;
   double* check_c = nullptr;       // L Up of the residual check
   size_t check_c_n = 0;
+  // optional caller allocator for the library's device memory
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
 };
 
 static int ensure_step_ws(aci_ctx* ctx);
+
+// Device memory for the library's own buffers: the caller's allocator when
+// the context has one, else hipMalloc.  Memory given back to a caller
+// allocator may be reused at once, so every stream that used it has been
+// synchronised before dev_free is called.
+static bool dev_alloc(aci_ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  if (ctx->alloc_fn) {
+    *p = ctx->alloc_fn(bytes, ctx->alloc_user);
+    return *p != nullptr;
+  }
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+  }
+  return true;
+}
+static void dev_free(aci_ctx* ctx, void* p) {
+  if (!p) return;
+  if (ctx->free_fn)
+    ctx->free_fn(p, ctx->alloc_user);
+  else
+    (void)hipFree(p);
+}
 
 namespace {
 
@@ -141,6 +170,12 @@ struct Plan {
   int* nJ = nullptr;   // |J_l|, l = 1..L+1
   int* prow = nullptr;
   int* pcol = nullptr;
+  // pivots of the last sweep per bond (the nested index sets): rows of the
+  // left-to-right update, rows and columns of the right-to-left update
+  int* pivLR = nullptr;
+  int* pivRLr = nullptr;
+  int* pivRLc = nullptr;
+  int* cprank = nullptr;   // rank slot written by the copies of traced pivots
   int* prank = nullptr;
   double* peps = nullptr;
   double* eps_bond = nullptr;
@@ -177,6 +212,10 @@ void layout(Plan& p, Arena& A, bool gen_init) {
   p.nJ = A.take<int>(L + 3);
   p.prow = A.take<int>(p.maxrank + 1);
   p.pcol = A.take<int>(p.maxrank + 1);
+  p.pivLR = A.take<int>((size_t)(L + 1) * p.maxrank);
+  p.pivRLr = A.take<int>((size_t)(L + 1) * p.maxrank);
+  p.pivRLc = A.take<int>((size_t)(L + 1) * p.maxrank);
+  p.cprank = A.take<int>(4);
   p.prank = A.take<int>(4);
   p.peps = A.take<double>(4);
   p.eps_bond = A.take<double>(L + 1);
@@ -242,6 +281,10 @@ struct Enq {
   // LDUs of all its products together)
   bool defer = false;
   bool has_pend = false;
+  // where the LDU of the current sweep update puts its pivots (untraced):
+  // the per-bond index-set arrays; null: the scratch rows / columns
+  int* rows_to = nullptr;
+  int* cols_to = nullptr;
   PrrluArgs pend{};
   int pend_mmax = 0, pend_nmax = 0;
 
@@ -294,8 +337,8 @@ struct Enq {
       a.cols = p.tr_cols + (size_t)rec * p.maxrank;
       a.eps = p.tr_eps + rec;
     } else {
-      a.rows = p.prow;
-      a.cols = p.pcol;
+      a.rows = rows_to ? rows_to : p.prow;
+      a.cols = cols_to ? cols_to : p.pcol;
       a.eps = p.peps;
     }
     a.meta = p.meta + (size_t)3 * slot;
@@ -421,11 +464,29 @@ struct Enq {
     return end();
   }
   // pointers the prrLU of the current record wrote its pivots to
-  const int* rows() const { return tracing() ? p.tr_rows + (size_t)rec * p.maxrank : p.prow; }
-  const int* cols() const { return tracing() ? p.tr_cols + (size_t)rec * p.maxrank : p.pcol; }
+  const int* rows() const {
+    return tracing() ? p.tr_rows + (size_t)rec * p.maxrank : (rows_to ? rows_to : p.prow);
+  }
+  const int* cols() const {
+    return tracing() ? p.tr_cols + (size_t)rec * p.maxrank : (cols_to ? cols_to : p.pcol);
+  }
+  // traced pivots also go to the per-bond index-set arrays
+  int copy_traced(const int* src, int* dst) {
+    if (!tracing() || !dst) return ACI_OK;
+    CopyRowsArgs a{};
+    a.src = src;
+    a.rank = p.prank;
+    a.dst = dst;
+    a.dst_rank = p.cprank;
+    a.maxrank = p.maxrank;
+    const hipError_t e = launch_copy_rows(a, s);
+    if (e != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("pivot copy: ") + hipGetErrorString(e));
+    return ACI_OK;
+  }
   void next_record() {
     ++rec;
     ++slot;
+    rows_to = cols_to = nullptr;
   }
 };
 
@@ -572,6 +633,8 @@ int enqueue_update(Enq& q, int u, int stage) {
   if (u < L - 1) {
     // ---- left to right
     const int l = u + 1;
+    q.rows_to = p.pivLR + (size_t)l * p.maxrank;
+    q.cols_to = nullptr;
     if (stage == 0) {
       ContractArgs c{};
       c.cplx = p.cplx;
@@ -603,7 +666,8 @@ int enqueue_update(Enq& q, int u, int stage) {
       return q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ddev(p.nJ + l + 2, p.d[l + 1]), dconst(p.ldm),
                      mmax, nmax2, p.nI + l, nullptr, nullptr, dconst(0), skip);
     }
-    int rc = 0;
+    int rc = q.copy_traced(q.rows(), p.pivLR + (size_t)l * p.maxrank);
+    if (rc) return rc;
     if (p.mlp && (rc = q.keep_rows(l, 0))) return rc;
     // L^n_l = A^n_l[I_l, :]  (Alg. 5, Leftframe)
     GatherArgs g{};
@@ -626,6 +690,8 @@ int enqueue_update(Enq& q, int u, int stage) {
   // ---- right to left
   const int l = 2 * (L - 1) - u;
   const Dim ncols = ddev(p.nJ + l + 2, p.d[l + 1]);
+  q.rows_to = p.pivRLr + (size_t)l * p.maxrank;
+  q.cols_to = p.pivRLc + (size_t)l * p.maxrank;
   if (stage == 0) {
     ContractArgs c{};
     c.cplx = p.cplx;
@@ -655,7 +721,9 @@ int enqueue_update(Enq& q, int u, int stage) {
     return q.prrlu(p.Mbuf, ddev(p.nI + l - 1, p.d[l]), ncols, dconst(p.ldm), p.d[l] * p.capI[l - 1],
                    p.d[l + 1] * p.capJ[l + 2], p.nJ + l + 1, p.eps_bond + (l - 1), p.Ycore[l + 1], ncols, skip);
   }
-  int rc = 0;
+  int rc = q.copy_traced(q.rows(), p.pivRLr + (size_t)l * p.maxrank);
+  if (rc) return rc;
+  if ((rc = q.copy_traced(q.cols(), p.pivRLc + (size_t)l * p.maxrank))) return rc;
   if (p.mlp) {
     // an accepted proposal's right factor (the LDU forms it otherwise)
     SolveArgs sa{};
@@ -889,13 +957,24 @@ int aci_ctx_create(aci_ctx** out, void* stream) {
   return ACI_OK;
 }
 
+int aci_ctx_create_with_allocator(aci_ctx** out, void* stream, void* (*alloc)(size_t bytes, void* user),
+                                  void (*release)(void* ptr, void* user), void* user) {
+  if (!out || !alloc || !release) return ACI_E_INVALID;
+  const int rc = aci_ctx_create(out, stream);
+  if (rc) return rc;
+  (*out)->alloc_fn = alloc;
+  (*out)->free_fn = release;
+  (*out)->alloc_user = user;
+  return ACI_OK;
+}
+
 void aci_ctx_destroy(aci_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
-  if (ctx->check_c) (void)hipFree(ctx->check_c);
   (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->step_err) (void)hipFree(ctx->step_err);
-  if (ctx->step_xbuf) (void)hipFree(ctx->step_xbuf);
+  dev_free(ctx, ctx->mlp_scratch);
+  dev_free(ctx, ctx->check_c);
+  dev_free(ctx, ctx->step_err);
+  dev_free(ctx, ctx->step_xbuf);
   delete ctx;
 }
 
@@ -907,6 +986,10 @@ void aci_result_free(aci_result* r) {
   free(r->rec_eps);
   free(r->rec_rows);
   free(r->rec_cols);
+  free(r->I_idx);
+  free(r->J_idx);
+  r->I_idx = nullptr;
+  r->J_idx = nullptr;
   r->rec_meta = nullptr;
   r->rec_eps = nullptr;
   r->rec_rows = nullptr;
@@ -928,7 +1011,7 @@ void aci_session_destroy(aci_session* S) {
   if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
   if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
   if (S->hbuf) (void)hipHostFree(S->hbuf);
-  if (S->ws) (void)hipFree(S->ws);
+  if (S->ws && S->ctx) dev_free(S->ctx, S->ws);
   for (hipEvent_t e : S->prof.pool) (void)hipEventDestroy(e);
   if (S->e0) (void)hipEventDestroy(S->e0);
   if (S->e1) (void)hipEventDestroy(S->e1);
@@ -999,10 +1082,7 @@ int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t
   const bool gen_init = (o.init == nullptr);
   Arena sz;
   layout(p, sz, gen_init);
-  if (hipMalloc(&S->ws, sz.off + 256) != hipSuccess) {
-    (void)hipGetLastError();
-    return set_err(ctx, ACI_E_NOMEM, "workspace allocation failed");
-  }
+  if (!dev_alloc(ctx, &S->ws, sz.off + 256)) return set_err(ctx, ACI_E_NOMEM, "workspace allocation failed");
   Arena ar;
   ar.base = (char*)S->ws;
   layout(p, ar, gen_init);
@@ -1238,6 +1318,80 @@ int aci_session_result(aci_session* S, void* out, int64_t out_capacity, aci_resu
     off += cnt;
   }
   result->out_elems = off;
+  {
+    // nested index sets of the last sweep, as the oracle keeps them: I_l
+    // from the rows of the right-to-left update at bond l (through the I_{l-1}
+    // of the left-to-right half), J_{l+1} from its columns (through J_{l+2})
+    const size_t per = (size_t)(L + 1) * maxrank;
+    std::vector<int> lr(per), rr(per), rc(per), nI(L + 2), nJ(L + 3);
+    HIPCHK(hipMemcpyAsync(lr.data(), p.pivLR, sizeof(int) * per, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rr.data(), p.pivRLr, sizeof(int) * per, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rc.data(), p.pivRLc, sizeof(int) * per, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(nI.data(), p.nI, sizeof(int) * (L + 2), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(nJ.data(), p.nJ, sizeof(int) * (L + 3), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // I^LR_l, l = 0..L-2, as nI[l] strings of l digits
+    std::vector<std::vector<uint8_t>> ilr(L);
+    ilr[0].clear();
+    bool ok = true;
+    for (int l = 1; l <= L - 2 && ok; ++l) {
+      const int cnt = nI[l], prev = l == 1 ? 1 : nI[l - 1], d = p.d[l];
+      ilr[l].resize((size_t)cnt * l);
+      for (int k = 0; k < cnt && ok; ++k) {
+        const int row = lr[(size_t)l * maxrank + k], a = row / d;
+        ok = row >= 0 && a < prev;
+        if (!ok) break;
+        for (int t = 0; t < l - 1; ++t) ilr[l][(size_t)k * l + t] = ilr[l - 1][(size_t)a * (l - 1) + t];
+        ilr[l][(size_t)k * l + l - 1] = (uint8_t)(row % d);
+      }
+    }
+    int64_t ni = 0, nj = 0;
+    for (int l = 1; l < L; ++l) {
+      ni += (int64_t)result->ranks[l] * l;
+      nj += (int64_t)result->ranks[l] * (L - l);
+    }
+    result->I_idx = (uint8_t*)calloc(std::max<int64_t>(ni, 1), 1);
+    result->J_idx = (uint8_t*)calloc(std::max<int64_t>(nj, 1), 1);
+    if (!result->I_idx || !result->J_idx) {
+      aci_result_free(result);
+      return set_err(ctx, ACI_E_NOMEM, "host allocation of the index sets");
+    }
+    int64_t oi = 0;
+    for (int l = 1; l < L && ok; ++l) {
+      const int cnt = result->ranks[l], prev = l == 1 ? 1 : nI[l - 1], d = p.d[l];
+      result->I_off[l - 1] = oi;
+      for (int k = 0; k < cnt && ok; ++k) {
+        const int row = rr[(size_t)l * maxrank + k], a = row / d;
+        ok = row >= 0 && a < prev;
+        if (!ok) break;
+        uint8_t* dst = result->I_idx + oi + (int64_t)k * l;
+        for (int t = 0; t < l - 1; ++t) dst[t] = ilr[l - 1][(size_t)a * (l - 1) + t];
+        dst[l - 1] = (uint8_t)(row % d);
+      }
+      oi += (int64_t)cnt * l;
+    }
+    // J_{l+1}, l = L-1 .. 1: ranks[l] strings of L - l digits
+    int64_t oj = nj;
+    std::vector<int64_t> joff(L + 2, 0);
+    for (int l = L - 1; l >= 1 && ok; --l) {
+      const int cnt = result->ranks[l], w = L - l, cR = l == L - 1 ? 1 : result->ranks[l + 1];
+      oj -= (int64_t)cnt * w;
+      joff[l] = oj;
+      result->J_off[l - 1] = oj;
+      for (int k = 0; k < cnt && ok; ++k) {
+        const int col = rc[(size_t)l * maxrank + k], b = col % cR;
+        ok = col >= 0 && col / cR < p.d[l + 1];
+        if (!ok) break;
+        uint8_t* dst = result->J_idx + oj + (int64_t)k * w;
+        dst[0] = (uint8_t)(col / cR);
+        for (int t = 1; t < w; ++t) dst[t] = result->J_idx[joff[l + 1] + (int64_t)b * (w - 1) + t - 1];
+      }
+    }
+    if (!ok) {
+      aci_result_free(result);
+      return set_err(ctx, ACI_E_LIMIT, "a pivot index fell outside its matrix");
+    }
+  }
   if (p.trace) {
     const int nr = std::min(S->rec, p.n_rec);
     result->n_records = nr;
@@ -1335,6 +1489,8 @@ struct aci_batch {
 
 void aci_batch_destroy(aci_batch* B) {
   if (!B) return;
+  if (B->jstream) (void)hipStreamSynchronize(B->jstream);
+  for (hipStream_t st : B->streams) (void)hipStreamSynchronize(st);
   for (aci_session* S : B->sess) aci_session_destroy(S);
   for (aci_ctx* c : B->ctxs) aci_ctx_destroy(c);
   for (hipStream_t st : B->streams) {
@@ -1560,6 +1716,9 @@ int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs
     aci_ctx* c = nullptr;
     int rc = aci_ctx_create(&c, st);
     if (rc) return set_err(ctx, rc, "context creation");
+    c->alloc_fn = ctx->alloc_fn;   // the products' memory comes from the caller's allocator too
+    c->free_fn = ctx->free_fn;
+    c->alloc_user = ctx->alloc_user;
     B->ctxs.push_back(c);
     Placement pl;
     pl.xcd = (B->serial || B->joint) ? 0 : -1;
@@ -1720,13 +1879,15 @@ namespace {
 template <typename T>
 int grow(aci_ctx* ctx, T*& buf, size_t& have, size_t need, const char* what) {
   if (have >= need) return ACI_OK;
-  if (buf) (void)hipFree(buf);
+  if (buf) {
+    (void)hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, buf);
+  }
   buf = nullptr;
   have = 0;
-  if (hipMalloc(&buf, need * sizeof(T)) != hipSuccess) {
-    (void)hipGetLastError();
-    return set_err(ctx, ACI_E_NOMEM, what);
-  }
+  void* p = nullptr;
+  if (!dev_alloc(ctx, &p, need * sizeof(T))) return set_err(ctx, ACI_E_NOMEM, what);
+  buf = (T*)p;
   have = need;
   return ACI_OK;
 }
@@ -1927,10 +2088,7 @@ int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t 
   if (rc) return rc;
   const size_t bytes = ((size_t)m * n + 8) * sizeof(double) + ((size_t)2 * ACI_MAX_MATRIX + 16) * sizeof(int);
   void* ws = nullptr;
-  if (hipMalloc(&ws, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return set_err(ctx, ACI_E_NOMEM, "tuning workspace");
-  }
+  if (!dev_alloc(ctx, &ws, bytes)) return set_err(ctx, ACI_E_NOMEM, "tuning workspace");
   double* M = (double*)ws;
   double* ep = M + (size_t)m * n;
   int* rows = (int*)(ep + 8);
@@ -1946,7 +2104,8 @@ int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t 
   auto cleanup = [&]() {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(ws);
+    (void)hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, ws);
   };
   if (hipMemcpy(M, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -2011,13 +2170,20 @@ int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t 
 // ------------------------------------------------------------ single steps
 static int ensure_step_ws(aci_ctx* ctx) {
   if (!ctx->step_err) {
-    if (hipMalloc(&ctx->step_err, 4 * sizeof(int)) != hipSuccess) return set_err(ctx, ACI_E_NOMEM, "step workspace");
+    void* p = nullptr;
+    if (!dev_alloc(ctx, &p, 4 * sizeof(int))) return set_err(ctx, ACI_E_NOMEM, "step workspace");
+    ctx->step_err = (int*)p;
   }
   const size_t words = prrlu_xbuf_words(ACI_MAX_MATRIX, ACI_MAX_MATRIX, 1);
   if (ctx->step_xwords < words) {
-    if (ctx->step_xbuf) (void)hipFree(ctx->step_xbuf);
+    if (ctx->step_xbuf) {
+      (void)hipStreamSynchronize(ctx->stream);
+      dev_free(ctx, ctx->step_xbuf);
+    }
     ctx->step_xbuf = nullptr;
-    if (hipMalloc(&ctx->step_xbuf, words * sizeof(uint64_t)) != hipSuccess) return set_err(ctx, ACI_E_NOMEM, "step exchange buffer");
+    void* p = nullptr;
+    if (!dev_alloc(ctx, &p, words * sizeof(uint64_t))) return set_err(ctx, ACI_E_NOMEM, "step exchange buffer");
+    ctx->step_xbuf = (uint64_t*)p;
     ctx->step_xwords = words;
   }
   return ACI_OK;

@@ -34,6 +34,10 @@ def check(ref, cores, info, label, full=True):
     np.testing.assert_allclose(info.eps, ref.eps, rtol=1e-9, atol=1e-14)
     for g, o in zip(cores, ref.cores):
         assert g.shape == o.shape
+    # the nested index sets the result reports are the oracle's
+    for l in range(1, len(cores)):
+        assert info.I[l] == [tuple(int(v) for v in t) for t in ref.I[l]], f"{label}: I_{l}"
+        assert info.J[l + 1] == [tuple(int(v) for v in t) for t in ref.J[l + 1]], f"{label}: J_{l + 1}"
     if full:
         y = W.tt_full(cores)
         yr = W.tt_full(ref.cores)
@@ -47,6 +51,20 @@ def test_random_pair_default_init():
     f = W.tt_full(x1) * W.tt_full(x2)
     assert rel_max_err(W.tt_full(cores), f) <= 1e-12
     assert info.ranks[1:-1] == [2, 4, 8, 16, 32, 64, 32, 16, 8, 4, 2]
+
+
+def test_index_sets_without_trace():
+    """Untraced runs keep the pivots of the last sweep per bond; the index
+    sets built from them equal the oracle's."""
+    x1, x2 = W.random_pair(L=10, chi=6, seeds=(1021, 1022))
+    ref = oracle.aci([x1, x2], "product", 1e-12, 36, seed=1023, log_gaps=True)
+    assert min(t["min_gap"] for t in ref.trace if t["min_gap"] is not None) > 1e-10
+    cores, info = aci.elementwise([to_dev(x1), to_dev(x2)], "product", 1e-12, 36, seed=1023)
+    assert info.ranks[1:-1] == ref.ranks
+    for l in range(1, 10):
+        assert info.I[l] == [tuple(int(v) for v in t) for t in ref.I[l]]
+        assert info.J[l + 1] == [tuple(int(v) for v in t) for t in ref.J[l + 1]]
+        assert len(info.I[l]) == len(info.J[l + 1]) == info.ranks[l]
 
 
 def test_random_pair_explicit_init():

@@ -105,8 +105,10 @@ typedef struct {
                             the low precision (sessions only, for timing) */
   int32_t use_graph;     /* 1: capture a sweep's launches once into a hipGraph
                             and replay it (ignored with profile or trace) */
-  int32_t tune;          /* batches: 1 = pick each product's LDU group count
-                            with aci_tune_prrlu (cached per context) */
+  int32_t tune;          /* 1 = pick the tile of every contraction launch
+                            with aci_tune_contract, and in overlapped batches
+                            each product's LDU group count with
+                            aci_tune_prrlu (both cached per context) */
   const float* proposal; /* learned pivot proposal (extension): device array of
                             ACI_MLP_PARAMS network parameters, or NULL.  Every
                             local update then scores the rows, runs the seeded
@@ -188,11 +190,15 @@ typedef struct {
  * kind: 0 LDU with full pivoting, 1 contraction, 2 frame gather.
  * variant: kind 0: 100000*complex + 10000*solo + 100*RS + CS, the instance
  *          prrlu_kernel<RS, CS, solo, complex> (RS row slots per wave, CS
- *          column slots per lane, solo = one workgroup), or 20001..20008 for
- *          the learned-proposal kernels; kind 1: 1000*complex +
+ *          column slots per lane, solo = one workgroup), 200000 +
+ *          100000*complex + 100*RS + CS for the joint batch LDU
+ *          prrlu_batch_kernel<RS, CS, complex>, or 20001..20008 for the
+ *          learned-proposal kernels; kind 1: 10000*tile + 1000*complex +
  *          100*precision + op + 1 with op the fused epilogue (-1 none, else
- *          aci_op): instance contract_kernel<op, complex> (FP64) or
- *          contract_lp_kernel<op, precision, complex>; kind 2: 0.
+ *          aci_op) and tile as in aci_tune_contract: instance
+ *          contract_kernel<op, complex, Tile<TM, TN> > (FP64) or
+ *          contract_lp_kernel<op, precision, complex, Tile<TM, TN> >;
+ *          kind 2: 0.
  * part: kind 1 only: 1 environment product, 2 two-site tensor (with f).
  * update: local update within its sweep, 0..2(L-1)-1 (left-to-right first).
  * flops: algorithmic flops of this launch, counted as in aci_sweep_stats. */
@@ -281,10 +287,12 @@ int aci_env_contract(aci_ctx* ctx, int32_t dtype, int32_t side, int32_t count,
 /* Two-site tensor with f applied (Eq. pifromframes, Eq. localupdate):
  *   M = f(A^1 B^1, ..., A^N B^N),  A^n: m x k[n] (ld k[n]), B^n: k[n] x n (ld n),
  *   M: m x n with leading dimension ldm >= n.
- * precision: aci_precision of the products; f is applied in FP64. */
+ * precision: aci_precision of the products; f is applied in FP64.
+ * tile: output tile per workgroup as in aci_tune_contract (0, 1, 2), or -1
+ *   for the default of the shape; the tile never changes the result. */
 int aci_pi_eval(aci_ctx* ctx, int32_t dtype, int32_t op, int32_t n_inputs,
                 const void* const* A, const void* const* B, const int32_t* k,
-                int32_t m, int32_t n, void* M, int32_t ldm, int32_t precision);
+                int32_t m, int32_t n, void* M, int32_t ldm, int32_t precision, int32_t tile);
 
 /* LDU with full pivoting (Alg. 2) of the m x n matrix M (ld ldm).  The input
  * is not modified.  Outputs (device): rows[r], cols[r] = pivot row/column ids
@@ -347,6 +355,22 @@ int aci_elementwise_batched(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n
                             int32_t n_products, int32_t dtype, int32_t op, double tol,
                             int32_t maxrank, const aci_options* opt, void* const* outs,
                             const int64_t* out_capacity, aci_result* results);
+
+/* Autotuner of the contraction tile shape (environment and two-site
+ * products of Eq. pifromframes): times ngroup (1..ACI_MAX_INPUTS) side-by-side
+ * copies of an m x k by k x n product (dtype, precision; operands seeded
+ * uniform on [-1, 1), one term, elements of the dtype) with each output tile
+ * per workgroup — 0: 64 x 64, 1: 32 x 64, 2: 32 x 32 (real-view elements) —
+ * one untimed and three timed launches each, and returns the fastest in
+ * *best_tile; us (optional, 3 floats) gets the mean microseconds per launch
+ * of each tile.  The choice is cached in the context per shape.  Sessions
+ * and batches created with options.tune pick the tile of every contraction
+ * launch of their sweeps this way; otherwise the largest tile that still
+ * gives every CU a workgroup is used.  Every output element is accumulated
+ * in the same order whatever the tile, so the choice never changes a
+ * result. */
+int aci_tune_contract(aci_ctx* ctx, int32_t dtype, int32_t precision, int32_t ngroup, int32_t m,
+                      int32_t k, int32_t n, int32_t* best_tile, float* us);
 
 /* Autotuner of the LDU launch shape (Alg. 2 kernel): times the LDU of a
  * seeded random m x n matrix (entries uniform on [-1, 1)) to rank

@@ -4,15 +4,15 @@ elementwise operations on tensor trains (M. K. Ritter).
 ``elementwise`` runs the full sweep (Alg. 1) in the HIP library
 ``libaci.so``; ``Session`` runs it sweep by sweep; ``elementwise_batched`` /
 ``Batch`` advance several products together; ``env_contract``, ``pi_eval``,
-``prrlu`` and ``gather`` expose its single steps; ``tune_prrlu`` times the
-LDU launch shapes.  The library must be built (``python -m
+``prrlu`` and ``gather`` expose its single steps; ``tune_prrlu`` and
+``tune_contract`` time the LDU launch shapes and the contraction tiles.  The library must be built (``python -m
 paper_2604_00037_amd.build``); nothing falls back to the CPU.
 """
 
 from .aci import (Batch, Context, Session, default_context, elementwise, elementwise_batched, env_contract,
                   gather, mlp_forward, mlp_train_step, pi_eval, proposal_features, prrlu, rook_check,
-                  rook_lu, rook_right_factor, tune_prrlu)
+                  rook_lu, rook_right_factor, tune_contract, tune_prrlu, TILES)
 
 __all__ = ["Batch", "Context", "Session", "default_context", "elementwise", "elementwise_batched",
            "env_contract", "gather", "mlp_forward", "mlp_train_step", "pi_eval", "proposal_features",
-           "prrlu", "rook_check", "rook_lu", "rook_right_factor", "tune_prrlu"]
+           "prrlu", "rook_check", "rook_lu", "rook_right_factor", "tune_contract", "tune_prrlu", "TILES"]

@@ -25,7 +25,7 @@ EXPORTED = [
     "aci_result_free", "aci_env_contract", "aci_pi_eval", "aci_prrlu", "aci_gather",
     "aci_session_create", "aci_session_sweep", "aci_session_result", "aci_session_launches",
     "aci_session_destroy", "aci_batch_create", "aci_batch_sweep", "aci_batch_result", "aci_batch_info",
-    "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu",
+    "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu", "aci_tune_contract",
     "aci_proposal_features", "aci_mlp_forward", "aci_mlp_train_step", "aci_rook_lu", "aci_rook_check",
     "aci_rook_right_factor",
 ]
@@ -153,7 +153,7 @@ def load(path=LIB_PATH):
                                      i32, i32, i32, i32, i32]
     lib.aci_env_contract.restype = C.c_int
     lib.aci_pi_eval.argtypes = [vp, i32, i32, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i32),
-                                i32, i32, vp, i32, i32]
+                                i32, i32, vp, i32, i32, i32]
     lib.aci_pi_eval.restype = C.c_int
     lib.aci_prrlu.argtypes = [vp, i32, vp, i32, i32, i32, C.c_double, i32, i32, vp, vp, vp, vp, vp, i32]
     lib.aci_prrlu.restype = C.c_int
@@ -186,6 +186,8 @@ def load(path=LIB_PATH):
     lib.aci_tune_prrlu.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32),
                                    C.POINTER(C.c_float), i32, C.POINTER(i32)]
     lib.aci_tune_prrlu.restype = C.c_int
+    lib.aci_tune_contract.argtypes = [vp, i32, i32, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(C.c_float)]
+    lib.aci_tune_contract.restype = C.c_int
     f32p = C.POINTER(C.c_float)
     i32p = C.POINTER(i32)
     lib.aci_proposal_features.argtypes = [vp, vp, i32, i32, i32, C.POINTER(vp), i32p, i32p, i32, vp, i32, vp]

@@ -249,10 +249,13 @@ def kernel_name(kind, variant):
         rs, cs = divmod(rest, 100)
         return f"prrlu_kernel<{rs}, {cs}, {b[solo]}, {b[cx]}>"
     if kind == 1:
-        cx, rest = divmod(variant, 1000)
+        tile, rest = divmod(variant, 10000)
+        cx, rest = divmod(rest, 1000)
         prec, op = divmod(rest, 100)
         op -= 1
-        return f"contract_kernel<{op}, {b[cx]}>" if prec == 0 else f"contract_lp_kernel<{op}, {prec}, {b[cx]}>"
+        tl = "Tile<%d, %d> " % ((64, 64), (32, 64), (32, 32))[tile]
+        return (f"contract_kernel<{op}, {b[cx]}, {tl}>" if prec == 0
+                else f"contract_lp_kernel<{op}, {prec}, {b[cx]}, {tl}>")
     return "gather_kernel"
 
 
@@ -263,7 +266,7 @@ class Session:
     def __init__(self, inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
                  stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False,
                  profile=False, low_precision_sweeps=0, use_graph=False, proposal=None, proposal_scans=0,
-                 ctx=None):
+                 tune=False, ctx=None):
         self.ctx = ctx or default_context()
         self.inputs = inputs            # the library reads these until close()
         self.maxrank = maxrank
@@ -272,6 +275,7 @@ class Session:
         tts = _inputs(inputs, self._keep)
         opts = _options(self._keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps,
                         profile, low_precision_sweeps, use_graph, proposal, proposal_scans)
+        opts.tune = 1 if tune else 0
         self._init = init
         h = C.c_void_p()
         st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), _code(inputs[0][0]), OPS[op], float(tol),
@@ -354,8 +358,9 @@ def env_contract(side, frames, cores, precision="fp64", ctx=None):
     return outs
 
 
-def pi_eval(op, A, B, precision="fp64", ctx=None):
-    """M = op(A[0] @ B[0], A[1] @ B[1], ...) on the matrix cores."""
+def pi_eval(op, A, B, precision="fp64", tile=None, ctx=None):
+    """M = op(A[0] @ B[0], A[1] @ B[1], ...) on the matrix cores; tile: one of
+    TILES, or None for the default of the shape."""
     ctx = ctx or default_context()
     n = len(A)
     for a, b in zip(A, B):
@@ -368,7 +373,7 @@ def pi_eval(op, A, B, precision="fp64", ctx=None):
     bp = (C.c_void_p * n)(*[b.data_ptr() for b in B])
     ks = (C.c_int32 * n)(*[int(a.shape[1]) for a in A])
     st = ctx.lib.aci_pi_eval(ctx.h, _code(A[0]), OPS[op], n, ap, bp, ks, m, ncol, C.c_void_p(M.data_ptr()), ncol,
-                             PRECISIONS[precision])
+                             PRECISIONS[precision], -1 if tile is None else TILES.index(tile))
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     return M
 
@@ -520,6 +525,20 @@ def elementwise_batched(products, op="product", tol=1e-12, maxrank=64, *, maxite
     finally:
         for b in range(len(products)):
             lib.aci_result_free(C.byref(res[b]))
+
+
+TILES = ["64x64", "32x64", "32x32"]
+
+
+def tune_contract(m, k, n, dtype="f64", precision="fp64", ngroup=1, ctx=None):
+    """aci_tune_contract: (best tile name, {tile name: mean us per launch})."""
+    ctx = ctx or default_context()
+    best = C.c_int32(0)
+    us = (C.c_float * 3)()
+    st = ctx.lib.aci_tune_contract(ctx.h, {"f64": 0, "c128": 1}[dtype], PRECISIONS[precision], int(ngroup),
+                                   int(m), int(k), int(n), C.byref(best), us)
+    _check(ctx.lib, ctx.h, st, allow_warning=False)
+    return TILES[best.value], {TILES[t]: float(us[t]) for t in range(3)}
 
 
 def tune_prrlu(m, n, maxrank, cap=0, ctx=None):

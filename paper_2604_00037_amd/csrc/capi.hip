@@ -36,6 +36,7 @@ struct aci_ctx {
   uint64_t* step_xbuf = nullptr;
   size_t step_xwords = 0;
   std::map<uint64_t, int> tuned;   // autotuned LDU group caps by shape
+  std::map<uint64_t, int> tuned_tiles;   // autotuned contraction tiles by shape
   float* mlp_scratch = nullptr;    // training scratch of the scoring network
   size_t mlp_scratch_n = 0;
   double* check_c = nullptr;       // L Up of the residual check
@@ -152,6 +153,9 @@ struct Plan {
   int rho[ACI_MAX_SITES + 1];                       // Y_init ranks
   const double* Yin[ACI_MAX_SITES + 1];             // Y_init cores (device)
   int capI[ACI_MAX_SITES + 2], capJ[ACI_MAX_SITES + 2];
+  // contraction tile per bond: [0] left environment, [1] right environment,
+  // [2] two-site tensor (-1: the default for the shape; set by the tuner)
+  int tiles[3][ACI_MAX_SITES + 2];
   int D = 1;          // max local dimension
   int ldm = 0;        // leading dimension of the two-site matrix
   int ldR = 0;        // leading dimension of right frames
@@ -250,7 +254,7 @@ void layout(Plan& p, Arena& A, bool gen_init) {
 }
 
 // Launch-log instance code of a contraction (see aci_launch).
-int contract_variant(int op, int prec, int cplx) { return 1000 * cplx + 100 * prec + op + 1; }
+int contract_variant(int op, int prec, int cplx, int tile) { return 10000 * tile + 1000 * cplx + 100 * prec + op + 1; }
 
 // Kernel classes of the profile (see aci_sweep_stats).
 enum { CLS_PRRLU = 0, CLS_CONTRACT = 1, CLS_GATHER = 2, NCLS = 3 };
@@ -507,6 +511,13 @@ struct Enq {
     if (rc_) return rc_;                     \
   } while (0)
 #define ENQP(q, cls, call) ENQPV(q, cls, 0, 0, call)
+// a profiled contraction launch with tile `tile` (-1: the default for the shape)
+#define ENQC(q, part, op, prec, c, mmax, nmax, tile)                                                   \
+  do {                                                                                                 \
+    const int t_ = (tile) >= 0 ? (tile) : contract_default_tile((mmax), (nmax), (c).ngroup, (q).p.cplx); \
+    ENQPV(q, CLS_CONTRACT, contract_variant(op, prec, (q).p.cplx, t_), part,                          \
+          launch_contract(op, prec, c, mmax, nmax, (q).s, t_));                                       \
+  } while (0)
 
 // Initialisation (Alg. 1, first two loops): CI-canonical form of Y_init from
 // right to left, initial right frames R^n_l and the cached B^n_{l-1}.
@@ -561,8 +572,7 @@ int enqueue_init(Enq& q) {
       gr.M = dconst(p.rho[l - 2] * p.d[l - 1]);
       gr.N = ddev(p.nJ + l);
       gr.ldc = ddev(p.nJ + l);
-      ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, PREC_FP64, p.cplx), 1,
-            launch_contract(OP_NONE, PREC_FP64, c, p.rho[l - 2] * p.d[l - 1], p.maxrank, s));
+      ENQC(q, 1, OP_NONE, PREC_FP64, c, p.rho[l - 2] * p.d[l - 1], p.maxrank, -1);
     }
     // B^n_{l-1} = X^n_l R^n_{l+1};  R^n_l = B^n_{l-1}[:, J_l]  (Alg. 5, Rightframe)
     ContractArgs c{};
@@ -579,7 +589,7 @@ int enqueue_init(Enq& q) {
       gr.ldc = ddev(p.nJ + l + 1);
       mmax = std::max(mmax, p.r[n][l - 1] * dl);
     }
-    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, PREC_FP64, p.cplx), 1, launch_contract(OP_NONE, PREC_FP64, c, mmax, p.capJ[l + 1], s));
+    ENQC(q, 1, OP_NONE, PREC_FP64, c, mmax, p.capJ[l + 1], -1);
     GatherArgs g{};
     g.esz = p.ew;
     g.count = p.N;
@@ -616,8 +626,7 @@ int enqueue_pi(Enq& q, int l) {
   gr.M = ddev(p.nI + l - 1, p.d[l]);
   gr.N = ddev(p.nJ + l + 2, p.d[l + 1]);
   gr.ldc = dconst(p.ldm);
-  ENQPV(q, CLS_CONTRACT, contract_variant(p.op, p.prec, p.cplx), 2,
-        launch_contract(p.op, p.prec, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], q.s));
+  ENQC(q, 2, p.op, p.prec, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], p.tiles[2][l]);
   return ACI_OK;
 }
 
@@ -651,8 +660,7 @@ int enqueue_update(Enq& q, int u, int stage) {
         gr.ldc = dconst(w);
         nmax = std::max(nmax, w);
       }
-      ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec, p.cplx), 1,
-            launch_contract(OP_NONE, p.prec, c, p.capI[l - 1], nmax, s));
+      ENQC(q, 1, OP_NONE, p.prec, c, p.capI[l - 1], nmax, p.tiles[0][l]);
       int rc = enqueue_pi(q, l);
       if (rc) return rc;
       const int mmax = p.d[l] * p.capI[l - 1], nmax2 = p.d[l + 1] * p.capJ[l + 2];
@@ -707,8 +715,7 @@ int enqueue_update(Enq& q, int u, int stage) {
       gr.ldc = ddev(p.nJ + l + 2);
       mmax = std::max(mmax, p.r[n][l] * p.d[l + 1]);
     }
-    ENQPV(q, CLS_CONTRACT, contract_variant(OP_NONE, p.prec, p.cplx), 1,
-          launch_contract(OP_NONE, p.prec, c, mmax, p.capJ[l + 2], s));
+    ENQC(q, 1, OP_NONE, p.prec, c, mmax, p.capJ[l + 2], p.tiles[1][l]);
     int rc = enqueue_pi(q, l);
     if (rc) return rc;
     const int* skip = nullptr;
@@ -1019,6 +1026,82 @@ void aci_session_destroy(aci_session* S) {
 }
 
 namespace {
+// Contraction tile autotuner: times ngroup copies of an m x k by k x n
+// product (seeded uniform operands, complex when cplx, one term) with every
+// output tile and keeps the fastest, cached per context.  us (optional):
+// mean time per launch of each tile.
+int tune_tile(aci_ctx* ctx, int cplx, int prec, int ngroup, int m, int k, int n, int* best, float* us) {
+  if (m < 1 || k < 1 || n < 1 || m > ACI_MAX_MATRIX || n > ACI_MAX_MATRIX || k > ACI_MAX_MATRIX ||
+      ngroup < 1 || ngroup > ACI_MAX_INPUTS)
+    return set_err(ctx, ACI_E_LIMIT, "tuning shape out of range");
+  const uint64_t key = ((uint64_t)m << 40) | ((uint64_t)k << 28) | ((uint64_t)n << 16) |
+                       ((uint64_t)ngroup << 8) | ((uint64_t)prec << 4) | (uint64_t)(cplx ? 1 : 0);
+  auto hit = ctx->tuned_tiles.find(key);
+  if (hit != ctx->tuned_tiles.end() && !us) {
+    *best = hit->second;
+    return ACI_OK;
+  }
+  const int ew = cplx ? 2 : 1;
+  const size_t na = (size_t)m * k * ew, nb = (size_t)k * n * ew, nc = (size_t)m * n * ew;
+  void* ws = nullptr;
+  if (!dev_alloc(ctx, &ws, (na + nb + nc * ngroup) * sizeof(double))) return set_err(ctx, ACI_E_NOMEM, "tuning workspace");
+  double* A = (double*)ws;
+  double* B = A + na;
+  double* Cb = B + nb;
+  std::vector<double> h(na + nb);
+  SplitMix64 rng{0x7113ull + (uint64_t)m * 131u + (uint64_t)k * 7u + (uint64_t)n};
+  for (double& x : h) x = rng.uniform();
+  ContractArgs c{};
+  c.cplx = cplx;
+  c.ngroup = ngroup;
+  for (int g = 0; g < ngroup; ++g) {
+    c.g[g].nterm = 1;
+    c.g[g].t[0] = Term{A, B, dconst(k), dconst(k), dconst(n)};
+    c.g[g].C = Cb + (size_t)g * nc;
+    c.g[g].M = dconst(m);
+    c.g[g].N = dconst(n);
+    c.g[g].ldc = dconst(n);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = ACI_OK;
+  float best_us = 1e30f;
+  int bt = contract_default_tile(m, n, ngroup, cplx);
+  if (hipMemcpy(A, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = set_err(ctx, ACI_E_HIP, "tuning set-up");
+  }
+  for (int t = 0; t < NUM_TILES && rc == ACI_OK; ++t) {
+    constexpr int reps = 3;
+    hipError_t e = launch_contract(OP_NONE, prec, c, m, n, ctx->stream, t);
+    if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_contract(OP_NONE, prec, c, m, n, ctx->stream, t);
+    if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      rc = set_err(ctx, ACI_E_HIP, std::string("tuning launch: ") + hipGetErrorString(e));
+      break;
+    }
+    const float t_us = 1e3f * ms / reps;
+    if (us) us[t] = t_us;
+    if (t_us < best_us) {
+      best_us = t_us;
+      bt = t;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, ws);
+  if (rc) return rc;
+  ctx->tuned_tiles[key] = bt;
+  *best = bt;
+  return ACI_OK;
+}
+
 struct Placement {
   int xcd = 0, max_groups = 0, cooperative = 1;
 };
@@ -1052,6 +1135,25 @@ int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t
   if (rc) return rc;
   S->fixed = p.fixed;
   S->prof.on = o.profile != 0;
+  for (auto& row : p.tiles) std::fill(row, row + ACI_MAX_SITES + 2, -1);
+  if (o.tune) {
+    // contraction tile of every environment and two-site launch shape
+    for (int l = 1; l < p.L; ++l) {
+      int wl = 1, kl = 1, mr = 1, kr = 1, kp = 1;
+      for (int n = 0; n < p.N; ++n) {
+        wl = std::max(wl, p.d[l] * p.r[n][l]);
+        kl = std::max(kl, p.r[n][l - 1]);
+        mr = std::max(mr, p.r[n][l] * p.d[l + 1]);
+        kr = std::max(kr, p.r[n][l + 1]);
+        kp = std::max(kp, p.r[n][l]);
+      }
+      if ((rc = tune_tile(ctx, p.cplx, p.prec, p.N, p.capI[l - 1], kl, wl, &p.tiles[0][l], nullptr))) return rc;
+      if ((rc = tune_tile(ctx, p.cplx, p.prec, p.N, mr, kr, p.capJ[l + 2], &p.tiles[1][l], nullptr))) return rc;
+      if ((rc = tune_tile(ctx, p.cplx, p.prec, 1, p.d[l] * p.capI[l - 1], kp, p.d[l + 1] * p.capJ[l + 2],
+                          &p.tiles[2][l], nullptr)))
+        return rc;
+    }
+  }
   // graphs need launches with static arguments: no events, no trace records
   S->use_graph = o.use_graph != 0 && !S->prof.on && !p.trace;
   p.xcd = pl.xcd;
@@ -1211,7 +1313,10 @@ int sweep_finish(aci_session* S, aci_sweep_stats& st) {
     rec.sweep = S->sweeps - 1;
     rec.update = S->prof.slot[i] - (L - 1);
     rec.us = 1e3f * kms;
-    if (rec.update >= 0 && rec.update < 2 * (L - 1) && c != CLS_GATHER && rec.variant < 20000) {
+    // flops of the LDU and contraction launches (not of the proposal kernels,
+    // which are logged in the LDU class with codes 20001..20008)
+    const bool proposal_kernel = c == CLS_PRRLU && rec.variant >= 20000 && rec.variant < 30000;
+    if (rec.update >= 0 && rec.update < 2 * (L - 1) && c != CLS_GATHER && !proposal_kernel) {
       int kind, bond;
       update_of(L, rec.update, kind, bond);
       const int* mt = meta + 3 * rec.update;
@@ -2063,6 +2168,16 @@ int aci_rook_right_factor(aci_ctx* ctx, const void* Up, int32_t ldu, const int32
 }
 
 // ------------------------------------------------------------ autotuner
+int aci_tune_contract(aci_ctx* ctx, int32_t dtype, int32_t precision, int32_t ngroup, int32_t m, int32_t k,
+                      int32_t n, int32_t* best_tile, float* us) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!best_tile) return set_err(ctx, ACI_E_INVALID, "null argument");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
+  if (precision < ACI_PREC_FP64 || precision > ACI_PREC_BF16X3) return set_err(ctx, ACI_E_DTYPE, "unknown precision");
+  return tune_tile(ctx, dtype == ACI_C128, precision, ngroup, m, k, n, best_tile, us);
+}
+
 int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t cap, int32_t* best_groups,
                    int32_t* candidates, float* us, int32_t capacity, int32_t* count) {
   if (!ctx) return ACI_E_INVALID;
@@ -2227,7 +2342,7 @@ int aci_env_contract(aci_ctx* ctx, int32_t dtype, int32_t side, int32_t count, c
 
 int aci_pi_eval(aci_ctx* ctx, int32_t dtype, int32_t op, int32_t n_inputs, const void* const* A,
                 const void* const* B, const int32_t* k, int32_t m, int32_t n, void* M, int32_t ldm,
-                int32_t precision) {
+                int32_t precision, int32_t tile) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
   if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
@@ -2254,7 +2369,8 @@ int aci_pi_eval(aci_ctx* ctx, int32_t dtype, int32_t op, int32_t n_inputs, const
   g.M = dconst(m);
   g.N = dconst(n);
   g.ldc = dconst(ldm);
-  HIPCHK(launch_contract(op, precision, a, m, n, ctx->stream));
+  if (tile < -1 || tile >= NUM_TILES) return set_err(ctx, ACI_E_INVALID, "tile must be -1, 0, 1 or 2");
+  HIPCHK(launch_contract(op, precision, a, m, n, ctx->stream, tile));
   int flags = 0;
   HIPCHK(hipMemcpyAsync(&flags, ctx->step_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));

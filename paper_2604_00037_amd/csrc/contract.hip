@@ -3,9 +3,12 @@
 // Environment contractions A = L_{l-1} X_l and B = X_{l+1} R_{l+2} and the
 // two-site tensors Pi^n = A^n B^n (Eq. pifromframes), with the elementwise f
 // of Eq. (localupdate) applied in the epilogue so that Pi = f(Pi^1..Pi^N) is
-// written once.  Each workgroup computes a 64x64 output tile; its four waves
-// each own a 32x32 quarter made of 2x2 blocks of 16x16 MFMA tiles.  Operands
-// are FP64 in HBM and the result is written in FP64 in every precision:
+// written once.  Each workgroup computes a TM x TN output tile (64x64, 32x64
+// or 32x32, picked per shape by a heuristic or the autotuner); its four
+// waves each own a quarter made of 16x16 MFMA blocks.  Every output element
+// is accumulated by the same MFMA sequence (k ascending) whatever the tile,
+// so the tile shape never changes a result.  Operands are FP64 in HBM and
+// the result is written in FP64 in every precision:
 //
 // * FP64: v_mfma_f64_16x16x4f64; 64x16 (A, k-major) and 16x64 (B) tiles in
 //   LDS so that every lane of an MFMA reads consecutive doubles.
@@ -35,59 +38,74 @@ namespace aci {
 
 namespace {
 
-constexpr int TM = 64;
-constexpr int TN = 64;
-constexpr int KC = 32;        // k per staged chunk (every precision)
-constexpr int LDA_S = TM + 2;
-constexpr int LDB_S = TN + 2;
+constexpr int KC = 32;        // k per load chunk (FP64 stages one, FP32 / BF16x3 two)
 
-// One staged chunk (64 x 32 of A, 32 x 64 of B in the real view) is loaded
-// by the 256 threads into registers, eight values of each operand per
-// thread, while the previous chunk is multiplied from LDS.
-//   A value e of thread t: row t / 4, k 8 (t % 4) + e.
-//   B value e, real:    k t / 8,               column 8 (t % 8) + e.
-//   B value e, complex: k 2 (t / 16) + e / 4,  column 4 (t % 16) + e % 4;
-// complex B is read once per element (two neighbouring elements per thread)
-// and expanded in registers into its 2 x 2 real block.
-__device__ __forceinline__ int a_row(int t) { return t >> 2; }
-__device__ __forceinline__ int a_k(int t, int e) { return ((t & 3) << 3) + e; }
-template <bool CPLX>
-__device__ __forceinline__ int b_k(int t, int e) { return CPLX ? 2 * (t >> 4) + (e >> 2) : t >> 3; }
-template <bool CPLX>
-__device__ __forceinline__ int b_col(int t, int e) { return CPLX ? ((t & 15) << 2) + (e & 3) : ((t & 7) << 3) + e; }
+// Shape of a TM x TN output tile (TM, TN in {32, 64}).  One chunk of A (TM x
+// 32) and B (32 x TN, real view) is loaded by the 256 threads into
+// registers, EA and EB values per thread, while the previous chunk is
+// multiplied from LDS.
+//   A value e of thread t: row t / TPA, k EA (t % TPA) + e.
+//   B value e, real:    k t / TPB, column EB (t % TPB) + e.
+//   B value e, complex: k 2 ct + e / (EB/2), column 2 cj0 + e % (EB/2) with
+//     ct = t / TPC, cj0 = CE (t % TPC): complex B is read once per element
+//     (CE neighbouring elements per thread) and expanded in registers into
+//     its 2 x 2 real block.
+template <int TM_, int TN_>
+struct Tile {
+  static constexpr int TM = TM_, TN = TN_;
+  static constexpr int EA = TM * KC / 256;
+  static constexpr int EB = TN * KC / 256;
+  static constexpr int TPA = KC / EA;
+  static constexpr int TPB = TN / EB;
+  static constexpr int CE = EB / 4;
+  static constexpr int TPC = (TN / 2) / CE;
+  static constexpr int MI = TM / 32;   // 16-row blocks per wave (waves are 2 x 2)
+  static constexpr int NJ = TN / 32;   // 16-column blocks per wave
+  static constexpr int LDA = TM + 2;   // FP64 LDS pitches ([k][row], [k][col])
+  static constexpr int LDB = TN + 2;
+  __device__ static int a_row(int t) { return t / TPA; }
+  __device__ static int a_k(int t, int e) { return (t % TPA) * EA + e; }
+  template <bool CPLX>
+  __device__ static int b_k(int t, int e) {
+    return CPLX ? 2 * (t / TPC) + e / (EB / 2) : t / TPB;
+  }
+  template <bool CPLX>
+  __device__ static int b_col(int t, int e) {
+    return CPLX ? 2 * CE * (t % TPC) + e % (EB / 2) : (t % TPB) * EB + e;
+  }
+};
 
-template <bool CPLX>
+template <class TL, bool CPLX>
 __device__ __forceinline__ void load_chunk(const Term& T, int M, int N, int K, int lda, int ldb, int m0, int n0,
-                                           int k0, int t, double (&av)[8], double (&bv)[8]) {
-  const int gr = m0 + a_row(t);
+                                           int k0, int t, double (&av)[TL::EA], double (&bv)[TL::EB]) {
+  const int gr = m0 + TL::a_row(t);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int gk = k0 + a_k(t, e);
+  for (int e = 0; e < TL::EA; ++e) {
+    const int gk = k0 + TL::a_k(t, e);
     av[e] = (gr < M && gk < K) ? T.A[(size_t)gr * lda + gk] : 0.0;
   }
   if (!CPLX) {
-    const int gk = k0 + b_k<false>(t, 0);
+    const int gk = k0 + TL::template b_k<false>(t, 0);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int gc = n0 + b_col<false>(t, e);
+    for (int e = 0; e < TL::EB; ++e) {
+      const int gc = n0 + TL::template b_col<false>(t, e);
       bv[e] = (gk < K && gc < N) ? T.B[(size_t)gk * ldb + gc] : 0.0;
     }
   } else {
-    // complex row (k0 + 2 (t / 16)) / 2, columns (n0 + 4 (t % 16)) / 2 + q
-    const int ct = (k0 >> 1) + (t >> 4);
-    const int cj = (n0 >> 1) + ((t & 15) << 1);
+    const int ct = (k0 >> 1) + t / TL::TPC;
+    const int cj = (n0 >> 1) + TL::CE * (t % TL::TPC);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < TL::CE; ++q) {
       double re = 0.0, im = 0.0;
       if (2 * ct < K && 2 * (cj + q) < N) {
         const double* e = T.B + 2 * ((size_t)ct * ldb + cj + q);
         re = e[0];
         im = e[1];
       }
-      bv[2 * q] = re;         // real row 2ct:     (re, im)
+      bv[2 * q] = re;                    // real row 2ct:     (re, im)
       bv[2 * q + 1] = im;
-      bv[4 + 2 * q] = -im;    // real row 2ct + 1: (-im, re)
-      bv[4 + 2 * q + 1] = re;
+      bv[TL::EB / 2 + 2 * q] = -im;      // real row 2ct + 1: (-im, re)
+      bv[TL::EB / 2 + 2 * q + 1] = re;
     }
   }
 }
@@ -115,112 +133,126 @@ __device__ __forceinline__ double abs2_mul(double x, double x_o, bool even) {
   return a * x;
 }
 
-template <int OP, bool CPLX>
-__global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
-  __shared__ double sA[KC * LDA_S];
-  __shared__ double sB[KC * LDB_S];
-  constexpr int W = CPLX ? 2 : 1;
-  const Group& g = args.g[blockIdx.z];
-  const int M = dget(g.M);
-  const int N = W * dget(g.N);
-  const int m0 = blockIdx.y * TM;
-  const int n0 = blockIdx.x * TN;
-  if (m0 >= M || n0 >= N) return;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lr = lane & 15, lk = lane >> 4;
-
-  const bool even = (lr & 1) == 0;
-  v4d res[2][2];
-  for (int t = 0; t < g.nterm; ++t) {
-    const Term& T = g.t[t];
-    const int K = W * dget(T.K);
-    const int lda = W * dget(T.lda);
-    const int ldb = dget(T.ldb);
-    v4d acc[2][2];
+// Epilogue of one term: fold the term's accumulators into the running
+// result (f of Eq. localupdate), element by element.
+template <int OP, bool CPLX, int MI, int NJ>
+__device__ __forceinline__ void fold_term(v4d (&res)[MI][NJ], const v4d (&x)[MI][NJ], int t, bool even) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-
-    double av[8], bv[8];
-    load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av, bv);
-    for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int j = 0; j < NJ; ++j) {
+      if (OP == OP_ABS2_MUL) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        sA[a_k(tid, e) * LDA_S + a_row(tid)] = av[e];
-        sB[b_k<CPLX>(tid, e) * LDB_S + b_col<CPLX>(tid, e)] = bv[e];
-      }
-      __syncthreads();
-      // the next chunk's loads are in flight while this one is multiplied
-      if (k0 + KC < K) load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KC, tid, av, bv);
-#pragma unroll
-      for (int ks = 0; ks < KC / 4; ++ks) {
-        const int kr = ks * 4 + lk;
-        double a[2], b[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = sA[kr * LDA_S + wm * 32 + i * 16 + lr];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = sB[kr * LDB_S + wn * 32 + j * 16 + lr];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if (OP == OP_ABS2_MUL) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const double x = acc[i][j][v];
-            const double xo = CPLX ? __shfl_xor(x, 1) : x;
-            res[i][j][v] = abs2_mul<CPLX>(x, xo, even);
-          }
-        } else if (OP == OP_NONE || t == 0) {
-          res[i][j] = acc[i][j];
-        } else if (CPLX && OP == OP_PRODUCT) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const double r0 = res[i][j][v], a0 = acc[i][j][v];
-            const double ro = __shfl_xor(r0, 1), ao = __shfl_xor(a0, 1);
-            res[i][j][v] = cplx_combine<OP>(r0, ro, a0, ao, even);
-          }
-        } else {
-          res[i][j] = combine<OP>(res[i][j], acc[i][j]);
+        for (int v = 0; v < 4; ++v) {
+          const double xv = x[i][j][v];
+          const double xo = CPLX ? __shfl_xor(xv, 1) : xv;
+          res[i][j][v] = abs2_mul<CPLX>(xv, xo, even);
         }
+      } else if (OP == OP_NONE || t == 0) {
+        res[i][j] = x[i][j];
+      } else if (CPLX && OP == OP_PRODUCT) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double r0 = res[i][j][v], a0 = x[i][j][v];
+          const double ro = __shfl_xor(r0, 1), ao = __shfl_xor(a0, 1);
+          res[i][j][v] = cplx_combine<OP>(r0, ro, a0, ao, even);
+        }
+      } else {
+        res[i][j] = combine<OP>(res[i][j], x[i][j]);
       }
-  }
+    }
+}
 
-  const int ldc = W * dget(g.ldc);
+// Store of the result tile; row of accumulator item v of a 16x16 block is
+// rowbase + RSTEP v (FP64 layout: lk + 4v; FP32: 4 lg + v).
+template <int OP, int MI, int NJ>
+__device__ __forceinline__ void store_tile(const Group& g, const v4d (&res)[MI][NJ], int M, int N, int ldc,
+                                           int row0, int col0, int rstep, int* err) {
   bool bad = false;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 32 + i * 16 + lk + 4 * v;
-        const int col = n0 + wn * 32 + j * 16 + lr;
+        const int row = row0 + i * 16 + rstep * v;
+        const int col = col0 + j * 16;
         if (row < M && col < N) {
           const double x = res[i][j][v];
           if (OP != OP_NONE && !__builtin_isfinite(x)) bad = true;
           g.C[(size_t)row * ldc + col] = x;
         }
       }
-  if (OP != OP_NONE && bad && args.err) atomicOr(args.err, ERR_NONFINITE);
+  if (OP != OP_NONE && bad && err) atomicOr(err, ERR_NONFINITE);
+}
+
+template <int OP, bool CPLX, class TL>
+__global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
+  __shared__ double sA[KC * TL::LDA];
+  __shared__ double sB[KC * TL::LDB];
+  constexpr int W = CPLX ? 2 : 1;
+  constexpr int MI = TL::MI, NJ = TL::NJ;
+  const Group& g = args.g[blockIdx.z];
+  const int M = dget(g.M);
+  const int N = W * dget(g.N);
+  const int m0 = blockIdx.y * TL::TM;
+  const int n0 = blockIdx.x * TL::TN;
+  if (m0 >= M || n0 >= N) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool even = (lr & 1) == 0;
+
+  v4d res[MI][NJ];
+  for (int t = 0; t < g.nterm; ++t) {
+    const Term& T = g.t[t];
+    const int K = W * dget(T.K);
+    const int lda = W * dget(T.lda);
+    const int ldb = dget(T.ldb);
+    v4d acc[MI][NJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    double av[TL::EA], bv[TL::EB];
+    load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av, bv);
+    for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+      for (int e = 0; e < TL::EA; ++e) sA[TL::a_k(tid, e) * TL::LDA + TL::a_row(tid)] = av[e];
+#pragma unroll
+      for (int e = 0; e < TL::EB; ++e)
+        sB[TL::template b_k<CPLX>(tid, e) * TL::LDB + TL::template b_col<CPLX>(tid, e)] = bv[e];
+      __syncthreads();
+      // the next chunk's loads are in flight while this one is multiplied
+      if (k0 + KC < K) load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KC, tid, av, bv);
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        const int kr = ks * 4 + lk;
+        double a[MI], b[NJ];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) a[i] = sA[kr * TL::LDA + wm * (TL::TM / 2) + i * 16 + lr];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) b[j] = sB[kr * TL::LDB + wn * (TL::TN / 2) + j * 16 + lr];
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+    fold_term<OP, CPLX, MI, NJ>(res, acc, t, even);
+  }
+  store_tile<OP, MI, NJ>(g, res, M, N, W * dget(g.ldc), m0 + wm * (TL::TM / 2) + lk,
+                         n0 + wn * (TL::TN / 2) + lr, 4, args.err);
 }
 
 // ---------------------------------------------------------------- FP32 / BF16x3
 constexpr int KL = 2 * KC;    // k per staged chunk: two load chunks (the
                               // low-precision products are cheaper per k)
-constexpr int LDF = TM + 4;   // FP32 tiles, k-major rows of 64 (+pad)
 constexpr int LDH = KL + 8;   // bf16 tiles, 64 k per row/column (+pad; 16-byte rows)
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -233,30 +265,32 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
-template <int PREC>
+template <int PREC, class TL>
 struct LpTiles;
 
-template <>
-struct LpTiles<PREC_FP32> {
-  float A[KL * LDF];   // [k][row]
-  float B[KL * LDF];   // [k][col]
+template <class TL>
+struct LpTiles<PREC_FP32, TL> {
+  float A[KL * (TL::TM + 4)];   // [k][row]
+  float B[KL * (TL::TN + 4)];   // [k][col]
 };
 
-template <>
-struct LpTiles<PREC_BF16X3> {
-  unsigned short Ah[TM * LDH], Al[TM * LDH];   // [row][k]
-  unsigned short Bh[TN * LDH], Bl[TN * LDH];   // [col][k]
+template <class TL>
+struct LpTiles<PREC_BF16X3, TL> {
+  unsigned short Ah[TL::TM * LDH], Al[TL::TM * LDH];   // [row][k]
+  unsigned short Bh[TL::TN * LDH], Bl[TL::TN * LDH];   // [col][k]
 };
 
-template <int OP, int PREC, bool CPLX>
+template <int OP, int PREC, bool CPLX, class TL>
 __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
-  __shared__ LpTiles<PREC> sh;
+  __shared__ LpTiles<PREC, TL> sh;
   constexpr int W = CPLX ? 2 : 1;
+  constexpr int MI = TL::MI, NJ = TL::NJ;
+  constexpr int LDFA = TL::TM + 4, LDFB = TL::TN + 4;
   const Group& g = args.g[blockIdx.z];
   const int M = dget(g.M);
   const int N = W * dget(g.N);
-  const int m0 = blockIdx.y * TM;
-  const int n0 = blockIdx.x * TN;
+  const int m0 = blockIdx.y * TL::TM;
+  const int n0 = blockIdx.x * TL::TN;
   if (m0 >= M || n0 >= N) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -265,43 +299,46 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
   const int lr = lane & 15, lg = lane >> 4;
   const bool even = (lr & 1) == 0;
 
-  v4d res[2][2];
+  v4d res[MI][NJ];
   for (int t = 0; t < g.nterm; ++t) {
     const Term& T = g.t[t];
     const int K = W * dget(T.K);
     const int lda = W * dget(T.lda);
     const int ldb = dget(T.ldb);
-    v4f acc[2][2];
+    v4f acc[MI][NJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < NJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    double av[2][8], bv[2][8];
-    load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av[0], bv[0]);
-    load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, KC, tid, av[1], bv[1]);
+    double av[2][TL::EA], bv[2][TL::EB];
+    load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av[0], bv[0]);
+    load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, KC, tid, av[1], bv[1]);
     for (int k0 = 0; k0 < K; k0 += KL) {
-      const int ar = a_row(tid);
+      const int ar = TL::a_row(tid);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int kh = KC * h;
         if (PREC == PREC_FP32) {
-          auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
+          auto& S = reinterpret_cast<LpTiles<PREC_FP32, TL>&>(sh);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            S.A[(kh + a_k(tid, e)) * LDF + ar] = (float)av[h][e];
-            S.B[(kh + b_k<CPLX>(tid, e)) * LDF + b_col<CPLX>(tid, e)] = (float)bv[h][e];
-          }
+          for (int e = 0; e < TL::EA; ++e) S.A[(kh + TL::a_k(tid, e)) * LDFA + ar] = (float)av[h][e];
+#pragma unroll
+          for (int e = 0; e < TL::EB; ++e)
+            S.B[(kh + TL::template b_k<CPLX>(tid, e)) * LDFB + TL::template b_col<CPLX>(tid, e)] = (float)bv[h][e];
         } else {
-          auto& S = reinterpret_cast<LpTiles<PREC_BF16X3>&>(sh);
+          auto& S = reinterpret_cast<LpTiles<PREC_BF16X3, TL>&>(sh);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int ak = kh + a_k(tid, e);
+          for (int e = 0; e < TL::EA; ++e) {
+            const int ak = kh + TL::a_k(tid, e);
             const float fa = (float)av[h][e];
             const unsigned short ha = bf16_bits(fa);
             S.Ah[ar * LDH + ak] = ha;
             S.Al[ar * LDH + ak] = bf16_bits(fa - bf16_value(ha));
-            const int bk = kh + b_k<CPLX>(tid, e), bc = b_col<CPLX>(tid, e);
+          }
+#pragma unroll
+          for (int e = 0; e < TL::EB; ++e) {
+            const int bk = kh + TL::template b_k<CPLX>(tid, e), bc = TL::template b_col<CPLX>(tid, e);
             const float fb = (float)bv[h][e];
             const unsigned short hb = bf16_bits(fb);
             S.Bh[bc * LDH + bk] = hb;
@@ -312,46 +349,46 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
       __syncthreads();
       // the next chunk's loads are in flight while this one is multiplied
       if (k0 + KL < K) {
-        load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL, tid, av[0], bv[0]);
-        load_chunk<CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL + KC, tid, av[1], bv[1]);
+        load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL, tid, av[0], bv[0]);
+        load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL + KC, tid, av[1], bv[1]);
       }
       if (PREC == PREC_FP32) {
-        auto& S = reinterpret_cast<LpTiles<PREC_FP32>&>(sh);
+        auto& S = reinterpret_cast<LpTiles<PREC_FP32, TL>&>(sh);
 #pragma unroll
         for (int ks = 0; ks < KL / 4; ++ks) {
           const int kr = ks * 4 + lg;
-          float a[2], b[2];
+          float a[MI], b[NJ];
 #pragma unroll
-          for (int i = 0; i < 2; ++i) a[i] = S.A[kr * LDF + wm * 32 + i * 16 + lr];
+          for (int i = 0; i < MI; ++i) a[i] = S.A[kr * LDFA + wm * (TL::TM / 2) + i * 16 + lr];
 #pragma unroll
-          for (int j = 0; j < 2; ++j) b[j] = S.B[kr * LDF + wn * 32 + j * 16 + lr];
+          for (int j = 0; j < NJ; ++j) b[j] = S.B[kr * LDFB + wn * (TL::TN / 2) + j * 16 + lr];
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < MI; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < NJ; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
       } else {
-        auto& S = reinterpret_cast<LpTiles<PREC_BF16X3>&>(sh);
+        auto& S = reinterpret_cast<LpTiles<PREC_BF16X3, TL>&>(sh);
 #pragma unroll
         for (int ks = 0; ks < KL / 32; ++ks) {
-          v8bf ah[2], al[2], bh[2], bl[2];
+          v8bf ah[MI], al[MI], bh[NJ], bl[NJ];
 #pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const int row = wm * 32 + i * 16 + lr;
+          for (int i = 0; i < MI; ++i) {
+            const int row = wm * (TL::TM / 2) + i * 16 + lr;
             ah[i] = *reinterpret_cast<const v8bf*>(&S.Ah[row * LDH + 32 * ks + 8 * lg]);
             al[i] = *reinterpret_cast<const v8bf*>(&S.Al[row * LDH + 32 * ks + 8 * lg]);
           }
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const int col = wn * 32 + j * 16 + lr;
+          for (int j = 0; j < NJ; ++j) {
+            const int col = wn * (TL::TN / 2) + j * 16 + lr;
             bh[j] = *reinterpret_cast<const v8bf*>(&S.Bh[col * LDH + 32 * ks + 8 * lg]);
             bl[j] = *reinterpret_cast<const v8bf*>(&S.Bl[col * LDH + 32 * ks + 8 * lg]);
           }
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < MI; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < NJ; ++j) {
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
@@ -360,90 +397,84 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
       }
       __syncthreads();
     }
+    v4d x[MI][NJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const v4d x = v4d{(double)acc[i][j][0], (double)acc[i][j][1], (double)acc[i][j][2], (double)acc[i][j][3]};
-        if (OP == OP_ABS2_MUL) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const double xv = x[v];
-            const double xo = CPLX ? __shfl_xor(xv, 1) : xv;
-            res[i][j][v] = abs2_mul<CPLX>(xv, xo, even);
-          }
-        } else if (OP == OP_NONE || t == 0) {
-          res[i][j] = x;
-        } else if (CPLX && OP == OP_PRODUCT) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const double r0 = res[i][j][v], a0 = x[v];
-            const double ro = __shfl_xor(r0, 1), ao = __shfl_xor(a0, 1);
-            res[i][j][v] = cplx_combine<OP>(r0, ro, a0, ao, even);
-          }
-        } else {
-          res[i][j] = combine<OP>(res[i][j], x);
-        }
-      }
+      for (int j = 0; j < NJ; ++j)
+        x[i][j] = v4d{(double)acc[i][j][0], (double)acc[i][j][1], (double)acc[i][j][2], (double)acc[i][j][3]};
+    fold_term<OP, CPLX, MI, NJ>(res, x, t, even);
   }
+  store_tile<OP, MI, NJ>(g, res, M, N, W * dget(g.ldc), m0 + wm * (TL::TM / 2) + 4 * lg,
+                         n0 + wn * (TL::TN / 2) + lr, 1, args.err);
+}
 
-  const int ldc = W * dget(g.ldc);
-  bool bad = false;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 32 + i * 16 + 4 * lg + v;
-        const int col = n0 + wn * 32 + j * 16 + lr;
-        if (row < M && col < N) {
-          const double x = res[i][j][v];
-          if (OP != OP_NONE && !__builtin_isfinite(x)) bad = true;
-          g.C[(size_t)row * ldc + col] = x;
-        }
-      }
-  if (OP != OP_NONE && bad && args.err) atomicOr(args.err, ERR_NONFINITE);
+using T64x64 = Tile<64, 64>;
+using T32x64 = Tile<32, 64>;
+using T32x32 = Tile<32, 32>;
+
+template <int OP, int PREC, bool CPLX, class TL>
+const void* kernel_of() {
+  if constexpr (PREC == PREC_FP64) return (const void*)contract_kernel<OP, CPLX, TL>;
+  else return (const void*)contract_lp_kernel<OP, PREC, CPLX, TL>;
+}
+
+template <int PREC, bool CPLX, class TL>
+const void* pick_op(int op) {
+  switch (op) {
+    case OP_NONE: return kernel_of<OP_NONE, PREC, CPLX, TL>();
+    case OP_PRODUCT: return kernel_of<OP_PRODUCT, PREC, CPLX, TL>();
+    case OP_SUM: return kernel_of<OP_SUM, PREC, CPLX, TL>();
+    case OP_ABS2_MUL: return kernel_of<OP_ABS2_MUL, PREC, CPLX, TL>();
+    default: return nullptr;
+  }
 }
 
 template <int PREC, bool CPLX>
-hipError_t launch_prec(int op, const ContractArgs& args, dim3 grid, dim3 block, hipStream_t s) {
-  switch (op) {
-    case OP_NONE: hipLaunchKernelGGL((contract_lp_kernel<OP_NONE, PREC, CPLX>), grid, block, 0, s, args); break;
-    case OP_PRODUCT: hipLaunchKernelGGL((contract_lp_kernel<OP_PRODUCT, PREC, CPLX>), grid, block, 0, s, args); break;
-    case OP_SUM: hipLaunchKernelGGL((contract_lp_kernel<OP_SUM, PREC, CPLX>), grid, block, 0, s, args); break;
-    case OP_ABS2_MUL: hipLaunchKernelGGL((contract_lp_kernel<OP_ABS2_MUL, PREC, CPLX>), grid, block, 0, s, args); break;
-    default: return hipErrorInvalidValue;
+const void* pick_tile(int op, int tile) {
+  switch (tile) {
+    case TILE_64x64: return pick_op<PREC, CPLX, T64x64>(op);
+    case TILE_32x64: return pick_op<PREC, CPLX, T32x64>(op);
+    case TILE_32x32: return pick_op<PREC, CPLX, T32x32>(op);
+    default: return nullptr;
   }
-  return hipGetLastError();
 }
 
-template <bool CPLX>
-hipError_t launch_fp64(int op, const ContractArgs& args, dim3 grid, dim3 block, hipStream_t s) {
-  switch (op) {
-    case OP_NONE: hipLaunchKernelGGL((contract_kernel<OP_NONE, CPLX>), grid, block, 0, s, args); break;
-    case OP_PRODUCT: hipLaunchKernelGGL((contract_kernel<OP_PRODUCT, CPLX>), grid, block, 0, s, args); break;
-    case OP_SUM: hipLaunchKernelGGL((contract_kernel<OP_SUM, CPLX>), grid, block, 0, s, args); break;
-    case OP_ABS2_MUL: hipLaunchKernelGGL((contract_kernel<OP_ABS2_MUL, CPLX>), grid, block, 0, s, args); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
+const int kTileM[3] = {64, 32, 32};
+const int kTileN[3] = {64, 64, 32};
 
 }  // namespace
 
-hipError_t launch_contract(int op, int prec, const ContractArgs& args, int mmax, int nmax, hipStream_t s) {
+int contract_tiles(int tile, int mmax, int nmax, int ngroup, int cplx) {
+  if (tile < 0 || tile >= NUM_TILES) return -1;
+  const int nreal = cplx ? 2 * nmax : nmax;
+  return ((nreal + kTileN[tile] - 1) / kTileN[tile]) * ((mmax + kTileM[tile] - 1) / kTileM[tile]) * ngroup;
+}
+
+int contract_default_tile(int mmax, int nmax, int ngroup, int cplx) {
+  // the largest tile that still gives every CU a workgroup
+  for (int t = 0; t < NUM_TILES; ++t)
+    if (contract_tiles(t, mmax, nmax, ngroup, cplx) >= 256) return t;
+  return NUM_TILES - 1;
+}
+
+hipError_t launch_contract(int op, int prec, const ContractArgs& args, int mmax, int nmax, hipStream_t s, int tile) {
   if (mmax <= 0 || nmax <= 0 || args.ngroup <= 0) return hipSuccess;
   const bool cplx = args.cplx != 0;
+  if (tile < 0) tile = contract_default_tile(mmax, nmax, args.ngroup, cplx);
+  if (tile >= NUM_TILES) return hipErrorInvalidValue;
+  const void* fn = nullptr;
+  if (prec == PREC_FP64) fn = cplx ? pick_tile<PREC_FP64, true>(op, tile) : pick_tile<PREC_FP64, false>(op, tile);
+  else if (prec == PREC_FP32) fn = cplx ? pick_tile<PREC_FP32, true>(op, tile) : pick_tile<PREC_FP32, false>(op, tile);
+  else if (prec == PREC_BF16X3) fn = cplx ? pick_tile<PREC_BF16X3, true>(op, tile) : pick_tile<PREC_BF16X3, false>(op, tile);
+  if (!fn) return hipErrorInvalidValue;
   const int nreal = cplx ? 2 * nmax : nmax;
-  dim3 grid((nreal + TN - 1) / TN, (mmax + TM - 1) / TM, args.ngroup);
-  dim3 block(256);
-  if (prec == PREC_FP32) return cplx ? launch_prec<PREC_FP32, true>(op, args, grid, block, s)
-                                     : launch_prec<PREC_FP32, false>(op, args, grid, block, s);
-  if (prec == PREC_BF16X3) return cplx ? launch_prec<PREC_BF16X3, true>(op, args, grid, block, s)
-                                       : launch_prec<PREC_BF16X3, false>(op, args, grid, block, s);
-  if (prec != PREC_FP64) return hipErrorInvalidValue;
-  return cplx ? launch_fp64<true>(op, args, grid, block, s) : launch_fp64<false>(op, args, grid, block, s);
+  dim3 grid((nreal + kTileN[tile] - 1) / kTileN[tile], (mmax + kTileM[tile] - 1) / kTileM[tile], args.ngroup);
+  ContractArgs a = args;
+  void* kp[] = {&a};
+  const hipError_t e = hipLaunchKernel(fn, grid, dim3(256), kp, 0, s);
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
 }
 
 }  // namespace aci

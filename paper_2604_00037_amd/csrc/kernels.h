@@ -37,7 +37,15 @@ struct ContractArgs {
 // op: OP_NONE (single term, plain GEMM), OP_PRODUCT, OP_SUM, OP_ABS2_MUL.
 // mmax/nmax bound the (possibly device-resident) output sizes of every group.
 // prec: PREC_FP64, PREC_FP32 or PREC_BF16X3 (operands and result FP64 in HBM).
-hipError_t launch_contract(int op, int prec, const ContractArgs& args, int mmax, int nmax, hipStream_t s);
+// tile: TILE_64x64, TILE_32x64, TILE_32x32 output tiles per workgroup, or
+// -1 for contract_default_tile.  The tile never changes a result.
+enum { TILE_64x64 = 0, TILE_32x64 = 1, TILE_32x32 = 2, NUM_TILES = 3 };
+hipError_t launch_contract(int op, int prec, const ContractArgs& args, int mmax, int nmax, hipStream_t s,
+                           int tile = -1);
+// workgroups of a launch with this tile; the default: the largest tile
+// that still gives every CU a workgroup
+int contract_tiles(int tile, int mmax, int nmax, int ngroup, int cplx);
+int contract_default_tile(int mmax, int nmax, int ngroup, int cplx);
 
 // ------------------------------------------------------------------- prrLU
 struct PrrluArgs {

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+import workloads as W
 from oracle import prrlu as oprrlu
 from oracle import cross_interpolate, apply_op
 from helpers import gemm_bound
@@ -186,3 +187,55 @@ def test_gathers():
     idx = [52, 3, 3, 9, 0]
     got = aci.gather("cols", dev(S), idx).cpu().numpy()
     np.testing.assert_array_equal(got, S[:, idx])
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_contraction_tiles_give_identical_results(cplx, precision):
+    """Every output tile shape accumulates each element in the same order,
+    so all tiles give the default launch's result bit for bit (ragged
+    sizes, two terms and the |z|^2 z epilogue)."""
+    rng = np.random.default_rng(77)
+
+    def mk(shape):
+        x = rng.standard_normal(shape)
+        return x + 1j * rng.standard_normal(shape) if cplx else x
+
+    m, k, n = 130, 77, 70
+    A = [torch.from_numpy(mk((m, k))).cuda(), torch.from_numpy(mk((m, k + 3))).cuda()]
+    B = [torch.from_numpy(mk((k, n))).cuda(), torch.from_numpy(mk((k + 3, n))).cuda()]
+    for op, a, b in (("product", A, B), ("abs2_mul", A[:1], B[:1])):
+        ref = aci.pi_eval(op, a, b, precision=precision)
+        for tile in aci.TILES:
+            assert torch.equal(aci.pi_eval(op, a, b, precision=precision, tile=tile), ref), (op, tile)
+
+
+def test_tune_contract_picks_the_fastest_tile():
+    best, us = aci.tune_contract(384, 128, 384)
+    assert set(us) == set(aci.TILES) and all(v > 0 for v in us.values())
+    assert us[best] == min(us.values())
+    best_c, us_c = aci.tune_contract(1024, 512, 1024, dtype="c128", precision="fp32")
+    assert us_c[best_c] == min(us_c.values())
+
+
+def test_tuned_session_equals_default():
+    """A session whose contraction tiles come from the autotuner gives the
+    default session's sweep bit for bit; its launch log names the tiles."""
+    x1, x2 = W.random_pair(L=12, chi=9, seeds=(2701, 2702))
+    d = [[torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in x] for x in (x1, x2)]
+    kw = dict(maxiter=4, seed=5, fixed_sweeps=True, profile=True)
+    S1 = aci.Session(d, "product", 1e-11, 81, tune=True, **kw)
+    S2 = aci.Session(d, "product", 1e-11, 81, **kw)
+    try:
+        S1.sweep(4)
+        S2.sweep(4)
+        c1, i1 = S1.result()
+        c2, i2 = S2.result()
+        names = {r["kernel"] for r in S1.launches() if r["kind"] == "contract"}
+    finally:
+        S1.close()
+        S2.close()
+    assert i1.ranks == i2.ranks and i1.eps == i2.eps
+    for a, b in zip(c1, c2):
+        assert torch.equal(a, b)
+    assert names and all("Tile<" in n for n in names)

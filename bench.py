@@ -266,7 +266,8 @@ def time_batched(aci, steps, warmup, device):
     second as one joint batch (one LDU launch per local update for all nine
     products, each on its own XCD, the sweep captured in a graph), as an
     overlapped batch (one stream per product), and with the same sessions
-    run one after another."""
+    run one after another; contraction tiles (and overlapped LDU group caps)
+    autotuned at creation."""
     import torch
     import workloads as W
     t = time.perf_counter()
@@ -281,7 +282,7 @@ def time_batched(aci, steps, warmup, device):
     kw = dict(maxiter=total, seed=INIT_SEED, fixed_sweeps=True)
     timed = {}
     for mode in ("joint", "overlapped"):
-        B = aci.Batch(products, "product", TOL, 256, use_graph=True, mode=mode, **kw)
+        B = aci.Batch(products, "product", TOL, 256, use_graph=True, mode=mode, tune=True, **kw)
         B.sweep(warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -295,7 +296,7 @@ def time_batched(aci, steps, warmup, device):
     batched, st = timed["joint"]
     seq = 0.0
     for p in products:
-        S = aci.Session(p, "product", TOL, 256, use_graph=True, **kw)
+        S = aci.Session(p, "product", TOL, 256, use_graph=True, tune=True, **kw)
         S.sweep(warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -367,6 +367,65 @@ def time_c5(aci, device, steps=2, warmup=1):
     return out
 
 
+CONTRACT_CASES = [  # (m, k, n, complex, terms): the C5 two-site product, C2/C3-sized real products
+    (1024, 512, 1024, True, 1), (384, 128, 384, False, 2), (512, 256, 512, False, 2), (1024, 1024, 1024, False, 2)]
+CONTRACT_PRECS = [("fp64", 78.6), ("fp32", 157.3), ("bf16x3", 2500.0)]
+CONTRACT_REPS = (3, 20)   # untimed, timed calls per case
+
+
+def time_contract(aci, device):
+    """Two-site products on their own (aci_pi_eval, seeded normal operands,
+    default tiles): the kernel-level matrix-core figures.  Each call
+    synchronises, so the kernel times come from a trace of this run
+    (--summarize-contract)."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(1)
+    for (m, k, n, cx, terms) in CONTRACT_CASES:
+        def mk(shape):
+            x = rng.standard_normal(shape)
+            return torch.from_numpy(x + 1j * rng.standard_normal(shape) if cx else x).to(device)
+        A, B = [mk((m, k)) for _ in range(terms)], [mk((k, n)) for _ in range(terms)]
+        op = "abs2_mul" if cx else "product"
+        for prec, _ in CONTRACT_PRECS:
+            for _ in range(sum(CONTRACT_REPS)):
+                aci.pi_eval(op, A, B, precision=prec)
+    torch.cuda.synchronize()
+    return {"cases": [list(c) for c in CONTRACT_CASES], "precisions": [p for p, _ in CONTRACT_PRECS],
+            "calls_per_case": list(CONTRACT_REPS)}
+
+
+def summarize_contract(directory):
+    """Per-case kernel time of a traced `--only contract` run."""
+    import csv
+    import glob
+    fn = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)[0]
+    rows = []
+    with open(fn) as f:
+        for r in csv.DictReader(f):
+            if "contract" in r["Kernel_Name"]:
+                nm = r["Kernel_Name"].replace("void aci::(anonymous namespace)::", "").replace(
+                    "aci::(anonymous namespace)::", "").split("(")[0]
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), nm))
+    rows.sort()
+    out = ["| m x k x n | dtype | terms | precision | kernel | us per launch | TFLOP/s | % of matrix peak |",
+           "|---|---|---|---|---|---|---|---|"]
+    i = 0
+    warm, timed = CONTRACT_REPS
+    for (m, k, n, cx, terms) in CONTRACT_CASES:
+        for prec, peak in CONTRACT_PRECS:
+            grp = rows[i:i + warm + timed]
+            i += warm + timed
+            us = sum(d for _, d, _ in grp[warm:]) / timed / 1e3
+            flops = terms * 2.0 * m * k * n * (4 if cx else 1)
+            tf = flops / us / 1e6
+            ref = f"{100 * tf / peak:.1f} % of {peak}" if prec != "bf16x3" else \
+                f"{100 * tf / (peak / 3):.1f} % of {peak / 3:.0f} (bf16 / 3)"
+            out.append(f"| {m} x {k} x {n} | {'complex' if cx else 'real'} | {terms} | {prec} | `{grp[-1][2]}` | "
+                       f"{us:.1f} | {tf:.2f} | {ref} |")
+    return "\n".join(out)
+
+
 def time_proposal(aci, device, steps=300):
     """Learned pivot proposal: a scoring network trained on the GPU from the
     pivots of plain FP64 ACI (the oracle) on products of 3D Fourier fields
@@ -449,8 +508,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the nine-product batch")
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-gp", action="store_true", help="skip the complex |psi|^2 psi workload")
-    ap.add_argument("--only", choices=["gp", "batched"],
+    ap.add_argument("--only", choices=["gp", "batched", "contract"],
                     help="run just one section and print its JSON (for profiling that workload)")
+    ap.add_argument("--summarize-contract", metavar="DIR", help="per-case table of a traced --only contract run")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="table of the library kernels of a rocprofv3 --stats run")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
@@ -468,6 +528,9 @@ def main():
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.bench_json))
         return
+    if args.summarize_contract:
+        print(summarize_contract(args.summarize_contract))
+        return
     if args.summarize_stats:
         print("\n".join(kernel_stats_table(args.summarize_stats)))
         return
@@ -483,6 +546,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.only == "gp":
         print(json.dumps(time_c5(aci, dev)), flush=True)
+        return
+    if args.only == "contract":
+        print(json.dumps(time_contract(aci, dev)), flush=True)
         return
     if args.only == "batched":
         print(json.dumps(time_batched(aci, max(2, args.steps // 3), 1, dev)), flush=True)

@@ -20,6 +20,9 @@ the algorithms of Appendix B of the paper in their order:
 * ``proposal``        -- extension: row features, the small scoring network
                          (forward, gradients, Adam) and the seeded rook
                          search with its acceptance test
+* ``tci``             -- 2-site TCI of a function given point by point (the
+                         construction of the inputs, Sec. 3; the index-set
+                         optimisation of Sec. 2.5 with Pi evaluated directly)
 
 Parity status of each function is stated in its docstring.
 """
@@ -30,9 +33,11 @@ from .aci import aci, ACIResult, apply_op, default_init_ranks
 from .splitmix import splitmix64_stream, default_init
 from . import reference
 from . import proposal
+from .tci import tci, TCIResult, two_site_points
 
 __all__ = [
     "prrlu", "PrrLU", "cross_interpolate", "local_update", "left_frame",
     "right_frame", "aci", "ACIResult", "apply_op", "default_init_ranks",
     "splitmix64_stream", "default_init", "reference", "proposal",
+    "tci", "TCIResult", "two_site_points",
 ]

@@ -356,6 +356,40 @@ int aci_elementwise_batched(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n
                             int32_t maxrank, const aci_options* opt, void* const* outs,
                             const int64_t* out_capacity, aci_result* results);
 
+/* ------------------------------------------------------------- 2-site TCI
+ * Point evaluator of aci_tci: fills val_buf[p] = f(idx_buf[p L .. p L + L)) for
+ * p < count (the buffers passed to aci_tci; digits int32, values of the
+ * dtype), with work ordered on `stream` (the context's hipStream_t).  Called
+ * from the host between the library's launches; returns 0 on success. */
+typedef int32_t (*aci_eval_fn)(int64_t count, int32_t L, void* user, void* stream);
+
+/* 2-site tensor cross interpolation of a function given point by point —
+ * the construction of the input TTs (Sec. 3), whose index-set optimisation
+ * ACI follows (Sec. 2.5): the sweeps of Alg. 1 with the two-site tensor
+ * evaluated directly, Pi[(a, s), (s', b)] = f(I_{l-1}[a], s, s', J_{l+2}[b])
+ * (row a d_l + s, column s' |J_{l+2}| + b), each factorised by the LDU of
+ * Alg. 2 (right-interpolative), the index sets taking its pivot rows and
+ * columns after every update.
+ *   L, d        sites and local dimensions (host, L values)
+ *   dtype       ACI_F64 or ACI_C128 values
+ *   f, user     the evaluator (above)
+ *   idx_buf     device, buf_points x L int32: the library writes the points
+ *   val_buf     device, buf_points values of the dtype: f writes the values;
+ *               buf_points >= (max_l d_l * maxrank)^2
+ *   pivots      host, n_pivots x L digits seeding the index sets (distinct
+ *               prefixes and suffixes); n_pivots = 0: the all-zero index
+ *   options     maxiter, stop_rule, fixed_sweeps (others ignored; FP64 / C128
+ *               throughout)
+ *   out, result as aci_elementwise (ranks, eps, cores of the last
+ *               right-to-left half, index sets; no trace).
+ * The evaluator is called once per local update, with the device synchronised
+ * once per update to size the next one.  ACI_E_INVALID if the evaluator
+ * fails or a pivot digit is out of range; ACI_E_NUMERIC if it produced NaN. */
+int aci_tci(aci_ctx* ctx, int32_t L, const int32_t* d, int32_t dtype, aci_eval_fn f, void* user,
+            int32_t* idx_buf, void* val_buf, int64_t buf_points, const int32_t* pivots,
+            int32_t n_pivots, double tol, int32_t maxrank, const aci_options* opt, void* out,
+            int64_t out_capacity, aci_result* result);
+
 /* Autotuner of the contraction tile shape (environment and two-site
  * products of Eq. pifromframes): times ngroup (1..ACI_MAX_INPUTS) side-by-side
  * copies of an m x k by k x n product (dtype, precision; operands seeded

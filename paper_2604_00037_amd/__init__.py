@@ -5,14 +5,15 @@ elementwise operations on tensor trains (M. K. Ritter).
 ``libaci.so``; ``Session`` runs it sweep by sweep; ``elementwise_batched`` /
 ``Batch`` advance several products together; ``env_contract``, ``pi_eval``,
 ``prrlu`` and ``gather`` expose its single steps; ``tune_prrlu`` and
-``tune_contract`` time the LDU launch shapes and the contraction tiles.  The library must be built (``python -m
+``tune_contract`` time the LDU launch shapes and the contraction tiles;
+``tci`` builds a TT from point evaluations (2-site TCI).  The library must be built (``python -m
 paper_2604_00037_amd.build``); nothing falls back to the CPU.
 """
 
 from .aci import (Batch, Context, Session, default_context, elementwise, elementwise_batched, env_contract,
                   gather, mlp_forward, mlp_train_step, pi_eval, proposal_features, prrlu, rook_check,
-                  rook_lu, rook_right_factor, tune_contract, tune_prrlu, TILES)
+                  rook_lu, rook_right_factor, tci, tune_contract, tune_prrlu, TILES)
 
 __all__ = ["Batch", "Context", "Session", "default_context", "elementwise", "elementwise_batched",
            "env_contract", "gather", "mlp_forward", "mlp_train_step", "pi_eval", "proposal_features",
-           "prrlu", "rook_check", "rook_lu", "rook_right_factor", "tune_contract", "tune_prrlu", "TILES"]
+           "prrlu", "rook_check", "rook_lu", "rook_right_factor", "tci", "tune_contract", "tune_prrlu", "TILES"]

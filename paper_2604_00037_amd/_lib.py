@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libaci.so")
 
 MAX_SITES = 128
 MAX_INPUTS = 4
+MAX_MATRIX = 1024
 
 ACI_OK = 0
 ACI_W_NOT_CONVERGED = 1
@@ -25,7 +26,7 @@ EXPORTED = [
     "aci_result_free", "aci_env_contract", "aci_pi_eval", "aci_prrlu", "aci_gather",
     "aci_session_create", "aci_session_sweep", "aci_session_result", "aci_session_launches",
     "aci_session_destroy", "aci_batch_create", "aci_batch_sweep", "aci_batch_result", "aci_batch_info",
-    "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu", "aci_tune_contract",
+    "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu", "aci_tune_contract", "aci_tci",
     "aci_proposal_features", "aci_mlp_forward", "aci_mlp_train_step", "aci_rook_lu", "aci_rook_check",
     "aci_rook_right_factor",
 ]
@@ -119,6 +120,8 @@ class HipError(RuntimeError):
 _lib = None
 
 
+# point evaluator of aci_tci
+EVAL_FN = C.CFUNCTYPE(C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p)
 # device allocator callbacks of aci_ctx_create_with_allocator
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -188,6 +191,9 @@ def load(path=LIB_PATH):
     lib.aci_tune_prrlu.restype = C.c_int
     lib.aci_tune_contract.argtypes = [vp, i32, i32, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(C.c_float)]
     lib.aci_tune_contract.restype = C.c_int
+    lib.aci_tci.argtypes = [vp, i32, C.POINTER(i32), i32, EVAL_FN, vp, vp, vp, C.c_int64, vp, i32, C.c_double,
+                            i32, C.POINTER(AciOptions), vp, C.c_int64, C.POINTER(AciResult)]
+    lib.aci_tci.restype = C.c_int
     f32p = C.POINTER(C.c_float)
     i32p = C.POINTER(i32)
     lib.aci_proposal_features.argtypes = [vp, vp, i32, i32, i32, C.POINTER(vp), i32p, i32p, i32, vp, i32, vp]

@@ -8,6 +8,8 @@ contiguous float64 (or complex128) tensors on the current HIP device.
 from __future__ import annotations
 
 import ctypes as C
+
+import numpy as np
 from dataclasses import dataclass, field
 
 import torch
@@ -525,6 +527,58 @@ def elementwise_batched(products, op="product", tol=1e-12, maxrank=64, *, maxite
     finally:
         for b in range(len(products)):
             lib.aci_result_free(C.byref(res[b]))
+
+
+def tci(f, dims, tol=1e-12, maxrank=64, *, dtype=None, maxiter=20, pivots=None, stop_rule="exclusive",
+        fixed_sweeps=False, ctx=None):
+    """aci_tci: 2-site TCI of ``f``, a callable taking a device int32 tensor of
+    multi-indices (count x L) and returning ``count`` values (float64 or,
+    with ``dtype=torch.complex128``, complex).  ``pivots``: multi-indices
+    seeding the index sets.  Returns (cores, info) as ``elementwise``."""
+    ctx = ctx or default_context()
+    dtype = dtype or torch.float64
+    if dtype not in (torch.float64, torch.complex128):
+        raise TypeError("dtype must be float64 or complex128")
+    L = len(dims)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    side = min(max(dims) * maxrank, _lib.MAX_MATRIX)
+    P = side * side
+    idx_t = torch.zeros((P, L), dtype=torch.int32, device=dev)
+    val_t = torch.zeros(P, dtype=dtype, device=dev)
+    failure = []
+
+    def evaluate(count, L_, user, stream):
+        try:
+            with torch.cuda.stream(ctx.stream):
+                vals = f(idx_t[:count])
+                val_t[:count].copy_(torch.as_tensor(vals, device=dev).reshape(-1).to(dtype))
+            return 0
+        except Exception as exc:     # reported after the call returns
+            failure.append(exc)
+            return 1
+
+    cb = _lib.EVAL_FN(evaluate)
+    keep = []
+    opts = _options(keep, maxiter, 0, None, stop_rule, "fp64", False, fixed_sweeps, False)
+    d = (C.c_int32 * L)(*[int(x) for x in dims])
+    if pivots is not None:
+        piv = np.ascontiguousarray(np.asarray(pivots, dtype=np.int32).reshape(-1, L))
+        pv, npv = piv.ctypes.data_as(C.c_void_p), piv.shape[0]
+    else:
+        piv, pv, npv = None, None, 0
+    cap = sum(maxrank * int(x) * maxrank for x in dims)
+    out = torch.zeros(cap, dtype=dtype, device=dev)
+    res = _lib.AciResult()
+    st = ctx.lib.aci_tci(ctx.h, L, d, 1 if dtype == torch.complex128 else 0, cb, None,
+                         C.c_void_p(idx_t.data_ptr()), C.c_void_p(val_t.data_ptr()), P, pv, npv, float(tol),
+                         int(maxrank), C.byref(opts), C.c_void_p(out.data_ptr()), cap, C.byref(res))
+    try:
+        if failure:
+            raise failure[0]
+        _check(ctx.lib, ctx.h, st)
+        return _unpack(res, out, [int(x) for x in dims], st, False)
+    finally:
+        ctx.lib.aci_result_free(C.byref(res))
 
 
 TILES = ["64x64", "32x64", "32x32"]

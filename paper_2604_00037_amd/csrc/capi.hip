@@ -1537,6 +1537,298 @@ int aci_session_result(aci_session* S, void* out, int64_t out_capacity, aci_resu
   return S->converged ? ACI_OK : ACI_W_NOT_CONVERGED;
 }
 
+int aci_tci(aci_ctx* ctx, int32_t L, const int32_t* d, int32_t dtype, aci_eval_fn f, void* user,
+            int32_t* idx_buf, void* val_buf, int64_t buf_points, const int32_t* pivots, int32_t n_pivots,
+            double tol, int32_t maxrank, const aci_options* opt, void* out, int64_t out_capacity,
+            aci_result* result) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!d || !f || !idx_buf || !val_buf || !out || !result) return set_err(ctx, ACI_E_INVALID, "null argument");
+  std::memset(result, 0, sizeof(*result));
+  if (L < 2 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
+  if (!(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "tol must be >= 0");
+  if (maxrank < 1 || maxrank > ACI_MAX_RANK) return set_err(ctx, ACI_E_LIMIT, "maxrank out of range");
+  if (n_pivots < 0 || (n_pivots > 0 && !pivots)) return set_err(ctx, ACI_E_INVALID, "bad pivots");
+  aci_options o{};
+  o.maxiter = 20;
+  if (opt) o = *opt;
+  if (o.maxiter < 1) return set_err(ctx, ACI_E_INVALID, "maxiter must be >= 1");
+  const int cplx = dtype == ACI_C128 ? 1 : 0, ew = cplx ? 2 : 1;
+  std::vector<int> dd(L + 2, 1);
+  int D = 1;
+  for (int l = 1; l <= L; ++l) {
+    dd[l] = d[l - 1];
+    if (dd[l] < 1 || dd[l] > ACI_MAX_DIM) return set_err(ctx, ACI_E_LIMIT, "local dimension out of range");
+    D = std::max(D, dd[l]);
+  }
+  if ((long long)D * maxrank > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "d * maxrank above ACI_MAX_MATRIX");
+  const int ldmax = D * maxrank;
+  if (buf_points < (int64_t)ldmax * ldmax) return set_err(ctx, ACI_E_LIMIT, "point buffers below (d maxrank)^2");
+  // ---- initial index sets: distinct prefixes / suffixes of the pivots
+  std::vector<std::vector<int32_t>> piv;
+  if (n_pivots == 0) piv.push_back(std::vector<int32_t>(L, 0));
+  for (int i = 0; i < n_pivots; ++i) {
+    std::vector<int32_t> v(pivots + (size_t)i * L, pivots + (size_t)(i + 1) * L);
+    for (int t = 0; t < L; ++t)
+      if (v[t] < 0 || v[t] >= dd[t + 1]) return set_err(ctx, ACI_E_INVALID, "pivot digit out of range");
+    piv.push_back(v);
+  }
+  std::vector<int> nI(L + 2, 0), nJ(L + 3, 0);
+  const size_t setw = (size_t)maxrank * L;   // one index set: maxrank digit rows of length L
+  std::vector<int32_t> hI((size_t)(L + 1) * setw, 0), hJ((size_t)(L + 2) * setw, 0);
+  nI[0] = 1;
+  nJ[L + 1] = 1;
+  for (int l = 1; l < L; ++l) {
+    std::vector<std::vector<int32_t>> seen;
+    for (auto& v : piv) {
+      std::vector<int32_t> pre(v.begin(), v.begin() + l);
+      if (std::find(seen.begin(), seen.end(), pre) == seen.end()) seen.push_back(pre);
+    }
+    if ((int)seen.size() > maxrank) return set_err(ctx, ACI_E_LIMIT, "more distinct pivot prefixes than maxrank");
+    nI[l] = (int)seen.size();
+    for (int k = 0; k < nI[l]; ++k) std::copy(seen[k].begin(), seen[k].end(), hI.begin() + l * setw + (size_t)k * L);
+  }
+  for (int l = 2; l <= L; ++l) {
+    std::vector<std::vector<int32_t>> seen;
+    for (auto& v : piv) {
+      std::vector<int32_t> suf(v.begin() + (l - 1), v.end());
+      if (std::find(seen.begin(), seen.end(), suf) == seen.end()) seen.push_back(suf);
+    }
+    if ((int)seen.size() > maxrank) return set_err(ctx, ACI_E_LIMIT, "more distinct pivot suffixes than maxrank");
+    nJ[l] = (int)seen.size();
+    for (int k = 0; k < nJ[l]; ++k) std::copy(seen[k].begin(), seen[k].end(), hJ.begin() + l * setw + (size_t)k * L);
+  }
+  // ---- device workspace
+  const size_t xwords = prrlu_xbuf_words(ldmax, ldmax, cplx);
+  size_t ycore = 0;
+  for (int l = 1; l <= L; ++l) ycore += (size_t)maxrank * dd[l] * maxrank * ew;
+  const size_t bytes = sizeof(int32_t) * ((size_t)(L + 1) * setw + (size_t)(L + 2) * setw) +
+                       sizeof(double) * ycore + sizeof(uint64_t) * xwords +
+                       sizeof(int) * (2 * (size_t)maxrank + 16) + sizeof(double) * 8 + 4096;
+  void* ws = nullptr;
+  if (!dev_alloc(ctx, &ws, bytes)) return set_err(ctx, ACI_E_NOMEM, "TCI workspace");
+  char* base = (char*)ws;
+  auto take = [&](size_t nbytes) {
+    char* q = base;
+    base += (nbytes + 255) & ~(size_t)255;
+    return q;
+  };
+  int32_t* dI = (int32_t*)take(sizeof(int32_t) * (size_t)(L + 1) * setw);
+  int32_t* dJ = (int32_t*)take(sizeof(int32_t) * (size_t)(L + 2) * setw);
+  uint64_t* xbuf = (uint64_t*)take(sizeof(uint64_t) * xwords);
+  int* rows = (int*)take(sizeof(int) * maxrank);
+  int* cols = (int*)take(sizeof(int) * maxrank);
+  int* misc = (int*)take(sizeof(int) * 16);   // [0] rank, [4] flags, [5] abort, [8] epoch
+  double* peps = (double*)take(sizeof(double) * 8);
+  std::vector<double*> Y(L + 1, nullptr);
+  for (int l = 1; l <= L; ++l) Y[l] = (double*)take(sizeof(double) * (size_t)maxrank * dd[l] * maxrank * ew);
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = ACI_OK;
+  auto fail = [&](int code, const std::string& msg) {
+    rc = set_err(ctx, code, msg);
+    return rc;
+  };
+#define TCICHK(call)                                                                      \
+  do {                                                                                    \
+    const hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                               \
+      (void)hipGetLastError();                                                            \
+      fail(ACI_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));                 \
+      goto done;                                                                          \
+    }                                                                                     \
+  } while (0)
+  {
+    std::vector<int> rho(L + 1, 1), rho_prev(L + 1, 1);
+    std::vector<double> eps_rl(L + 1, 0.0);
+    for (int l = 1; l < L; ++l) rho_prev[l] = nJ[l + 1];
+    int sweeps = 0;
+    bool converged = false;
+    float ms_total = 0.f;
+    TCICHK(hipMemcpyAsync(dI, hI.data(), sizeof(int32_t) * hI.size(), hipMemcpyHostToDevice, s));
+    TCICHK(hipMemcpyAsync(dJ, hJ.data(), sizeof(int32_t) * hJ.size(), hipMemcpyHostToDevice, s));
+    TCICHK(launch_fill_int((int*)xbuf, 2 * xwords, 0, s));
+    TCICHK(launch_fill_int(misc, 16, 0, s));
+    TCICHK(launch_fill_int(misc + 8, 1, 1, s));
+    TCICHK(hipEventCreate(&e0));
+    TCICHK(hipEventCreate(&e1));
+    for (int it = 1; it <= o.maxiter; ++it) {
+      sweeps = it;
+      TCICHK(hipEventRecord(e0, s));
+      for (int u = 0; u < 2 * (L - 1); ++u) {
+        const bool lr = u < L - 1;
+        const int l = lr ? u + 1 : 2 * (L - 1) - u;
+        const int cR = nJ[l + 2], m = nI[l - 1] * dd[l], n = dd[l + 1] * cR;
+        TciPointsArgs pa{};
+        pa.I_prev = dI + (size_t)(l - 1) * setw;
+        pa.J_next = dJ + (size_t)(l + 2) * setw;
+        pa.pts = idx_buf;
+        pa.m = m;
+        pa.n = n;
+        pa.d = dd[l];
+        pa.cR = cR;
+        pa.l = l;
+        pa.L = L;
+        TCICHK(launch_tci_points(pa, s));
+        if (f((int64_t)m * n, L, user, (void*)s) != 0) {
+          fail(ACI_E_INVALID, "the point evaluator failed");
+          goto done;
+        }
+        PrrluArgs a{};
+        a.cplx = cplx;
+        a.M = (const double*)val_buf;
+        a.m = dconst(m);
+        a.n = dconst(n);
+        a.ldm = dconst(n);
+        a.tol = tol;
+        a.maxrank = maxrank;
+        a.rule = o.stop_rule == 1 ? RULE_LITERAL : RULE_EXCLUSIVE;
+        a.xbuf = xbuf;
+        a.xbuf_words = xwords;
+        a.spin_limit = kSpinLimit;
+        a.rows = rows;
+        a.cols = cols;
+        a.rank = misc;
+        a.eps = peps;
+        a.Y = lr ? nullptr : Y[l + 1];
+        a.ldy = dconst(n);
+        a.err = misc + 4;
+        a.abort_word = misc + 5;
+        a.epoch = (uint32_t*)(misc + 8);
+        a.xcd = 0;
+        a.max_groups = 0;
+        a.cooperative = 1;
+        TCICHK(launch_prrlu(a, m, n, s));
+        TciSetsArgs sa{};
+        sa.rows = rows;
+        sa.cols = cols;
+        sa.rank = misc;
+        sa.I_prev = pa.I_prev;
+        sa.J_next = pa.J_next;
+        sa.I_out = dI + (size_t)l * setw;
+        sa.J_out = dJ + (size_t)(l + 1) * setw;
+        sa.d = dd[l];
+        sa.cR = cR;
+        sa.l = l;
+        sa.L = L;
+        TCICHK(launch_tci_sets(sa, std::min(maxrank, std::min(m, n)), s));
+        if (!lr && l == 1) {
+          // Y_1 = M[:, J_2] (the left factor of the last update, Alg. 3)
+          GatherArgs g{};
+          g.esz = ew;
+          g.count = 1;
+          g.side = 1;
+          g.idx = cols;
+          g.rank = misc;
+          g.err = misc + 4;
+          g.it[0] = GatherItem{(const double*)val_buf, Y[1], dconst(n), ddev(misc), dconst(m), dconst(n)};
+          TCICHK(launch_gather(g, std::min(maxrank, n), m, s));
+        }
+        int hr[8];
+        double he = 0.0;
+        TCICHK(hipMemcpyAsync(hr, misc, sizeof(int) * 8, hipMemcpyDeviceToHost, s));
+        TCICHK(hipMemcpyAsync(&he, peps, sizeof(double), hipMemcpyDeviceToHost, s));
+        TCICHK(hipStreamSynchronize(s));
+        if (hr[4] & ERR_TIMEOUT) {
+          fail(ACI_E_TIMEOUT, "a pivot exchange exceeded its spin limit");
+          goto done;
+        }
+        if (hr[4] & ERR_LIMIT) {
+          fail(ACI_E_LIMIT, "a pivot index fell outside its matrix");
+          goto done;
+        }
+        if (!(he == he)) {
+          fail(ACI_E_NUMERIC, "NaN in the evaluated two-site tensor");
+          goto done;
+        }
+        nI[l] = hr[0];
+        nJ[l + 1] = hr[0];
+        if (!lr) {
+          rho[l] = hr[0];
+          eps_rl[l] = he;
+        }
+      }
+      TCICHK(hipEventRecord(e1, s));
+      TCICHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      TCICHK(hipEventElapsedTime(&ms, e0, e1));
+      ms_total += ms;
+      bool grew = false;
+      double emax = 0.0;
+      for (int l = 1; l < L; ++l) {
+        grew = grew || rho[l] > rho_prev[l];
+        emax = std::max(emax, eps_rl[l]);
+      }
+      rho_prev = rho;
+      converged = !grew && emax <= tol;
+      if (converged && !o.fixed_sweeps) break;
+    }
+    // ---- result
+    result->L = L;
+    result->sweeps = sweeps;
+    result->converged = converged ? 1 : 0;
+    result->sweep_ms = ms_total;
+    result->ranks[0] = result->ranks[L] = 1;
+    result->init_ranks[0] = result->init_ranks[L] = 1;
+    for (int l = 1; l < L; ++l) {
+      result->ranks[l] = rho[l];
+      result->eps[l - 1] = eps_rl[l];
+      result->init_ranks[l] = (int)std::min<size_t>(piv.size(), (size_t)maxrank);
+    }
+    int64_t off = 0;
+    for (int l = 1; l <= L; ++l) off += (int64_t)result->ranks[l - 1] * dd[l] * result->ranks[l];
+    if (off > out_capacity) {
+      fail(ACI_E_NOMEM, "output buffer too small");
+      goto done;
+    }
+    off = 0;
+    for (int l = 1; l <= L; ++l) {
+      const int64_t cnt = (int64_t)result->ranks[l - 1] * dd[l] * result->ranks[l];
+      result->core_offset[l - 1] = off;
+      TCICHK(hipMemcpyAsync((double*)out + off * ew, Y[l], cnt * ew * sizeof(double), hipMemcpyDeviceToDevice, s));
+      off += cnt;
+    }
+    result->out_elems = off;
+    // index sets I_l, J_{l+1} of the last updates (right to left)
+    TCICHK(hipMemcpyAsync(hI.data(), dI, sizeof(int32_t) * hI.size(), hipMemcpyDeviceToHost, s));
+    TCICHK(hipMemcpyAsync(hJ.data(), dJ, sizeof(int32_t) * hJ.size(), hipMemcpyDeviceToHost, s));
+    TCICHK(hipStreamSynchronize(s));
+    int64_t ni = 0, nj = 0;
+    for (int l = 1; l < L; ++l) {
+      ni += (int64_t)rho[l] * l;
+      nj += (int64_t)rho[l] * (L - l);
+    }
+    result->I_idx = (uint8_t*)calloc(std::max<int64_t>(ni, 1), 1);
+    result->J_idx = (uint8_t*)calloc(std::max<int64_t>(nj, 1), 1);
+    if (!result->I_idx || !result->J_idx) {
+      aci_result_free(result);
+      fail(ACI_E_NOMEM, "host allocation of the index sets");
+      goto done;
+    }
+    int64_t oi = 0, oj = 0;
+    for (int l = 1; l < L; ++l) {
+      result->I_off[l - 1] = oi;
+      result->J_off[l - 1] = oj;
+      for (int k = 0; k < rho[l]; ++k) {
+        for (int t = 0; t < l; ++t) result->I_idx[oi + (int64_t)k * l + t] = (uint8_t)hI[l * setw + (size_t)k * L + t];
+        for (int t = 0; t < L - l; ++t)
+          result->J_idx[oj + (int64_t)k * (L - l) + t] = (uint8_t)hJ[(l + 1) * setw + (size_t)k * L + t];
+      }
+      oi += (int64_t)rho[l] * l;
+      oj += (int64_t)rho[l] * (L - l);
+    }
+    rc = converged ? ACI_OK : ACI_W_NOT_CONVERGED;
+  }
+done:
+#undef TCICHK
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  dev_free(ctx, ws);
+  return rc;
+}
+
 int aci_elementwise(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
                     double tol, int32_t maxrank, const aci_options* opt, void* out, int64_t out_capacity,
                     aci_result* result) {

@@ -237,6 +237,26 @@ struct GatherArgs {
 };
 hipError_t launch_gather(const GatherArgs& a, int rmax, int extent_max, hipStream_t s);
 
+// ------------------------------------------------------------ 2-site TCI
+struct TciPointsArgs {
+  const int32_t* I_prev;   // |I_{l-1}| digit rows of length L
+  const int32_t* J_next;   // |J_{l+2}| digit rows of length L
+  int32_t* pts;            // m n rows of L digits out
+  int m, n, d, cR, l, L;   // m = |I_{l-1}| d, n = d' cR
+};
+struct TciSetsArgs {
+  const int* rows;         // pivot rows / columns of the bond's LDU
+  const int* cols;
+  const int* rank;         // their number (device)
+  const int32_t* I_prev;
+  const int32_t* J_next;
+  int32_t* I_out;          // I_l digit rows out
+  int32_t* J_out;          // J_{l+1} digit rows out
+  int d, cR, l, L;
+};
+hipError_t launch_tci_points(const TciPointsArgs& a, hipStream_t s);
+hipError_t launch_tci_sets(const TciSetsArgs& a, int rmax, hipStream_t s);
+
 // Fill `count` doubles with `value` (used instead of a memset so the sweep can
 // be captured in a graph).
 hipError_t launch_fill(double* p, size_t count, double value, hipStream_t s);

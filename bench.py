@@ -367,6 +367,56 @@ def time_c5(aci, device, steps=2, warmup=1):
     return out
 
 
+def time_tci(aci, device):
+    """The paper's first example end to end on the GPU: the Gaussians
+    g_+/- = exp(-(x +/- delta/2)^2 / (2 w^2)) on the quantics grid of
+    [-1/2, 1/2) with 25 bits (w = 0.15, delta = 0.4) built as QTTs by 2-site
+    TCI from point evaluations (tol 1e-12, rank cap 32, seeded at both
+    peaks), then their product by ACI at the paper's rank chi' = 15, checked
+    against exp(-x^2/w^2) exp(-delta^2/(4 w^2)) at 4096 random points."""
+    import numpy as np
+    import torch
+    L, w, delta = 25, 0.15, 0.4
+    scale = torch.tensor([2.0 ** -(l + 1) for l in range(L)], dtype=torch.float64, device=device)
+
+    def g(sign):
+        return lambda idx: torch.exp(-((idx.double() @ scale - 0.5) + sign * delta / 2) ** 2 / (2 * w * w))
+
+    def bits(x):
+        i = int(round((x + 0.5) * 2 ** L))
+        return [(i >> (L - 1 - t)) & 1 for t in range(L)]
+
+    out = {"workload": "g_+ g_- of the paper's Gaussians (w=0.15, delta=0.4) on 2^25 quantics points: "
+                       "2-site TCI from point evaluations (tol 1e-12, rank cap 32), then ACI at chi'=15"}
+    cores = {}
+    for name, sign in (("g_plus", 1.0), ("g_minus", -1.0)):
+        piv = [bits(-sign * delta / 2), bits(sign * delta / 2 * 0.0)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c, info = aci.tci(g(sign), [2] * L, 1e-12, 32, pivots=piv)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        cores[name] = c
+        out[name] = {"seconds": el, "sweeps": info.sweeps, "converged": info.converged,
+                     "max_rank": max(info.ranks), "max_eps": max(info.eps)}
+        log(f"TCI {name}: {info.sweeps} sweeps in {el:.3f} s, ranks <= {max(info.ranks)}, max eps {max(info.eps):.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y, info = aci.elementwise([cores["g_plus"], cores["g_minus"]], "product", 1e-14, 15, seed=INIT_SEED)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rng = np.random.default_rng(7)
+    pts = rng.integers(0, 2, (4096, L))
+    x = pts @ np.array([2.0 ** -(l + 1) for l in range(L)]) - 0.5
+    exact = np.exp(-x * x / (w * w)) * np.exp(-delta * delta / (4 * w * w))
+    import workloads as W
+    err = np.abs(W.tt_eval([c.cpu().numpy() for c in y], pts) - exact).max()
+    out["aci_product"] = {"seconds": el, "sweeps": info.sweeps, "ranks_max": max(info.ranks),
+                          "sampled_max_error": float(err)}
+    log(f"ACI g+ g- at chi'=15: {info.sweeps} sweeps in {el:.3f} s, sampled max error {err:.2e}")
+    return out
+
+
 CONTRACT_CASES = [  # (m, k, n, complex, terms): the C5 two-site product, C2/C3-sized real products
     (1024, 512, 1024, True, 1), (384, 128, 384, False, 2), (512, 256, 512, False, 2), (1024, 1024, 1024, False, 2)]
 CONTRACT_PRECS = [("fp64", 78.6), ("fp32", 157.3), ("bf16x3", 2500.0)]
@@ -508,7 +558,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the nine-product batch")
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-gp", action="store_true", help="skip the complex |psi|^2 psi workload")
-    ap.add_argument("--only", choices=["gp", "batched", "contract"],
+    ap.add_argument("--no-tci", action="store_true", help="skip the TCI + ACI Gaussian example")
+    ap.add_argument("--only", choices=["gp", "batched", "contract", "tci"],
                     help="run just one section and print its JSON (for profiling that workload)")
     ap.add_argument("--summarize-contract", metavar="DIR", help="per-case table of a traced --only contract run")
     ap.add_argument("--summarize-stats", metavar="DIR",
@@ -546,6 +597,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.only == "gp":
         print(json.dumps(time_c5(aci, dev)), flush=True)
+        return
+    if args.only == "tci":
+        print(json.dumps(time_tci(aci, dev)), flush=True)
         return
     if args.only == "contract":
         print(json.dumps(time_contract(aci, dev)), flush=True)
@@ -636,6 +690,8 @@ def main():
         out["proposal"] = time_proposal(aci, dev)
     if not args.no_gp:
         out["gp"] = time_c5(aci, dev)
+    if not args.no_tci:
+        out["tci"] = time_tci(aci, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u, v)
         out["speedup_vs_cpu_oracle"] = out["value"] / out["cpu_baseline"]["value"]

@@ -59,8 +59,22 @@ extern "C" {
 typedef enum { ACI_F64 = 0, ACI_C128 = 1 } aci_dtype;
 
 /* f of Eq. (localupdate), applied elementwise to the N two-site tensors:
- * PRODUCT: ((x1*x2)*x3)...; SUM: ((x1+x2)+x3)...; ABS2_MUL (N = 1): |x|^2 x. */
-typedef enum { ACI_OP_PRODUCT = 0, ACI_OP_SUM = 1, ACI_OP_ABS2_MUL = 2 } aci_op;
+ * PRODUCT: ((x1*x2)*x3)...; SUM: ((x1+x2)+x3)...; ABS2_MUL (N = 1): |x|^2 x;
+ * CUSTOM: any f, applied by the caller's aci_pointwise_fn (options). */
+typedef enum { ACI_OP_PRODUCT = 0, ACI_OP_SUM = 1, ACI_OP_ABS2_MUL = 2, ACI_OP_CUSTOM = 3 } aci_op;
+
+/* A general elementwise f (the problem statement's f: C^N -> C, Sec. 2):
+ * for every i < rows, j < cols, out[i ld + j] = f(pis[0][i ld + j], ...,
+ * pis[n-1][i ld + j]), where pis are device pointers to the N two-site
+ * tensors Pi^n of the local update (elements of the dtype) and out is the
+ * matrix the LDU then factorises.  rows x cols bounds the update's two-site
+ * tensor (its exact extent lives on the device); entries outside it hold
+ * arbitrary values and their results are never read.  Called from the host
+ * once per local update while the sweep is enqueued; the work must be
+ * ordered on `stream` (a hipStream_t) and must not wait for the device.
+ * Returns 0 on success. */
+typedef int32_t (*aci_pointwise_fn)(void* const* pis, int32_t n, void* out, int64_t rows, int64_t cols,
+                                    int64_t ld, void* user, void* stream);
 
 /* Precision of the contractions that form the two-site tensors.  The pivot
  * search, the Schur updates, the pivot-matrix solve and the error estimate are
@@ -124,6 +138,9 @@ typedef struct {
                             product sweeps on its own stream, LDU groups
                             spread over the XCDs; 3 = one product after
                             another */
+  aci_pointwise_fn pointwise;   /* f of ACI_OP_CUSTOM (NULL otherwise); sweeps
+                                   with it are never captured into graphs */
+  void* pointwise_user;         /* passed to pointwise */
 } aci_options;
 
 /* Result of aci_elementwise.  Output cores are written compactly, site after

@@ -58,6 +58,8 @@ class AciOptions(C.Structure):
         ("proposal", C.c_void_p),
         ("proposal_scans", C.c_int32),
         ("batch_mode", C.c_int32),
+        ("pointwise", C.c_void_p),
+        ("pointwise_user", C.c_void_p),
     ]
 
 
@@ -120,6 +122,9 @@ class HipError(RuntimeError):
 _lib = None
 
 
+# general elementwise f of ACI_OP_CUSTOM
+POINTWISE_FN = C.CFUNCTYPE(C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_int64, C.c_int64,
+                           C.c_int64, C.c_void_p, C.c_void_p)
 # point evaluator of aci_tci
 EVAL_FN = C.CFUNCTYPE(C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p)
 # device allocator callbacks of aci_ctx_create_with_allocator

@@ -127,6 +127,48 @@ class Info:
     J: list = field(default_factory=list)    # J_1..J_{L+1} at index 1..L+1 (J_1, J_{L+1} empty)
 
 
+class _DevArray:
+    """A device buffer of the library seen by torch without a copy."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"data": (int(ptr), False), "shape": tuple(shape), "typestr": typestr,
+                                         "version": 3, "strides": None}
+
+
+def _op_code(op, opts, keep, complex_):
+    """The aci_op of ``op``; a callable f(*tensors) -> tensor becomes
+    ACI_OP_CUSTOM with options.pointwise applying it (torch ops on the
+    library's stream, on (rows, ld) views of the two-site tensors)."""
+    if not callable(op):
+        return OPS[op]
+    typestr = "<c16" if complex_ else "<f8"
+    dev = torch.device("cuda", torch.cuda.current_device())
+    failures = []
+
+    def apply(pis, n, out, rows, cols, ld, user, stream):
+        try:
+            st = torch.cuda.ExternalStream(stream) if stream else torch.cuda.default_stream(dev)
+            with torch.cuda.stream(st):
+                xs = [torch.as_tensor(_DevArray(pis[i], (rows, ld), typestr), device=dev) for i in range(n)]
+                o = torch.as_tensor(_DevArray(out, (rows, ld), typestr), device=dev)
+                o.copy_(op(*xs))
+            return 0
+        except Exception as exc:       # reported by the caller after the call returns
+            failures.append(exc)
+            return 1
+
+    cb = _lib.POINTWISE_FN(apply)
+    keep.extend([cb, failures])
+    opts.pointwise = C.cast(cb, C.c_void_p)
+    return 3
+
+
+def _raise_pointwise(keep):
+    for k in keep:
+        if isinstance(k, list) and k and isinstance(k[0], Exception):
+            raise k[0]
+
+
 def _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, profile,
              low_precision_sweeps=0, use_graph=False, proposal=None, proposal_scans=0):
     opts = _lib.AciOptions()
@@ -222,11 +264,13 @@ def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed
     tts = _inputs(inputs, keep)
     opts = _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, False,
                     low_precision_sweeps, False, proposal, proposal_scans)
+    code = _op_code(op, opts, keep, _code(inputs[0][0]) == 1)
     out, cap = _out_buffer(inputs, maxrank)
     res = _lib.AciResult()
-    status = lib.aci_elementwise(ctx.h, tts, len(inputs), _code(inputs[0][0]), OPS[op], float(tol), int(maxrank),
+    status = lib.aci_elementwise(ctx.h, tts, len(inputs), _code(inputs[0][0]), code, float(tol), int(maxrank),
                                  C.byref(opts), C.c_void_p(out.data_ptr()), cap, C.byref(res))
     try:
+        _raise_pointwise(keep)
         _check(lib, ctx.h, status)
         return _unpack(res, out, [int(c.shape[1]) for c in inputs[0]], status, trace)
     finally:
@@ -280,7 +324,8 @@ class Session:
         opts.tune = 1 if tune else 0
         self._init = init
         h = C.c_void_p()
-        st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), _code(inputs[0][0]), OPS[op], float(tol),
+        code = _op_code(op, opts, self._keep, _code(inputs[0][0]) == 1)
+        st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), _code(inputs[0][0]), code, float(tol),
                                              int(maxrank), C.byref(opts), C.byref(h))
         _check(self.ctx.lib, self.ctx.h, st, allow_warning=False)
         self.h = h
@@ -288,6 +333,7 @@ class Session:
     def sweep(self, n=1):
         stats = _lib.AciSweepStats()
         st = self.ctx.lib.aci_session_sweep(self.h, int(n), C.byref(stats))
+        _raise_pointwise(self._keep)
         _check(self.ctx.lib, self.ctx.h, st)
         L = len(self.inputs[0])
         return dict(status=st, sweeps_done=stats.sweeps_done, converged=bool(stats.converged),
@@ -459,7 +505,8 @@ class Batch:
         opts.tune = 1 if tune else 0
         opts.batch_mode = BATCH_MODES[mode]
         h = C.c_void_p()
-        st = self.ctx.lib.aci_batch_create(self.ctx.h, tts, counts, len(products), _code(products[0][0][0]), OPS[op],
+        code = _op_code(op, opts, self._keep, _code(products[0][0][0]) == 1)
+        st = self.ctx.lib.aci_batch_create(self.ctx.h, tts, counts, len(products), _code(products[0][0][0]), code,
                                            float(tol),
                                            int(maxrank), C.byref(opts), C.byref(h))
         _check(self.ctx.lib, self.ctx.h, st, allow_warning=False)
@@ -468,6 +515,7 @@ class Batch:
     def sweep(self, n=1):
         stats = _lib.AciSweepStats()
         st = self.ctx.lib.aci_batch_sweep(self.h, int(n), C.byref(stats))
+        _raise_pointwise(self._keep)
         _check(self.ctx.lib, self.ctx.h, st)
         d = _stats_dict(stats, len(self.products[0][0]))
         d["status"] = st
@@ -517,10 +565,12 @@ def elementwise_batched(products, op="product", tol=1e-12, maxrank=64, *, maxite
     outs = (C.c_void_p * len(products))(*[C.c_void_p(b.data_ptr()) for b, _ in bufs])
     caps = (C.c_int64 * len(products))(*[c for _, c in bufs])
     res = (_lib.AciResult * len(products))()
-    status = lib.aci_elementwise_batched(ctx.h, tts, counts, len(products), _code(products[0][0][0]), OPS[op],
+    code = _op_code(op, opts, keep, _code(products[0][0][0]) == 1)
+    status = lib.aci_elementwise_batched(ctx.h, tts, counts, len(products), _code(products[0][0][0]), code,
                                          float(tol),
                                          int(maxrank), C.byref(opts), outs, caps, res)
     try:
+        _raise_pointwise(keep)
         _check(lib, ctx.h, status)
         return [_unpack(res[b], bufs[b][0], [int(c.shape[1]) for c in products[b][0]], status, False)
                 for b in range(len(products))]

@@ -131,6 +131,9 @@ struct SplitMix64 {
 
 struct Plan {
   int L = 0, N = 0, op = 0, maxrank = 0, maxiter = 20, rule = 0;
+  aci_pointwise_fn pointwise = nullptr;   // f of ACI_OP_CUSTOM
+  void* pointwise_user = nullptr;
+  double* Pibuf[ACI_MAX_INPUTS] = {};      // the N two-site tensors it reads
   int cplx = 0, ew = 1;       // complex entries; doubles per entry
   int prec_req = PREC_FP64;   // requested contraction precision
   int prec = PREC_FP64;       // precision of the sweep being enqueued
@@ -204,6 +207,8 @@ void layout(Plan& p, Arena& A, bool gen_init) {
     }
   }
   p.Mbuf = A.take<double>((size_t)p.ew * p.ldm * p.ldm);
+  if (p.op == ACI_OP_CUSTOM)
+    for (int n = 0; n < p.N; ++n) p.Pibuf[n] = A.take<double>((size_t)p.ew * p.ldm * p.ldm);
   int rho_max = 1;
   for (int l = 0; l <= L; ++l) rho_max = std::max(rho_max, p.rho[l]);
   for (int l = 1; l <= L; ++l) {
@@ -614,9 +619,28 @@ int enqueue_pi(Enq& q, int l) {
   Plan& p = q.p;
   ContractArgs c{};
   c.cplx = p.cplx;
-    c.cplx = p.cplx;
-  c.ngroup = 1;
   c.err = p.flags;
+  const int mmax = p.d[l] * p.capI[l - 1], nmax = p.d[l + 1] * p.capJ[l + 2];
+  if (p.op == ACI_OP_CUSTOM) {
+    // the N two-site tensors side by side, then the caller's f into M
+    c.ngroup = p.N;
+    for (int n = 0; n < p.N; ++n) {
+      Group& gr = c.g[n];
+      gr.nterm = 1;
+      gr.t[0] = Term{p.Ac[n][l], p.Bc[n][l], dconst(p.r[n][l]), dconst(p.r[n][l]), ddev(p.nJ + l + 2, p.d[l + 1])};
+      gr.C = p.Pibuf[n];
+      gr.M = ddev(p.nI + l - 1, p.d[l]);
+      gr.N = ddev(p.nJ + l + 2, p.d[l + 1]);
+      gr.ldc = dconst(p.ldm);
+    }
+    ENQC(q, 2, OP_NONE, p.prec, c, mmax, nmax, p.tiles[2][l]);
+    void* pis[ACI_MAX_INPUTS];
+    for (int n = 0; n < p.N; ++n) pis[n] = p.Pibuf[n];
+    if (p.pointwise(pis, p.N, p.Mbuf, mmax, nmax, p.ldm, p.pointwise_user, (void*)q.s) != 0)
+      return set_err(ctx, ACI_E_INVALID, "the pointwise f failed");
+    return ACI_OK;
+  }
+  c.ngroup = 1;
   Group& gr = c.g[0];
   gr.nterm = p.N;
   for (int n = 0; n < p.N; ++n)
@@ -626,7 +650,7 @@ int enqueue_pi(Enq& q, int l) {
   gr.M = ddev(p.nI + l - 1, p.d[l]);
   gr.N = ddev(p.nJ + l + 2, p.d[l + 1]);
   gr.ldc = dconst(p.ldm);
-  ENQC(q, 2, p.op, p.prec, c, p.d[l] * p.capI[l - 1], p.d[l + 1] * p.capJ[l + 2], p.tiles[2][l]);
+  ENQC(q, 2, p.op, p.prec, c, mmax, nmax, p.tiles[2][l]);
   return ACI_OK;
 }
 
@@ -835,7 +859,10 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
   if (!inputs) return set_err(ctx, ACI_E_INVALID, "null inputs");
   if (n_inputs < 1 || n_inputs > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
   if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
-  if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL) return set_err(ctx, ACI_E_INVALID, "unknown op");
+  if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL && op != ACI_OP_CUSTOM)
+    return set_err(ctx, ACI_E_INVALID, "unknown op");
+  if ((op == ACI_OP_CUSTOM) != (o.pointwise != nullptr))
+    return set_err(ctx, ACI_E_INVALID, "ACI_OP_CUSTOM goes with options.pointwise (and only it)");
   if (op == ACI_OP_ABS2_MUL && n_inputs != 1) return set_err(ctx, ACI_E_INVALID, "ABS2_MUL takes one input");
   if (!(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "tol must be >= 0");
   if (maxrank < 1) return set_err(ctx, ACI_E_INVALID, "maxrank must be >= 1");
@@ -848,6 +875,8 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
   p.L = L;
   p.N = n_inputs;
   p.op = op;
+  p.pointwise = o.pointwise;
+  p.pointwise_user = o.pointwise_user;
   p.tol = tol;
   p.maxrank = maxrank;
   p.maxiter = o.maxiter;
@@ -1155,7 +1184,7 @@ int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t
     }
   }
   // graphs need launches with static arguments: no events, no trace records
-  S->use_graph = o.use_graph != 0 && !S->prof.on && !p.trace;
+  S->use_graph = o.use_graph != 0 && !S->prof.on && !p.trace && p.op != ACI_OP_CUSTOM;
   p.xcd = pl.xcd;
   p.max_groups = pl.max_groups;
   if (S->use_graph) {
@@ -2087,7 +2116,7 @@ int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs
     if (o.batch_mode == 3) B->serial = true;
     if (B->joint) {
       B->serial = false;
-      B->jgraph = o.use_graph && !o.profile && !o.trace;
+      B->jgraph = o.use_graph && !o.profile && !o.trace && op != ACI_OP_CUSTOM;
     }
   }
   aci_options os = o;

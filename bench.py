@@ -233,10 +233,17 @@ def measured_traffic(kernel):
     return None
 
 
-def time_mode(aci, inputs, precision, steps, warmup):
+def sampled_points(L, count=4096, seed=11):
+    import numpy as np
+    return np.random.default_rng(seed).integers(0, 2, (count, L))
+
+
+def time_mode(aci, inputs, precision, steps, warmup, ref_values=None):
     """Sweeps/s with the contractions in a lower precision (the LDU, the
     solve and the error estimate stay FP64); the precision ladder is held
-    (no switch to FP64) so that every timed sweep runs in that precision."""
+    (no switch to FP64) so that every timed sweep runs in that precision.
+    With ref_values (the FP64 run's output at sampled_points), the output's
+    largest relative difference to it is reported too."""
     import torch
     total = steps + warmup
     sess = aci.Session(inputs, "product", TOL, MAXRANK, maxiter=total, seed=INIT_SEED, fixed_sweeps=True,
@@ -248,11 +255,19 @@ def time_mode(aci, inputs, precision, steps, warmup):
     st = sess.sweep(steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    diff = None
+    if ref_values is not None:
+        import numpy as np
+        import workloads as W
+        cores, _ = sess.result()
+        vals = W.tt_eval([c.cpu().numpy() for c in cores], sampled_points(len(cores)))
+        diff = float(np.abs(vals - ref_values).max() / np.abs(ref_values).max())
     sess.close()
     con_tf = st["flops"][1] / (st["kernel_ms"][1] * 1e-3) / 1e12 if st["kernel_ms"][1] else 0.0
     log(f"{precision}: {steps} sweeps in {elapsed:.3f} s; contractions {con_tf:.2f} TFLOP/s; "
-        f"max eps {st['max_eps']:.3e}")
+        f"max eps {st['max_eps']:.3e}; vs FP64 output {diff}")
     return {"sweeps_per_s": steps / elapsed, "ms_per_sweep": 1e3 * elapsed / steps,
+            "vs_fp64_sampled_max_rel": diff,
             "contraction_tflops": con_tf, "contraction_frac": con_tf / PEAK_MFMA[precision],
             "contraction_ms_per_sweep": st["kernel_ms"][1] / steps,
             "prrlu_ms_per_sweep": st["kernel_ms"][0] / steps, "max_eps": st["max_eps"],
@@ -677,13 +692,16 @@ def main():
         "ranks": st["ranks"],
         "max_eps": st["max_eps"],
     }
+    import workloads as W
+    fp64_cores, _ = sess.result()
+    ref_values = W.tt_eval([c.cpu().numpy() for c in fp64_cores], sampled_points(len(fp64_cores)))
     sess.close()
     out["modes"] = {"fp64": {"sweeps_per_s": out["value"], "ms_per_sweep": ms_per_step,
                              "contraction_tflops": con_tf,
                              "contraction_frac": con_tf / PEAK_MFMA["fp64"]}}
     if not args.no_mixed:
         for prec in ("fp32", "bf16x3"):
-            out["modes"][prec] = time_mode(aci, inputs, prec, args.steps, args.warmup)
+            out["modes"][prec] = time_mode(aci, inputs, prec, args.steps, args.warmup, ref_values)
     if not args.no_batched:
         out["batched"] = time_batched(aci, max(2, args.steps // 3), 1, dev)
     if not args.no_proposal:

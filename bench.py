@@ -199,7 +199,7 @@ def summarize_pmc(fetch_dir, write_dir, bench_json):
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = read_counters(d, counter)
         mine = [v for k, v in rows if name + "(" in k]
-        copy = [v for _, v in rows[-3:]]        # the three calibration copies end the run
+        copy = [v for k, v in rows if "neg" in k][-3:]   # the three calibration passes
         kib_launch = sum(mine) / len(mine)
         kib_copy = sum(copy) / len(copy)
         factor = kib_copy * 1024.0 / CALIB_BYTES

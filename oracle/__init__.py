@@ -23,6 +23,10 @@ the algorithms of Appendix B of the paper in their order:
 * ``tci``             -- 2-site TCI of a function given point by point (the
                          construction of the inputs, Sec. 3; the index-set
                          optimisation of Sec. 2.5 with Pi evaluated directly)
+* ``timestep``        -- TT operators on quantics grids (periodic stencil
+                         MPOs, exact MPO-TT contraction) and one explicit
+                         step of a cubic nonlinear equation with ACI started
+                         from the current state (the use named in Sec. 5)
 
 Parity status of each function is stated in its docstring.
 """
@@ -34,10 +38,11 @@ from .splitmix import splitmix64_stream, default_init
 from . import reference
 from . import proposal
 from .tci import tci, TCIResult, two_site_points
+from . import timestep
 
 __all__ = [
     "prrlu", "PrrLU", "cross_interpolate", "local_update", "left_frame",
     "right_frame", "aci", "ACIResult", "apply_op", "default_init_ranks",
     "splitmix64_stream", "default_init", "reference", "proposal",
-    "tci", "TCIResult", "two_site_points",
+    "tci", "TCIResult", "two_site_points", "timestep",
 ]

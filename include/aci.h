@@ -60,8 +60,13 @@ typedef enum { ACI_F64 = 0, ACI_C128 = 1 } aci_dtype;
 
 /* f of Eq. (localupdate), applied elementwise to the N two-site tensors:
  * PRODUCT: ((x1*x2)*x3)...; SUM: ((x1+x2)+x3)...; ABS2_MUL (N = 1): |x|^2 x;
- * CUSTOM: any f, applied by the caller's aci_pointwise_fn (options). */
-typedef enum { ACI_OP_PRODUCT = 0, ACI_OP_SUM = 1, ACI_OP_ABS2_MUL = 2, ACI_OP_CUSTOM = 3 } aci_op;
+ * CUSTOM: any f, applied by the caller's aci_pointwise_fn (options);
+ * LINEAR_CUBIC: a1 x1 + a2 x2 + ... + aN xN + b |x1|^2 x1, coefficients from
+ * options.coef, the right-hand side of an explicit step of a cubic
+ * nonlinear equation (aci_cubic_step); evaluated as
+ * (((a1 x1 + b (|x1|^2 x1)) + a2 x2) + ...) with |z|^2 = re*re + im*im. */
+typedef enum { ACI_OP_PRODUCT = 0, ACI_OP_SUM = 1, ACI_OP_ABS2_MUL = 2, ACI_OP_CUSTOM = 3,
+               ACI_OP_LINEAR_CUBIC = 4 } aci_op;
 
 /* A general elementwise f (the problem statement's f: C^N -> C, Sec. 2):
  * for every i < rows, j < cols, out[i ld + j] = f(pis[0][i ld + j], ...,
@@ -141,6 +146,9 @@ typedef struct {
   aci_pointwise_fn pointwise;   /* f of ACI_OP_CUSTOM (NULL otherwise); sweeps
                                    with it are never captured into graphs */
   void* pointwise_user;         /* passed to pointwise */
+  const double* coef;           /* host, ACI_OP_LINEAR_CUBIC only: a1..aN, b;
+                                   N+1 doubles for ACI_F64, N+1 (re, im)
+                                   pairs for ACI_C128; copied at the call */
 } aci_options;
 
 /* Result of aci_elementwise.  Output cores are written compactly, site after
@@ -406,6 +414,73 @@ int aci_tci(aci_ctx* ctx, int32_t L, const int32_t* d, int32_t dtype, aci_eval_f
             int32_t* idx_buf, void* val_buf, int64_t buf_points, const int32_t* pivots,
             int32_t n_pivots, double tol, int32_t maxrank, const aci_options* opt, void* out,
             int64_t out_capacity, aci_result* result);
+
+/* ---- TT operators and an explicit time step --------------------------------
+ * In TT solvers of nonlinear differential equations the contractions are with
+ * TT operators (MPOs) of small, constant bond dimension, such as finite-
+ * difference derivatives, and the elementwise nonlinearity is what ACI
+ * evaluates (Sec. 5).  These calls provide both parts of an explicit step on
+ * a periodic quantics grid. */
+
+/* A TT operator with real cores in caller device memory: core l has shape
+ * ranks[l] x d[l] x d[l] x ranks[l+1] (C order: left bond, output digit s,
+ * input digit t, right bond); the operator maps x to
+ * y[s_1..s_L] = sum_t W_1[s_1, t_1] ... W_L[s_L, t_L] x[t_1..t_L]. */
+typedef struct {
+  int32_t L;
+  const int32_t* d;            /* host, L local dimensions */
+  const int32_t* ranks;        /* host, L+1 bond ranks, ranks[0] = ranks[L] = 1 */
+  const double* const* cores;  /* host array of L device pointers */
+} aci_mpo;
+
+/* The periodic three-point stencil sum_{delta = -1, 0, 1} w_delta S^delta
+ * along `axis` of a box with 2^R points per axis in `ndim` dimensions, where
+ * (S^delta psi)(x) = psi(x + delta h), as an MPO of L = R ndim sites, d = 2,
+ * bond dimension 3 (1 at both ends).  Quantics order: site ndim b + a
+ * (0-based) holds bit R-1-b of axis a, most significant bit first.  The
+ * bonds carry the carry of adding delta, from the least significant bit to
+ * the most significant one, where it is dropped (periodicity).
+ *   weights  host, {w_-1, w_0, w_+1}
+ *   cores    host, 36 L doubles: core l at cores + 36 l, ranks[l] x 2 x 2 x
+ *            ranks[l+1] doubles in C order
+ *   ranks    host, L+1 values
+ * Host computation only; no context needed.  ACI_E_INVALID for R < 1,
+ * ndim < 1, axis outside [0, ndim) or a NULL pointer; ACI_E_LIMIT if
+ * R ndim > ACI_MAX_SITES. */
+int aci_mpo_stencil(int32_t R, int32_t ndim, int32_t axis, const double* weights, double* cores,
+                    int32_t* ranks);
+
+/* Exact MPO-TT contraction y = W x.  Core l of y has shape
+ * (w_{l-1} r_{l-1}) x d_l x (w_l r_l) with bond index a r + c (MPO bond a,
+ * TT bond c) and entries sum_t W_l[a, s, t, b] x_l[c, t, e]; for complex x
+ * the real operator acts on real and imaginary parts alike.
+ *   x        TT of the dtype (ACI_F64 or ACI_C128), device cores
+ *   out      host array of L device pointers, core l with room for its
+ *            (w_{l-1} r_{l-1}) d_l (w_l r_l) elements of the dtype; must not
+ *            overlap x or the operator
+ * ACI_E_INVALID on a length or local-dimension mismatch or a NULL pointer;
+ * ACI_E_LIMIT if an output core exceeds 2^31 - 1 doubles. */
+int aci_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t dtype, void* const* out);
+
+/* One explicit step of a cubic nonlinear equation,
+ *   y = c0 psi + c_lap sum_a D_a psi + c3 |psi|^2 psi,
+ * with D_a the periodic second difference (psi(x+h) - 2 psi(x) + psi(x-h)) /
+ * h^2 along axis a of the box [0,1)^ndim with 2^R points per axis (R = L /
+ * ndim, h = 2^-R, every d_l = 2, quantics order of aci_mpo_stencil).  The
+ * time step is folded into coef = {c0, c_lap, c3}: 3 doubles for ACI_F64, 3
+ * (re, im) pairs for ACI_C128 (Gross-Pitaevskii i psi_t = -1/2 Lap psi +
+ * g |psi|^2 psi: c0 = 1, c_lap = i dt / 2, c3 = -i g dt).  The D_a psi are
+ * formed exactly by aci_mpo_apply (bond ranks 3 r); then ACI evaluates
+ * LINEAR_CUBIC of (psi, D_1 psi, ..., D_ndim psi) with coefficients
+ * {c0, c_lap, ..., c_lap, c3}, started from Y_init = psi (the warm start)
+ * unless options.init is set; options.coef is ignored.  ndim <=
+ * ACI_MAX_INPUTS - 1; the ranks 3 r of D_a psi must stay <= ACI_MAX_MATRIX.
+ * The operators and the D_a psi take temporary device memory from the
+ * context's allocator, released before the return.  out, out_capacity,
+ * result and the return value as aci_elementwise. */
+int aci_cubic_step(aci_ctx* ctx, const aci_tt* psi, int32_t dtype, int32_t ndim, const double* coef,
+                   double tol, int32_t maxrank, const aci_options* opt, void* out, int64_t out_capacity,
+                   aci_result* result);
 
 /* Autotuner of the contraction tile shape (environment and two-site
  * products of Eq. pifromframes): times ngroup (1..ACI_MAX_INPUTS) side-by-side

@@ -8,11 +8,12 @@ with TT operators (MPOs) of small, constant bond dimension -- here periodic
 finite-difference stencils -- and an elementwise nonlinearity, which ACI
 evaluates.  For
 
-    dpsi/dt = c_lap * Laplacian(psi) + c_cub * |psi|^2 psi      (+ c_lin psi)
+    dpsi/dt = k_lap Laplacian(psi) + k_lin psi + k_cub |psi|^2 psi
 
 one explicit Euler step is the elementwise map
 
-    y = c0 * psi + c_lap_dt * sum_a D_a psi + c3 * |psi|^2 psi
+    y = c0 psi + c_lap sum_a D_a psi + c3 |psi|^2 psi,
+    c0 = 1 + dt k_lin, c_lap = dt k_lap, c3 = dt k_cub,
 
 of the N = 1 + ndim TTs (psi, D_1 psi, ..., D_ndim psi), with D_a the
 second-difference operator along axis a.  The D_a psi are exact MPO-TT
@@ -103,7 +104,8 @@ def mpo_dense(W):
 
 def linear_cubic(alpha, beta):
     """f(x^1, ..., x^N) = sum_n alpha_n x^n + beta |x^1|^2 x^1 with
-    |z|^2 = re*re + im*im."""
+    |z|^2 = re*re + im*im, summed as (((alpha_1 x^1 + beta |x^1|^2 x^1) +
+    alpha_2 x^2) + ...), the order in which the library defines the op."""
     alpha = list(alpha)
 
     def f(*P):
@@ -111,10 +113,10 @@ def linear_cubic(alpha, beta):
             raise ValueError("one coefficient per input")
         z = P[0]
         a = (z.real * z.real + z.imag * z.imag) if np.iscomplexobj(z) else z * z
-        out = alpha[0] * z
+        out = alpha[0] * z + beta * (a * z)
         for c, x in zip(alpha[1:], P[1:]):
             out = out + c * x
-        return out + beta * (a * z)
+        return out
 
     return f
 

@@ -6,14 +6,18 @@ elementwise operations on tensor trains (M. K. Ritter).
 ``Batch`` advance several products together; ``env_contract``, ``pi_eval``,
 ``prrlu`` and ``gather`` expose its single steps; ``tune_prrlu`` and
 ``tune_contract`` time the LDU launch shapes and the contraction tiles;
-``tci`` builds a TT from point evaluations (2-site TCI).  The library must be built (``python -m
+``tci`` builds a TT from point evaluations (2-site TCI); ``mpo_stencil``,
+``mpo_apply`` and ``cubic_step`` apply TT operators and take an explicit step
+of a cubic nonlinear equation (operator, then ACI of the nonlinearity).  The library must be built (``python -m
 paper_2604_00037_amd.build``); nothing falls back to the CPU.
 """
 
-from .aci import (Batch, Context, Session, default_context, elementwise, elementwise_batched, env_contract,
-                  gather, mlp_forward, mlp_train_step, pi_eval, proposal_features, prrlu, rook_check,
-                  rook_lu, rook_right_factor, tci, tune_contract, tune_prrlu, TILES)
+from .aci import (Batch, Context, Session, cubic_step, default_context, elementwise, elementwise_batched,
+                  env_contract, gather, linear_cubic, mlp_forward, mlp_train_step, mpo_apply, mpo_stencil,
+                  pi_eval, proposal_features, prrlu, rook_check, rook_lu, rook_right_factor, tci,
+                  tune_contract, tune_prrlu, TILES)
 
 __all__ = ["Batch", "Context", "Session", "default_context", "elementwise", "elementwise_batched",
            "env_contract", "gather", "mlp_forward", "mlp_train_step", "pi_eval", "proposal_features",
-           "prrlu", "rook_check", "rook_lu", "rook_right_factor", "tci", "tune_contract", "tune_prrlu", "TILES"]
+           "prrlu", "rook_check", "rook_lu", "rook_right_factor", "tci", "tune_contract", "tune_prrlu", "TILES",
+           "cubic_step", "linear_cubic", "mpo_apply", "mpo_stencil"]

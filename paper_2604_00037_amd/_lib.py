@@ -28,12 +28,21 @@ EXPORTED = [
     "aci_session_destroy", "aci_batch_create", "aci_batch_sweep", "aci_batch_result", "aci_batch_info",
     "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu", "aci_tune_contract", "aci_tci",
     "aci_proposal_features", "aci_mlp_forward", "aci_mlp_train_step", "aci_rook_lu", "aci_rook_check",
-    "aci_rook_right_factor",
+    "aci_rook_right_factor", "aci_mpo_stencil", "aci_mpo_apply", "aci_cubic_step",
 ]
 MLP_PARAMS = 7 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
 
 class AciTT(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32),
+        ("d", C.POINTER(C.c_int32)),
+        ("ranks", C.POINTER(C.c_int32)),
+        ("cores", C.POINTER(C.c_void_p)),
+    ]
+
+
+class AciMPO(C.Structure):
     _fields_ = [
         ("L", C.c_int32),
         ("d", C.POINTER(C.c_int32)),
@@ -60,6 +69,7 @@ class AciOptions(C.Structure):
         ("batch_mode", C.c_int32),
         ("pointwise", C.c_void_p),
         ("pointwise_user", C.c_void_p),
+        ("coef", C.POINTER(C.c_double)),
     ]
 
 
@@ -213,6 +223,13 @@ def load(path=LIB_PATH):
     lib.aci_rook_check.restype = C.c_int
     lib.aci_rook_right_factor.argtypes = [vp, vp, i32, vp, vp, i32, vp, i32]
     lib.aci_rook_right_factor.restype = C.c_int
+    lib.aci_mpo_stencil.argtypes = [i32, i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), i32p]
+    lib.aci_mpo_stencil.restype = C.c_int
+    lib.aci_mpo_apply.argtypes = [vp, C.POINTER(AciMPO), C.POINTER(AciTT), i32, C.POINTER(vp)]
+    lib.aci_mpo_apply.restype = C.c_int
+    lib.aci_cubic_step.argtypes = [vp, C.POINTER(AciTT), i32, i32, C.POINTER(C.c_double), C.c_double, i32,
+                                   C.POINTER(AciOptions), vp, C.c_int64, C.POINTER(AciResult)]
+    lib.aci_cubic_step.restype = C.c_int
     lib.aci_session_destroy.argtypes = [vp]
     lib.aci_session_destroy.restype = None
     _lib = lib

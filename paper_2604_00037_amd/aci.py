@@ -135,10 +135,36 @@ class _DevArray:
                                          "version": 3, "strides": None}
 
 
-def _op_code(op, opts, keep, complex_):
+def linear_cubic(alpha, beta):
+    """The op a_1 x_1 + ... + a_N x_N + b |x_1|^2 x_1 (ACI_OP_LINEAR_CUBIC)
+    with alpha = (a_1, ..., a_N) and beta = b, for ``elementwise``,
+    ``Session`` and ``Batch``."""
+    return ("linear_cubic", tuple(alpha), beta)
+
+
+def _coef_array(values, complex_, keep):
+    vals = []
+    for v in values:
+        v = complex(v)
+        if not complex_ and v.imag != 0.0:
+            raise ValueError("complex coefficient for real inputs")
+        vals.extend([v.real, v.imag] if complex_ else [v.real])
+    arr = (C.c_double * len(vals))(*vals)
+    keep.append(arr)
+    return arr
+
+
+def _op_code(op, opts, keep, complex_, n_inputs=None):
     """The aci_op of ``op``; a callable f(*tensors) -> tensor becomes
     ACI_OP_CUSTOM with options.pointwise applying it (torch ops on the
-    library's stream, on (rows, ld) views of the two-site tensors)."""
+    library's stream, on (rows, ld) views of the two-site tensors);
+    ``linear_cubic(alpha, beta)`` sets options.coef."""
+    if isinstance(op, tuple) and op and op[0] == "linear_cubic":
+        _, alpha, beta = op
+        if n_inputs is not None and len(alpha) != n_inputs:
+            raise ValueError("linear_cubic needs one coefficient per input")
+        opts.coef = _coef_array(list(alpha) + [beta], complex_, keep)
+        return 4
     if not callable(op):
         return OPS[op]
     typestr = "<c16" if complex_ else "<f8"
@@ -264,7 +290,7 @@ def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed
     tts = _inputs(inputs, keep)
     opts = _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, False,
                     low_precision_sweeps, False, proposal, proposal_scans)
-    code = _op_code(op, opts, keep, _code(inputs[0][0]) == 1)
+    code = _op_code(op, opts, keep, _code(inputs[0][0]) == 1, len(inputs))
     out, cap = _out_buffer(inputs, maxrank)
     res = _lib.AciResult()
     status = lib.aci_elementwise(ctx.h, tts, len(inputs), _code(inputs[0][0]), code, float(tol), int(maxrank),
@@ -324,7 +350,7 @@ class Session:
         opts.tune = 1 if tune else 0
         self._init = init
         h = C.c_void_p()
-        code = _op_code(op, opts, self._keep, _code(inputs[0][0]) == 1)
+        code = _op_code(op, opts, self._keep, _code(inputs[0][0]) == 1, len(inputs))
         st = self.ctx.lib.aci_session_create(self.ctx.h, tts, len(inputs), _code(inputs[0][0]), code, float(tol),
                                              int(maxrank), C.byref(opts), C.byref(h))
         _check(self.ctx.lib, self.ctx.h, st, allow_warning=False)
@@ -742,3 +768,79 @@ def rook_right_factor(rk, ctx=None):
     st = ctx.lib.aci_rook_right_factor(ctx.h, _p(Up), n, _p(rk["_cols"]), _p(rk["_rank"]), n, _p(Y), n)
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     return Y[:rk["rank"]]
+
+
+# ------------------------------------------------------------ TT operators
+def mpo_stencil(R, ndim, axis, weights, device=None):
+    """Periodic stencil sum_delta w_delta S^delta along ``axis`` (weights =
+    (w_-1, w_0, w_+1), (S^delta psi)(x) = psi(x + delta h)) of a box with 2^R
+    points per axis, as MPO cores (w_{l-1}, 2, 2, w_l) on the device
+    (aci_mpo_stencil builds them on the host)."""
+    lib = _lib.load()
+    L = int(R) * int(ndim)
+    cores = (C.c_double * (36 * max(L, 1)))()
+    ranks = (C.c_int32 * (L + 1))()
+    w = (C.c_double * 3)(*[float(x) for x in weights])
+    status = lib.aci_mpo_stencil(int(R), int(ndim), int(axis), w, cores, ranks)
+    if status != 0:
+        raise _lib.HipError(f"{_lib.STATUS_NAMES.get(status, status)}: aci_mpo_stencil")
+    flat = np.ctypeslib.as_array(cores)
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = []
+    for l in range(L):
+        shape = (ranks[l], 2, 2, ranks[l + 1])
+        out.append(torch.from_numpy(flat[36 * l:36 * l + int(np.prod(shape))].reshape(shape).copy()).to(dev))
+    return out
+
+
+def mpo_apply(mpo, x, ctx=None):
+    """Exact MPO-TT contraction (aci_mpo_apply): returns the cores of W x,
+    shapes (w_{l-1} r_{l-1}, d_l, w_l r_l), bond index a r + c."""
+    ctx = ctx or default_context()
+    lib = ctx.lib
+    keep = []
+    L = len(x)
+    if len(mpo) != L:
+        raise ValueError("operator and TT differ in length")
+    for l, c in enumerate(x):
+        _dev_tensor(c, f"x[{l}]")
+    for l, w in enumerate(mpo):
+        _dev_tensor(w, f"mpo[{l}]", torch.float64)
+        if w.dim() != 4:
+            raise ValueError("operator cores must be 4-dimensional")
+    tt = _tt_struct(x, keep)
+    d = (C.c_int32 * L)(*[int(w.shape[1]) for w in mpo])
+    wr = (C.c_int32 * (L + 1))(*([int(mpo[0].shape[0])] + [int(w.shape[3]) for w in mpo]))
+    wp = (C.c_void_p * L)(*[w.data_ptr() for w in mpo])
+    op = _lib.AciMPO(L, d, wr, wp)
+    out = [torch.empty((wr[l] * int(x[l].shape[0]), int(x[l].shape[1]), wr[l + 1] * int(x[l].shape[2])),
+                       dtype=x[0].dtype, device=x[0].device) for l in range(L)]
+    optr = (C.c_void_p * L)(*[o.data_ptr() for o in out])
+    _check(lib, ctx.h, lib.aci_mpo_apply(ctx.h, C.byref(op), C.byref(tt), _code(x[0]), optr), False)
+    return out
+
+
+def cubic_step(psi, ndim, c0, c_lap, c3, tol=1e-12, maxrank=64, *, maxiter=20, init=None,
+               stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False, ctx=None):
+    """One explicit step y = c0 psi + c_lap sum_a D_a psi + c3 |psi|^2 psi on a
+    periodic quantics grid (aci_cubic_step): the second differences D_a psi
+    by exact MPO application, then ACI started from psi (or ``init``).
+    Returns (cores, info) like ``elementwise``."""
+    ctx = ctx or default_context()
+    lib = ctx.lib
+    keep = []
+    for l, c in enumerate(psi):
+        _dev_tensor(c, f"psi[{l}]")
+    tt = _tt_struct(psi, keep)
+    cx = _code(psi[0]) == 1
+    coef = _coef_array([c0, c_lap, c3], cx, keep)
+    opts = _options(keep, maxiter, 0, init, stop_rule, precision, trace, fixed_sweeps, False)
+    out, cap = _out_buffer([psi], maxrank)
+    res = _lib.AciResult()
+    status = lib.aci_cubic_step(ctx.h, C.byref(tt), _code(psi[0]), int(ndim), coef, float(tol), int(maxrank),
+                                C.byref(opts), C.c_void_p(out.data_ptr()), cap, C.byref(res))
+    try:
+        _check(lib, ctx.h, status)
+        return _unpack(res, out, [int(c.shape[1]) for c in psi], status, trace)
+    finally:
+        lib.aci_result_free(C.byref(res))

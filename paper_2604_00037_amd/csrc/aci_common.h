@@ -33,7 +33,7 @@ enum : int { RULE_EXCLUSIVE = 0, RULE_LITERAL = 1 };
 
 // Elementwise operations of the two-site tensor.
 enum : int { OP_NONE = -1, OP_PRODUCT = ACI_OP_PRODUCT, OP_SUM = ACI_OP_SUM,
-             OP_ABS2_MUL = ACI_OP_ABS2_MUL };
+             OP_ABS2_MUL = ACI_OP_ABS2_MUL, OP_LINEAR_CUBIC = ACI_OP_LINEAR_CUBIC };
 // contraction precision (same values as aci_precision)
 enum : int { PREC_FP64 = ACI_PREC_FP64, PREC_FP32 = ACI_PREC_FP32, PREC_BF16X3 = ACI_PREC_BF16X3 };
 

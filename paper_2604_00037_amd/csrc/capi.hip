@@ -133,6 +133,7 @@ struct Plan {
   int L = 0, N = 0, op = 0, maxrank = 0, maxiter = 20, rule = 0;
   aci_pointwise_fn pointwise = nullptr;   // f of ACI_OP_CUSTOM
   void* pointwise_user = nullptr;
+  double coef[2 * (ACI_MAX_INPUTS + 1)] = {};   // ACI_OP_LINEAR_CUBIC: b, a_1..a_N (re, im)
   double* Pibuf[ACI_MAX_INPUTS] = {};      // the N two-site tensors it reads
   int cplx = 0, ew = 1;       // complex entries; doubles per entry
   int prec_req = PREC_FP64;   // requested contraction precision
@@ -641,6 +642,7 @@ int enqueue_pi(Enq& q, int l) {
     return ACI_OK;
   }
   c.ngroup = 1;
+  std::memcpy(c.coef, p.coef, sizeof c.coef);
   Group& gr = c.g[0];
   gr.nterm = p.N;
   for (int n = 0; n < p.N; ++n)
@@ -859,10 +861,23 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
   if (!inputs) return set_err(ctx, ACI_E_INVALID, "null inputs");
   if (n_inputs < 1 || n_inputs > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
   if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
-  if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL && op != ACI_OP_CUSTOM)
+  if (op != ACI_OP_PRODUCT && op != ACI_OP_SUM && op != ACI_OP_ABS2_MUL && op != ACI_OP_CUSTOM &&
+      op != ACI_OP_LINEAR_CUBIC)
     return set_err(ctx, ACI_E_INVALID, "unknown op");
   if ((op == ACI_OP_CUSTOM) != (o.pointwise != nullptr))
     return set_err(ctx, ACI_E_INVALID, "ACI_OP_CUSTOM goes with options.pointwise (and only it)");
+  if (op == ACI_OP_LINEAR_CUBIC) {
+    if (!o.coef) return set_err(ctx, ACI_E_INVALID, "ACI_OP_LINEAR_CUBIC needs options.coef");
+    const bool cx = dtype == ACI_C128;
+    for (int t = 0; t <= n_inputs; ++t) {
+      // API order a_1..a_N, b; kernel order b, a_1..a_N
+      const int k = t < n_inputs ? t + 1 : 0;
+      p.coef[2 * k] = o.coef[cx ? 2 * t : t];
+      p.coef[2 * k + 1] = cx ? o.coef[2 * t + 1] : 0.0;
+      if (!std::isfinite(p.coef[2 * k]) || !std::isfinite(p.coef[2 * k + 1]))
+        return set_err(ctx, ACI_E_INVALID, "non-finite coefficient");
+    }
+  }
   if (op == ACI_OP_ABS2_MUL && n_inputs != 1) return set_err(ctx, ACI_E_INVALID, "ABS2_MUL takes one input");
   if (!(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "tol must be >= 0");
   if (maxrank < 1) return set_err(ctx, ACI_E_INVALID, "maxrank must be >= 1");
@@ -2768,6 +2783,186 @@ int aci_gather(aci_ctx* ctx, int32_t dtype, int32_t side, const void* src, int32
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (flags & ERR_LIMIT) return set_err(ctx, ACI_E_INVALID, "gather index out of range");
   return ACI_OK;
+}
+
+// ------------------------------------------------ TT operators, time step
+int aci_mpo_stencil(int32_t R, int32_t ndim, int32_t axis, const double* weights, double* cores,
+                    int32_t* ranks) {
+  if (R < 1 || ndim < 1 || axis < 0 || axis >= ndim || !weights || !cores || !ranks) return ACI_E_INVALID;
+  if ((long long)R * ndim > ACI_MAX_SITES) return ACI_E_LIMIT;
+  const int L = R * ndim;
+  for (int l = 0; l <= L; ++l) ranks[l] = (l == 0 || l == L) ? 1 : 3;
+  // bond state k = carry + 1; the right bond of a site holds the carry coming
+  // from the less significant bits, the left bond the carry going on
+  for (int l = 0; l < L; ++l) {
+    double* W = cores + 36 * l;
+    std::fill(W, W + 36, 0.0);
+    const int wb = ranks[l + 1];
+    for (int kin = 0; kin < 3; ++kin)
+      for (int sb = 0; sb < 2; ++sb) {
+        int tb = sb, kout = kin;
+        if (l % ndim == axis) {
+          const int v = sb + kin - 1;               // output bit plus carry, in [-1, 2]
+          tb = (v + 2) & 1;
+          kout = (v < 0 ? -1 : v / 2) + 1;
+        }
+        // left end: the carry out of the top bit is dropped (all states
+        // summed); right end: the carry into the lowest bit is delta,
+        // weighted by w_delta
+        const int ia = l == 0 ? 0 : kout;
+        const int ib = l == L - 1 ? 0 : kin;
+        const double wt = l == L - 1 ? weights[kin] : 1.0;
+        W[((ia * 2 + sb) * 2 + tb) * wb + ib] += wt;
+      }
+  }
+  return ACI_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Enqueues Z_l = W_l X_l for every site (real operator; ew doubles per TT
+// element).  The caller has validated the shapes.
+int enqueue_mpo_apply(aci_ctx* ctx, int L, const int32_t* d, const int32_t* w, const double* const* Wc,
+                      const int32_t* r, const void* const* X, void* const* Z, int ew) {
+  for (int l0 = 0; l0 < L; l0 += kMpoSitesPerLaunch) {
+    MpoArgs a{};
+    int blocks = 0;
+    for (int l = l0; l < std::min(L, l0 + kMpoSitesPerLaunch); ++l) {
+      MpoSite& m = a.site[a.nsite++];
+      m.W = Wc[l];
+      m.X = (const double*)X[l];
+      m.Z = (double*)Z[l];
+      m.wa = w[l];
+      m.wb = w[l + 1];
+      m.ra = r[l];
+      m.xe = ew * r[l + 1];
+      m.d = d[l];
+      m.block0 = blocks;
+      blocks += mpo_site_blocks(m);
+    }
+    HIPCHK(launch_mpo_apply(a, blocks, ctx->stream));
+  }
+  return ACI_OK;
+}
+
+int validate_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t dtype) {
+  if (!W || !x || !W->d || !W->ranks || !W->cores) return set_err(ctx, ACI_E_INVALID, "null pointer");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
+  const int L = W->L;
+  if (L < 1 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
+  if (x->L != L || !x->d || !x->ranks || !x->cores) return set_err(ctx, ACI_E_INVALID, "TT and operator differ in length");
+  if (W->ranks[0] != 1 || W->ranks[L] != 1 || x->ranks[0] != 1 || x->ranks[L] != 1)
+    return set_err(ctx, ACI_E_INVALID, "boundary ranks must be 1");
+  const int ew = dtype == ACI_C128 ? 2 : 1;
+  for (int l = 0; l < L; ++l) {
+    if (W->d[l] != x->d[l]) return set_err(ctx, ACI_E_INVALID, "local dimensions differ");
+    if (x->d[l] < 1 || x->d[l] > ACI_MAX_DIM) return set_err(ctx, ACI_E_LIMIT, "local dimension out of range");
+    if (W->ranks[l + 1] < 1 || x->ranks[l + 1] < 1) return set_err(ctx, ACI_E_INVALID, "ranks must be >= 1");
+    if (!W->cores[l] || !x->cores[l]) return set_err(ctx, ACI_E_INVALID, "null core pointer");
+    const long long elems =
+        (long long)W->ranks[l] * x->ranks[l] * x->d[l] * W->ranks[l + 1] * x->ranks[l + 1] * ew;
+    if (elems > 0x7fffffffLL) return set_err(ctx, ACI_E_LIMIT, "output core too large");
+  }
+  return ACI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aci_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t dtype, void* const* out) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  int rc = validate_mpo_apply(ctx, W, x, dtype);
+  if (rc) return rc;
+  if (!out) return set_err(ctx, ACI_E_INVALID, "null output");
+  for (int l = 0; l < W->L; ++l)
+    if (!out[l]) return set_err(ctx, ACI_E_INVALID, "null output core");
+  rc = enqueue_mpo_apply(ctx, W->L, W->d, W->ranks, W->cores, x->ranks, x->cores, out, dtype == ACI_C128 ? 2 : 1);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ACI_OK;
+}
+
+int aci_cubic_step(aci_ctx* ctx, const aci_tt* psi, int32_t dtype, int32_t ndim, const double* coef,
+                   double tol, int32_t maxrank, const aci_options* opt, void* out, int64_t out_capacity,
+                   aci_result* result) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!psi || !coef) return set_err(ctx, ACI_E_INVALID, "null pointer");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
+  if (ndim < 1 || ndim > ACI_MAX_INPUTS - 1) return set_err(ctx, ACI_E_LIMIT, "ndim out of range");
+  const int L = psi->L;
+  if (L < 2 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
+  if (L % ndim != 0) return set_err(ctx, ACI_E_INVALID, "L must be a multiple of ndim");
+  int rc = validate_tt(ctx, *psi, L);
+  if (rc) return rc;
+  for (int l = 0; l < L; ++l)
+    if (psi->d[l] != 2) return set_err(ctx, ACI_E_INVALID, "quantics grids have d = 2 at every site");
+  const int R = L / ndim, ew = dtype == ACI_C128 ? 2 : 1;
+
+  // the second-difference operators (1, -2, 1) / h^2 along each axis
+  const double inv_h2 = std::ldexp(1.0, 2 * R);
+  const double wts[3] = {inv_h2, -2.0 * inv_h2, inv_h2};
+  std::vector<double> hcores((size_t)ndim * 36 * L);
+  std::vector<int32_t> wr(L + 1);
+  for (int a = 0; a < ndim; ++a) {
+    rc = aci_mpo_stencil(R, ndim, a, wts, hcores.data() + (size_t)a * 36 * L, wr.data());
+    if (rc) return set_err(ctx, rc, "stencil operator");
+  }
+  // device memory: the operators, then the D_a psi
+  std::vector<int32_t> zr(L + 1);
+  std::vector<size_t> zoff(L + 1, 0);
+  for (int l = 0; l <= L; ++l) zr[l] = wr[l] * psi->ranks[l];
+  for (int l = 0; l < L; ++l) {
+    if (zr[l + 1] > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "3 x rank of psi above ACI_MAX_MATRIX");
+    zoff[l + 1] = zoff[l] + (size_t)zr[l] * 2 * zr[l + 1] * ew;
+  }
+  const size_t wbytes = hcores.size() * sizeof(double);
+  void* buf = nullptr;
+  if (!dev_alloc(ctx, &buf, wbytes + (size_t)ndim * zoff[L] * sizeof(double)))
+    return set_err(ctx, ACI_E_NOMEM, "step workspace");
+  double* dW = (double*)buf;
+  double* dZ = dW + hcores.size();
+  std::vector<int32_t> d2(L, 2);
+  std::vector<const double*> Wp((size_t)ndim * L);
+  std::vector<void*> Zp((size_t)ndim * L);
+  std::vector<aci_tt> in(ndim + 1);
+  in[0] = *psi;
+  for (int a = 0; a < ndim; ++a)
+    for (int l = 0; l < L; ++l) {
+      Wp[(size_t)a * L + l] = dW + ((size_t)a * L + l) * 36;
+      Zp[(size_t)a * L + l] = dZ + (size_t)a * zoff[L] + zoff[l];
+    }
+  const hipError_t ce = hipMemcpyAsync(dW, hcores.data(), wbytes, hipMemcpyHostToDevice, ctx->stream);
+  rc = ce == hipSuccess ? ACI_OK : set_err(ctx, ACI_E_HIP, std::string("operator upload: ") + hipGetErrorString(ce));
+  for (int a = 0; a < ndim && rc == ACI_OK; ++a) {
+    rc = enqueue_mpo_apply(ctx, L, d2.data(), wr.data(), Wp.data() + (size_t)a * L, psi->ranks, psi->cores,
+                           Zp.data() + (size_t)a * L, ew);
+    in[a + 1] = aci_tt{L, d2.data(), zr.data(), (const void* const*)(Zp.data() + (size_t)a * L)};
+  }
+  if (rc == ACI_OK) {
+    // f = c0 psi + c_lap (D_1 psi + ... ) + c3 |psi|^2 psi, started from psi
+    aci_options o{};
+    if (opt) o = *opt;
+    if (!o.init) o.init = psi;
+    double cf[2 * (ACI_MAX_INPUTS + 1)];
+    for (int t = 0; t <= ndim + 1; ++t) {
+      const int src = t == 0 ? 0 : (t <= ndim ? 1 : 2);
+      for (int k = 0; k < ew; ++k) cf[ew * t + k] = coef[ew * src + k];
+    }
+    o.coef = cf;
+    o.pointwise = nullptr;
+    rc = aci_elementwise(ctx, in.data(), ndim + 1, dtype, ACI_OP_LINEAR_CUBIC, tol, maxrank, &o, out,
+                         out_capacity, result);
+  }
+  const std::string keep = ctx->err;
+  (void)hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, buf);
+  ctx->err = keep;
+  return rc;
 }
 
 }  // extern "C"

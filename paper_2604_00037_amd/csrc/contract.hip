@@ -133,15 +133,41 @@ __device__ __forceinline__ double abs2_mul(double x, double x_o, bool even) {
   return a * x;
 }
 
+// c x for a constant c = (cr, ci) of the dtype; xo is the neighbouring
+// lane's value (the other part of the same complex element).
+template <bool CPLX>
+__device__ __forceinline__ double scale(double cr, double ci, double x, double xo, bool even) {
+  if (!CPLX) return cr * x;
+  return even ? cr * x - ci * xo : cr * x + ci * xo;
+}
+
 // Epilogue of one term: fold the term's accumulators into the running
-// result (f of Eq. localupdate), element by element.
+// result (f of Eq. localupdate), element by element.  coef (OP_LINEAR_CUBIC
+// only): b, then a_1, a_2, ... as (re, im) pairs.
 template <int OP, bool CPLX, int MI, int NJ>
-__device__ __forceinline__ void fold_term(v4d (&res)[MI][NJ], const v4d (&x)[MI][NJ], int t, bool even) {
+__device__ __forceinline__ void fold_term(v4d (&res)[MI][NJ], const v4d (&x)[MI][NJ], int t, bool even,
+                                          const double* coef) {
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      if (OP == OP_ABS2_MUL) {
+      if (OP == OP_LINEAR_CUBIC) {
+        const double ar = coef[2 * t + 2], ai = coef[2 * t + 3];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double xv = x[i][j][v];
+          const double xo = CPLX ? __shfl_xor(xv, 1) : xv;
+          const double y = scale<CPLX>(ar, ai, xv, xo, even);
+          if (t == 0) {
+            // a_1 x_1 + b |x_1|^2 x_1
+            const double c = abs2_mul<CPLX>(xv, xo, even);
+            const double co = CPLX ? __shfl_xor(c, 1) : c;
+            res[i][j][v] = y + scale<CPLX>(coef[0], coef[1], c, co, even);
+          } else {
+            res[i][j][v] = res[i][j][v] + y;
+          }
+        }
+      } else if (OP == OP_ABS2_MUL) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const double xv = x[i][j][v];
@@ -244,7 +270,7 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
       }
       __syncthreads();
     }
-    fold_term<OP, CPLX, MI, NJ>(res, acc, t, even);
+    fold_term<OP, CPLX, MI, NJ>(res, acc, t, even, args.coef);
   }
   store_tile<OP, MI, NJ>(g, res, M, N, W * dget(g.ldc), m0 + wm * (TL::TM / 2) + lk,
                          n0 + wn * (TL::TN / 2) + lr, 4, args.err);
@@ -403,7 +429,7 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
         x[i][j] = v4d{(double)acc[i][j][0], (double)acc[i][j][1], (double)acc[i][j][2], (double)acc[i][j][3]};
-    fold_term<OP, CPLX, MI, NJ>(res, x, t, even);
+    fold_term<OP, CPLX, MI, NJ>(res, x, t, even, args.coef);
   }
   store_tile<OP, MI, NJ>(g, res, M, N, W * dget(g.ldc), m0 + wm * (TL::TM / 2) + 4 * lg,
                          n0 + wn * (TL::TN / 2) + lr, 1, args.err);
@@ -426,6 +452,7 @@ const void* pick_op(int op) {
     case OP_PRODUCT: return kernel_of<OP_PRODUCT, PREC, CPLX, TL>();
     case OP_SUM: return kernel_of<OP_SUM, PREC, CPLX, TL>();
     case OP_ABS2_MUL: return kernel_of<OP_ABS2_MUL, PREC, CPLX, TL>();
+    case OP_LINEAR_CUBIC: return kernel_of<OP_LINEAR_CUBIC, PREC, CPLX, TL>();
     default: return nullptr;
   }
 }

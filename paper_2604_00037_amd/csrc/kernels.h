@@ -32,6 +32,8 @@ struct ContractArgs {
   int* err;  // ERR_NONFINITE is or-ed in when an output is NaN/Inf (may be null)
   int cplx;  // 1: operands and result are complex (interleaved re, im); dims
              // and leading dimensions count complex elements
+  // OP_LINEAR_CUBIC: a_1..a_N, b as (re, im) pairs (im ignored when real)
+  double coef[2 * (ACI_MAX_INPUTS + 1)];
 };
 
 // op: OP_NONE (single term, plain GEMM), OP_PRODUCT, OP_SUM, OP_ABS2_MUL.
@@ -256,6 +258,25 @@ struct TciSetsArgs {
 };
 hipError_t launch_tci_points(const TciPointsArgs& a, hipStream_t s);
 hipError_t launch_tci_sets(const TciSetsArgs& a, int rmax, hipStream_t s);
+
+// ------------------------------------------------------- TT operators
+// One site of an MPO-TT contraction Z = W X (real W; X and Z in real units:
+// a complex core is a real one whose right bond counts re and im).
+struct MpoSite {
+  const double* W;   // wa x d x d x wb
+  const double* X;   // ra x d x xe     (xe = right rank in doubles)
+  double* Z;         // (wa ra) x d x (wb xe)
+  int wa, wb, ra, xe, d;
+  int block0;        // first workgroup of this site within the launch
+};
+constexpr int kMpoSitesPerLaunch = 32;
+struct MpoArgs {
+  MpoSite site[kMpoSitesPerLaunch];
+  int nsite;
+};
+// workgroups one site needs (4 output rows of xe doubles each per group)
+int mpo_site_blocks(const MpoSite& m);
+hipError_t launch_mpo_apply(const MpoArgs& a, int blocks, hipStream_t s);
 
 // Fill `count` doubles with `value` (used instead of a memset so the sweep can
 // be captured in a graph).

@@ -47,3 +47,39 @@ def test_null_context_is_rejected_without_device():
                          None, None, None, None, None, 1) == -1
     lib.aci_last_error.restype = ctypes.c_char_p
     assert lib.aci_last_error(None) == b"null context"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libaci.so not built")
+@pytest.mark.parametrize("R,ndim", [(1, 1), (4, 1), (3, 2), (2, 3), (5, 3)])
+def test_host_stencil_builder_matches_the_oracle(R, ndim):
+    """aci_mpo_stencil is host logic: its cores equal the oracle's,
+    entry for entry, for every axis (both written from the carry rule)."""
+    import numpy as np
+    from oracle import timestep as T
+    lib = ctypes.CDLL(LIB)
+    lib.aci_mpo_stencil.restype = ctypes.c_int
+    L = R * ndim
+    for axis in range(ndim):
+        w = np.random.default_rng(10 * R + ndim + axis).standard_normal(3)
+        cores = (ctypes.c_double * (36 * L))()
+        ranks = (ctypes.c_int32 * (L + 1))()
+        assert lib.aci_mpo_stencil(R, ndim, axis, (ctypes.c_double * 3)(*w), cores, ranks) == 0
+        flat = np.ctypeslib.as_array(cores)
+        ref = T.stencil_mpo(R, ndim, axis, w)
+        for l in range(L):
+            shape = (ranks[l], 2, 2, ranks[l + 1])
+            assert shape == ref[l].shape
+            assert np.array_equal(flat[36 * l:36 * l + int(np.prod(shape))].reshape(shape), ref[l])
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libaci.so not built")
+def test_host_stencil_builder_rejects_bad_arguments():
+    lib = ctypes.CDLL(LIB)
+    lib.aci_mpo_stencil.restype = ctypes.c_int
+    w = (ctypes.c_double * 3)(1.0, -2.0, 1.0)
+    cores = (ctypes.c_double * (36 * 200))()
+    ranks = (ctypes.c_int32 * 201)()
+    assert lib.aci_mpo_stencil(0, 1, 0, w, cores, ranks) == -1       # R < 1
+    assert lib.aci_mpo_stencil(4, 2, 2, w, cores, ranks) == -1       # axis >= ndim
+    assert lib.aci_mpo_stencil(4, 2, 0, None, cores, ranks) == -1
+    assert lib.aci_mpo_stencil(65, 2, 0, w, cores, ranks) == -6      # L > ACI_MAX_SITES

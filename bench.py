@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 METRIC = "ACI sweeps/s + contraction TFLOP/s vs plain FP64 GPU ACI at rel err 1e-8"
 PEAK_FP64_VALU = 78.6      # TFLOP/s, MI355X FP64 vector
 PEAK_FP64_MFMA = 78.6      # TFLOP/s, MI355X FP64 matrix
+PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
 PEAK_MFMA = {"fp64": 78.6, "fp32": 157.3,
              # bf16x3 runs three bf16 products per algorithmic product
              "bf16x3": 2500.0 / 3}
@@ -332,6 +333,22 @@ def time_batched(aci, steps, warmup, device):
             "max_eps": st["max_eps"], "pivots_per_sweep": st["pivots"] / steps}
 
 
+_GP_FIELD = {}
+
+
+def gp_psi(device):
+    """The Gross-Pitaevskii input field (compressed once per run)."""
+    import torch
+    import workloads as W
+    if "psi" not in _GP_FIELD:
+        t = time.perf_counter()
+        _GP_FIELD["psi"] = W.gp_field(R=14, chi=512, seed=5001, device=device, waves=16, kmax=256)
+        torch.cuda.synchronize()
+        log(f"GP field compressed in {time.perf_counter() - t:.1f} s; "
+            f"ranks {max(c.shape[2] for c in _GP_FIELD['psi'])}")
+    return _GP_FIELD["psi"]
+
+
 def time_c5(aci, device, steps=2, warmup=1):
     """Gross-Pitaevskii nonlinear term |psi|^2 psi: a complex field of 32
     Gaussian vortex modes, each carrying a speckle of 16 random plane waves
@@ -340,11 +357,7 @@ def time_c5(aci, device, steps=2, warmup=1):
     complex128 contractions (FP64 matrix cores) and with complex64
     contractions (FP32 matrix cores); the LDU stays complex128 in both."""
     import torch
-    import workloads as W
-    t = time.perf_counter()
-    psi = W.gp_field(R=14, chi=512, seed=5001, device=device, waves=16, kmax=256)
-    torch.cuda.synchronize()
-    log(f"GP field compressed in {time.perf_counter() - t:.1f} s; ranks {max(c.shape[2] for c in psi)}")
+    psi = gp_psi(device)
     cores = [[torch.from_numpy(c).to(device) for c in psi]]
     out = {"workload": "|psi|^2 psi of a GP vortex field, 32 Gaussian modes x 16 plane waves (|k|<=256), "
                        "(2^14)^2 grid, 2D quantics L=28 d=2, "
@@ -378,6 +391,94 @@ def time_c5(aci, device, steps=2, warmup=1):
             f"({con_tf / peak:.1%} of peak; launches >= 1 GFLOP {big_tf:.2f} TFLOP/s, {big_tf / peak:.1%}); LDU {out['complex128' if prec == 'fp64' else 'complex64']['prrlu_us_per_pivot']:.2f} "
             f"us/pivot; max eps {st['max_eps']:.3e}")
     del cores
+    torch.cuda.empty_cache()
+    return out
+
+
+def step_exact_sampled(psi, pts, R, ndim, c0, c_lap, c3):
+    """The explicit step evaluated from psi at each point and its 2 ndim grid
+    neighbours (periodic second differences), one point at a time."""
+    import numpy as np
+    import workloads as W
+
+    def shifted(axis, delta):
+        out = pts.copy()
+        sites = [ndim * b + axis for b in range(R)]
+        coord = np.zeros(pts.shape[0], dtype=np.int64)
+        for b, s in enumerate(sites):
+            coord |= pts[:, s].astype(np.int64) << (R - 1 - b)
+        coord = (coord + delta) % (1 << R)
+        for b, s in enumerate(sites):
+            out[:, s] = (coord >> (R - 1 - b)) & 1
+        return out
+
+    z = W.tt_eval(psi, pts)
+    lap = 0.0
+    for a in range(ndim):
+        lap = lap + (W.tt_eval(psi, shifted(a, 1)) - 2 * z + W.tt_eval(psi, shifted(a, -1))) * 4.0 ** R
+    return c0 * z + c_lap * lap + c3 * (z.real * z.real + z.imag * z.imag) * z
+
+
+def time_step(aci, device, sweeps=3):
+    """One explicit Gross-Pitaevskii step i psi_t = -1/2 Lap psi + |psi|^2 psi
+    of the same field ((2^14)^2 grid, L=28, TT rank 512): the periodic
+    second differences along both axes as exact MPO-TT contractions (bond
+    dimension 3, outputs of rank 1536), then ACI of
+    psi + i dt/2 (D_x psi + D_y psi) - i dt |psi|^2 psi started from psi
+    (rank cap 512, tol 1e-8, a fixed number of sweeps), dt = 0.1 h^2.
+    Reports the MPO kernel against the HBM roofline and the step's time and
+    sampled error."""
+    import numpy as np
+    import torch
+    import workloads as W
+    psi = gp_psi(device)
+    cores = [torch.from_numpy(c).to(device) for c in psi]
+    R, ndim, L = 14, 2, len(psi)
+    inv_h2 = 4.0 ** R
+    dt = 0.1 / inv_h2
+    c0, c_lap, c3 = 1.0, 0.5j * dt, -1j * dt
+    out = {"workload": "one explicit GP step of the vortex-speckle field ((2^14)^2 grid, L=28, rank 512): "
+                       "second differences by MPO (rank 1536), then ACI from psi, cap 512, tol 1e-8, "
+                       f"{sweeps} sweeps, complex128"}
+    ops = [aci.mpo_stencil(R, ndim, a, (inv_h2, -2.0 * inv_h2, inv_h2), device=device) for a in range(ndim)]
+    aci.mpo_apply(ops[0], cores)            # warm-up
+    reps = 5
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        for a in range(ndim):
+            z = aci.mpo_apply(ops[a], cores)
+            del z
+    ev1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * ev0.elapsed_time(ev1) / (reps * ndim)
+    # algorithmic bytes of one application: operator and input cores read
+    # once, output cores written once
+    nbytes = 0
+    for l, c in enumerate(psi):
+        w0 = 1 if l == 0 else 3
+        w1 = 1 if l == L - 1 else 3
+        nbytes += 8 * w0 * 4 * w1 + 16 * c.size + 16 * (w0 * c.shape[0]) * 2 * (w1 * c.shape[2])
+    gbs = nbytes / (us * 1e-6) / 1e9
+    out["mpo_apply"] = {"us_per_operator": us, "algorithmic_bytes": nbytes, "achieved_GBs": gbs,
+                        "hbm_frac": gbs / (PEAK_HBM / 1e9)}
+    log(f"MPO second difference: {us:.1f} us per operator (28 sites), {nbytes / 1e6:.1f} MB, "
+        f"{gbs:.0f} GB/s ({gbs / (PEAK_HBM / 1e9):.1%} of HBM peak)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y, info = aci.cubic_step(cores, ndim, c0, c_lap, c3, 1e-8, 512, maxiter=sweeps, fixed_sweeps=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pts = np.random.default_rng(94).integers(0, 2, (4096, L))
+    f = step_exact_sampled(psi, pts, R, ndim, c0, c_lap, c3)
+    err = np.abs(W.tt_eval([c.cpu().numpy() for c in y], pts) - f).max() / np.abs(f).max()
+    out["step"] = {"seconds": el, "sweeps": info.sweeps, "sweep_ms": info.sweep_ms / max(1, info.sweeps),
+                   "max_rank": max(info.ranks), "max_eps": max(info.eps),
+                   "sampled_max_rel_error": float(err)}
+    log(f"GP step: {el:.3f} s ({info.sweeps} sweeps, {info.sweep_ms / max(1, info.sweeps):.1f} ms each), "
+        f"ranks <= {max(info.ranks)}, max eps {max(info.eps):.2e}, sampled rel error {err:.2e}")
+    del cores, y
     torch.cuda.empty_cache()
     return out
 
@@ -574,7 +675,8 @@ def main():
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-gp", action="store_true", help="skip the complex |psi|^2 psi workload")
     ap.add_argument("--no-tci", action="store_true", help="skip the TCI + ACI Gaussian example")
-    ap.add_argument("--only", choices=["gp", "batched", "contract", "tci"],
+    ap.add_argument("--no-step", action="store_true", help="skip the explicit GP time step")
+    ap.add_argument("--only", choices=["gp", "batched", "contract", "tci", "step"],
                     help="run just one section and print its JSON (for profiling that workload)")
     ap.add_argument("--summarize-contract", metavar="DIR", help="per-case table of a traced --only contract run")
     ap.add_argument("--summarize-stats", metavar="DIR",
@@ -615,6 +717,9 @@ def main():
         return
     if args.only == "tci":
         print(json.dumps(time_tci(aci, dev)), flush=True)
+        return
+    if args.only == "step":
+        print(json.dumps(time_step(aci, dev)), flush=True)
         return
     if args.only == "contract":
         print(json.dumps(time_contract(aci, dev)), flush=True)
@@ -708,6 +813,8 @@ def main():
         out["proposal"] = time_proposal(aci, dev)
     if not args.no_gp:
         out["gp"] = time_c5(aci, dev)
+    if not args.no_step:
+        out["gp_step"] = time_step(aci, dev)
     if not args.no_tci:
         out["tci"] = time_tci(aci, dev)
     if not args.no_cpu_baseline:

@@ -50,6 +50,7 @@ extern "C" {
 #define ACI_MAX_RANK 512        /* maxrank (output bond dimension cap) */
 #define ACI_MAX_INPUTS 4        /* N */
 #define ACI_MAX_MATRIX 1024     /* rows and columns of a matricised two-site tensor */
+#define ACI_MAX_INPUT_RANK 2048 /* bond ranks of the input TTs (and of Y_init: ACI_MAX_MATRIX) */
 #define ACI_MAX_BATCH 64        /* products of one batch */
 #define ACI_MAX_MLP_BATCH 4096  /* samples of one training step of the scoring network */
 #define ACI_MLP_FEATURES 7
@@ -127,7 +128,9 @@ typedef struct {
   int32_t tune;          /* 1 = pick the tile of every contraction launch
                             with aci_tune_contract, and in overlapped batches
                             each product's LDU group count with
-                            aci_tune_prrlu (both cached per context) */
+                            aci_tune_prrlu (both cached per context);
+                            launch shapes beyond ACI_MAX_MATRIX keep the
+                            default tile */
   const float* proposal; /* learned pivot proposal (extension): device array of
                             ACI_MLP_PARAMS network parameters, or NULL.  Every
                             local update then scores the rows, runs the seeded
@@ -474,7 +477,8 @@ int aci_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t dtype
  * LINEAR_CUBIC of (psi, D_1 psi, ..., D_ndim psi) with coefficients
  * {c0, c_lap, ..., c_lap, c3}, started from Y_init = psi (the warm start)
  * unless options.init is set; options.coef is ignored.  ndim <=
- * ACI_MAX_INPUTS - 1; the ranks 3 r of D_a psi must stay <= ACI_MAX_MATRIX.
+ * ACI_MAX_INPUTS - 1; the ranks 3 r of D_a psi must stay <=
+ * ACI_MAX_INPUT_RANK.
  * The operators and the D_a psi take temporary device memory from the
  * context's allocator, released before the return.  out, out_capacity,
  * result and the return value as aci_elementwise. */

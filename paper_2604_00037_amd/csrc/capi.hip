@@ -913,7 +913,7 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
       if (inputs[n].d[l] != inputs[0].d[l]) return set_err(ctx, ACI_E_INVALID, "inputs differ in local dimensions");
     for (int l = 0; l <= L; ++l) {
       p.r[n][l] = inputs[n].ranks[l];
-      if (p.r[n][l] > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "input rank above limit");
+      if (p.r[n][l] > ACI_MAX_INPUT_RANK) return set_err(ctx, ACI_E_LIMIT, "input rank above ACI_MAX_INPUT_RANK");
     }
     for (int l = 1; l <= L; ++l) p.X[n][l] = (const double*)inputs[n].cores[l - 1];
   }
@@ -1191,9 +1191,19 @@ int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t
         kr = std::max(kr, p.r[n][l + 1]);
         kp = std::max(kp, p.r[n][l]);
       }
-      if ((rc = tune_tile(ctx, p.cplx, p.prec, p.N, p.capI[l - 1], kl, wl, &p.tiles[0][l], nullptr))) return rc;
-      if ((rc = tune_tile(ctx, p.cplx, p.prec, p.N, mr, kr, p.capJ[l + 2], &p.tiles[1][l], nullptr))) return rc;
-      if ((rc = tune_tile(ctx, p.cplx, p.prec, 1, p.d[l] * p.capI[l - 1], kp, p.d[l + 1] * p.capJ[l + 2],
+      // shapes beyond the tuner's range (inputs of rank > ACI_MAX_MATRIX)
+      // keep the default tile
+      auto tunable = [](int m, int k, int n) {
+        return m <= ACI_MAX_MATRIX && k <= ACI_MAX_MATRIX && n <= ACI_MAX_MATRIX;
+      };
+      if (tunable(p.capI[l - 1], kl, wl) &&
+          (rc = tune_tile(ctx, p.cplx, p.prec, p.N, p.capI[l - 1], kl, wl, &p.tiles[0][l], nullptr)))
+        return rc;
+      if (tunable(mr, kr, p.capJ[l + 2]) &&
+          (rc = tune_tile(ctx, p.cplx, p.prec, p.N, mr, kr, p.capJ[l + 2], &p.tiles[1][l], nullptr)))
+        return rc;
+      if (tunable(p.d[l] * p.capI[l - 1], kp, p.d[l + 1] * p.capJ[l + 2]) &&
+          (rc = tune_tile(ctx, p.cplx, p.prec, 1, p.d[l] * p.capI[l - 1], kp, p.d[l + 1] * p.capJ[l + 2],
                           &p.tiles[2][l], nullptr)))
         return rc;
     }
@@ -2917,7 +2927,7 @@ int aci_cubic_step(aci_ctx* ctx, const aci_tt* psi, int32_t dtype, int32_t ndim,
   std::vector<size_t> zoff(L + 1, 0);
   for (int l = 0; l <= L; ++l) zr[l] = wr[l] * psi->ranks[l];
   for (int l = 0; l < L; ++l) {
-    if (zr[l + 1] > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "3 x rank of psi above ACI_MAX_MATRIX");
+    if (zr[l + 1] > ACI_MAX_INPUT_RANK) return set_err(ctx, ACI_E_LIMIT, "3 x rank of psi above ACI_MAX_INPUT_RANK");
     zoff[l + 1] = zoff[l] + (size_t)zr[l] * 2 * zr[l + 1] * ew;
   }
   const size_t wbytes = hcores.size() * sizeof(double);

@@ -7,7 +7,11 @@ from the definition of the result), the rank caps, and the error estimate.
 * product of two random 3D Fourier fields (1024^3 grid, L = 30, d = 2, TT
   rank 128), tol 1e-8, rank cap 192, FP64, fixed sweeps;
 * |psi|^2 psi of a 2D vortex-speckle field ((2^14)^2 grid, L = 28, TT rank
-  512), rank cap 512, complex128 and complex64 contractions.
+  512), rank cap 512, complex128 and complex64 contractions;
+* one explicit Gross-Pitaevskii step of the same field (second differences
+  by MPO, inputs of rank 1536, then ACI started from psi), against the
+  Euler step evaluated from psi at each sample point and its four
+  neighbours.
 
 Bounds.  A cross interpolation reproduces the function exactly on its
 pivots; between them the error of each two-site update is estimated by the
@@ -84,3 +88,43 @@ def test_gross_pitaevskii_full_size_sampled(precision, gp_psi):
     err = sampled_error(cores, f, pts)
     print(f"GP {precision}: sampled max err {err / scale:.3e} (relative), max eps {st['max_eps']:.3e}")
     assert err <= 4 * (L - 1) * st["max_eps"] + 1e-12 * scale
+
+
+def quantics_neighbours(pts, R, ndim, axis, delta):
+    """Quantics digits of the grid points one step along ``axis`` (periodic);
+    site ndim*b + a holds bit R-1-b of axis a."""
+    out = pts.copy()
+    sites = [ndim * b + axis for b in range(R)]
+    coord = np.zeros(pts.shape[0], dtype=np.int64)
+    for b, s in enumerate(sites):
+        coord |= pts[:, s].astype(np.int64) << (R - 1 - b)
+    coord = (coord + delta) % (1 << R)
+    for b, s in enumerate(sites):
+        out[:, s] = (coord >> (R - 1 - b)) & 1
+    return out
+
+
+def test_gross_pitaevskii_step_full_size_sampled(gp_psi):
+    dev = torch.device("cuda:0")
+    psi = gp_psi
+    R, ndim, L = 14, 2, len(psi)
+    dt = 0.1 / 4.0 ** R
+    c0, c_lap, c3 = 1.0, 0.5j * dt, -1j * dt
+    cores, info = aci.cubic_step(cores_on(psi, dev), ndim, c0, c_lap, c3, 1e-8, 512, maxiter=3,
+                                 fixed_sweeps=True)
+    assert max(info.ranks) <= 512
+    rng = np.random.default_rng(93)
+    pts = rng.integers(0, 2, (SAMPLES, L))
+    z = W.tt_eval(psi, pts)
+    lap = 0.0
+    for a in range(ndim):
+        lap = lap + (W.tt_eval(psi, quantics_neighbours(pts, R, ndim, a, 1)) - 2 * z
+                     + W.tt_eval(psi, quantics_neighbours(pts, R, ndim, a, -1))) * 4.0 ** R
+    f = c0 * z + c_lap * lap + c3 * (z.real * z.real + z.imag * z.imag) * z
+    scale = max(np.abs(f).max(), 1e-300)
+    err = sampled_error(cores, f, pts)
+    max_eps = max(info.eps)
+    print(f"GP step: sampled max err {err / scale:.3e} (relative), max eps {max_eps:.3e}, "
+          f"ranks <= {max(info.ranks)}")
+    assert err <= 4 * (L - 1) * max_eps + 1e-12 * scale
+

@@ -149,3 +149,24 @@ def test_cubic_step_custom_init_and_errors():
         aci.cubic_step(to_dev(psi), 3, 1.0, 0.0, 0.0, 1e-10, 64)
     with pytest.raises(aci._lib.HipError):       # ndim above ACI_MAX_INPUTS - 1
         aci.cubic_step(to_dev(psi), 4, 1.0, 0.0, 0.0, 1e-10, 64)
+
+
+def test_inputs_of_rank_above_the_matrix_limit():
+    """Input ranks up to ACI_MAX_INPUT_RANK (the second differences of a
+    rank-512 field have rank 1536): a non-minimal random TT of interior rank
+    1100 times a rank-3 TT, against the oracle."""
+    L = 6
+    x1 = W.random_tt(L, 2, 1100, 2951)
+    x2 = W.random_tt(L, 2, 3, 2952)
+    ref = oracle.aci([x1, x2], "product", 1e-12, 32, seed=8, log_gaps=True)
+    cores, info = aci.elementwise([to_dev(x1), to_dev(x2)], "product", 1e-12, 32, seed=8, trace=True)
+    n = compare_records(info.records, ref.trace, "rank 1100 input")
+    assert n == len(ref.trace)
+    y = W.tt_full([c.cpu().numpy() for c in cores])
+    assert rel_max_err(y, W.tt_full(x1) * W.tt_full(x2)) <= 1e-10
+    # tuned tiles: shapes beyond the tuner's range keep the default tile
+    S = aci.Session([to_dev(x1), to_dev(x2)], "product", 1e-12, 32, maxiter=2, seed=8, tune=True)
+    S.sweep(2)
+    c2, _ = S.result()
+    S.close()
+    assert rel_max_err(W.tt_full([c.cpu().numpy() for c in c2]), y) <= 1e-12

@@ -78,14 +78,20 @@ def tt_full(cores):
 
 def tt_eval(cores, points):
     """Evaluate the TT at integer multi-indices ``points`` (shape P x L) by
-    multiplying the selected core slices left to right."""
+    multiplying the selected core slices left to right: at each site the
+    points sharing a digit value take one matrix product."""
     points = np.asarray(points)
     P = points.shape[0]
     dtype = np.result_type(*[c.dtype for c in cores])
     v = np.ones((P, 1), dtype=dtype)
     for s, c in enumerate(cores):
-        sl = np.asarray(c)[:, points[:, s], :]          # r0 x P x r1
-        v = np.einsum("pa,apb->pb", v, sl)
+        c = np.asarray(c)
+        nxt = np.empty((P, c.shape[2]), dtype=dtype)
+        for sigma in range(c.shape[1]):
+            sel = points[:, s] == sigma
+            if sel.any():
+                nxt[sel] = v[sel] @ c[:, sigma, :]
+        v = nxt
     return v[:, 0]
 
 

@@ -461,9 +461,12 @@ int aci_mpo_stencil(int32_t R, int32_t ndim, int32_t axis, const double* weights
  *   out      host array of L device pointers, core l with room for its
  *            (w_{l-1} r_{l-1}) d_l (w_l r_l) elements of the dtype; must not
  *            overlap x or the operator
+ *   kernel_ms optional (NULL): device time of the launches, from HIP events
+ *            on the context stream
  * ACI_E_INVALID on a length or local-dimension mismatch or a NULL pointer;
  * ACI_E_LIMIT if an output core exceeds 2^31 - 1 doubles. */
-int aci_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t dtype, void* const* out);
+int aci_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t dtype, void* const* out,
+                  float* kernel_ms);
 
 /* One explicit step of a cubic nonlinear equation,
  *   y = c0 psi + c_lap sum_a D_a psi + c3 |psi|^2 psi,

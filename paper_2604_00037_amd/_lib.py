@@ -225,7 +225,7 @@ def load(path=LIB_PATH):
     lib.aci_rook_right_factor.restype = C.c_int
     lib.aci_mpo_stencil.argtypes = [i32, i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), i32p]
     lib.aci_mpo_stencil.restype = C.c_int
-    lib.aci_mpo_apply.argtypes = [vp, C.POINTER(AciMPO), C.POINTER(AciTT), i32, C.POINTER(vp)]
+    lib.aci_mpo_apply.argtypes = [vp, C.POINTER(AciMPO), C.POINTER(AciTT), i32, C.POINTER(vp), C.POINTER(C.c_float)]
     lib.aci_mpo_apply.restype = C.c_int
     lib.aci_cubic_step.argtypes = [vp, C.POINTER(AciTT), i32, i32, C.POINTER(C.c_double), C.c_double, i32,
                                    C.POINTER(AciOptions), vp, C.c_int64, C.POINTER(AciResult)]

@@ -793,9 +793,10 @@ def mpo_stencil(R, ndim, axis, weights, device=None):
     return out
 
 
-def mpo_apply(mpo, x, ctx=None):
+def mpo_apply(mpo, x, ctx=None, timing=False):
     """Exact MPO-TT contraction (aci_mpo_apply): returns the cores of W x,
-    shapes (w_{l-1} r_{l-1}, d_l, w_l r_l), bond index a r + c."""
+    shapes (w_{l-1} r_{l-1}, d_l, w_l r_l), bond index a r + c; with
+    ``timing`` also the device milliseconds of its launches."""
     ctx = ctx or default_context()
     lib = ctx.lib
     keep = []
@@ -816,8 +817,10 @@ def mpo_apply(mpo, x, ctx=None):
     out = [torch.empty((wr[l] * int(x[l].shape[0]), int(x[l].shape[1]), wr[l + 1] * int(x[l].shape[2])),
                        dtype=x[0].dtype, device=x[0].device) for l in range(L)]
     optr = (C.c_void_p * L)(*[o.data_ptr() for o in out])
-    _check(lib, ctx.h, lib.aci_mpo_apply(ctx.h, C.byref(op), C.byref(tt), _code(x[0]), optr), False)
-    return out
+    ms = C.c_float(0.0)
+    _check(lib, ctx.h, lib.aci_mpo_apply(ctx.h, C.byref(op), C.byref(tt), _code(x[0]), optr,
+                                         C.byref(ms) if timing else None), False)
+    return (out, ms.value) if timing else out
 
 
 def cubic_step(psi, ndim, c0, c_lap, c3, tol=1e-12, maxrank=64, *, maxiter=20, init=None,

@@ -2849,6 +2849,7 @@ int enqueue_mpo_apply(aci_ctx* ctx, int L, const int32_t* d, const int32_t* w, c
       m.ra = r[l];
       m.xe = ew * r[l + 1];
       m.d = d[l];
+      m.vec = (m.xe % 2 == 0 && (uintptr_t)m.X % 16 == 0 && (uintptr_t)m.Z % 16 == 0) ? 1 : 0;
       m.block0 = blocks;
       blocks += mpo_site_blocks(m);
     }
@@ -2882,7 +2883,8 @@ int validate_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t 
 
 extern "C" {
 
-int aci_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t dtype, void* const* out) {
+int aci_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t dtype, void* const* out,
+                  float* kernel_ms) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
   int rc = validate_mpo_apply(ctx, W, x, dtype);
@@ -2890,9 +2892,25 @@ int aci_mpo_apply(aci_ctx* ctx, const aci_mpo* W, const aci_tt* x, int32_t dtype
   if (!out) return set_err(ctx, ACI_E_INVALID, "null output");
   for (int l = 0; l < W->L; ++l)
     if (!out[l]) return set_err(ctx, ACI_E_INVALID, "null output core");
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (kernel_ms) {
+    HIPCHK(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+      (void)hipEventDestroy(ev[0]);
+      return set_err(ctx, ACI_E_HIP, "hipEventCreate");
+    }
+    (void)hipEventRecord(ev[0], ctx->stream);
+  }
   rc = enqueue_mpo_apply(ctx, W->L, W->d, W->ranks, W->cores, x->ranks, x->cores, out, dtype == ACI_C128 ? 2 : 1);
+  if (kernel_ms && rc == ACI_OK) (void)hipEventRecord(ev[1], ctx->stream);
+  const hipError_t se = hipStreamSynchronize(ctx->stream);
+  if (kernel_ms) {
+    if (rc == ACI_OK && se == hipSuccess && hipEventElapsedTime(kernel_ms, ev[0], ev[1]) != hipSuccess) *kernel_ms = -1.f;
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+  }
   if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (se != hipSuccess) return set_err(ctx, ACI_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(se));
   return ACI_OK;
 }
 

@@ -267,6 +267,7 @@ struct MpoSite {
   const double* X;   // ra x d x xe     (xe = right rank in doubles)
   double* Z;         // (wa ra) x d x (wb xe)
   int wa, wb, ra, xe, d;
+  int vec;           // 1: xe even and X, Z 16-byte aligned (two doubles per access)
   int block0;        // first workgroup of this site within the launch
 };
 constexpr int kMpoSitesPerLaunch = 32;
@@ -274,7 +275,7 @@ struct MpoArgs {
   MpoSite site[kMpoSitesPerLaunch];
   int nsite;
 };
-// workgroups one site needs (4 output rows of xe doubles each per group)
+// workgroups one site needs (4 row groups (a, c, s) of wb x xe doubles each)
 int mpo_site_blocks(const MpoSite& m);
 hipError_t launch_mpo_apply(const MpoArgs& a, int blocks, hipStream_t s);
 

@@ -3,15 +3,20 @@
 // Sec. 5).  Core by core,
 //   Z[(a, c), s, (b, e)] = sum_t W[a, s, t, b] X[c, t, e],
 // so the output is w^2 times the input: the kernel is bound by its HBM
-// writes.  One wave writes one output row (a, c, s, b), xe contiguous
-// doubles; the rows are dealt in the order (c, a, s, b) so that the
-// workgroups running together read the same rows of X from L2.
+// writes.  One wave produces the wb output rows (a, c, s, 0..wb-1), which
+// are contiguous (wb xe doubles), from the d rows X[c, t, :]: every element
+// of X is loaded once per (a, s) and every output element stored once,
+// 16 bytes per lane and access, with non-temporal stores (the output is not
+// read again by this kernel).  Row groups are dealt in the order (c, a, s)
+// so that the workgroups running together read the same rows of X from L2.
 #include "kernels.h"
 
 namespace aci {
 namespace {
 
-constexpr int kRowsPerGroup = 4;   // one row per wave of a 256-thread workgroup
+constexpr int kRowsPerGroup = 4;   // one row group per wave of a 256-thread workgroup
+
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(256) void mpo_apply_kernel(MpoArgs args) {
   int si = 0;
@@ -20,31 +25,50 @@ __global__ __launch_bounds__(256) void mpo_apply_kernel(MpoArgs args) {
   const MpoSite& m = args.site[si];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = ((int)blockIdx.x - m.block0) * kRowsPerGroup + wave;
-  if (row >= m.ra * m.wa * m.d * m.wb) return;
-  int q = row;
-  const int b = q % m.wb;
-  q /= m.wb;
-  const int s = q % m.d;
-  q /= m.d;
-  const int a = q % m.wa;
-  const int c = q / m.wa;
-  double w[ACI_MAX_DIM];
+  if (row >= m.ra * m.wa * m.d) return;
+  const int s = row % m.d;
+  const int a = (row / m.d) % m.wa;
+  const int c = row / (m.d * m.wa);
+  const int d = m.d, wb = m.wb, xe = m.xe;
+  const double* x = m.X + (size_t)c * d * xe;
+  const double* w = m.W + (size_t)(a * d + s) * d * wb;   // w[t wb + b] = W[a, s, t, b]
+  double* z = m.Z + ((size_t)(a * m.ra + c) * d + s) * wb * xe;
+  if (m.vec) {
+    const int n2 = xe / 2;
+    for (int e = lane; e < n2; e += 64) {
+      v2d xv[ACI_MAX_DIM];
 #pragma unroll
-  for (int t = 0; t < ACI_MAX_DIM; ++t)
-    w[t] = t < m.d ? m.W[((size_t)(a * m.d + s) * m.d + t) * m.wb + b] : 0.0;
-  const double* x = m.X + (size_t)c * m.d * m.xe;
-  double* z = m.Z + ((size_t)((a * m.ra + c) * m.d + s) * m.wb + b) * m.xe;
-  for (int e = lane; e < m.xe; e += 64) {
-    double acc = w[0] * x[e];
-    for (int t = 1; t < m.d; ++t) acc += w[t] * x[(size_t)t * m.xe + e];
-    z[e] = acc;
+      for (int t = 0; t < ACI_MAX_DIM; ++t)
+        if (t < d) xv[t] = reinterpret_cast<const v2d*>(x + (size_t)t * xe)[e];
+      for (int b = 0; b < wb; ++b) {
+        v2d acc = w[b] * xv[0];
+#pragma unroll
+        for (int t = 1; t < ACI_MAX_DIM; ++t)
+          if (t < d) acc += w[t * wb + b] * xv[t];
+        __builtin_nontemporal_store(acc, reinterpret_cast<v2d*>(z + (size_t)b * xe) + e);
+      }
+    }
+  } else {
+    for (int e = lane; e < xe; e += 64) {
+      double xv[ACI_MAX_DIM];
+#pragma unroll
+      for (int t = 0; t < ACI_MAX_DIM; ++t)
+        if (t < d) xv[t] = x[(size_t)t * xe + e];
+      for (int b = 0; b < wb; ++b) {
+        double acc = w[b] * xv[0];
+#pragma unroll
+        for (int t = 1; t < ACI_MAX_DIM; ++t)
+          if (t < d) acc += w[t * wb + b] * xv[t];
+        __builtin_nontemporal_store(acc, z + (size_t)b * xe + e);
+      }
+    }
   }
 }
 
 }  // namespace
 
 int mpo_site_blocks(const MpoSite& m) {
-  const long long rows = (long long)m.ra * m.wa * m.d * m.wb;
+  const long long rows = (long long)m.ra * m.wa * m.d;
   return (int)((rows + kRowsPerGroup - 1) / kRowsPerGroup);
 }
 

@@ -1,9 +1,11 @@
 """Input generators: the torch (device) path of the quantics reordering
-agrees with the numpy definition (a transpose of the bit axes)."""
+agrees with the numpy definition (a transpose of the bit axes), and the
+central-difference derivative of a Fourier field is the grid stencil."""
 
 import numpy as np
 import pytest
 
+import workloads as W
 from workloads.fields import grid_to_quantics, quantics_to_grid
 
 torch = pytest.importorskip("torch")
@@ -29,3 +31,14 @@ def test_interleaved_site_holds_axis_bit():
         i0 = sum(idx[ndim * b + 0] << (R - 1 - b) for b in range(R))
         i1 = sum(idx[ndim * b + 1] << (R - 1 - b) for b in range(R))
         assert Q[idx] == i0 * 1000 + i1
+
+
+def test_central_difference_derivative_is_the_grid_stencil():
+    """deriv="central" equals (u(x+h e_j) - u(x-h e_j)) / 2h of the sampled
+    field on the periodic grid, for every axis."""
+    R = 4
+    u = W.fourier3d_full(R, 3, 3001)
+    for j in range(3):
+        du = W.fourier3d_full(R, 3, 3001, deriv_axis=j, deriv="central")
+        fd = (np.roll(u, -1, j) - np.roll(u, 1, j)) * 2 ** R / 2
+        assert np.abs(du - fd).max() <= 1e-13 * np.abs(fd).max()

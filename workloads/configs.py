@@ -78,10 +78,11 @@ def gp_field(R=14, chi=512, seed=5001, device=None, width_scale=1.0, waves=0, km
 
 
 def velocity_set(R=10, kmax=32, seeds=(3001, 3002, 3003),
-                 chi_u=(64, 96, 128), chi_du=(128, 192, 256), device=None):
-    """u_j compressed to chi_u[j]; d_j u_k (spectral derivative of the same
-    Fourier field) compressed to chi_du[(j + k) % 3].  Returns (u, du) with
-    du[j][k] the TT of d u_k / d x_j."""
+                 chi_u=(64, 96, 128), chi_du=(128, 192, 256), device=None, deriv="central"):
+    """u_j compressed to chi_u[j]; d_j u_k (periodic central difference of
+    the same Fourier field on the grid, or its spectral derivative) compressed
+    to chi_du[(j + k) % 3].  Returns (u, du) with du[j][k] the TT of
+    d u_k / d x_j."""
     u = []
     for j, s in enumerate(seeds):
         g = fourier3d_full(R, kmax, s, device=device)
@@ -90,7 +91,7 @@ def velocity_set(R=10, kmax=32, seeds=(3001, 3002, 3003),
     du = [[None] * 3 for _ in range(3)]
     for j in range(3):
         for k, s in enumerate(seeds):
-            g = fourier3d_full(R, kmax, s, device=device, deriv_axis=j)
+            g = fourier3d_full(R, kmax, s, device=device, deriv_axis=j, deriv=deriv)
             du[j][k] = _compress(g, R, 3, chi_du[(j + k) % 3], device)
             del g
     return u, du

@@ -140,17 +140,26 @@ def fourier3d_modes(kmax, seed, slope=-11.0 / 6.0):
     return k, amp, phase
 
 
-def fourier3d_full(R, kmax, seed, device=None, deriv_axis=None):
+def fourier3d_full(R, kmax, seed, device=None, deriv_axis=None, deriv="spectral"):
     """u(x) = sum_k A_k cos(2 pi k.x + phi_k) on the (2^R)^3 grid of [0,1)^3,
     normalised to RMS 1 (over the grid the modes are orthogonal, so the RMS is
     sqrt(sum A_k^2 / 2)).  With ``deriv_axis=j`` returns d u / d x_j under the
-    same normalisation factor.  Computed as three separable small-DFT sums.
+    same normalisation factor: ``deriv="spectral"`` the exact derivative,
+    ``"central"`` the periodic central difference (u(x + h e_j) -
+    u(x - h e_j)) / 2h on the grid (h = 2^-R), which multiplies each mode by
+    i sin(2 pi k_j h) / h.  Computed as three separable small-DFT sums.
     Returns a (2^R)^3 array (numpy, or a torch tensor on ``device``)."""
     k, amp, phase = fourier3d_modes(kmax, seed)
     norm = np.sqrt((amp * amp).sum() / 2.0)
     coef = amp * np.exp(1j * phase) / norm             # u = Re sum coef e^{2 pi i k.x}
     if deriv_axis is not None:
-        coef = coef * (2j * np.pi * k[:, deriv_axis])
+        if deriv == "spectral":
+            coef = coef * (2j * np.pi * k[:, deriv_axis])
+        elif deriv == "central":
+            h = 2.0 ** -R
+            coef = coef * (1j * np.sin(2 * np.pi * k[:, deriv_axis] * h) / h)
+        else:
+            raise ValueError(f"unknown derivative {deriv!r}")
     nk = 2 * kmax + 1
     C = np.zeros((nk, nk, nk), dtype=np.complex128)
     np.add.at(C, (k[:, 0] + kmax, k[:, 1] + kmax, k[:, 2] + kmax), coef)

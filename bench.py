@@ -277,7 +277,7 @@ def time_mode(aci, inputs, precision, steps, warmup, ref_values=None):
 
 def time_batched(aci, steps, warmup, device):
     """The nine convective products u_j * d_j u_k (three velocity components
-    of the same random Fourier kind, spectral derivatives, uneven ranks
+    of the same random Fourier kind, central-difference derivatives, uneven ranks
     64..256), tol 1e-8, output rank cap 256: sweeps of the whole set per
     second as one joint batch (one LDU launch per local update for all nine
     products, each on its own XCD, the sweep captured in a graph), as an
@@ -322,7 +322,7 @@ def time_batched(aci, steps, warmup, device):
         S.close()
     log(f"batched: {steps} sweeps of 9 products in {batched:.3f} s (joint); one after another {seq:.3f} s")
     return {"workload": "u_j * d_j u_k, j,k = 1..3: 9 products of 3D Fourier velocity fields (|k|<=32) and "
-                        "their spectral derivatives, 1024^3 grid, L=30 d=2, input ranks "
+                        "their central differences, 1024^3 grid, L=30 d=2, input ranks "
                         f"{ranks_in}, tol {TOL}, rank cap 256, FP64",
             "products": len(products), "sweeps_per_s": steps / batched,
             "product_sweeps_per_s": len(products) * steps / batched,

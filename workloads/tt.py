@@ -126,7 +126,7 @@ def tt_svd(full, d, maxrank, rtol=0.0, method="auto"):
             W = Wn
         else:
             if is_torch:
-                G = (W @ W.conj().T).cpu().numpy()
+                G = _gram_fixed_order(W).cpu().numpy()
             else:
                 G = W @ W.conj().T
             lam, U = np.linalg.eigh(G)
@@ -151,6 +151,25 @@ def tt_svd(full, d, maxrank, rtol=0.0, method="auto"):
         last = last.cpu().numpy()
     cores.append(np.ascontiguousarray(last))
     return cores
+
+
+def _gram_fixed_order(W, chunk=8192):
+    """W W^H for a device matrix W (m x K, K large) with a fixed summation
+    order: the products of K-chunks of ``chunk`` columns as one batched
+    product, then a sum over the chunks.  A single library GEMM may split a
+    long K across workgroups and accumulate the parts atomically, so its
+    result can differ in the last bits from run to run, and the
+    eigenvectors of nearly equal eigenvalues (hence the TT cores) with it."""
+    import torch
+    m, K = W.shape
+    if K <= chunk or K % chunk:
+        return W @ W.conj().T.contiguous()
+    B = K // chunk
+    Wb = W.reshape(m, B, chunk).permute(1, 0, 2).contiguous()      # B x m x chunk
+    Wh = Wb.conj().transpose(1, 2).contiguous()                     # B x chunk x m
+    G = torch.bmm(Wb, Wh)
+    del Wb, Wh
+    return G.sum(dim=0)
 
 
 def _keep(sv, maxrank, rtol):

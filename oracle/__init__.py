@@ -23,6 +23,9 @@ the algorithms of Appendix B of the paper in their order:
 * ``tci``             -- 2-site TCI of a function given point by point (the
                          construction of the inputs, Sec. 3; the index-set
                          optimisation of Sec. 2.5 with Pi evaluated directly)
+* ``patched``         -- patched ACI: f on patches of fixed leading indices,
+                         refined where one TT at the rank cap does not
+                         converge (the patched scheme named in Sec. 5)
 * ``timestep``        -- TT operators on quantics grids (periodic stencil
                          MPOs, exact MPO-TT contraction) and one explicit
                          step of a cubic nonlinear equation with ACI started
@@ -39,10 +42,11 @@ from . import reference
 from . import proposal
 from .tci import tci, TCIResult, two_site_points
 from . import timestep
+from . import patched
 
 __all__ = [
     "prrlu", "PrrLU", "cross_interpolate", "local_update", "left_frame",
     "right_frame", "aci", "ACIResult", "apply_op", "default_init_ranks",
     "splitmix64_stream", "default_init", "reference", "proposal",
-    "tci", "TCIResult", "two_site_points", "timestep",
+    "tci", "TCIResult", "two_site_points", "timestep", "patched",
 ]

@@ -489,6 +489,48 @@ int aci_cubic_step(aci_ctx* ctx, const aci_tt* psi, int32_t dtype, int32_t ndim,
                    double tol, int32_t maxrank, const aci_options* opt, void* out, int64_t out_capacity,
                    aci_result* result);
 
+/* ---- patched ACI --------------------------------------------------------
+ * f(x^1..x^N) as tensor trains on patches of the index space (the patched
+ * elementwise scheme named in Sec. 5).  A patch is a prefix of k fixed
+ * leading indices (sigma_1..sigma_k); its tensor, f restricted to them, is a
+ * TT over sites k+1..L.  The inputs are restricted exactly on the device:
+ * the prefix vector X_1[:, sigma_1, :] ... X_k[:, sigma_k, :] is absorbed
+ * into the first free core.  Breadth first from the empty prefix, every
+ * patch of a level runs ACI (Alg. 1; one batch per level, as
+ * aci_elementwise_batched, with the same tol, maxrank and options, hence the
+ * same seeded default Y_init); a patch whose sweeps converged is kept, the
+ * others split into their d children, down to max_depth fixed indices, where
+ * patches are kept whatever their state.  Patches are listed level by level,
+ * prefixes in lexicographic order within a level. */
+typedef struct {
+  int32_t n_patches;
+  int32_t L;
+  int32_t levels;         /* levels run (1 + deepest prefix length) */
+  int32_t* prefix_len;    /* host, n_patches: k */
+  uint8_t* prefix;        /* host, n_patches x L digits; the first k used */
+  int32_t* ranks;         /* host, n_patches x (L+1): bond ranks of the patch
+                             TT over its L-k sites (first L-k+1 used) */
+  int64_t* core_offset;   /* host, n_patches x L: element offsets of its
+                             cores in `cores` (first L-k used); core j has
+                             shape ranks[j] x d_{k+j} x ranks[j+1] */
+  int32_t* converged;     /* host, n_patches */
+  int32_t* sweeps;        /* host, n_patches */
+  double* max_eps;        /* host, n_patches: largest error estimate */
+  void* cores;            /* device, from the context's allocator: all cores */
+  int64_t cores_elems;    /* elements of the dtype in `cores` */
+} aci_patched_result;
+
+/* Patched ACI of the inputs (as aci_elementwise) down to max_depth fixed
+ * indices, 0 <= max_depth <= L - 2 (max_depth 0: one patch, the unpatched
+ * ACI).  result is filled on return; release it with aci_patched_free on the
+ * same context.  Returns ACI_OK if every kept patch converged, else
+ * ACI_W_NOT_CONVERGED (patches at max_depth that did not converge), or an
+ * error. */
+int aci_patched(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
+                double tol, int32_t maxrank, int32_t max_depth, const aci_options* opt,
+                aci_patched_result* result);
+void aci_patched_free(aci_ctx* ctx, aci_patched_result* result);
+
 /* Autotuner of the contraction tile shape (environment and two-site
  * products of Eq. pifromframes): times ngroup (1..ACI_MAX_INPUTS) side-by-side
  * copies of an m x k by k x n product (dtype, precision; operands seeded

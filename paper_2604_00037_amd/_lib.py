@@ -28,7 +28,8 @@ EXPORTED = [
     "aci_session_destroy", "aci_batch_create", "aci_batch_sweep", "aci_batch_result", "aci_batch_info",
     "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu", "aci_tune_contract", "aci_tci",
     "aci_proposal_features", "aci_mlp_forward", "aci_mlp_train_step", "aci_rook_lu", "aci_rook_check",
-    "aci_rook_right_factor", "aci_mpo_stencil", "aci_mpo_apply", "aci_cubic_step",
+    "aci_rook_right_factor", "aci_mpo_stencil", "aci_mpo_apply", "aci_cubic_step", "aci_patched",
+    "aci_patched_free",
 ]
 MLP_PARAMS = 7 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -39,6 +40,23 @@ class AciTT(C.Structure):
         ("d", C.POINTER(C.c_int32)),
         ("ranks", C.POINTER(C.c_int32)),
         ("cores", C.POINTER(C.c_void_p)),
+    ]
+
+
+class AciPatchedResult(C.Structure):
+    _fields_ = [
+        ("n_patches", C.c_int32),
+        ("L", C.c_int32),
+        ("levels", C.c_int32),
+        ("prefix_len", C.POINTER(C.c_int32)),
+        ("prefix", C.POINTER(C.c_uint8)),
+        ("ranks", C.POINTER(C.c_int32)),
+        ("core_offset", C.POINTER(C.c_int64)),
+        ("converged", C.POINTER(C.c_int32)),
+        ("sweeps", C.POINTER(C.c_int32)),
+        ("max_eps", C.POINTER(C.c_double)),
+        ("cores", C.c_void_p),
+        ("cores_elems", C.c_int64),
     ]
 
 
@@ -230,6 +248,11 @@ def load(path=LIB_PATH):
     lib.aci_cubic_step.argtypes = [vp, C.POINTER(AciTT), i32, i32, C.POINTER(C.c_double), C.c_double, i32,
                                    C.POINTER(AciOptions), vp, C.c_int64, C.POINTER(AciResult)]
     lib.aci_cubic_step.restype = C.c_int
+    lib.aci_patched.argtypes = [vp, C.POINTER(AciTT), i32, i32, i32, C.c_double, i32, i32, C.POINTER(AciOptions),
+                                C.POINTER(AciPatchedResult)]
+    lib.aci_patched.restype = C.c_int
+    lib.aci_patched_free.argtypes = [vp, C.POINTER(AciPatchedResult)]
+    lib.aci_patched_free.restype = None
     lib.aci_session_destroy.argtypes = [vp]
     lib.aci_session_destroy.restype = None
     _lib = lib

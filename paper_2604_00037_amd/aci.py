@@ -847,3 +847,56 @@ def cubic_step(psi, ndim, c0, c_lap, c3, tol=1e-12, maxrank=64, *, maxiter=20, i
         return _unpack(res, out, [int(c.shape[1]) for c in psi], status, trace)
     finally:
         lib.aci_result_free(C.byref(res))
+
+
+# ------------------------------------------------------------ patched ACI
+@dataclass
+class Patch:
+    prefix: tuple            # fixed leading indices
+    cores: list              # TT over the remaining sites (device tensors)
+    ranks: list
+    converged: bool
+    sweeps: int
+    max_eps: float
+
+
+def patched(inputs, op="product", tol=1e-12, maxrank=64, max_depth=2, *, maxiter=20, seed=0,
+            stop_rule="exclusive", precision="fp64", ctx=None):
+    """Patched ACI (aci_patched): f on patches of fixed leading indices,
+    split where one TT at the rank cap does not converge.  Returns the kept
+    patches (level by level, prefixes in lexicographic order) and the
+    status."""
+    ctx = ctx or default_context()
+    lib = ctx.lib
+    keep = []
+    tts = _inputs(inputs, keep)
+    opts = _options(keep, maxiter, seed, None, stop_rule, precision, False, False, False)
+    cx = _code(inputs[0][0]) == 1
+    code = _op_code(op, opts, keep, cx, len(inputs))
+    res = _lib.AciPatchedResult()
+    status = lib.aci_patched(ctx.h, tts, len(inputs), _code(inputs[0][0]), code, float(tol), int(maxrank),
+                             int(max_depth), C.byref(opts), C.byref(res))
+    try:
+        _raise_pointwise(keep)
+        _check(lib, ctx.h, status)
+        L = res.L
+        dims = [int(c.shape[1]) for c in inputs[0]]
+        typestr = "<c16" if cx else "<f8"
+        dev = inputs[0][0].device
+        allc = torch.as_tensor(_DevArray(res.cores, (max(res.cores_elems, 1),), typestr), device=dev)
+        out = []
+        for i in range(res.n_patches):
+            k = res.prefix_len[i]
+            prefix = tuple(int(res.prefix[i * L + j]) for j in range(k))
+            ranks = [int(res.ranks[i * (L + 1) + j]) for j in range(L - k + 1)]
+            cores = []
+            for j in range(L - k):
+                off = res.core_offset[i * L + j]
+                cnt = ranks[j] * dims[k + j] * ranks[j + 1]
+                cores.append(allc[off:off + cnt].view(ranks[j], dims[k + j], ranks[j + 1]).clone())
+            out.append(Patch(prefix, cores, ranks, bool(res.converged[i]), int(res.sweeps[i]),
+                             float(res.max_eps[i])))
+        torch.cuda.current_stream().synchronize()
+        return out, status
+    finally:
+        lib.aci_patched_free(ctx.h, C.byref(res))

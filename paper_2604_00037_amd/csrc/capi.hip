@@ -2994,3 +2994,248 @@ int aci_cubic_step(aci_ctx* ctx, const aci_tt* psi, int32_t dtype, int32_t ndim,
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ patched ACI
+namespace {
+
+struct PatchNode {
+  std::vector<uint8_t> prefix;
+  std::vector<const void*> first;   // per input: restricted first core (depth > 0)
+  void* out = nullptr;              // output cores of the patch's ACI
+  int64_t cap = 0;
+  int32_t ranks[ACI_MAX_SITES + 1] = {};
+  int64_t offs[ACI_MAX_SITES] = {};
+  int64_t elems = 0;
+  int converged = 0, sweeps = 0;
+  double eps = 0.0;
+};
+
+// Elements that always hold the output cores of a TT over sites with local
+// dimensions d[0..n) and bond ranks capped by maxrank.
+int64_t patch_capacity(const int32_t* d, int n, int maxrank) {
+  std::vector<int64_t> left(n + 1, 1), right(n + 1, 1);
+  for (int l = 0; l < n; ++l) left[l + 1] = std::min<int64_t>(left[l] * d[l], maxrank);
+  for (int l = n - 1; l >= 0; --l) right[l] = std::min<int64_t>(right[l + 1] * d[l], maxrank);
+  int64_t cap = 0;
+  for (int l = 0; l < n; ++l) {
+    const int64_t r0 = std::min(left[l], right[l]), r1 = std::min(left[l + 1], right[l + 1]);
+    cap += r0 * d[l] * r1;
+  }
+  return cap;
+}
+
+}  // namespace
+
+extern "C" {
+
+void aci_patched_free(aci_ctx* ctx, aci_patched_result* r) {
+  if (!r) return;
+  std::free(r->prefix_len);
+  std::free(r->prefix);
+  std::free(r->ranks);
+  std::free(r->core_offset);
+  std::free(r->converged);
+  std::free(r->sweeps);
+  std::free(r->max_eps);
+  if (ctx && r->cores) {
+    (void)hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, r->cores);
+  }
+  std::memset(r, 0, sizeof(*r));
+}
+
+int aci_patched(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
+                double tol, int32_t maxrank, int32_t max_depth, const aci_options* opt,
+                aci_patched_result* result) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!inputs || !result) return set_err(ctx, ACI_E_INVALID, "null pointer");
+  std::memset(result, 0, sizeof(*result));
+  if (n_inputs < 1 || n_inputs > ACI_MAX_INPUTS) return set_err(ctx, ACI_E_LIMIT, "n_inputs out of range");
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
+  if (maxrank < 1 || maxrank > ACI_MAX_RANK) return set_err(ctx, ACI_E_LIMIT, "maxrank out of range");
+  const int L = inputs[0].L;
+  if (L < 2 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
+  if (max_depth < 0 || max_depth > L - 2) return set_err(ctx, ACI_E_INVALID, "max_depth must lie in [0, L - 2]");
+  for (int n = 0; n < n_inputs; ++n) {
+    const int rc = validate_tt(ctx, inputs[n], L);
+    if (rc) return rc;
+    for (int l = 0; l < L; ++l)
+      if (inputs[n].d[l] != inputs[0].d[l]) return set_err(ctx, ACI_E_INVALID, "inputs differ in local dimensions");
+  }
+  const int ew = dtype == ACI_C128 ? 2 : 1;
+  const int32_t* dims = inputs[0].d;
+  std::vector<void*> bufs;   // every device buffer of the call, released at the end
+  auto release = [&]() {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* b : bufs) dev_free(ctx, b);
+    bufs.clear();
+  };
+  auto alloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (!dev_alloc(ctx, &p, bytes)) return nullptr;
+    bufs.push_back(p);
+    return p;
+  };
+
+  std::vector<PatchNode> level(1), kept;
+  int rc = ACI_OK, worst = ACI_OK, levels = 0;
+  for (int depth = 0; depth <= max_depth && !level.empty() && rc >= 0; ++depth) {
+    levels = depth + 1;
+    const int Lp = L - depth;
+    const int64_t cap = patch_capacity(dims + depth, Lp, maxrank);
+    // restricted inputs of every patch of the level
+    std::vector<std::vector<int32_t>> ranks(level.size() * n_inputs, std::vector<int32_t>(Lp + 1));
+    std::vector<std::vector<const void*>> cores(level.size() * n_inputs, std::vector<const void*>(Lp));
+    std::vector<aci_tt> tts(level.size() * n_inputs);
+    for (size_t p = 0; p < level.size(); ++p)
+      for (int n = 0; n < n_inputs; ++n) {
+        const size_t i = p * n_inputs + n;
+        ranks[i][0] = 1;
+        for (int j = 1; j <= Lp; ++j) ranks[i][j] = inputs[n].ranks[depth + j];
+        for (int j = 0; j < Lp; ++j) cores[i][j] = inputs[n].cores[depth + j];
+        if (depth > 0) cores[i][0] = level[p].first[n];
+        tts[i] = aci_tt{Lp, dims + depth, ranks[i].data(), cores[i].data()};
+      }
+    for (PatchNode& nd : level) {
+      nd.cap = cap;
+      nd.out = alloc((size_t)cap * ew * sizeof(double));
+      if (!nd.out) {
+        release();
+        return set_err(ctx, ACI_E_NOMEM, "patch output");
+      }
+    }
+    // ACI on the level, ACI_MAX_BATCH patches per batch
+    for (size_t p0 = 0; p0 < level.size() && rc >= 0; p0 += ACI_MAX_BATCH) {
+      const int cnt = (int)std::min<size_t>(ACI_MAX_BATCH, level.size() - p0);
+      std::vector<int32_t> nin(cnt, n_inputs);
+      std::vector<void*> outs(cnt);
+      std::vector<int64_t> caps(cnt, cap);
+      std::vector<aci_result> res(cnt);
+      for (int b = 0; b < cnt; ++b) outs[b] = level[p0 + b].out;
+      rc = aci_elementwise_batched(ctx, tts.data() + p0 * n_inputs, nin.data(), cnt, dtype, op, tol, maxrank, opt,
+                                   outs.data(), caps.data(), res.data());
+      for (int b = 0; b < cnt; ++b) {
+        PatchNode& nd = level[p0 + b];
+        if (rc >= 0) {
+          nd.converged = res[b].converged;
+          nd.sweeps = res[b].sweeps;
+          nd.elems = res[b].out_elems;
+          for (int j = 0; j <= Lp; ++j) nd.ranks[j] = res[b].ranks[j];
+          for (int j = 0; j < Lp; ++j) nd.offs[j] = res[b].core_offset[j];
+          nd.eps = 0.0;
+          for (int j = 0; j < Lp - 1; ++j) nd.eps = std::max(nd.eps, res[b].eps[j]);
+        }
+        aci_result_free(&res[b]);
+      }
+    }
+    if (rc < 0) break;
+    // keep the converged patches (all of them at the last level), split the rest
+    std::vector<PatchNode> next;
+    for (PatchNode& nd : level) {
+      if (nd.converged || depth == max_depth) {
+        if (!nd.converged) worst = ACI_W_NOT_CONVERGED;
+        kept.push_back(nd);
+        continue;
+      }
+      // child sigma: first core v @ X_{depth+1}, v = row sigma of this
+      // patch's first core (1 x r_{depth+1})
+      for (int sg = 0; sg < dims[depth]; ++sg) {
+        PatchNode ch;
+        ch.prefix = nd.prefix;
+        ch.prefix.push_back((uint8_t)sg);
+        ch.first.resize(n_inputs);
+        ContractArgs c{};
+        c.cplx = ew == 2 ? 1 : 0;
+        c.ngroup = n_inputs;
+        int nmax = 1;
+        for (int n = 0; n < n_inputs; ++n) {
+          const int r1 = inputs[n].ranks[depth + 1];
+          const int w = dims[depth + 1] * inputs[n].ranks[depth + 2];
+          void* buf = alloc((size_t)w * ew * sizeof(double));
+          if (!buf) {
+            release();
+            return set_err(ctx, ACI_E_NOMEM, "patch inputs");
+          }
+          const double* parent = (const double*)(depth == 0 ? inputs[n].cores[0] : nd.first[n]);
+          Group& g = c.g[n];
+          g.nterm = 1;
+          g.t[0] = Term{parent + (size_t)sg * r1 * ew, (const double*)inputs[n].cores[depth + 1], dconst(r1),
+                        dconst(r1), dconst(w)};
+          g.C = (double*)buf;
+          g.M = dconst(1);
+          g.N = dconst(w);
+          g.ldc = dconst(w);
+          ch.first[n] = buf;
+          nmax = std::max(nmax, w);
+        }
+        const hipError_t e = launch_contract(OP_NONE, PREC_FP64, c, 1, nmax, ctx->stream);
+        if (e != hipSuccess) {
+          release();
+          return set_err(ctx, ACI_E_HIP, std::string("patch restriction: ") + hipGetErrorString(e));
+        }
+        next.push_back(std::move(ch));
+      }
+    }
+    level = std::move(next);
+  }
+  if (rc < 0) {
+    const std::string keep = ctx->err;
+    release();
+    ctx->err = keep;
+    return rc;
+  }
+  // gather the kept patches into one buffer of the context's allocator
+  const int np = (int)kept.size();
+  int64_t total = 0;
+  for (const PatchNode& nd : kept) total += nd.elems;
+  void* all = nullptr;
+  if (!dev_alloc(ctx, &all, (size_t)std::max<int64_t>(total, 1) * ew * sizeof(double))) {
+    release();
+    return set_err(ctx, ACI_E_NOMEM, "patch result");
+  }
+  result->n_patches = np;
+  result->L = L;
+  result->levels = levels;
+  result->prefix_len = (int32_t*)std::calloc(np, sizeof(int32_t));
+  result->prefix = (uint8_t*)std::calloc((size_t)np * L, 1);
+  result->ranks = (int32_t*)std::calloc((size_t)np * (L + 1), sizeof(int32_t));
+  result->core_offset = (int64_t*)std::calloc((size_t)np * L, sizeof(int64_t));
+  result->converged = (int32_t*)std::calloc(np, sizeof(int32_t));
+  result->sweeps = (int32_t*)std::calloc(np, sizeof(int32_t));
+  result->max_eps = (double*)std::calloc(np, sizeof(double));
+  result->cores = all;
+  result->cores_elems = total;
+  if (!result->prefix_len || !result->prefix || !result->ranks || !result->core_offset || !result->converged ||
+      !result->sweeps || !result->max_eps) {
+    release();
+    aci_patched_free(ctx, result);
+    return set_err(ctx, ACI_E_NOMEM, "host result arrays");
+  }
+  int64_t off = 0;
+  for (int i = 0; i < np; ++i) {
+    const PatchNode& nd = kept[i];
+    const int k = (int)nd.prefix.size(), Lp = L - k;
+    result->prefix_len[i] = k;
+    for (int j = 0; j < k; ++j) result->prefix[(size_t)i * L + j] = nd.prefix[j];
+    for (int j = 0; j <= Lp; ++j) result->ranks[(size_t)i * (L + 1) + j] = nd.ranks[j];
+    for (int j = 0; j < Lp; ++j) result->core_offset[(size_t)i * L + j] = off + nd.offs[j];
+    result->converged[i] = nd.converged;
+    result->sweeps[i] = nd.sweeps;
+    result->max_eps[i] = nd.eps;
+    if (nd.elems > 0) {
+      const hipError_t e = hipMemcpyAsync((double*)all + (size_t)off * ew, nd.out, (size_t)nd.elems * ew * sizeof(double),
+                                          hipMemcpyDeviceToDevice, ctx->stream);
+      if (e != hipSuccess) {
+        release();
+        aci_patched_free(ctx, result);
+        return set_err(ctx, ACI_E_HIP, std::string("patch copy: ") + hipGetErrorString(e));
+      }
+    }
+    off += nd.elems;
+  }
+  release();
+  return worst;
+}
+
+}  // extern "C"

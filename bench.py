@@ -480,6 +480,50 @@ def time_step(aci, device, sweeps=3):
     return out
 
 
+def time_patched(aci, device, depth=3, sweeps=3):
+    """Patched ACI of the GP term |psi|^2 psi (the same field, rank cap 512,
+    tol 1e-8, at most ``sweeps`` sweeps per patch): patches of up to
+    ``depth`` fixed leading indices (the coarsest bits of x and y), each
+    level one batch.  Reports the time, the patches and the sampled error of
+    the assembled result against |psi|^2 psi at 4096 points, beside the
+    unpatched sweep (depth 0) at the same settings."""
+    import numpy as np
+    import torch
+    import workloads as W
+    psi = gp_psi(device)
+    cores = [torch.from_numpy(c).to(device) for c in psi]
+    L = len(psi)
+    pts = np.random.default_rng(95).integers(0, 2, (4096, L))
+    z = W.tt_eval(psi, pts)
+    f = (z.real * z.real + z.imag * z.imag) * z
+    out = {"workload": "patched |psi|^2 psi of the GP vortex-speckle field ((2^14)^2 grid, L=28, rank 512), "
+                       f"rank cap 512, tol 1e-8, <= {sweeps} sweeps per patch, complex128"}
+    for dp in (0, depth):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        patches, status = aci.patched([cores], "abs2_mul", 1e-8, 512, dp, maxiter=sweeps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        y = np.zeros(len(pts), dtype=complex)
+        for p in patches:
+            k = len(p.prefix)
+            sel = np.all(pts[:, :k] == np.array(p.prefix, dtype=pts.dtype), axis=1) if k else np.ones(len(pts), bool)
+            if sel.any():
+                y[sel] = W.tt_eval([c.cpu().numpy() for c in p.cores], pts[sel][:, k:])
+        err = float(np.abs(y - f).max() / np.abs(f).max())
+        out[f"depth_{dp}"] = {"seconds": el, "patches": len(patches),
+                              "converged": sum(p.converged for p in patches),
+                              "max_eps": max(p.max_eps for p in patches),
+                              "max_rank": max(max(p.ranks) for p in patches),
+                              "sampled_max_rel_error": err}
+        log(f"patched depth {dp}: {len(patches)} patches in {el:.3f} s, max eps "
+            f"{out[f'depth_{dp}']['max_eps']:.2e}, sampled rel error {err:.2e}")
+        del patches
+    del cores
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_tci(aci, device):
     """The paper's first example end to end on the GPU: the Gaussians
     g_+/- = exp(-(x +/- delta/2)^2 / (2 w^2)) on the quantics grid of
@@ -673,7 +717,8 @@ def main():
     ap.add_argument("--no-gp", action="store_true", help="skip the complex |psi|^2 psi workload")
     ap.add_argument("--no-tci", action="store_true", help="skip the TCI + ACI Gaussian example")
     ap.add_argument("--no-step", action="store_true", help="skip the explicit GP time step")
-    ap.add_argument("--only", choices=["gp", "batched", "contract", "tci", "step"],
+    ap.add_argument("--no-patched", action="store_true", help="skip the patched GP term")
+    ap.add_argument("--only", choices=["gp", "batched", "contract", "tci", "step", "patched"],
                     help="run just one section and print its JSON (for profiling that workload)")
     ap.add_argument("--summarize-contract", metavar="DIR", help="per-case table of a traced --only contract run")
     ap.add_argument("--summarize-stats", metavar="DIR",
@@ -717,6 +762,9 @@ def main():
         return
     if args.only == "step":
         print(json.dumps(time_step(aci, dev)), flush=True)
+        return
+    if args.only == "patched":
+        print(json.dumps(time_patched(aci, dev)), flush=True)
         return
     if args.only == "contract":
         print(json.dumps(time_contract(aci, dev)), flush=True)
@@ -812,6 +860,8 @@ def main():
         out["gp"] = time_c5(aci, dev)
     if not args.no_step:
         out["gp_step"] = time_step(aci, dev)
+    if not args.no_patched:
+        out["patched"] = time_patched(aci, dev)
     if not args.no_tci:
         out["tci"] = time_tci(aci, dev)
     if not args.no_cpu_baseline:

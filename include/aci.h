@@ -393,7 +393,7 @@ typedef int32_t (*aci_eval_fn)(int64_t count, int32_t L, void* user, void* strea
 
 /* 2-site tensor cross interpolation of a function given point by point —
  * the construction of the input TTs (Sec. 3), whose index-set optimisation
- * ACI follows (Sec. 2.5): the sweeps of Alg. 1 with the two-site tensor
+ * ACI follows (Sec. 2.6): the sweeps of Alg. 1 with the two-site tensor
  * evaluated directly, Pi[(a, s), (s', b)] = f(I_{l-1}[a], s, s', J_{l+2}[b])
  * (row a d_l + s, column s' |J_{l+2}| + b), each factorised by the LDU of
  * Alg. 2 (right-interpolative), the index sets taking its pivot rows and
@@ -422,7 +422,7 @@ int aci_tci(aci_ctx* ctx, int32_t L, const int32_t* d, int32_t dtype, aci_eval_f
  * In TT solvers of nonlinear differential equations the contractions are with
  * TT operators (MPOs) of small, constant bond dimension, such as finite-
  * difference derivatives, and the elementwise nonlinearity is what ACI
- * evaluates (Sec. 5).  These calls provide both parts of an explicit step on
+ * evaluates (Sec. 4).  These calls provide both parts of an explicit step on
  * a periodic quantics grid. */
 
 /* A TT operator with real cores in caller device memory: core l has shape
@@ -491,7 +491,7 @@ int aci_cubic_step(aci_ctx* ctx, const aci_tt* psi, int32_t dtype, int32_t ndim,
 
 /* ---- patched ACI --------------------------------------------------------
  * f(x^1..x^N) as tensor trains on patches of the index space (the patched
- * elementwise scheme named in Sec. 5).  A patch is a prefix of k fixed
+ * elementwise scheme named in Sec. 4).  A patch is a prefix of k fixed
  * leading indices (sigma_1..sigma_k); its tensor, f restricted to them, is a
  * TT over sites k+1..L.  The inputs are restricted exactly on the device:
  * the prefix vector X_1[:, sigma_1, :] ... X_k[:, sigma_k, :] is absorbed

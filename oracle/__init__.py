@@ -22,14 +22,14 @@ the algorithms of Appendix B of the paper in their order:
                          search with its acceptance test
 * ``tci``             -- 2-site TCI of a function given point by point (the
                          construction of the inputs, Sec. 3; the index-set
-                         optimisation of Sec. 2.5 with Pi evaluated directly)
+                         optimisation of Sec. 2.6 with Pi evaluated directly)
 * ``patched``         -- patched ACI: f on patches of fixed leading indices,
                          refined where one TT at the rank cap does not
-                         converge (the patched scheme named in Sec. 5)
+                         converge (the patched scheme named in Sec. 4)
 * ``timestep``        -- TT operators on quantics grids (periodic stencil
                          MPOs, exact MPO-TT contraction) and one explicit
                          step of a cubic nonlinear equation with ACI started
-                         from the current state (the use named in Sec. 5)
+                         from the current state (the use named in Sec. 4)
 
 Parity status of each function is stated in its docstring.
 """

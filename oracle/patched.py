@@ -1,6 +1,6 @@
 """Patched ACI: f(x^1, ..., x^N) as a collection of tensor trains on patches
 of the index space, refined where one TT of bounded rank does not reach the
-tolerance (the patched elementwise scheme named in Sec. 5).
+tolerance (the patched elementwise scheme named in Sec. 4).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 

@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-The paper asks for "a random TT with bond dimensions equal to the minimum of
-the input bond dimensions" (section 2.6) without naming a distribution.
+The paper starts from a random TT whose bond dimensions are the smallest
+of the inputs' (section 2.6) and names no distribution.
 Reading R10: entries are uniform on [-1, 1), produced by SplitMix64
 (S. Vigna's published generator: state += 0x9E3779B97F4A7C15, then the
 xor-shift-multiply finaliser with constants 0xBF58476D1CE4E5B9 and

@@ -1,7 +1,6 @@
 """2-site tensor cross interpolation (TCI) of a function given point by
 point: the construction the paper uses for its input TTs (Sec. 3), whose
-index-set optimisation ACI follows step for step (Sec. 2.5: "Optimizing
-index sets").
+index-set optimisation ACI follows step for step (Sec. 2.6).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 

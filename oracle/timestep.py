@@ -1,5 +1,5 @@
 """TT operators on quantics grids and one explicit time step of a cubic
-nonlinear equation, the use the outlook (Sec. 5) names for ACI.
+nonlinear equation, the use the outlook (Sec. 4) names for ACI.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 

@@ -1,6 +1,6 @@
 // Exact contraction of a TT operator (MPO) with a tensor train, the operator
 // half of an explicit step of a nonlinear equation (the use of ACI named in
-// Sec. 5).  Core by core,
+// Sec. 4).  Core by core,
 //   Z[(a, c), s, (b, e)] = sum_t W[a, s, t, b] X[c, t, e],
 // so the output is w^2 times the input: the kernel is bound by its HBM
 // writes.  One wave produces the wb output rows (a, c, s, 0..wb-1), which

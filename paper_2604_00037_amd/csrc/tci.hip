@@ -1,5 +1,5 @@
 // 2-site TCI of a function given point by point (the construction of the
-// inputs in Sec. 3; the index-set optimisation of Sec. 2.5 with the two-site
+// inputs in Sec. 3; the index-set optimisation of Sec. 2.6 with the two-site
 // tensor evaluated directly): the multi-indices of a bond's two-site tensor,
 // and the update of the nested index sets from the pivots of its LDU.
 //

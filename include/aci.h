@@ -525,7 +525,8 @@ typedef struct {
  * ACI).  result is filled on return; release it with aci_patched_free on the
  * same context.  Returns ACI_OK if every kept patch converged, else
  * ACI_W_NOT_CONVERGED (patches at max_depth that did not converge), or an
- * error. */
+ * error; ACI_E_INVALID if options.init is set (every patch starts from the
+ * seeded default Y_init). */
 int aci_patched(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
                 double tol, int32_t maxrank, int32_t max_depth, const aci_options* opt,
                 aci_patched_result* result);

@@ -3057,6 +3057,7 @@ int aci_patched(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dt
   const int L = inputs[0].L;
   if (L < 2 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
   if (max_depth < 0 || max_depth > L - 2) return set_err(ctx, ACI_E_INVALID, "max_depth must lie in [0, L - 2]");
+  if (opt && opt->init) return set_err(ctx, ACI_E_INVALID, "patches start from the seeded default Y_init (options.init must be NULL)");
   for (int n = 0; n < n_inputs; ++n) {
     const int rc = validate_tt(ctx, inputs[n], L);
     if (rc) return rc;

@@ -94,3 +94,19 @@ def test_patched_rejects_bad_depth():
     x1, x2 = W.random_pair(L=6, chi=3, seeds=(3241, 3242))
     with pytest.raises(aci._lib.HipError):
         aci.patched([to_dev(x1), to_dev(x2)], "product", 1e-12, 8, 5)
+
+
+def test_patched_rejects_an_explicit_init():
+    import ctypes as C
+    from paper_2604_00037_amd import aci as mod
+    x1, x2 = W.random_pair(L=6, chi=3, seeds=(3251, 3252))
+    d1, d2 = to_dev(x1), to_dev(x2)
+    ctx = mod.default_context()
+    keep = []
+    tts = mod._inputs([d1, d2], keep)
+    opts = mod._options(keep, 4, 0, d1, "exclusive", "fp64", False, False, False)
+    res = mod._lib.AciPatchedResult()
+    status = ctx.lib.aci_patched(ctx.h, tts, 2, 0, 0, 1e-12, 8, 1, C.byref(opts), C.byref(res))
+    assert status == -1
+    assert b"init" in ctx.lib.aci_last_error(ctx.h)
+    ctx.lib.aci_patched_free(ctx.h, C.byref(res))

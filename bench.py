@@ -69,7 +69,7 @@ def cpu_baseline(u, v):
     total = time.perf_counter() - t
     sweep_s = (res.times[3] - res.times[1]) / 2
     log(f"oracle: init+3 sweeps {total:.1f} s, mean of sweeps 2-3 {sweep_s:.2f} s")
-    return {
+    out = {
         "value": 1.0 / sweep_s,
         "unit": "sweeps/s",
         "cores": threads,
@@ -78,6 +78,22 @@ def cpu_baseline(u, v):
                   f"rate from sweeps 2-3, at saturated ranks ({sweep_s:.2f} s each); "
                   "NumPy float64, BLAS threads as reported by threadpoolctl",
     }
+    # the paper times its implementation on one thread: the same run with the
+    # BLAS pool limited to one thread, rate from sweep 2
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t = time.perf_counter()
+            res1 = oracle.aci([u, v], "product", TOL, MAXRANK, maxiter=2, seed=INIT_SEED)
+            total1 = time.perf_counter() - t
+        sweep1 = res1.times[2] - res1.times[1]
+        out["single_thread"] = {"value": 1.0 / sweep1, "unit": "sweeps/s", "cores": 1,
+                                "sample": f"initialisation + 2 sweeps ({total1:.1f} s); rate from sweep 2 "
+                                          f"({sweep1:.2f} s)"}
+        log(f"oracle, one thread: init+2 sweeps {total1:.1f} s, sweep 2 {sweep1:.2f} s")
+    except ImportError:
+        pass
+    return out
 
 
 def cpu_time_to_solution(tts):
@@ -954,7 +970,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(u, v)
         if "time_to_solution" in out:
             out["cpu_time_to_solution"] = cpu_time_to_solution(dict(out["time_to_solution"], **_TTS))
-        out["speedup_vs_cpu_oracle"] = out["value"] / out["cpu_baseline"]["value"]
+        # against the faster of the oracle's two thread settings
+        best_cpu = max(out["cpu_baseline"]["value"], out["cpu_baseline"].get("single_thread", {}).get("value", 0.0))
+        out["speedup_vs_cpu_oracle"] = out["value"] / best_cpu
     print(json.dumps(out), flush=True)
 
 

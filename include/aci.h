@@ -217,8 +217,12 @@ typedef struct {
 /* One kernel launch of a profiled aci_session_sweep call (options.profile).
  * kind: 0 LDU with full pivoting, 1 contraction, 2 frame gather.
  * variant: kind 0: 100000*complex + 10000*solo + 100*RS + CS, the instance
- *          prrlu_kernel<RS, CS, solo, complex> (RS row slots per wave, CS
- *          column slots per lane, solo = one workgroup), 200000 +
+ *          prrlu_kernel<RS, CS, solo, complex, 4> (RS row slots per wave, CS
+ *          column slots per lane, solo = one workgroup, four waves), or
+ *          1000000 + 100*RS + CS for the eight-wave instance
+ *          prrlu_kernel<RS, CS, false, false, 8> of real multi-group
+ *          factorisations with 16 or more rows per group and RS CS <= 24,
+ *          200000 +
  *          100000*complex + 100*RS + CS for the joint batch LDU
  *          prrlu_batch_kernel<RS, CS, complex>, or 20001..20008 for the
  *          learned-proposal kernels; kind 1: 10000*tile + 1000*complex +

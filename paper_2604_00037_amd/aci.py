@@ -307,6 +307,9 @@ def kernel_name(kind, variant):
     """Kernel instance behind a launch-log entry, spelled as in the device
     profiler's kernel names."""
     b = {0: "false", 1: "true"}
+    if kind == 0 and variant >= 1000000:
+        rs, cs = divmod(variant - 1000000, 100)
+        return f"prrlu_kernel<{rs}, {cs}, false, false, 8>"
     if kind == 0 and variant >= 200000:
         cx, rest = divmod(variant - 200000, 100000)
         rs, cs = divmod(rest, 100)
@@ -319,7 +322,7 @@ def kernel_name(kind, variant):
         cx, rest = divmod(variant, 100000)
         solo, rest = divmod(rest, 10000)
         rs, cs = divmod(rest, 100)
-        return f"prrlu_kernel<{rs}, {cs}, {b[solo]}, {b[cx]}>"
+        return f"prrlu_kernel<{rs}, {cs}, {b[solo]}, {b[cx]}, 4>"
     if kind == 1:
         tile, rest = divmod(variant, 10000)
         cx, rest = divmod(rest, 1000)

@@ -117,16 +117,16 @@ __device__ __forceinline__ void xw_put(uint64_t* p, uint32_t data, uint32_t flag
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Poll `cnt` flagged words src[0 .. cnt) (thread t takes words t, t + NT, ...)
+// Poll `cnt` flagged words src[0 .. cnt) (thread t of NTH takes words t, t + NTH, ...)
 // until their flags match, then store the payloads to dst.  Returns false
 // after a timeout; the abort word is then set for every waiting wave.
-template <int MAXW>
+template <int MAXW, int NTH>
 __device__ __forceinline__ bool poll_words(const uint64_t* src, int cnt, uint32_t flag, int* abort_word,
                                            uint32_t limit, uint32_t* dst) {
   uint64_t raw[MAXW];
 #pragma unroll
   for (int i = 0; i < MAXW; ++i) {
-    const int t = threadIdx.x + NT * i;
+    const int t = threadIdx.x + NTH * i;
     raw[i] = t < cnt ? __hip_atomic_load(src + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                      : ((uint64_t)flag << 32);
   }
@@ -136,7 +136,7 @@ __device__ __forceinline__ bool poll_words(const uint64_t* src, int cnt, uint32_
     bool all = true;
 #pragma unroll
     for (int i = 0; i < MAXW; ++i) {
-      const int t = threadIdx.x + NT * i;
+      const int t = threadIdx.x + NTH * i;
       if (t < cnt && (uint32_t)(raw[i] >> 32) != flag) {
         all = false;
         raw[i] = __hip_atomic_load(src + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -155,7 +155,7 @@ __device__ __forceinline__ bool poll_words(const uint64_t* src, int cnt, uint32_
   }
 #pragma unroll
   for (int i = 0; i < MAXW; ++i) {
-    const int t = threadIdx.x + NT * i;
+    const int t = threadIdx.x + NTH * i;
     if (t < cnt) dst[t] = (uint32_t)raw[i];
   }
   return ok;
@@ -186,8 +186,9 @@ __device__ __forceinline__ double cabs2(double re, double im) {
 //
 // The factorisation itself, run by group w (0 <= w < a.P) of the
 // cooperating groups.
-template <int RS, int CS, bool SOLO, bool CX>
+template <int RS, int CS, bool SOLO, bool CX, int WAVES>
 __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
+  constexpr int NT = 64 * WAVES;   // threads of the workgroup
   // flags of this launch: step k uses fbase + k
   const uint32_t fbase = a.epoch ? __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                  : a.flag_base;
@@ -448,7 +449,7 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
       }
       // round trip 2: the winner's row (already published with its candidate)
       const int wg = (widx >> 16) % P;
-      ok = poll_words<(128 * EW * CS + NT - 1) / NT>(slot_base + (size_t)wg * per + 3, 2 * EW * n, flag,
+      ok = poll_words<(128 * EW * CS + NT - 1) / NT, NT>(slot_base + (size_t)wg * per + 3, 2 * EW * n, flag,
                                                      a.abort_word, a.spin_limit, xrow);
       if (!ok) failed = true;
       __syncthreads();
@@ -686,13 +687,13 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   }
 }
 
-template <int RS, int CS, bool SOLO, bool CX>
-__global__ __launch_bounds__(NT) void prrlu_kernel(PrrluArgs a) {
+template <int RS, int CS, bool SOLO, bool CX, int W>
+__global__ __launch_bounds__(64 * W) void prrlu_kernel(PrrluArgs a) {
   if ((int)(blockIdx.x % a.stride) != (a.stride == 8 ? a.xcd : 0)) return;
   // a proposal already supplied this factorisation (every group reads the
   // same word, so the whole launch leaves together; the epoch is untouched)
   if (a.skip && *a.skip) return;
-  prrlu_body<RS, CS, SOLO, CX>(a, blockIdx.x / a.stride);
+  prrlu_body<RS, CS, SOLO, CX, W>(a, blockIdx.x / a.stride);
 }
 
 // Several products' factorisations in one launch.  Workgroup b runs on XCD
@@ -707,13 +708,13 @@ __global__ __launch_bounds__(NT) void prrlu_batch_kernel(PrrluBatchArgs bt) {
   if (prod < 0) return;
   const PrrluArgs& a = bt.a[prod];
   if (a.skip && *a.skip) return;
-  prrlu_body<RS, CS, false, CX>(a, bt.group[x][slot]);
+  prrlu_body<RS, CS, false, CX, WAVES>(a, bt.group[x][slot]);
 }
 
 // Resident workgroups per CU of one kernel instance.
-int resident_per_cu(const void* fn, size_t lds) {
+int resident_per_cu(const void* fn, int threads, size_t lds) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, lds) != hipSuccess) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds) != hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }
@@ -759,25 +760,34 @@ struct Shape {
 };
 constexpr Shape kShapes[] = {{1, 16}, {2, 16}, {4, 16}, {6, 8}, {8, 8}, {12, 4}, {16, 4}};
 
-hipError_t do_launch(const void* fn, dim3 grid, size_t lds, PrrluArgs& args, hipStream_t s) {
+hipError_t do_launch(const void* fn, dim3 grid, int threads, size_t lds, PrrluArgs& args, hipStream_t s) {
   hipError_t e;
   if (args.cooperative) {
     void* kp[] = {&args};
-    e = hipLaunchCooperativeKernel(fn, grid, dim3(NT), kp, (unsigned)lds, s);
+    e = hipLaunchCooperativeKernel(fn, grid, dim3(threads), kp, (unsigned)lds, s);
   } else {
     // plain launch (stream capture): at most one XCD's worth of groups, one
     // per CU, so all of them become resident once the CUs are free
     void* kp[] = {&args};
-    e = hipLaunchKernel(fn, grid, dim3(NT), kp, lds, s);
+    e = hipLaunchKernel(fn, grid, dim3(threads), kp, lds, s);
   }
   if (e != hipSuccess) (void)hipGetLastError();
   return e;
 }
 
+// Real groups of at least 16 rows run as eight waves of half the row slots
+// (same rows per group, same exchange): two waves per SIMD hide each other's
+// latencies in the in-CU part of a step.  Complex groups, smaller groups and
+// rows too wide for half the registers keep four waves.
+template <int RS, int CS, bool CX>
+constexpr bool eight_waves() { return !CX && RS >= 4 && (RS / 2) * CS <= 24; }
+
 template <int RS, int CS, bool CX>
 hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
   PrrluArgs args = a;
   constexpr int EW = CX ? 2 : 1;
+  constexpr bool W8 = eight_waves<RS, CS, CX>();
+  constexpr int RSG = W8 ? RS / 2 : RS, WG = W8 ? 8 : WAVES;
   // xcd < 0 ("spread"): exactly P workgroups, dealt round robin over the
   // XCDs, for launches that overlap with other spinning launches: a launch
   // of 8P workgroups would also need CUs on the other XCDs for its idle
@@ -787,22 +797,22 @@ hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
     // one group: 8 workgroups of which the one on the requested XCD runs
     args.stride = (a.cooperative || spread) ? 1 : 8;
     const size_t lds = (size_t)(kCandWords + 128 * EW * CS) * 4;
-    return do_launch((const void*)prrlu_kernel<RS, CS, true, CX>, dim3(args.stride), lds, args, s);
+    return do_launch((const void*)prrlu_kernel<RS, CS, true, CX, WAVES>, dim3(args.stride), NT, lds, args, s);
   }
-  const void* fn = (const void*)prrlu_kernel<RS, CS, false, CX>;
+  const void* fn = (const void*)prrlu_kernel<RSG, CS, false, CX, WG>;
   const size_t lds = group_lds((size_t)(kCandWords + 128 * EW * CS) * 4);
   if (spread) {
     args.stride = 1;
-    return do_launch(fn, dim3(args.P), lds, args, s);
+    return do_launch(fn, dim3(args.P), 64 * WG, lds, args, s);
   }
-  static int per_cu = resident_per_cu(fn, lds);
+  static int per_cu = resident_per_cu(fn, 64 * WG, lds);
   // Workgroups are dealt to the 8 XCDs round robin, so launching 8x the
   // groups and keeping every 8th (offset by the XCD index) puts the
   // cooperating groups on one XCD, which lets the exchange stay in that
   // XCD's L2.  Only when they all fit.
   args.stride = (a.P <= per_cu * cus_per_xcd()) ? 8 : 1;
   if (!a.cooperative && args.stride != 8) return hipErrorInvalidValue;
-  return do_launch(fn, dim3(args.P * args.stride), lds, args, s);
+  return do_launch(fn, dim3(args.P * args.stride), 64 * WG, lds, args, s);
 }
 
 // Register shapes of complex matrices (two doubles per entry).
@@ -925,6 +935,8 @@ int prrlu_variant(int mmax, int nmax, int max_groups, int cplx) {
   if (!sh) return -1;
   const int rs = pick_rs(*sh, mmax, max_groups);
   const int P = (mmax + WAVES * rs - 1) / (WAVES * rs);
+  if (P > 1 && !cplx && rs >= 4 && (rs / 2) * sh->cs <= 24)   // eight waves of rs / 2 slots (eight_waves)
+    return 1000000 + 100 * (rs / 2) + sh->cs;
   return (cplx ? 100000 : 0) + (P == 1 ? 10000 : 0) + 100 * rs + sh->cs;
 }
 

@@ -307,13 +307,16 @@ def kernel_name(kind, variant):
     """Kernel instance behind a launch-log entry, spelled as in the device
     profiler's kernel names."""
     b = {0: "false", 1: "true"}
+    if kind == 0 and variant >= 2000000:
+        rs, cs = divmod(variant - 2000000, 100)
+        return f"prrlu_batch_kernel<{rs}, {cs}, false, 8>"
     if kind == 0 and variant >= 1000000:
         rs, cs = divmod(variant - 1000000, 100)
         return f"prrlu_kernel<{rs}, {cs}, false, false, 8>"
     if kind == 0 and variant >= 200000:
         cx, rest = divmod(variant - 200000, 100000)
         rs, cs = divmod(rest, 100)
-        return f"prrlu_batch_kernel<{rs}, {cs}, {b[cx]}>"
+        return f"prrlu_batch_kernel<{rs}, {cs}, {b[cx]}, 4>"
     if kind == 0 and 20000 <= variant < 30000:
         return {20001: "features_kernel", 20002: "mlp_forward_kernel", 20003: "rook_kernel",
                 20004: "contract_kernel<-1, false>", 20005: "check_kernel", 20006: "commit_kernel",

@@ -701,14 +701,14 @@ __global__ __launch_bounds__(64 * W) void prrlu_kernel(PrrluArgs a) {
 // b / 8 of that XCD belongs to the product and group the placement names, or
 // is idle.  Every product's groups share one XCD, so its exchange stays in
 // that XCD's L2.
-template <int RS, int CS, bool CX>
-__global__ __launch_bounds__(NT) void prrlu_batch_kernel(PrrluBatchArgs bt) {
+template <int RS, int CS, bool CX, int W>
+__global__ __launch_bounds__(64 * W) void prrlu_batch_kernel(PrrluBatchArgs bt) {
   const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int prod = bt.prod[x][slot];
   if (prod < 0) return;
   const PrrluArgs& a = bt.a[prod];
   if (a.skip && *a.skip) return;
-  prrlu_body<RS, CS, false, CX, WAVES>(a, bt.group[x][slot]);
+  prrlu_body<RS, CS, false, CX, W>(a, bt.group[x][slot]);
 }
 
 // Resident workgroups per CU of one kernel instance.
@@ -780,7 +780,7 @@ hipError_t do_launch(const void* fn, dim3 grid, int threads, size_t lds, PrrluAr
 // latencies in the in-CU part of a step.  Complex groups, smaller groups and
 // rows too wide for half the registers keep four waves.
 template <int RS, int CS, bool CX>
-constexpr bool eight_waves() { return !CX && RS >= 4 && (RS / 2) * CS <= 24; }
+constexpr bool eight_waves() { return !CX && RS >= 4 && CS < 16 && (RS / 2) * CS <= 32; }
 
 template <int RS, int CS, bool CX>
 hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
@@ -935,7 +935,7 @@ int prrlu_variant(int mmax, int nmax, int max_groups, int cplx) {
   if (!sh) return -1;
   const int rs = pick_rs(*sh, mmax, max_groups);
   const int P = (mmax + WAVES * rs - 1) / (WAVES * rs);
-  if (P > 1 && !cplx && rs >= 4 && (rs / 2) * sh->cs <= 24)   // eight waves of rs / 2 slots (eight_waves)
+  if (P > 1 && !cplx && rs >= 4 && sh->cs < 16 && (rs / 2) * sh->cs <= 32)   // eight waves (eight_waves)
     return 1000000 + 100 * (rs / 2) + sh->cs;
   return (cplx ? 100000 : 0) + (P == 1 ? 10000 : 0) + 100 * rs + sh->cs;
 }
@@ -988,11 +988,13 @@ static bool batch_place(const int* mmax, int count, const Shape& sh, int& rs, in
 template <int RS, int CS, bool CX>
 hipError_t launch_batch_shape(const PrrluBatchArgs& bt, int slots, hipStream_t s) {
   constexpr int EW = CX ? 2 : 1;
-  const void* fn = (const void*)prrlu_batch_kernel<RS, CS, CX>;
+  constexpr bool W8 = eight_waves<RS, CS, CX>();
+  constexpr int RSG = W8 ? RS / 2 : RS, WG = W8 ? 8 : WAVES;
+  const void* fn = (const void*)prrlu_batch_kernel<RSG, CS, CX, WG>;
   const size_t lds = group_lds((size_t)(kCandWords + 128 * EW * CS) * 4);
   PrrluBatchArgs args = bt;
   void* kp[] = {&args};
-  const hipError_t e = hipLaunchKernel(fn, dim3(8 * slots), dim3(NT), kp, lds, s);
+  const hipError_t e = hipLaunchKernel(fn, dim3(8 * slots), dim3(64 * WG), kp, lds, s);
   if (e != hipSuccess) (void)hipGetLastError();
   return e;
 }
@@ -1078,6 +1080,8 @@ int prrlu_batch_variant(const int* mmax, int count, int nmax, int cplx) {
   if (!sh) return -1;
   int rs = 0, P[kBatchMaxProducts];
   if (!batch_place(mmax, count, *sh, rs, P, nullptr)) return -1;
+  if (!cplx && rs >= 4 && sh->cs < 16 && (rs / 2) * sh->cs <= 32)   // eight waves (eight_waves)
+    return 2000000 + 100 * (rs / 2) + sh->cs;
   return 200000 + (cplx ? 100000 : 0) + 100 * rs + sh->cs;
 }
 

@@ -221,10 +221,11 @@ typedef struct {
  *          column slots per lane, solo = one workgroup, four waves), or
  *          1000000 + 100*RS + CS for the eight-wave instance
  *          prrlu_kernel<RS, CS, false, false, 8> of real multi-group
- *          factorisations with 16 or more rows per group and RS CS <= 24,
- *          200000 +
- *          100000*complex + 100*RS + CS for the joint batch LDU
- *          prrlu_batch_kernel<RS, CS, complex>, or 20001..20008 for the
+ *          factorisations with 16 or more rows per group, CS < 16 and
+ *          RS CS <= 32, 200000 + 100000*complex + 100*RS + CS for the joint
+ *          batch LDU prrlu_batch_kernel<RS, CS, complex, 4>, 2000000 +
+ *          100*RS + CS for its eight-wave instance
+ *          prrlu_batch_kernel<RS, CS, false, 8>, or 20001..20008 for the
  *          learned-proposal kernels; kind 1: 10000*tile + 1000*complex +
  *          100*precision + op + 1 with op the fused epilogue (-1 none, else
  *          aci_op) and tile as in aci_tune_contract: instance

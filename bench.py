@@ -176,12 +176,13 @@ def summarize_rocprof(directory, bench_json):
     timed = [d for _, d in durs[-roof["launches"]:]]
     mean_us = sum(timed) / len(timed) / 1e3
     out += ["", f"Dominant instance `{roof['kernel']}`: {len(durs)} dispatches in the run; "
-                f"the last {len(timed)} (the timed sweeps) average **{mean_us:.1f} us** in the trace, "
+                f"the last {len(timed)} (the timed sweeps of the profiled pass) average **{mean_us:.1f} us** in the trace, "
                 f"against **{roof['avg_launch_us']:.1f} us** measured by the run itself with HIP events "
                 f"({100 * (roof['avg_launch_us'] / mean_us - 1):+.1f} %).",
             f"Algorithmic flops per launch {roof['flops_per_launch']:.4g}; "
             f"{roof['achieved']:.4g} {roof['unit']} against a peak of {roof['peak']} ({roof['bound']}).",
-            f"Run: {b['value']:.2f} {b['unit']}, {b['ms_per_step']:.2f} ms per sweep."]
+            f"Run: {b['value']:.2f} {b['unit']} ({b['ms_per_step']:.2f} ms per sweep) replayed from a hipGraph; "
+            f"{b.get('profiled_sweeps_per_s', float('nan')):.2f} {b['unit']} in the profiled pass."]
     return "\n".join(out)
 
 

@@ -3131,13 +3131,21 @@ int aci_patched(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dt
       }
     }
     if (rc < 0) break;
-    // keep the converged patches (all of them at the last level), split the rest
+    // keep the converged patches (all of them at the last level), split the
+    // rest; a split patch's own output is not needed any more (the batch
+    // call has synchronised its streams)
     std::vector<PatchNode> next;
     for (PatchNode& nd : level) {
       if (nd.converged || depth == max_depth) {
         if (!nd.converged) worst = ACI_W_NOT_CONVERGED;
         kept.push_back(nd);
         continue;
+      }
+      auto it = std::find(bufs.begin(), bufs.end(), nd.out);
+      if (it != bufs.end()) {
+        bufs.erase(it);
+        dev_free(ctx, nd.out);
+        nd.out = nullptr;
       }
       // child sigma: first core v @ X_{depth+1}, v = row sigma of this
       // patch's first core (1 x r_{depth+1})

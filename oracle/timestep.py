@@ -104,19 +104,20 @@ def mpo_dense(W):
 
 def linear_cubic(alpha, beta):
     """f(x^1, ..., x^N) = sum_n alpha_n x^n + beta |x^1|^2 x^1 with
-    |z|^2 = re*re + im*im, summed as (((alpha_1 x^1 + beta |x^1|^2 x^1) +
-    alpha_2 x^2) + ...), the order in which the library defines the op."""
+    |z|^2 = re*re + im*im: the right-hand side of an explicit step of a cubic
+    equation (the nonlinear term evaluated by ACI, Sec. 4), written as the
+    formula reads, the linear terms first and the cubic term last."""
     alpha = list(alpha)
 
     def f(*P):
         if len(P) != len(alpha):
             raise ValueError("one coefficient per input")
-        z = P[0]
-        a = (z.real * z.real + z.imag * z.imag) if np.iscomplexobj(z) else z * z
-        out = alpha[0] * z + beta * (a * z)
+        out = alpha[0] * P[0]
         for c, x in zip(alpha[1:], P[1:]):
             out = out + c * x
-        return out
+        z = P[0]
+        a = (z.real * z.real + z.imag * z.imag) if np.iscomplexobj(z) else z * z
+        return out + beta * (a * z)
 
     return f
 

@@ -120,3 +120,34 @@ def test_adam_learns_a_separable_rule():
         P.adam_step(net, g, st, lr=1e-2)
     _, l1 = P.mlp_grads(net, X, y)
     assert l1 < 0.5 * l0
+
+
+class _Toy:
+    """Two scalar parameters, the shape adam_step expects of a network."""
+
+    def __init__(self, a, b):
+        self.p = [np.array([a], np.float32), np.array([b], np.float32)]
+
+    def params(self):
+        return self.p
+
+
+def test_adam_two_steps_by_hand():
+    """Adam (Kingma and Ba, Algorithm 1) on two scalars, lr 0.1, b1 0.9,
+    b2 0.999 and a large eps = 0.1 so that its place (added to sqrt(v_hat),
+    not inside the root) shows.  Step 1: the bias corrections make
+    m_hat = g and v_hat = g^2, so theta_1 = theta_0 - lr g / (|g| + eps):
+    1 - 0.1 * 0.5 / 0.6 = 11/12 and -2 + 0.1 * 0.25 / 0.35 = -27/14.
+    Step 2, by hand: m = (0.9 * 0.1 g1 + 0.1 g2), v = (0.999 * 0.001 g1^2 +
+    0.001 g2^2), m_hat = m / 0.19, v_hat = v / 0.001999:
+      a: m_hat = -0.055 / 0.19 = -0.2894737, sqrt(v_hat) = 0.7906881,
+         theta_2 = 11/12 + 0.1 * 0.2894737 / 0.8906881 = 0.9491667;
+      b: m_hat = -0.01 / 0.19 = -0.0526316, sqrt(v_hat) = 0.1976127,
+         theta_2 = -27/14 + 0.1 * 0.0526316 / 0.2976127 = -1.9108868."""
+    net = _Toy(1.0, -2.0)
+    st = {}
+    P.adam_step(net, [np.array([0.5], np.float32), np.array([-0.25], np.float32)], st, lr=0.1, eps=0.1)
+    np.testing.assert_allclose([net.p[0][0], net.p[1][0]], [11 / 12, -27 / 14], rtol=2e-7)
+    P.adam_step(net, [np.array([-1.0], np.float32), np.array([0.125], np.float32)], st, lr=0.1, eps=0.1)
+    np.testing.assert_allclose([net.p[0][0], net.p[1][0]], [0.9491667, -1.9108868], rtol=3e-7)
+    assert st["t"] == 2

@@ -10,7 +10,10 @@ rule takes one pivot of rounding noise once an update's exact rank is
 exhausted), and then ranks,
 error estimates (to 1e-9, above a rounding floor of 1e-12 |f|) and outputs
 (1e-10 relative) must agree whenever no such tie was met (outputs compared entry by entry up to 2^20 entries, else at
-4096 random points).""" 
+4096 random points).  Past a tie the two runs are different but equally
+valid cross interpolations: the library's output must still match f itself
+(brute force, or 4096 sampled points) within 10 tol when the oracle's run
+converged, and at least 30 of the 40 cases must be compared in full."""
 
 import numpy as np
 import pytest
@@ -26,6 +29,13 @@ torch = pytest.importorskip("torch")
 aci = pytest.importorskip("paper_2604_00037_amd")
 
 CASES = 40
+_DONE = set()       # cases that ran
+_PARTIAL = set()    # cases whose pivots were compared only up to a near tie
+
+
+def ref_f(op, P):
+    """f of the dense (or sampled) inputs, written out by the oracle."""
+    return op(*P) if callable(op) else oracle.apply_op(op, list(P))
 
 
 def config(seed):
@@ -101,10 +111,28 @@ def test_random_configuration(case):
     n = compare(info.records, ref.trace, rule == "literal", tol, f"case {case}")
     if n < len(ref.trace):
         # either choice is correct and later steps depend on it; the pivots
-        # agreed on every record before it (checked in compare)
+        # agreed on every record before it (checked in compare).  The output
+        # is still checked against f itself.
         print(f"case {case}: pivots compared up to record {n} of {len(ref.trace)} (near tie or "
               "literal-rule noise pivot)")
+        _PARTIAL.add(case)
+        if ref.converged:
+            assert info.converged, f"case {case}: the oracle converged, the library did not"
+            out = [c.cpu().numpy() for c in cores]
+            dims = [c.shape[1] for c in inputs[0]]
+            if np.prod(dims) <= 1 << 20:
+                exact = ref_f(ref_op, [W.tt_full(x) for x in inputs])
+                y = W.tt_full(out)
+            else:
+                pts = np.stack([np.random.default_rng(case).integers(0, d, 4096) for d in dims], axis=1)
+                exact = ref_f(ref_op, [W.tt_eval(x, pts) for x in inputs])
+                y = W.tt_eval(out, pts)
+            err = float(np.abs(y - exact).max())
+            print(f"case {case}: max |y - f| = {err:.3e} (tol {tol:.3e})")
+            assert err <= 10 * tol, (case, err, tol)
+        _DONE.add(case)
         return
+    _DONE.add(case)
     assert info.ranks[1:-1] == ref.ranks
     assert info.sweeps == ref.sweeps and info.converged == ref.converged
     # error estimates left after the exact rank is reached are rounding
@@ -117,3 +145,13 @@ def test_random_configuration(case):
     else:
         pts = np.stack([np.random.default_rng(case).integers(0, d, 4096) for d in dims], axis=1)
         assert rel_max_err(W.tt_eval(out, pts), W.tt_eval(ref.cores, pts)) <= 1e-10
+
+
+def test_most_random_configurations_are_compared_in_full():
+    """Runs after the cases (pytest keeps file order): at least 30 of the 40
+    configurations compared record by record to the end."""
+    if len(_DONE) < CASES:
+        pytest.skip(f"only {len(_DONE)} of {CASES} cases ran in this session")
+    full = CASES - len(_PARTIAL)
+    print(f"random configurations compared in full: {full} of {CASES} (partial: {sorted(_PARTIAL)})")
+    assert full >= 30, sorted(_PARTIAL)

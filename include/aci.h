@@ -289,6 +289,24 @@ int aci_ctx_create_with_allocator(aci_ctx** ctx, void* stream, void* (*alloc)(si
 void aci_ctx_destroy(aci_ctx* ctx);
 const char* aci_last_error(const aci_ctx* ctx);
 
+/* Waits of the LDU pivot exchange (Alg. 2's global argmax and pivot-row
+ * broadcast between cooperating workgroups), for failure-handling tests and
+ * long-running contexts.  Applies to LDU launches enqueued after the call
+ * (graphs captured earlier keep their settings).
+ *   spin_limit      polls before one wait gives up and the launch ends with
+ *                   ACI_E_TIMEOUT; 0 restores the default 2^22.
+ *   stall_step      -1: off.  s >= 0: from pivot step s on, readers wait for
+ *                   a step flag that no workgroup publishes, so every LDU
+ *                   launch that needs more than one workgroup gives up after
+ *                   at most spin_limit polls per wait and its call returns
+ *                   ACI_E_TIMEOUT.  All kernels still exit; the context stays
+ *                   usable once the hook is switched off.
+ *   epoch_launches  LDU launches after which a session clears its exchange
+ *                   words and restarts its step flags (0: the default,
+ *                   2^21 - 1, just before the 32-bit flags would wrap).
+ * ACI_E_INVALID for stall_step < -1 or epoch_launches outside [0, 2^21 - 1]. */
+int aci_ctx_set_exchange_hooks(aci_ctx* ctx, uint32_t spin_limit, int32_t stall_step, int64_t epoch_launches);
+
 /* Alg. 1: approximate f(x^1..x^N) as a TT with error estimate <= tol and bond
  * dimensions <= maxrank.
  *   inputs     host array of n_inputs TTs (device cores, dtype as given)

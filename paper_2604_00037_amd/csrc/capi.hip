@@ -31,6 +31,13 @@ struct aci_ctx {
   int device = 0;
   std::string err;
   uint32_t flag_next = 1;
+  bool step_flags_wrapped = false;   // flag_next wrapped since step_xbuf was cleared
+  // exchange waits of the LDU launches enqueued from now on (see
+  // aci_ctx_set_exchange_hooks): spin limit, and the test stall
+  uint32_t spin_limit = 1u << 22;
+  uint32_t poll_xor = 0;
+  int stall_from = 0;
+  uint64_t epoch_launches = 0;   // session epoch reset period (0: the default)
   // small persistent workspace of the single-step entry points
   int* step_err = nullptr;     // [0] error flags, [1] abort word
   uint64_t* step_xbuf = nullptr;
@@ -76,7 +83,14 @@ static void dev_free(aci_ctx* ctx, void* p) {
 
 namespace {
 
-constexpr uint32_t kSpinLimit = 1u << 22;   // polls before an exchange gives up
+constexpr uint32_t kSpinLimit = 1u << 22;   // polls before an exchange gives up (default)
+
+// The exchange-wait settings of the context on an LDU launch.
+void exchange_waits(const aci_ctx* c, PrrluArgs& a) {
+  a.spin_limit = c->spin_limit;
+  a.poll_xor = c->poll_xor;
+  a.stall_from = c->stall_from;
+}
 
 int set_err(aci_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -94,8 +108,25 @@ uint32_t next_flag(aci_ctx* c) {
   // each prrLU launch uses flags base .. base + min(m, n) <= base + 1024
   uint32_t f = c->flag_next;
   c->flag_next += 2048u;
-  if (c->flag_next < 2048u) c->flag_next = 1;  // wrapped
+  if (c->flag_next < 2048u) {
+    // wrapped: words of the step exchange buffer may carry flags that the
+    // next launches reuse, so the buffer is cleared before the next launch
+    c->flag_next = 1;
+    c->step_flags_wrapped = true;
+  }
   return f;
+}
+
+// Flag base of an LDU launch on the step exchange buffer; after a wrap of
+// the flags the buffer is cleared first, on the context's stream.
+hipError_t step_flag(aci_ctx* c, uint32_t* f) {
+  *f = next_flag(c);
+  if (c->step_flags_wrapped) {
+    const hipError_t e = launch_fill_int((int*)c->step_xbuf, (int)(2 * c->step_xwords), 0, c->stream);
+    if (e != hipSuccess) return e;
+    c->step_flags_wrapped = false;
+  }
+  return hipSuccess;
 }
 
 // ---- bump allocator: pass 0 sizes the workspace, pass 1 hands out pointers
@@ -143,6 +174,7 @@ struct Plan {
   // placement of the LDU launches (batches): XCD, group cap, launch kind
   int xcd = 0, max_groups = 0, cooperative = 1;
   uint32_t* epoch = nullptr;  // device word: flag base of the next LDU launch
+  uint64_t ldu_launches = 0;  // LDU launches enqueued since epoch and xbuf were reset
   // learned proposal (options.proposal): network, scan limit and buffers
   const float* mlp = nullptr;
   int rook_iter = 8;
@@ -259,6 +291,22 @@ void layout(Plan& p, Arena& A, bool gen_init) {
   }
 }
 
+// Session LDUs take their step flags from a device epoch that every launch
+// advances by kFlagStride; after 2^32 / kFlagStride launches the flags would
+// wrap and reuse values that words written long before may still carry.
+// Before that, the exchange words are cleared and the epoch restarts at 1.
+constexpr uint64_t kEpochLaunches = (1ull << 32) / kFlagStride - 1;
+int epoch_guard(aci_ctx* ctx, Plan& p, int launches, hipStream_t s) {
+  const uint64_t limit = ctx->epoch_launches ? ctx->epoch_launches : kEpochLaunches;
+  if (p.ldu_launches + (uint64_t)launches > limit) {
+    HIPCHK(launch_fill_int((int*)p.xbuf, (int)(2 * p.xbuf_words), 0, s));
+    HIPCHK(launch_fill_int((int*)p.epoch, 1, 1, s));
+    p.ldu_launches = 0;
+  }
+  p.ldu_launches += (uint64_t)launches;
+  return ACI_OK;
+}
+
 // Launch-log instance code of a contraction (see aci_launch).
 int contract_variant(int op, int prec, int cplx, int tile) { return 10000 * tile + 1000 * cplx + 100 * prec + op + 1; }
 
@@ -339,7 +387,7 @@ struct Enq {
     a.xcd = p.xcd;
     a.max_groups = p.max_groups;
     a.cooperative = p.cooperative;
-    a.spin_limit = kSpinLimit;
+    exchange_waits(ctx, a);
     a.xbuf = p.xbuf;
     a.xbuf_words = p.xbuf_words;
     if (tracing()) {
@@ -547,6 +595,7 @@ int enqueue_init(Enq& q) {
   // the LDU exchange words: flag 0 is never used, and the session's flags
   // restart at 1, so memory left by an earlier session must not look valid
   ENQ(launch_fill_int((int*)p.xbuf, 2 * p.xbuf_words, 0, s));
+  p.ldu_launches = L - 1;
   for (int l = L; l >= 2; --l) {
     const int dl = p.d[l];
     const double* Msrc = (l == L) ? p.Yin[L] : p.G[l];
@@ -1031,6 +1080,18 @@ void aci_ctx_destroy(aci_ctx* ctx) {
 
 const char* aci_last_error(const aci_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+int aci_ctx_set_exchange_hooks(aci_ctx* ctx, uint32_t spin_limit, int32_t stall_step, int64_t epoch_launches) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (stall_step < -1 || epoch_launches < 0 || (uint64_t)epoch_launches > kEpochLaunches)
+    return set_err(ctx, ACI_E_INVALID, "stall_step < -1 or epoch_launches out of range");
+  ctx->spin_limit = spin_limit ? spin_limit : kSpinLimit;
+  ctx->poll_xor = stall_step >= 0 ? 0x80000000u : 0u;
+  ctx->stall_from = stall_step >= 0 ? stall_step : 0;
+  ctx->epoch_launches = (uint64_t)epoch_launches;
+  return ACI_OK;
+}
+
 void aci_result_free(aci_result* r) {
   if (!r) return;
   free(r->rec_meta);
@@ -1304,6 +1365,7 @@ int sweep_enqueue(aci_session* S) {
   hipStream_t s = ctx->stream;
   S->prof.clear();
   S->swept_prec = p.prec;
+  if (int rc = epoch_guard(ctx, p, 2 * (L - 1), s)) return rc;
   HIPCHK(hipEventRecord(S->e0, s));
   if (S->use_graph) {
     if (!S->gexec || S->gprec != p.prec) {
@@ -1740,7 +1802,7 @@ int aci_tci(aci_ctx* ctx, int32_t L, const int32_t* d, int32_t dtype, aci_eval_f
         a.rule = o.stop_rule == 1 ? RULE_LITERAL : RULE_EXCLUSIVE;
         a.xbuf = xbuf;
         a.xbuf_words = xwords;
-        a.spin_limit = kSpinLimit;
+        exchange_waits(ctx, a);
         a.rows = rows;
         a.cols = cols;
         a.rank = misc;
@@ -2023,6 +2085,11 @@ int joint_enqueue(aci_batch* B, const std::vector<int>& ids, bool timed) {
 // when the batch uses graphs, followed by every product's read-back.
 int joint_sweep(aci_batch* B, const std::vector<int>& ids) {
   aci_ctx* ctx = B->parent;
+  // the joint LDU launches run on the joint stream
+  for (int b : ids) {
+    Plan& p = *B->sess[b]->plan;
+    if (int rc = epoch_guard(ctx, p, 2 * (p.L - 1), B->jstream)) return rc;
+  }
   if (!B->jgraph) {
     if (int rc = joint_enqueue(B, ids, true)) return rc;
   } else {
@@ -2170,6 +2237,11 @@ int aci_batch_create(aci_ctx* ctx, const aci_tt* inputs, const int32_t* n_inputs
     c->alloc_fn = ctx->alloc_fn;   // the products' memory comes from the caller's allocator too
     c->free_fn = ctx->free_fn;
     c->alloc_user = ctx->alloc_user;
+    // and the exchange waits of the parent (aci_ctx_set_exchange_hooks)
+    c->spin_limit = ctx->spin_limit;
+    c->poll_xor = ctx->poll_xor;
+    c->stall_from = ctx->stall_from;
+    c->epoch_launches = ctx->epoch_launches;
     B->ctxs.push_back(c);
     Placement pl;
     pl.xcd = (B->serial || B->joint) ? 0 : -1;
@@ -2584,8 +2656,7 @@ int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t 
       a.tol = 0.0;
       a.maxrank = std::min(maxrank, std::min(m, n));
       a.rule = RULE_EXCLUSIVE;
-      a.flag_base = next_flag(ctx);
-      a.spin_limit = kSpinLimit;
+      exchange_waits(ctx, a);
       a.xbuf = ctx->step_xbuf;
       a.xbuf_words = ctx->step_xwords;
       a.rows = rows;
@@ -2596,7 +2667,8 @@ int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t 
       a.abort_word = ctx->step_err + 1;
       a.max_groups = c;
       a.cooperative = 1;
-      hipError_t e = hipEventRecord(e0, ctx->stream);
+      hipError_t e = step_flag(ctx, &a.flag_base);
+      if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
       if (e == hipSuccess) e = launch_fill_int(ctx->step_err, 2, 0, ctx->stream);
       if (e == hipSuccess) e = launch_prrlu(a, m, n, ctx->stream);
       if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
@@ -2646,6 +2718,11 @@ static int ensure_step_ws(aci_ctx* ctx) {
     if (!dev_alloc(ctx, &p, words * sizeof(uint64_t))) return set_err(ctx, ACI_E_NOMEM, "step exchange buffer");
     ctx->step_xbuf = (uint64_t*)p;
     ctx->step_xwords = words;
+    // recycled memory may hold words whose flags a launch of this context
+    // will use (flags restart at 1 in every context): clear it, as the
+    // sessions clear theirs
+    HIPCHK(launch_fill_int((int*)ctx->step_xbuf, (int)(2 * words), 0, ctx->stream));
+    ctx->step_flags_wrapped = false;
   }
   return ACI_OK;
 }
@@ -2747,9 +2824,9 @@ int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, 
   a.tol = tol;
   a.maxrank = maxrank;
   a.rule = stop_rule;
-  a.flag_base = next_flag(ctx);
+  HIPCHK(step_flag(ctx, &a.flag_base));
   a.cooperative = 1;
-  a.spin_limit = kSpinLimit;
+  exchange_waits(ctx, a);
   a.xbuf = ctx->step_xbuf;
   a.xbuf_words = ctx->step_xwords;
   a.rows = rows;

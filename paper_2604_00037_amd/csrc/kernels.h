@@ -63,6 +63,11 @@ struct PrrluArgs {
   int xwords;       // words per exchange slot
   uint32_t flag_base;
   uint32_t spin_limit;
+  // failure-handling tests: from pivot step stall_from on, readers of the
+  // exchange wait for flag ^ poll_xor, which no group publishes, so each
+  // wait ends at its spin limit (poll_xor 0: off)
+  uint32_t poll_xor;
+  int stall_from;
   int* rows;        // out: pivot rows, pivot order
   int* cols;        // out: pivot columns
   int* rank;        // out: rank

@@ -211,6 +211,9 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   __shared__ double red_k[2][WAVES];
   __shared__ int red_i[2][WAVES];
   __shared__ int red_f[2][WAVES];
+  // set once any thread of the group saw a wait time out (only ever 0 -> 1)
+  __shared__ int gfail;
+  if (threadIdx.x == 0) gfail = 0;
   extern __shared__ uint32_t xs[];
   uint32_t* xrow = xs + kCandWords;
 
@@ -365,6 +368,9 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
       }
     } else {
       const uint32_t flag = fbase + (uint32_t)k;
+      // the flag readers wait for: the published one, unless a test stalls
+      // this step (then no word ever carries it)
+      const uint32_t want = k >= a.stall_from ? (flag ^ a.poll_xor) : flag;
       uint64_t* slot_base = a.xbuf + (size_t)par * P * a.xwords;
       uint64_t* mine = slot_base + (size_t)w * per;
       if (wv == 0 && lane < 3) {
@@ -403,7 +409,7 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
         const uint64_t* src = slot_base + (size_t)g * per + (t - 3 * g);
         uint64_t raw = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t spins = 0;
-        while ((uint32_t)(raw >> 32) != flag) {
+        while ((uint32_t)(raw >> 32) != want) {
           ++spins;
           if ((spins & 255u) == 0u) {
             if (__hip_atomic_load(a.abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || spins >= a.spin_limit) {
@@ -449,10 +455,14 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
       }
       // round trip 2: the winner's row (already published with its candidate)
       const int wg = (widx >> 16) % P;
-      ok = poll_words<(128 * EW * CS + NT - 1) / NT, NT>(slot_base + (size_t)wg * per + 3, 2 * EW * n, flag,
+      ok = poll_words<(128 * EW * CS + NT - 1) / NT, NT>(slot_base + (size_t)wg * per + 3, 2 * EW * n, want,
                                                      a.abort_word, a.spin_limit, xrow);
       if (!ok) failed = true;
+      if (failed) gfail = 1;
       __syncthreads();
+      // a failed wait anywhere in the group fails the whole group, so that
+      // every lane takes the same path out
+      failed = gfail != 0;
 #pragma unroll
       for (int b = 0; b < CS; ++b) {
         const int j = lane + 64 * b;

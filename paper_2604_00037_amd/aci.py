@@ -7,7 +7,9 @@ contiguous float64 (or complex128) tensors on the current HIP device.
 
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 from dataclasses import dataclass, field
@@ -15,6 +17,26 @@ from dataclasses import dataclass, field
 import torch
 
 from . import _lib
+
+# Library objects still alive, released explicitly at interpreter exit
+# (sessions and batches before the contexts they use), while the HIP runtime
+# and the torch allocator a context may call back into are still up.
+_live_children = weakref.WeakSet()
+_live_contexts = weakref.WeakSet()
+
+
+def _teardown():
+    global _default_ctx
+    if torch.cuda.is_available() and torch.cuda.is_initialized():
+        torch.cuda.synchronize()
+    for obj in list(_live_children):
+        obj.close()
+    for ctx in list(_live_contexts):
+        ctx.close()
+    _default_ctx = None
+
+
+atexit.register(_teardown)
 
 OPS = {"product": 0, "sum": 1, "abs2_mul": 2}
 RULES = {"exclusive": 0, "literal": 1}
@@ -81,6 +103,14 @@ class Context:
             raise ValueError("allocator must be None or 'torch'")
         _check(self.lib, None, st)
         self.h = h
+        _live_contexts.add(self)
+
+    def set_exchange_hooks(self, spin_limit=0, stall_step=-1, epoch_launches=0):
+        """aci_ctx_set_exchange_hooks: spin limit of the LDU exchange waits,
+        a test stall from pivot step ``stall_step`` on (-1: off), and the
+        session epoch reset period (0: default)."""
+        _check(self.lib, self.h, self.lib.aci_ctx_set_exchange_hooks(self.h, int(spin_limit), int(stall_step),
+                                                                     int(epoch_launches)))
 
     def close(self):
         if getattr(self, "h", None):
@@ -361,6 +391,7 @@ class Session:
                                              int(maxrank), C.byref(opts), C.byref(h))
         _check(self.ctx.lib, self.ctx.h, st, allow_warning=False)
         self.h = h
+        _live_children.add(self)
 
     def sweep(self, n=1):
         stats = _lib.AciSweepStats()
@@ -543,6 +574,7 @@ class Batch:
                                            int(maxrank), C.byref(opts), C.byref(h))
         _check(self.ctx.lib, self.ctx.h, st, allow_warning=False)
         self.h = h
+        _live_children.add(self)
 
     def sweep(self, n=1):
         stats = _lib.AciSweepStats()

@@ -355,6 +355,23 @@ int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, 
               int32_t* rows, int32_t* cols, int32_t* rank, double* eps,
               void* Y, int32_t ldy);
 
+/* The LDU of aci_prrlu for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, outputs, results and errors, but the exchange
+ * and error words live in a fixed static device array of the library
+ * (2.1 MB per GPU, held until the process ends) instead of memory the
+ * context allocates; no hipMalloc, hipFree or other allocating call is made.
+ * Limit: the factorisation's exchange must fit that array, which holds every
+ * real matrix up to ACI_MAX_MATRIX x ACI_MAX_MATRIX and complex matrices of up
+ * to 512 columns; larger ones return ACI_E_LIMIT.  The array is cleared at
+ * the start of every call on the context's stream.  All calls on one GPU
+ * share it: calls that overlap in time on one GPU (several streams, several
+ * threads or contexts) race and must be serialised by the caller. */
+int aci_prrlu_noalloc(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, int32_t ldm,
+                      double tol, int32_t maxrank, int32_t stop_rule,
+                      int32_t* rows, int32_t* cols, int32_t* rank, double* eps,
+                      void* Y, int32_t ldy);
+
 /* ---------------------------------------------------------------- batches
  * Several independent elementwise operations (for instance the convective
  * terms u_j d_j u_k of a Navier-Stokes right-hand side), each run as Alg. 1

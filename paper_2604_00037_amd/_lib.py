@@ -29,7 +29,7 @@ EXPORTED = [
     "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu", "aci_tune_contract", "aci_tci",
     "aci_proposal_features", "aci_mlp_forward", "aci_mlp_train_step", "aci_rook_lu", "aci_rook_check",
     "aci_rook_right_factor", "aci_mpo_stencil", "aci_mpo_apply", "aci_cubic_step", "aci_patched",
-    "aci_patched_free", "aci_ctx_set_exchange_hooks",
+    "aci_patched_free", "aci_ctx_set_exchange_hooks", "aci_prrlu_noalloc",
 ]
 MLP_PARAMS = 7 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -195,6 +195,8 @@ def load(path=LIB_PATH):
     lib.aci_pi_eval.restype = C.c_int
     lib.aci_prrlu.argtypes = [vp, i32, vp, i32, i32, i32, C.c_double, i32, i32, vp, vp, vp, vp, vp, i32]
     lib.aci_prrlu.restype = C.c_int
+    lib.aci_prrlu_noalloc.argtypes = lib.aci_prrlu.argtypes
+    lib.aci_prrlu_noalloc.restype = C.c_int
     lib.aci_gather.argtypes = [vp, i32, i32, vp, i32, i32, i32, vp, vp, vp, i32]
     lib.aci_gather.restype = C.c_int
     lib.aci_session_create.argtypes = [vp, C.POINTER(AciTT), i32, i32, i32, C.c_double, i32,

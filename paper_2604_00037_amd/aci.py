@@ -489,8 +489,10 @@ def pi_eval(op, A, B, precision="fp64", tile=None, ctx=None):
     return M
 
 
-def prrlu(M, tol, maxrank, stop_rule="exclusive", want_y=False, ctx=None):
-    """Alg. 2 on the device matrix M.  Returns dict(rows, cols, rank, eps, Y)."""
+def prrlu(M, tol, maxrank, stop_rule="exclusive", want_y=False, ctx=None, noalloc=False):
+    """Alg. 2 on the device matrix M.  Returns dict(rows, cols, rank, eps, Y).
+    noalloc: call aci_prrlu_noalloc (library workspace in a static device
+    array) instead of aci_prrlu."""
     ctx = ctx or default_context()
     _dev_tensor(M, "M")
     m, n = (int(s) for s in M.shape)
@@ -501,10 +503,11 @@ def prrlu(M, tol, maxrank, stop_rule="exclusive", want_y=False, ctx=None):
     rank = torch.zeros(1, dtype=torch.int32, device=dev)
     eps = torch.zeros(1, dtype=torch.float64, device=dev)
     Y = torch.zeros(kcap, n, dtype=M.dtype, device=dev) if want_y else None
-    st = ctx.lib.aci_prrlu(ctx.h, _code(M), C.c_void_p(M.data_ptr()), m, n, n, float(tol), int(maxrank),
-                           RULES[stop_rule], C.c_void_p(rows.data_ptr()), C.c_void_p(cols.data_ptr()),
-                           C.c_void_p(rank.data_ptr()), C.c_void_p(eps.data_ptr()),
-                           C.c_void_p(Y.data_ptr() if Y is not None else 0), n)
+    fn = ctx.lib.aci_prrlu_noalloc if noalloc else ctx.lib.aci_prrlu
+    st = fn(ctx.h, _code(M), C.c_void_p(M.data_ptr()), m, n, n, float(tol), int(maxrank),
+            RULES[stop_rule], C.c_void_p(rows.data_ptr()), C.c_void_p(cols.data_ptr()),
+            C.c_void_p(rank.data_ptr()), C.c_void_p(eps.data_ptr()),
+            C.c_void_p(Y.data_ptr() if Y is not None else 0), n)
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     r = int(rank.item())
     return dict(rows=rows[:r].cpu().numpy(), cols=cols[:r].cpu().numpy(), rank=r,

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2840,6 +2841,104 @@ int aci_prrlu(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, 
   HIPCHK(launch_prrlu(a, m, n, ctx->stream));
   int flags = 0;
   HIPCHK(hipMemcpyAsync(&flags, ctx->step_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (flags & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "pivot exchange timed out");
+  return ACI_OK;
+}
+
+}  // extern "C"
+
+// ---- LDU without allocation
+// Fixed device workspace of aci_prrlu_noalloc: kNoAllocFlagWords words for
+// the error and abort words, then the exchange words of one factorisation.
+// The exchange size covers every real matrix up to ACI_MAX_MATRIX x
+// ACI_MAX_MATRIX (64 groups of 1024-column rows) and complex matrices up to
+// 512 columns; larger exchanges are refused.  Every GPU holds its own copy
+// until the process ends.
+namespace {
+constexpr size_t kNoAllocFlagWords = 32;   // keeps the exchange 256-byte aligned
+constexpr size_t kNoAllocXWords = (size_t)2 * 64 * (4 + 2 * 64 * 16);
+constexpr size_t kNoAllocWords = kNoAllocFlagWords + kNoAllocXWords;
+}  // namespace
+static __device__ __align__(256) uint64_t scratch[kNoAllocWords];
+
+namespace {
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+uint64_t* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (in host code the symbol's name is not a device address).
+int noalloc_scratch(aci_ctx* ctx, uint64_t** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return set_err(ctx, ACI_E_LIMIT, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return set_err(ctx, ACI_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_noalloc_ptr[dev] = (uint64_t*)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return ACI_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int aci_prrlu_noalloc(aci_ctx* ctx, int32_t dtype, const void* M, int32_t m, int32_t n, int32_t ldm, double tol,
+                      int32_t maxrank, int32_t stop_rule, int32_t* rows, int32_t* cols, int32_t* rank, double* eps,
+                      void* Y, int32_t ldy) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (dtype != ACI_F64 && dtype != ACI_C128) return set_err(ctx, ACI_E_DTYPE, "unknown dtype");
+  if (!M || !rows || !cols || !rank || !eps) return set_err(ctx, ACI_E_INVALID, "null pointer");
+  if (m < 1 || n < 1 || ldm < n || maxrank < 1 || !(tol >= 0.0)) return set_err(ctx, ACI_E_INVALID, "bad dims or tolerance");
+  if (m > ACI_MAX_MATRIX || n > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "matrix above ACI_MAX_MATRIX");
+  if (stop_rule != 0 && stop_rule != 1) return set_err(ctx, ACI_E_INVALID, "stop_rule");
+  if (Y && ldy < n) return set_err(ctx, ACI_E_INVALID, "ldy < n");
+  const int cplx = dtype == ACI_C128 ? 1 : 0;
+  const size_t used = prrlu_xbuf_used(m, n, 0, cplx);
+  if (used == 0) return set_err(ctx, ACI_E_LIMIT, "no LDU shape for these dimensions");
+  if (used > kNoAllocXWords)
+    return set_err(ctx, ACI_E_LIMIT, "exchange of " + std::to_string(used) + " words exceeds the static scratch of " +
+                                         std::to_string(kNoAllocXWords) + " (complex matrices above 512 columns)");
+  uint64_t* ws = nullptr;
+  if (int rc = noalloc_scratch(ctx, &ws)) return rc;
+  int* err = (int*)ws;
+  // The scratch keeps the previous call's words: clear the flags and the
+  // exchange words this launch uses, so that its step flags (from 1) match
+  // nothing stale.
+  HIPCHK(launch_fill_int((int*)ws, 2 * (kNoAllocFlagWords + used), 0, ctx->stream));
+  PrrluArgs a{};
+  a.M = (const double*)M;
+  a.cplx = cplx;
+  a.m = dconst(m);
+  a.n = dconst(n);
+  a.ldm = dconst(ldm);
+  a.tol = tol;
+  a.maxrank = maxrank;
+  a.rule = stop_rule;
+  a.flag_base = 1;
+  a.cooperative = 1;
+  exchange_waits(ctx, a);
+  a.xbuf = ws + kNoAllocFlagWords;
+  a.xbuf_words = used;
+  a.rows = rows;
+  a.cols = cols;
+  a.rank = rank;
+  a.eps = eps;
+  a.Y = (double*)Y;
+  a.ldy = dconst(ldy);
+  a.err = err;
+  a.abort_word = err + 1;
+  HIPCHK(launch_prrlu(a, m, n, ctx->stream));
+  int flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (flags & ERR_TIMEOUT) return set_err(ctx, ACI_E_TIMEOUT, "pivot exchange timed out");
   return ACI_OK;

@@ -96,6 +96,9 @@ struct PrrluArgs {
 hipError_t launch_prrlu(const PrrluArgs& a, int mmax, int nmax, hipStream_t s);
 // Exchange-buffer words needed for matrices up to mmax x nmax.
 size_t prrlu_xbuf_words(int mmax, int nmax, int cplx = 0);
+// Exchange-buffer words one launch_prrlu call for exactly these bounds and
+// group cap reads and writes (both parities), or 0 if out of range.
+size_t prrlu_xbuf_used(int mmax, int nmax, int max_groups, int cplx = 0);
 // Instance launch_prrlu picks for these bounds: 100000*cplx + 10000*solo +
 // 100*RS + CS, or -1 if the bounds are out of range.
 int prrlu_variant(int mmax, int nmax, int max_groups = 0, int cplx = 0);

@@ -939,6 +939,15 @@ size_t prrlu_xbuf_words(int mmax, int nmax, int cplx) {
   return (size_t)2 * kMaxGroups * (4 + 2 * ew * 64 * sh->cs);
 }
 
+size_t prrlu_xbuf_used(int mmax, int nmax, int max_groups, int cplx) {
+  if (mmax < 1 || nmax < 1 || mmax > ACI_MAX_MATRIX || nmax > ACI_MAX_MATRIX) return 0;
+  const Shape* sh = pick_shape(nmax, cplx != 0);
+  if (!sh) return 0;
+  const int rs = pick_rs(*sh, mmax, max_groups);
+  const int P = (mmax + WAVES * rs - 1) / (WAVES * rs);
+  return (size_t)2 * P * (4 + 2 * (cplx ? 2 : 1) * 64 * sh->cs);
+}
+
 int prrlu_variant(int mmax, int nmax, int max_groups, int cplx) {
   if (mmax < 1 || nmax < 1 || mmax > ACI_MAX_MATRIX || nmax > ACI_MAX_MATRIX) return -1;
   const Shape* sh = pick_shape(nmax, cplx != 0);

@@ -739,43 +739,34 @@ def summarize_contract(directory):
 
 
 def time_proposal(aci, device, steps=300):
-    """Learned pivot proposal: a scoring network trained on the GPU from the
-    pivots of plain FP64 ACI (the oracle) on products of 3D Fourier fields
-    (4 bits per axis, |k| <= 4, rank 24, training seeds 1..6), then used in
-    the sweeps of a held-out product of the same kind at 5 bits per axis
-    (L = 15, rank 48), tol 1e-8, rank cap 128: sweeps to convergence and
-    wall time with and without proposals, and how many were accepted."""
+    """Learned pivot proposal: a scoring network initialised and trained on
+    the GPU from the library's own plain FP64 sweeps (aci_proposal_dataset)
+    on products of 3D Fourier fields (4 bits per axis, |k| <= 4, rank 24,
+    training seeds 1..6), then used in the sweeps of a held-out product of the
+    same kind at 5 bits per axis (L = 15, rank 48), tol 1e-8, rank cap 128:
+    sweeps to convergence and wall time with and without proposals, and how
+    many were accepted."""
     import numpy as np
     import torch
-    import oracle
     import workloads as W
-    from oracle import proposal as P
 
     def field(R, kmax, s, chi):
         g = W.fourier3d_full(R, kmax, s)
         q = np.ascontiguousarray(W.grid_to_quantics(g, R, 3)).reshape(-1)
         return W.tt_svd(q, 2, chi, rtol=1e-12)
 
+    def tdev(cores):
+        return [torch.from_numpy(np.ascontiguousarray(c)).to(device) for c in cores]
+
     t = time.perf_counter()
     Xs, ys = [], []
     for sd in range(1, 7):
-        rec = []
-        oracle.aci([field(4, 4, sd, 24), field(4, 4, sd + 1000, 24)], "product", TOL, 64, maxiter=3, seed=sd,
-                   record=rec)
-        prev = {}
-        for r in rec:
-            key = (r["bond"], r["dir"])
-            pr = prev.get(key, np.zeros(0, np.int32)).astype(np.int32)
-            prev[key] = r["rows"]
-            M = torch.from_numpy(r["M"]).to(device)
-            X = aci.proposal_features(M, [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in r["A"]],
-                                      torch.from_numpy(pr).to(device) if len(pr) else None)
-            y = np.zeros(r["M"].shape[0], np.float32)
-            y[r["rows"][:max(1, len(r["rows"]) // 2)]] = 1
-            Xs.append(X)
-            ys.append(torch.from_numpy(y).to(device))
+        X, y, _ = aci.proposal_dataset([tdev(field(4, 4, sd, 24)), tdev(field(4, 4, sd + 1000, 24))], "product",
+                                       TOL, 64, maxiter=3, seed=sd)
+        Xs.append(X)
+        ys.append(y)
     X, y = torch.cat(Xs), torch.cat(ys)
-    p = torch.from_numpy(np.concatenate([q.reshape(-1) for q in P.mlp_init(7).params()])).to(device)
+    p = aci.mlp_init(7, device=device)
     m, v = torch.zeros_like(p), torch.zeros_like(p)
     rng = np.random.default_rng(0)
     torch.cuda.synchronize()
@@ -785,8 +776,8 @@ def time_proposal(aci, device, steps=300):
         loss, _ = aci.mlp_train_step(p, m, v, step, X[idx].contiguous(), y[idx].contiguous(), lr=3e-3)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
-    log(f"proposal: {X.shape[0]} training rows from oracle runs, {steps} Adam steps in {train_s:.2f} s, "
-        f"loss {loss:.3f}")
+    log(f"proposal: {X.shape[0]} training rows recorded from the library's sweeps, {steps} Adam steps in "
+        f"{train_s:.2f} s, loss {loss:.3f}")
     g1, g2 = field(5, 4, 151, 48), field(5, 4, 1151, 48)
     d = [[torch.from_numpy(c).to(device) for c in g] for g in (g1, g2)]
     out = {"workload": "u*v of two random 3D Fourier fields (|k|<=4) on a 32^3 grid, L=15 d=2, TT rank 48, "
@@ -824,7 +815,7 @@ def main():
     ap.add_argument("--no-step", action="store_true", help="skip the explicit GP time step")
     ap.add_argument("--no-patched", action="store_true", help="skip the patched GP term")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution product")
-    ap.add_argument("--only", choices=["gp", "batched", "contract", "tci", "step", "patched", "tts"],
+    ap.add_argument("--only", choices=["gp", "batched", "contract", "tci", "step", "patched", "tts", "proposal"],
                     help="run just one section and print its JSON (for profiling that workload)")
     ap.add_argument("--summarize-contract", metavar="DIR", help="per-case table of a traced --only contract run")
     ap.add_argument("--summarize-stats", metavar="DIR",
@@ -880,6 +871,9 @@ def main():
         return
     if args.only == "batched":
         print(json.dumps(time_batched(aci, max(2, args.steps // 3), 1, dev)), flush=True)
+        return
+    if args.only == "proposal":
+        print(json.dumps(time_proposal(aci, dev)), flush=True)
         return
     u, v = make_inputs(args.bits, dev)
     inputs = [[torch.from_numpy(c).to(dev) for c in x] for x in (u, v)]

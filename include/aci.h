@@ -212,6 +212,8 @@ typedef struct {
   int32_t last_precision;            /* aci_precision of the last sweep run */
   int32_t proposals_tried;           /* local updates with a learned proposal */
   int32_t proposals_accepted;        /* of which the rook result was kept */
+  int64_t proposal_scans;            /* rook row/column scans of all proposals */
+  int64_t proposal_pivots;           /* pivots of all rook searches (kept or not) */
 } aci_sweep_stats;
 
 /* One kernel launch of a profiled aci_session_sweep call (options.profile).
@@ -618,6 +620,32 @@ int aci_tune_prrlu(aci_ctx* ctx, int32_t m, int32_t n, int32_t maxrank, int32_t 
 int aci_proposal_features(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int32_t ldm,
                           const void* const* env, const int32_t* env_w, const int32_t* env_ld,
                           int32_t n_env, const int32_t* prev_rows, int32_t n_prev, float* X);
+/* Training set of the scoring network from the library's own plain FP64
+ * sweeps: runs Alg. 1 on real inputs (options as for aci_elementwise, at most
+ * options.maxiter sweeps, stopping at convergence unless fixed_sweeps;
+ * options.proposal must be NULL and precision FP64) and, after the LDU of
+ * Alg. 2 of every local update of every sweep (left to right, then right to
+ * left), appends that update's m rows of the two-site matrix M: their
+ * features (as aci_proposal_features, with env = the update's left
+ * environments A^n for the first two inputs and prev_rows = the pivot rows
+ * of the previous update of the same bond and direction, none in the first
+ * sweep) to X (capacity x 7 float32, device) and their labels to y (capacity
+ * float32, device): 1 for the first max(1, r / 2) pivot rows of the update's
+ * rank-r factorisation, else 0.  *count (host) receives the rows written,
+ * *sweeps (host, optional) the sweeps run.  An update whose rows would pass
+ * `capacity` is not recorded, nor is any later one; the call then returns
+ * ACI_E_NOMEM with *count the rows of the updates that fit.  Otherwise
+ * returns ACI_OK or ACI_W_NOT_CONVERGED as aci_elementwise would. */
+int aci_proposal_dataset(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t op, double tol,
+                         int32_t maxrank, const aci_options* options, float* X, float* y,
+                         int64_t capacity, int64_t* count, int32_t* sweeps);
+/* Initial parameters of the scoring network (device, ACI_MLP_PARAMS float32,
+ * layout as below): W1, W2 and w3 in this order, each in C order, from one
+ * SplitMix64 stream seeded with `seed` (S. Vigna's generator, as for the
+ * default Y_init): entry = u sqrt(6 / fan_in) rounded to float32, with
+ * u = (z >> 11) 2^-53 2 - 1 uniform on [-1, 1) and fan_in 7, 64, 64; all
+ * biases zero. */
+int aci_mlp_init(aci_ctx* ctx, uint64_t seed, float* params);
 /* Network 7 -> 64 -> 64 -> 1 (ReLU), parameters: ACI_MLP_PARAMS float32 in
  * the order W1 (7 x 64, row-major), b1, W2 (64 x 64), b2, w3, b3.  Each
  * layer rounds inputs and weights to float16, accumulates the exact products

@@ -15,11 +15,12 @@ paper_2604_00037_amd.build``); nothing falls back to the CPU.
 """
 
 from .aci import (Batch, Context, Patch, Session, cubic_step, patched, default_context, elementwise, elementwise_batched,
-                  env_contract, gather, linear_cubic, mlp_forward, mlp_train_step, mpo_apply, mpo_stencil,
-                  pi_eval, proposal_features, prrlu, rook_check, rook_lu, rook_right_factor, tci,
+                  env_contract, gather, linear_cubic, mlp_forward, mlp_init, mlp_train_step, mpo_apply, mpo_stencil,
+                  pi_eval, proposal_dataset, proposal_features, prrlu, rook_check, rook_lu, rook_right_factor, tci,
                   tune_contract, tune_prrlu, TILES)
 
 __all__ = ["Batch", "Context", "Session", "default_context", "elementwise", "elementwise_batched",
-           "env_contract", "gather", "mlp_forward", "mlp_train_step", "pi_eval", "proposal_features",
+           "env_contract", "gather", "mlp_forward", "mlp_init", "mlp_train_step", "pi_eval", "proposal_dataset",
+           "proposal_features",
            "prrlu", "rook_check", "rook_lu", "rook_right_factor", "tci", "tune_contract", "tune_prrlu", "TILES",
            "cubic_step", "linear_cubic", "mpo_apply", "mpo_stencil", "Patch", "patched"]

@@ -30,6 +30,7 @@ EXPORTED = [
     "aci_proposal_features", "aci_mlp_forward", "aci_mlp_train_step", "aci_rook_lu", "aci_rook_check",
     "aci_rook_right_factor", "aci_mpo_stencil", "aci_mpo_apply", "aci_cubic_step", "aci_patched",
     "aci_patched_free", "aci_ctx_set_exchange_hooks", "aci_prrlu_noalloc",
+    "aci_proposal_dataset", "aci_mlp_init",
 ]
 MLP_PARAMS = 7 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -128,6 +129,8 @@ class AciSweepStats(C.Structure):
         ("last_precision", C.c_int32),
         ("proposals_tried", C.c_int32),
         ("proposals_accepted", C.c_int32),
+        ("proposal_scans", C.c_int64),
+        ("proposal_pivots", C.c_int64),
     ]
 
 
@@ -235,6 +238,11 @@ def load(path=LIB_PATH):
     i32p = C.POINTER(i32)
     lib.aci_proposal_features.argtypes = [vp, vp, i32, i32, i32, C.POINTER(vp), i32p, i32p, i32, vp, i32, vp]
     lib.aci_proposal_features.restype = C.c_int
+    lib.aci_proposal_dataset.argtypes = [vp, C.POINTER(AciTT), i32, i32, C.c_double, i32, C.POINTER(AciOptions),
+                                         vp, vp, C.c_int64, C.POINTER(C.c_int64), i32p]
+    lib.aci_proposal_dataset.restype = C.c_int
+    lib.aci_mlp_init.argtypes = [vp, C.c_uint64, vp]
+    lib.aci_mlp_init.restype = C.c_int
     lib.aci_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
     lib.aci_mlp_forward.restype = C.c_int
     lib.aci_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, vp, vp, i32, C.c_float, vp, f32p]

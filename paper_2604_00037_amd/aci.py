@@ -404,7 +404,8 @@ class Session:
                     flops=list(stats.flops), pivots=stats.pivots,
                     ranks=[stats.ranks[i] for i in range(L + 1)], max_eps=stats.max_eps,
                     last_precision=[k for k, v in PRECISIONS.items() if v == stats.last_precision][0],
-                    proposals_tried=stats.proposals_tried, proposals_accepted=stats.proposals_accepted)
+                    proposals_tried=stats.proposals_tried, proposals_accepted=stats.proposals_accepted,
+                    proposal_scans=stats.proposal_scans, proposal_pivots=stats.proposal_pivots)
 
     def launches(self):
         """Launch log of the last ``sweep`` call (needs ``profile=True``): one
@@ -746,6 +747,38 @@ def proposal_features(M, env, prev_rows=None, ctx=None):
                                        _p(prev_rows) if npv else None, npv, _p(X))
     _check(ctx.lib, ctx.h, st, allow_warning=False)
     return X
+
+
+def proposal_dataset(inputs, op="product", tol=1e-12, maxrank=64, *, capacity=1 << 20, maxiter=20, seed=0,
+                     init=None, stop_rule="exclusive", fixed_sweeps=False, ctx=None):
+    """aci_proposal_dataset: training rows (features X, labels y) recorded
+    from the library's own plain FP64 sweeps of op(inputs).  Returns
+    (X, y, sweeps) with X (count x 7) and y (count) device float32 views."""
+    ctx = ctx or default_context()
+    keep = []
+    tts = _inputs(inputs, keep)
+    if _code(inputs[0][0]) != F64:
+        raise TypeError("the dataset is recorded from real inputs")
+    opts = _options(keep, maxiter, seed, init, stop_rule, "fp64", False, fixed_sweeps, False)
+    code = _op_code(op, opts, keep, False, len(inputs))
+    dev = inputs[0][0].device
+    X = torch.empty((capacity, 7), dtype=torch.float32, device=dev)
+    y = torch.empty(capacity, dtype=torch.float32, device=dev)
+    count = C.c_int64(0)
+    sweeps = C.c_int32(0)
+    st = ctx.lib.aci_proposal_dataset(ctx.h, tts, len(inputs), code, float(tol), int(maxrank), C.byref(opts),
+                                      _p(X), _p(y), int(capacity), C.byref(count), C.byref(sweeps))
+    _check(ctx.lib, ctx.h, st)
+    return X[:count.value], y[:count.value], sweeps.value
+
+
+def mlp_init(seed, device=None, ctx=None):
+    """aci_mlp_init: initial network parameters (ACI_MLP_PARAMS float32 on
+    the device) from SplitMix64(seed)."""
+    ctx = ctx or default_context()
+    p = torch.empty(_lib.MLP_PARAMS, dtype=torch.float32, device=device or torch.cuda.current_device())
+    _check(ctx.lib, ctx.h, ctx.lib.aci_mlp_init(ctx.h, int(seed) & ((1 << 64) - 1), _p(p)), allow_warning=False)
+    return p
 
 
 def mlp_forward(params, X, ctx=None):

@@ -181,8 +181,15 @@ struct Plan {
   int rook_iter = 8;
   float *feat = nullptr, *scores = nullptr;
   double *rkL = nullptr, *rkUp = nullptr, *rkC = nullptr, *rkeps = nullptr, *chkeps = nullptr;
-  int *rkrows = nullptr, *rkcols = nullptr, *rkrank = nullptr, *acc = nullptr, *acc_count = nullptr;
+  int *rkrows = nullptr, *rkcols = nullptr, *rkrank = nullptr, *acc = nullptr, *rkscans = nullptr;
+  int* acc_count = nullptr;   // per sweep: [0] accepted proposals, [1] rook scans, [2] rook pivots
   int *prevr = nullptr, *prevk = nullptr;   // previous pivot rows per (direction, bond)
+  // training set of the scoring network recorded from the sweeps
+  // (aci_proposal_dataset): features and pivot labels of every local update
+  bool rec_on = false;
+  float *recX = nullptr, *recY = nullptr;
+  int64_t rec_cap = 0;
+  long long* rec_count = nullptr;   // [0] rows, [1] overflow
   double tol = 0.0;
   int d[ACI_MAX_SITES + 1];                         // d[l], l = 1..L
   int r[ACI_MAX_INPUTS][ACI_MAX_SITES + 1];         // r[n][l], l = 0..L
@@ -267,9 +274,14 @@ void layout(Plan& p, Arena& A, bool gen_init) {
   p.xbuf_words = prrlu_xbuf_words(p.ldm, p.ldm, p.cplx);
   p.xbuf = A.take<uint64_t>(p.xbuf_words);
   p.meta = A.take<int>((size_t)3 * 3 * (L - 1));
+  if (p.mlp || p.rec_on) {
+    p.feat = A.take<float>((size_t)p.D * p.maxrank * MLP_FEATURES);
+    p.prevr = A.take<int>((size_t)2 * (L + 1) * p.maxrank);
+    p.prevk = A.take<int>((size_t)2 * (L + 1));
+  }
+  if (p.rec_on) p.rec_count = A.take<long long>(2);
   if (p.mlp) {
     const size_t rows = (size_t)p.D * p.maxrank;
-    p.feat = A.take<float>(rows * MLP_FEATURES);
     p.scores = A.take<float>(rows);
     p.rkL = A.take<double>(rows * p.maxrank);
     p.rkUp = A.take<double>((size_t)p.maxrank * p.ldm);
@@ -280,9 +292,8 @@ void layout(Plan& p, Arena& A, bool gen_init) {
     p.rkcols = A.take<int>(p.maxrank);
     p.rkrank = A.take<int>(1);
     p.acc = A.take<int>(2);
-    p.acc_count = A.take<int>(1);
-    p.prevr = A.take<int>((size_t)2 * (L + 1) * p.maxrank);
-    p.prevk = A.take<int>((size_t)2 * (L + 1));
+    p.acc_count = A.take<int>(3);
+    p.rkscans = A.take<int>(1);
   }
   if (p.trace) {
     p.tr_meta = A.take<int>((size_t)3 * p.n_rec);
@@ -428,6 +439,12 @@ struct Enq {
   // the places the LDU would write them.  p.acc[0] then tells the LDU to
   // skip, p.acc[1] the right-factor solve.
   int propose(int l, int dir, Dim m, Dim n, int mrows, int ncols_max, int* rank2, double* eps2) {
+    if (int rc = features(l, dir, m, n)) return rc;
+    if (int rc = stepf(20002, [&] { return launch_mlp_forward(p.mlp, p.feat, mrows, p.scores, s); })) return rc;
+    return rook(m, n, mrows, ncols_max, rank2, eps2);
+  }
+  // row features of the two-site matrix in p.Mbuf at bond l into p.feat
+  int features(int l, int dir, Dim m, Dim n) {
     FeatureArgs fa{};
     fa.M = p.Mbuf;
     fa.m = m;
@@ -442,8 +459,10 @@ struct Enq {
     fa.prev_rows = p.prevr + (size_t)(dir * (p.L + 1) + l) * p.maxrank;
     fa.prev_rank = p.prevk + dir * (p.L + 1) + l;
     fa.X = p.feat;
-    if (int rc = stepf(20001, [&] { return launch_features(fa, s); })) return rc;
-    if (int rc = stepf(20002, [&] { return launch_mlp_forward(p.mlp, p.feat, mrows, p.scores, s); })) return rc;
+    return stepf(20001, [&] { return launch_features(fa, s); });
+  }
+  // seeded rook search, residual check and commit of an accepted proposal
+  int rook(Dim m, Dim n, int mrows, int ncols_max, int* rank2, double* eps2) {
     RookArgs ra{};
     ra.M = p.Mbuf;
     ra.m = m;
@@ -461,6 +480,7 @@ struct Enq {
     ra.cols = p.rkcols;
     ra.rank = p.rkrank;
     ra.eps = p.rkeps;
+    ra.scans = p.rkscans;
     if (int rc = stepf(20003, [&] { return launch_rook(ra, s); })) return rc;
     ContractArgs c{};
     c.ngroup = 1;
@@ -501,7 +521,24 @@ struct Enq {
     cm.m = m;
     cm.n = n;
     cm.maxrank = p.maxrank;
+    cm.src_scans = p.rkscans;
+    cm.scan_total = p.acc_count + 1;
     return stepf(20006, [&] { return launch_commit(cm, s); });
+  }
+  // the update's training rows (features of M, labels from the LDU's
+  // pivots), appended to the recorded dataset
+  int record(int l, int dir, Dim m, Dim n) {
+    if (int rc = features(l, dir, m, n)) return rc;
+    RecordArgs a{};
+    a.feat = p.feat;
+    a.m = m;
+    a.rows = rows();
+    a.rank = p.prank;
+    a.X = p.recX;
+    a.y = p.recY;
+    a.capacity = p.rec_cap;
+    a.count = p.rec_count;
+    return stepf(20009, [&] { return launch_record(a, s); });
   }
   // keep this update's pivot rows for the next update of the same bond
   int keep_rows(int l, int dir) {
@@ -592,7 +629,8 @@ int enqueue_init(Enq& q) {
   ENQ(launch_fill_int(p.nJ + L + 1, 1, 1, s));
   ENQ(launch_fill_int(p.flags, 4, 0, s));
   ENQ(launch_fill_int((int*)p.epoch, 1, 1, s));
-  if (p.mlp) ENQ(launch_fill_int(p.prevk, 2 * (L + 1), 0, s));
+  if (p.mlp || p.rec_on) ENQ(launch_fill_int(p.prevk, 2 * (L + 1), 0, s));
+  if (p.rec_on) ENQ(launch_fill_int((int*)p.rec_count, 4, 0, s));
   // the LDU exchange words: flag 0 is never used, and the session's flags
   // restart at 1, so memory left by an earlier session must not look valid
   ENQ(launch_fill_int((int*)p.xbuf, 2 * p.xbuf_words, 0, s));
@@ -752,7 +790,8 @@ int enqueue_update(Enq& q, int u, int stage) {
     }
     int rc = q.copy_traced(q.rows(), p.pivLR + (size_t)l * p.maxrank);
     if (rc) return rc;
-    if (p.mlp && (rc = q.keep_rows(l, 0))) return rc;
+    if (p.rec_on && (rc = q.record(l, 0, ddev(p.nI + l - 1, p.d[l]), ddev(p.nJ + l + 2, p.d[l + 1])))) return rc;
+    if ((p.mlp || p.rec_on) && (rc = q.keep_rows(l, 0))) return rc;
     // L^n_l = A^n_l[I_l, :]  (Alg. 5, Leftframe)
     GatherArgs g{};
     g.esz = p.ew;
@@ -820,8 +859,9 @@ int enqueue_update(Enq& q, int u, int stage) {
     sa.skip = p.acc + 1;
     rc = q.stepf(20008, [&] { return launch_rook_solve(sa, s); });
     if (rc) return rc;
-    if ((rc = q.keep_rows(l, 1))) return rc;
   }
+  if (p.rec_on && (rc = q.record(l, 1, ddev(p.nI + l - 1, p.d[l]), ncols))) return rc;
+  if ((p.mlp || p.rec_on) && (rc = q.keep_rows(l, 1))) return rc;
   // R^n_{l+1} = B^n_l[:, J_{l+1}]  (Alg. 5, Rightframe)
   GatherArgs g{};
   g.esz = p.ew;
@@ -851,7 +891,7 @@ int enqueue_sweep(Enq& q) {
   aci_ctx* ctx = q.ctx;
   Plan& p = q.p;
   q.slot = p.L - 1;
-  if (p.mlp) ENQ(launch_fill_int(p.acc_count, 1, 0, q.s));
+  if (p.mlp) ENQ(launch_fill_int(p.acc_count, 3, 0, q.s));
   for (int u = 0; u < 2 * (p.L - 1); ++u)
     for (int stage = 0; stage < 2; ++stage)
       if (int rc = enqueue_update(q, u, stage)) return rc;
@@ -1211,8 +1251,15 @@ int tune_tile(aci_ctx* ctx, int cplx, int prec, int ngroup, int m, int k, int n,
 struct Placement {
   int xcd = 0, max_groups = 0, cooperative = 1;
 };
+// the training set aci_proposal_dataset records into
+struct RecordSpec {
+  float* X = nullptr;
+  float* y = nullptr;
+  int64_t capacity = 0;
+};
 int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op, double tol,
-                   int32_t maxrank, const aci_options* opt, const Placement& pl, aci_session** out);
+                   int32_t maxrank, const aci_options* opt, const Placement& pl, aci_session** out,
+                   const RecordSpec* record = nullptr);
 }  // namespace
 
 int aci_session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op,
@@ -1222,7 +1269,8 @@ int aci_session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int
 
 namespace {
 int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t dtype, int32_t op, double tol,
-                   int32_t maxrank, const aci_options* opt, const Placement& pl, aci_session** out) {
+                   int32_t maxrank, const aci_options* opt, const Placement& pl, aci_session** out,
+                   const RecordSpec* record) {
   if (!ctx) return ACI_E_INVALID;
   ctx->err.clear();
   if (!out) return set_err(ctx, ACI_E_INVALID, "null session pointer");
@@ -1239,6 +1287,12 @@ int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t
   Plan& p = *S->plan;
   int rc = plan_problem(ctx, inputs, n_inputs, dtype, op, tol, maxrank, o, p);
   if (rc) return rc;
+  if (record) {
+    p.rec_on = true;
+    p.recX = record->X;
+    p.recY = record->y;
+    p.rec_cap = record->capacity;
+  }
   S->fixed = p.fixed;
   S->prof.on = o.profile != 0;
   for (auto& row : p.tiles) std::fill(row, row + ACI_MAX_SITES + 2, -1);
@@ -1271,7 +1325,7 @@ int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t
     }
   }
   // graphs need launches with static arguments: no events, no trace records
-  S->use_graph = o.use_graph != 0 && !S->prof.on && !p.trace && p.op != ACI_OP_CUSTOM;
+  S->use_graph = o.use_graph != 0 && !S->prof.on && !p.trace && p.op != ACI_OP_CUSTOM && !p.rec_on;
   p.xcd = pl.xcd;
   p.max_groups = pl.max_groups;
   if (S->use_graph) {
@@ -1355,7 +1409,7 @@ int sweep_readback(aci_session* S, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(S->h_eps, p.eps_bond, sizeof(double) * (L - 1), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(S->h_meta, p.meta + 3 * (L - 1), sizeof(int) * 3 * 2 * (L - 1), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(S->h_flags, p.flags, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
-  if (p.mlp) HIPCHK(hipMemcpyAsync(S->h_flags + 2, p.acc_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (p.mlp) HIPCHK(hipMemcpyAsync(S->h_flags + 2, p.acc_count, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   return ACI_OK;
 }
 
@@ -1458,6 +1512,8 @@ int sweep_finish(aci_session* S, aci_sweep_stats& st) {
   if (p.mlp) {
     st.proposals_tried += 2 * (L - 1);
     st.proposals_accepted += S->h_flags[2];
+    st.proposal_scans += S->h_flags[3];
+    st.proposal_pivots += S->h_flags[4];
   }
   if (S->swept_prec == PREC_FP64) {
     S->converged = !grew && emax <= p.tol;
@@ -2448,6 +2504,63 @@ int aci_proposal_features(aci_ctx* ctx, const void* M, int32_t m, int32_t n, int
   HIPCHK(launch_features(a, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return ACI_OK;
+}
+
+int aci_mlp_init(aci_ctx* ctx, uint64_t seed, float* params) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!params) return set_err(ctx, ACI_E_INVALID, "null params");
+  // W1 (7 x 64), W2 (64 x 64), w3 (64) in this order from one stream, each
+  // entry u sqrt(6 / fan_in) with u uniform on [-1, 1); biases zero
+  std::vector<float> h(ACI_MLP_PARAMS, 0.f);
+  SplitMix64 rng{seed};
+  const int H = ACI_MLP_HIDDEN, F = ACI_MLP_FEATURES;
+  const size_t oW1 = 0, oW2 = (size_t)F * H + H, ow3 = oW2 + (size_t)H * H + H;
+  const double s1 = std::sqrt(6.0 / F), s2 = std::sqrt(6.0 / H);
+  for (int i = 0; i < F * H; ++i) h[oW1 + i] = (float)(rng.uniform() * s1);
+  for (int i = 0; i < H * H; ++i) h[oW2 + i] = (float)(rng.uniform() * s2);
+  for (int i = 0; i < H; ++i) h[ow3 + i] = (float)(rng.uniform() * s2);
+  HIPCHK(hipMemcpyAsync(params, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ACI_OK;
+}
+
+int aci_proposal_dataset(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t op, double tol,
+                         int32_t maxrank, const aci_options* opt, float* X, float* y, int64_t capacity,
+                         int64_t* count, int32_t* sweeps) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!X || !y || !count) return set_err(ctx, ACI_E_INVALID, "null argument");
+  if (capacity < 0) return set_err(ctx, ACI_E_INVALID, "capacity < 0");
+  *count = 0;
+  if (sweeps) *sweeps = 0;
+  aci_options o{};
+  o.maxiter = 20;
+  if (opt) o = *opt;
+  if (o.maxiter <= 0) o.maxiter = 20;
+  if (o.proposal) return set_err(ctx, ACI_E_INVALID, "the dataset records the full search: options.proposal must be NULL");
+  if (o.precision != ACI_PREC_FP64) return set_err(ctx, ACI_E_INVALID, "the dataset records plain FP64 sweeps");
+  o.use_graph = 0;
+  RecordSpec rs;
+  rs.X = X;
+  rs.y = y;
+  rs.capacity = capacity;
+  aci_session* S = nullptr;
+  int rc = session_create(ctx, inputs, n_inputs, ACI_F64, op, tol, maxrank, &o, Placement{}, &S, &rs);
+  if (rc < 0) return rc;
+  rc = aci_session_sweep(S, o.maxiter, nullptr);
+  long long cnt[2] = {0, 0};
+  if (rc >= 0) {
+    const hipError_t e1 = hipMemcpyAsync(cnt, S->plan->rec_count, sizeof cnt, hipMemcpyDeviceToHost, ctx->stream);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(ctx->stream) : e1;
+    if (e2 != hipSuccess) rc = set_err(ctx, ACI_E_HIP, std::string("dataset count: ") + hipGetErrorString(e2));
+  }
+  if (sweeps) *sweeps = S->sweeps;
+  aci_session_destroy(S);
+  if (rc < 0) return rc;
+  *count = cnt[0];
+  if (cnt[1]) return set_err(ctx, ACI_E_NOMEM, "dataset capacity reached; count holds the rows of the updates that fit");
+  return rc;
 }
 
 int aci_mlp_forward(aci_ctx* ctx, const float* params, const float* X, int32_t count, float* scores) {

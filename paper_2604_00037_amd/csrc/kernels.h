@@ -196,6 +196,10 @@ struct CommitArgs {
   int *meta, *meta2;
   Dim m, n;
   int maxrank;
+  // optional: scan_total[0] += *src_scans, scan_total[1] += *src_rank (every
+  // proposal, accepted or not)
+  const int* src_scans;
+  int* scan_total;
 };
 
 // dst[0 .. *rank) = src, *dst_rank = *rank
@@ -205,6 +209,22 @@ struct CopyRowsArgs {
   int* dst;
   int* dst_rank;
   int maxrank;
+};
+
+// Appends one local update's rows to a training set of the scoring network:
+// X[count + i] = feat[i] (7 floats), y[count + i] = 1 for the first
+// max(1, rank / 2) pivot rows, else 0, for i < m; then count += m.  An update
+// that would pass `capacity` writes nothing and sets count[1] (and so does
+// every later one).
+struct RecordArgs {
+  const float* feat;    // m x 7 features of the update
+  Dim m;
+  const int* rows;      // pivot rows of the update, in pivot order
+  const int* rank;
+  float* X;             // capacity x 7
+  float* y;             // capacity
+  int64_t capacity;
+  long long* count;     // [0] rows so far, [1] overflow flag
 };
 
 struct SolveArgs {
@@ -226,6 +246,7 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t s);
 hipError_t launch_rook_solve(const SolveArgs& a, hipStream_t s);
 hipError_t launch_commit(const CommitArgs& a, hipStream_t s);
 hipError_t launch_copy_rows(const CopyRowsArgs& a, hipStream_t s);
+hipError_t launch_record(const RecordArgs& a, hipStream_t s);
 
 // ----------------------------------------------------------------- gathers
 struct GatherItem {

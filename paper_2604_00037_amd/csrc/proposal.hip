@@ -422,6 +422,10 @@ __global__ __launch_bounds__(NT) void check_kernel(CheckArgs a) {
 }
 
 __global__ void commit_kernel(CommitArgs a) {
+  if (a.scan_total && threadIdx.x == 0) {
+    a.scan_total[0] += *a.src_scans;
+    a.scan_total[1] += *a.src_rank;
+  }
   if (!*a.accepted) return;
   const int r = *a.src_rank;
   for (int k = threadIdx.x; k < r && k < a.maxrank; k += blockDim.x) {
@@ -451,6 +455,29 @@ __global__ void copy_rows_kernel(CopyRowsArgs a) {
   const int r = *a.rank;
   for (int k = threadIdx.x; k < r && k < a.maxrank; k += blockDim.x) a.dst[k] = a.src[k];
   if (threadIdx.x == 0) *a.dst_rank = r < a.maxrank ? r : a.maxrank;
+}
+
+// Training rows of one local update (one workgroup): features and pivot
+// labels appended at the dataset's current end.
+__global__ __launch_bounds__(NT) void record_kernel(RecordArgs a) {
+  const long long off = a.count[0];
+  const int m = dget(a.m);
+  if (a.count[1] != 0 || off + m > a.capacity) {
+    if (threadIdx.x == 0) a.count[1] = 1;
+    return;
+  }
+  for (int i = threadIdx.x; i < m; i += NT) {
+    for (int f = 0; f < NF; ++f) a.X[(size_t)(off + i) * NF + f] = a.feat[(size_t)i * NF + f];
+    a.y[off + i] = 0.f;
+  }
+  __syncthreads();
+  const int r = *a.rank;
+  const int npos = r / 2 > 1 ? r / 2 : 1;
+  for (int k = threadIdx.x; k < npos && k < r; k += NT) {
+    const int i = a.rows[k];
+    if (i >= 0 && i < m) a.y[off + i] = 1.f;
+  }
+  if (threadIdx.x == 0) a.count[0] = off + m;
 }
 
 // ------------------------------------------------------- right factor
@@ -515,6 +542,11 @@ hipError_t launch_commit(const CommitArgs& a, hipStream_t s) {
 
 hipError_t launch_copy_rows(const CopyRowsArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(copy_rows_kernel, dim3(1), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_record(const RecordArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(record_kernel, dim3(1), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 

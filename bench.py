@@ -707,6 +707,71 @@ def time_contract(aci, device):
             "calls_per_case": list(CONTRACT_REPS)}
 
 
+MFMA_COUNTERS = ["MfmaUtil", "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+                 "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE"]
+
+
+def _counter_table(directory):
+    """{dispatch id: (kernel, {counter: value})} of a rocprofv3 --pmc run."""
+    import csv
+    import glob
+    out = {}
+    for fn in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                k = row["Kernel_Name"].replace("void aci::(anonymous namespace)::", "").replace(
+                    "aci::(anonymous namespace)::", "").split("(")[0]
+                d = out.setdefault(int(row["Dispatch_Id"]), (k, {}))
+                d[1][row["Counter_Name"]] = d[1].get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    return out
+
+
+def _mfma_row(label, kernel, recs, flops):
+    """One table row: means over the dispatches `recs` of the matrix-core
+    busy share (MfmaUtil: MFMA busy cycles over active cycles x SIMDs), the
+    flops the MFMA op counters imply (512 per op) against the algorithmic
+    flops, and LDS bank conflicts per active LDS cycle."""
+    n = len(recs)
+    mean = lambda c: sum(r.get(c, 0.0) for r in recs) / max(n, 1)   # noqa: E731
+    mops = sum(mean(c) for c in MFMA_COUNTERS[1:4]) * 512
+    lds = mean("SQ_LDS_IDX_ACTIVE")
+    conf = mean("SQ_LDS_BANK_CONFLICT")
+    ratio = f"{mops / flops:.2f}" if flops else "-"
+    return (f"| {label} | `{kernel}` | {n} | {mean('MfmaUtil'):.1f} | {mops / 1e6:.1f} | {ratio} | "
+            f"{100 * conf / lds if lds else 0.0:.1f} |")
+
+
+MFMA_HEADER = ["| case | kernel | dispatches | MFMA busy (% of SIMD cycles) | MFMA MFLOP per dispatch "
+               "(ops x 512) | counted / algorithmic flops | LDS bank conflicts (% of LDS cycles) |",
+               "|---|---|---|---|---|---|---|"]
+
+
+def summarize_mfma(directory, mode):
+    """Matrix-core counters of the contraction kernels from a rocprofv3 --pmc
+    run: per case of `--only contract` (mode "contract"), or per kernel
+    instance over a run of the main workload (mode "sweep")."""
+    tab = _counter_table(directory)
+    ids = sorted(i for i, (k, _) in tab.items() if "contract" in k)
+    out = list(MFMA_HEADER)
+    if mode == "contract":
+        warm, timed = CONTRACT_REPS
+        i = 0
+        for (m, k, n, cx, terms) in CONTRACT_CASES:
+            for prec, _ in CONTRACT_PRECS:
+                grp = ids[i:i + warm + timed][warm:]
+                i += warm + timed
+                flops = terms * 2.0 * m * k * n * (4 if cx else 1) * (3 if prec == "bf16x3" else 1)
+                out.append(_mfma_row(f"{m} x {k} x {n} {'complex' if cx else 'real'} {prec}", tab[grp[-1]][0],
+                                     [tab[d][1] for d in grp], flops))
+    else:
+        by = {}
+        for d in ids:
+            by.setdefault(tab[d][0], []).append(tab[d][1])
+        for kname, recs in sorted(by.items(), key=lambda kv: -len(kv[1])):
+            out.append(_mfma_row("sweep", kname, recs, 0.0))
+    return "\n".join(out)
+
+
 def summarize_contract(directory):
     """Per-case kernel time of a traced `--only contract` run."""
     import csv
@@ -818,6 +883,8 @@ def main():
     ap.add_argument("--only", choices=["gp", "batched", "contract", "tci", "step", "patched", "tts", "proposal"],
                     help="run just one section and print its JSON (for profiling that workload)")
     ap.add_argument("--summarize-contract", metavar="DIR", help="per-case table of a traced --only contract run")
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("DIR", "MODE"),
+                    help="matrix-core counters of a --pmc run (MODE contract: per --only contract case; sweep)")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="table of the library kernels of a rocprofv3 --stats run")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
@@ -837,6 +904,9 @@ def main():
         return
     if args.summarize_contract:
         print(summarize_contract(args.summarize_contract))
+        return
+    if args.summarize_mfma:
+        print(summarize_mfma(*args.summarize_mfma))
         return
     if args.summarize_stats:
         print("\n".join(kernel_stats_table(args.summarize_stats)))

@@ -318,10 +318,43 @@ def time_mode(aci, inputs, precision, steps, warmup, ref_values=None):
             "ranks": st["ranks"]}
 
 
+def mpo_velocity_set(aci, device, R=10, kmax=KMAX, seeds=(3001, 3002, 3003), chi_u=(64, 96, 128),
+                     chi_du=(128, 192, 256), unit_rms=False):
+    """Velocity components u_j (3D Fourier fields, rank chi_u[j]) and their
+    derivatives d_j u_k by the library's central-difference MPO
+    (aci_mpo_stencil with weights (-1, 0, 1) / 2h along axis j, applied by
+    aci_mpo_apply: exact, rank 3 chi_u[k]), rounded by QR + SVD to rank
+    chi_du[(j + k) % 3] (chi_du None: rounded at 1e-14 only).  With
+    unit_rms every derivative is scaled to RMS 1 at 4096 sampled points (as
+    the fields are), so that an absolute tolerance is a relative one for the
+    products too.  Returns (u, du) as device cores, du[j][k] = d u_k / d x_j
+    (times its scale)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    h = 2.0 ** -R
+    u = []
+    for j, s in enumerate(seeds):
+        u.append([torch.from_numpy(c).to(device) for c in W.fourier3d_field(R, kmax, chi_u[j], s, device)])
+    du = [[None] * 3 for _ in range(3)]
+    for j in range(3):
+        D = aci.mpo_stencil(R, 3, j, (-0.5 / h, 0.0, 0.5 / h), device=device)
+        for k in range(3):
+            exact = [c.cpu().numpy() for c in aci.mpo_apply(D, u[k])]
+            cap = chi_du[(j + k) % 3] if chi_du else 1 << 30
+            r = W.tt_round(exact, cap, rtol=1e-14)
+            if unit_rms:
+                pts = np.random.default_rng(97).integers(0, 2, (4096, len(r)))
+                r[0] = r[0] / np.sqrt(np.mean(W.tt_eval(r, pts) ** 2))
+            du[j][k] = [torch.from_numpy(np.ascontiguousarray(c)).to(device) for c in r]
+    return u, du
+
+
 def time_batched(aci, steps, warmup, device):
     """The nine convective products u_j * d_j u_k (three velocity components
-    of the same random Fourier kind, central-difference derivatives, uneven ranks
-    64..256), tol 1e-8, output rank cap 256: sweeps of the whole set per
+    of the same random Fourier kind, derivatives by the library's
+    central-difference MPO then rounded, uneven ranks 64..256), tol 1e-8,
+    output rank cap 256: sweeps of the whole set per
     second as one joint batch (one LDU launch per local update for all nine
     products, each on its own XCD, the sweep captured in a graph), as an
     overlapped batch (one stream per product), and with the same sessions
@@ -330,12 +363,12 @@ def time_batched(aci, steps, warmup, device):
     import torch
     import workloads as W
     t = time.perf_counter()
-    u, du = W.velocity_set(R=10, kmax=KMAX, device=device)
+    u, du = mpo_velocity_set(aci, device)
     log(f"velocity set generated in {time.perf_counter() - t:.1f} s")
     products = []
     for j in range(3):
         for k in range(3):
-            products.append([[torch.from_numpy(c).to(device) for c in x] for x in (u[j], du[j][k])])
+            products.append([u[j], du[j][k]])
     ranks_in = sorted({max(c.shape[2] for c in x) for p in products for x in p})
     total = steps + warmup
     kw = dict(maxiter=total, seed=INIT_SEED, fixed_sweeps=True)
@@ -365,7 +398,8 @@ def time_batched(aci, steps, warmup, device):
         S.close()
     log(f"batched: {steps} sweeps of 9 products in {batched:.3f} s (joint); one after another {seq:.3f} s")
     return {"workload": "u_j * d_j u_k, j,k = 1..3: 9 products of 3D Fourier velocity fields (|k|<=32) and "
-                        "their central differences, 1024^3 grid, L=30 d=2, input ranks "
+                        "their central differences (TT finite-difference MPO, then rounded), 1024^3 grid, L=30 "
+                        "d=2, input ranks "
                         f"{ranks_in}, tol {TOL}, rank cap 256, FP64",
             "products": len(products), "sweeps_per_s": steps / batched,
             "product_sweeps_per_s": len(products) * steps / batched,
@@ -571,17 +605,23 @@ _TTS = {}
 
 
 def time_to_solution(aci, device, kmax=2):
-    """A product that reaches the tolerance: u*v of two random 3D Fourier
-    fields with |k| <= kmax (same recipe as the main workload otherwise:
-    1024^3 grid, L=30, seeds 2001/2002), compressed at rank cap 256 (exact
-    to 1e-14), tol 1e-8, rank cap 256.  Time to solution = initialisation +
-    the sweeps until the sampled relative error of the output against u*v
-    at 4096 points is within tol + the output cores; each sweep and each
-    output are timed on their own, the error check between sweeps is not.
-    (Alg. 1's own test asks in addition for ranks that did not grow, which a
-    bond whose last pivot sits at tol can keep failing; the per-bond error
-    estimates reach tol before the index sets are good enough, so neither
-    is the stop here.)"""
+    """Time to a common accuracy: u*v of two random 3D Fourier fields with
+    |k| <= kmax (same recipe as the main workload otherwise: 1024^3 grid,
+    L=30, seeds 2001/2002), compressed at rank cap 256 (exact to 1e-14), tol
+    1e-8, rank cap 256.  Time to solution = initialisation + the sweeps until
+    the sampled relative error of the output against u*v at 4096 points is
+    within tol + the output cores; each sweep and each output are timed on
+    their own, the error check between sweeps is not.  (Alg. 1's own test
+    asks in addition for ranks that did not grow, which a bond whose last
+    pivot sits at tol can keep failing; the per-bond error estimates reach
+    tol before the index sets are good enough, so neither is the stop here.)
+    Modes, all to the same sampled error: plain FP64 sweeps (eager, and
+    replayed from a captured graph), the FP32 and BF16x3 precision ladders
+    (low-precision contractions, then FP64 sweeps), and the learned pivot
+    proposal (network trained from the library's own sweeps on other fields
+    of the same kind); plus nine convective products of |k| <= 1 velocity
+    fields with derivatives by the library's finite-difference MPO, as one
+    joint batch against the same products solved one after another."""
     import numpy as np
     import torch
     import workloads as W
@@ -590,7 +630,6 @@ def time_to_solution(aci, device, kmax=2):
     inputs = [[torch.from_numpy(c).to(device) for c in x] for x in (u, v)]
     pts = np.random.default_rng(96).integers(0, 2, (4096, L))
     f = W.tt_eval(u, pts) * W.tt_eval(v, pts)
-    scale = np.abs(f).max()
 
     def clock(fn):
         torch.cuda.synchronize()
@@ -599,33 +638,113 @@ def time_to_solution(aci, device, kmax=2):
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
-    def solve():
-        S, t_init = clock(lambda: aci.Session(inputs, "product", TOL, 256, maxiter=20, seed=INIT_SEED))
+    def sampled(cores, fx):
+        return float(np.abs(W.tt_eval([c.cpu().numpy() for c in cores], pts) - fx).max() / np.abs(fx).max())
+
+    def solve(make, fx):
+        S, t_init = clock(make)
         total, trace = t_init, []
         for k in range(1, 21):
             st, t_sw = clock(lambda: S.sweep(1))
             (cores, info), t_out = clock(S.result)
-            err = float(np.abs(W.tt_eval([c.cpu().numpy() for c in cores], pts) - f).max() / scale)
+            err = sampled(cores, fx)
             total += t_sw
             trace.append({"sweep": k, "max_eps": st["max_eps"], "sampled_rel_error": err,
-                          "alg1_converged": bool(st["converged"]), "max_rank": max(st["ranks"])})
-            if err <= TOL:
+                          "alg1_converged": bool(st["converged"]), "max_rank": max(st["ranks"]),
+                          "precision": st["last_precision"]})
+            if err <= TOL and st["last_precision"] == "fp64":
                 break
         S.close()
         return total + t_out, t_init, trace
 
-    solve()                                   # warm-up (code objects, allocator)
-    runs = [solve() for _ in range(3)]
-    runs.sort(key=lambda r: r[0])
-    total, t_init, trace = runs[1]
-    last = trace[-1]
+    def median_of(make, fx, runs=3):
+        solve(make, fx)                       # warm-up (code objects, allocator, graph capture)
+        rs = sorted((solve(make, fx) for _ in range(runs)), key=lambda r: r[0])
+        total, t_init, trace = rs[len(rs) // 2]
+        last = trace[-1]
+        return {"seconds_median": total, "init_seconds": t_init, "sweeps": len(trace),
+                "reached": last["sampled_rel_error"] <= TOL, "sampled_rel_error": last["sampled_rel_error"],
+                "max_rank": last["max_rank"], "per_sweep": trace}
+
+    common = dict(maxiter=20, seed=INIT_SEED)
     out = {"workload": f"u*v of two 3D Fourier fields with |k|<={kmax}, 1024^3 grid, L=30 d=2, input ranks "
-                       f"{max(c.shape[2] for c in u)}/{max(c.shape[2] for c in v)}, tol {TOL}, rank cap 256, FP64",
-           "seconds_median": total, "init_seconds": t_init, "sweeps": len(trace),
-           "reached": last["sampled_rel_error"] <= TOL, "per_sweep": trace}
+                       f"{max(c.shape[2] for c in u)}/{max(c.shape[2] for c in v)}, tol {TOL}, rank cap 256"}
+    modes = {}
+    modes["fp64"] = median_of(lambda: aci.Session(inputs, "product", TOL, 256, **common), f)
+    modes["fp64_graph"] = median_of(lambda: aci.Session(inputs, "product", TOL, 256, use_graph=True, **common), f)
+    for prec in ("fp32", "bf16x3"):
+        modes[prec + "_ladder"] = median_of(
+            lambda: aci.Session(inputs, "product", TOL, 256, precision=prec, use_graph=True, **common), f)
+    # learned proposal: network trained from the library's own FP64 sweeps on two other products
+    Xs, ys = [], []
+    for sd in (4001, 4003):
+        a, b = W.fourier3d_pair(R=10, kmax=kmax, chi=256, seeds=(sd, sd + 1), device=device)
+        X, y, _ = aci.proposal_dataset([[torch.from_numpy(c).to(device) for c in x] for x in (a, b)], "product",
+                                       TOL, 256, maxiter=3, seed=sd, capacity=1 << 19)
+        Xs.append(X)
+        ys.append(y)
+    X, y = torch.cat(Xs), torch.cat(ys)
+    p = aci.mlp_init(7, device=device)
+    m_, v_ = torch.zeros_like(p), torch.zeros_like(p)
+    rng = np.random.default_rng(0)
+    for step in range(1, 301):
+        idx = torch.from_numpy(rng.choice(X.shape[0], 512, replace=False)).to(device)
+        aci.mlp_train_step(p, m_, v_, step, X[idx].contiguous(), y[idx].contiguous(), lr=3e-3)
+    modes["proposal"] = median_of(lambda: aci.Session(inputs, "product", TOL, 256, proposal=p, **common), f, runs=1)
+    modes["proposal"]["training_rows"] = int(X.shape[0])
+    base = modes["fp64"]["seconds_median"]
+    for name, r in modes.items():
+        r["vs_fp64"] = base / r["seconds_median"]
+        log(f"time to solution {name}: {r['seconds_median'] * 1e3:.1f} ms ({r['sweeps']} sweeps, sampled rel error "
+            f"{r['sampled_rel_error']:.2e}, {r['vs_fp64']:.2f}x plain FP64)")
+    out.update(modes["fp64"])
+    out["modes"] = modes
+
+    # nine convective products of |k| <= kmax velocity fields, derivatives by the library's MPO (exact, rank 3r,
+    # rounded at 1e-14)
+    # |k| <= 1 velocity fields: with |k| <= 2 the products have up to 128 modes (rank up to 256 at the middle
+    # bonds) and the derivative weights the high ones up, so rank cap 256 stops them near 2e-8
+    kb = min(kmax, 1)
+    uu, du = mpo_velocity_set(aci, device, kmax=kb, chi_u=(256, 256, 256), chi_du=None, unit_rms=True)
+    prods = [[uu[j], du[j][k]] for j in range(3) for k in range(3)]
+    fx = [W.tt_eval([c.cpu().numpy() for c in uu[j]], pts) * W.tt_eval([c.cpu().numpy() for c in du[j][k]], pts)
+          for j in range(3) for k in range(3)]
+
+    def solve_batch():
+        B, t_init = clock(lambda: aci.Batch(prods, "product", TOL, 256, use_graph=True, **common))
+        total, done, sweeps, errs = t_init, [False] * 9, 0, [1.0] * 9
+        for k in range(1, 21):
+            _, t_sw = clock(lambda: B.sweep(1))
+            total += t_sw
+            sweeps = k
+            t_out = 0.0
+            for b in range(9):
+                (cores, _), t1 = clock(lambda: B.result(b))
+                t_out += t1
+                errs[b] = sampled(cores, fx[b])
+            if max(errs) <= TOL:
+                break
+        B.close()
+        return total + t_out, sweeps, max(errs)
+
+    solve_batch()
+    rb = sorted((solve_batch() for _ in range(3)), key=lambda r: r[0])[1]
+    seq = 0.0
+    seq_err = 0.0
+    for b in range(9):
+        r = median_of(lambda: aci.Session(prods[b], "product", TOL, 256, use_graph=True, **common), fx[b], runs=1)
+        seq += r["seconds_median"]
+        seq_err = max(seq_err, r["sampled_rel_error"])
+    ranks_in = sorted({max(c.shape[2] for c in x) for p_ in prods for x in p_})
+    out["batch"] = {"workload": f"u_j * d_j u_k, j,k = 1..3, |k|<={kb} velocity fields (ranks "
+                                f"{ranks_in}) with derivatives by the library's central-difference MPO (scaled to RMS 1), "
+                                f"tol {TOL}, rank cap 256",
+                    "joint_seconds_median": rb[0], "joint_sweeps": rb[1], "joint_max_sampled_rel_error": rb[2],
+                    "sequential_seconds": seq, "sequential_max_sampled_rel_error": seq_err,
+                    "speedup_vs_sequential": seq / rb[0]}
+    log(f"time to solution, 9 products: joint batch {rb[0] * 1e3:.1f} ms ({rb[1]} sweeps, max sampled error "
+        f"{rb[2]:.2e}); one after another {seq * 1e3:.1f} ms: {seq / rb[0]:.2f}x")
     _TTS["inputs"] = (u, v, pts, f)
-    log(f"time to solution: {total * 1e3:.1f} ms (init {t_init * 1e3:.1f} ms, {len(trace)} sweeps, ranks <= "
-        f"{last['max_rank']}, max eps {last['max_eps']:.2e}, sampled rel error {last['sampled_rel_error']:.2e})")
     return out
 
 

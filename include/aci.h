@@ -115,8 +115,11 @@ typedef struct {
                             never count as converged; the sweeps switch to FP64
                             after a low-precision sweep that kept the
                             right-to-left ranks, or after low_precision_sweeps
-                            of them.  aci_elementwise always ends with an FP64
-                            sweep. */
+                            of them.  In a low-precision sweep the LDU stops at
+                            max(tol, floor |first pivot|) with floor
+                            32 x 2^-24 (FP32) or 4 x 2^-15 (BF16X3), the
+                            noise of its two-site matrix.  aci_elementwise
+                            always ends with an FP64 sweep. */
   int32_t trace;         /* 1: record the pivots of every local update */
   int32_t fixed_sweeps;  /* 1: run exactly maxiter sweeps, no early exit */
   int32_t profile;       /* 1: time every kernel launch with HIP events

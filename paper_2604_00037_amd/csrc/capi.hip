@@ -85,6 +85,11 @@ static void dev_free(aci_ctx* ctx, void* p) {
 namespace {
 
 constexpr uint32_t kSpinLimit = 1u << 22;   // polls before an exchange gives up (default)
+// Noise floors of the precision ladder's low-precision sweeps, relative to
+// the largest entry of the two-site matrix: 32 units of FP32 rounding, and
+// 4 x 2^-15 for BF16x3 (operands split to about 16 significant bits).
+constexpr double kNoiseFP32 = 32.0 * 0x1.0p-24;
+constexpr double kNoiseBF16X3 = 4.0 * 0x1.0p-15;
 
 // The exchange-wait settings of the context on an LDU launch.
 void exchange_waits(const aci_ctx* c, PrrluArgs& a) {
@@ -347,6 +352,7 @@ struct Enq {
   int rec = 0;          // prrLU calls so far (trace record index)
   int slot = 0;         // meta slot: init calls 0..L-2, sweep calls L-1 ..
   Prof* prof = nullptr;
+  bool sweeping = false;  // enqueuing the local updates of a sweep (not the initialisation)
   // deferred LDU: prrlu() only records its arguments (a batch launches the
   // LDUs of all its products together)
   bool defer = false;
@@ -392,6 +398,9 @@ struct Enq {
     a.n = n;
     a.ldm = ldm;
     a.tol = p.tol;
+    // low-precision sweeps of the ladder stop at the contraction's noise
+    // floor instead of factorising its rounding errors
+    a.tol_rel = !sweeping ? 0.0 : (p.prec == PREC_FP32 ? kNoiseFP32 : (p.prec == PREC_BF16X3 ? kNoiseBF16X3 : 0.0));
     a.maxrank = p.maxrank;
     a.rule = p.rule;
     a.flag_base = 0;
@@ -891,6 +900,7 @@ int enqueue_sweep(Enq& q) {
   aci_ctx* ctx = q.ctx;
   Plan& p = q.p;
   q.slot = p.L - 1;
+  q.sweeping = true;
   if (p.mlp) ENQ(launch_fill_int(p.acc_count, 3, 0, q.s));
   for (int u = 0; u < 2 * (p.L - 1); ++u)
     for (int stage = 0; stage < 2; ++stage)
@@ -2099,6 +2109,7 @@ int joint_enqueue(aci_batch* B, const std::vector<int>& ids, bool timed) {
     if (timed) HIPCHK(hipEventRecord(S->e0, B->streams[b]));
     qs.push_back(Enq{B->ctxs[b], *S->plan, B->streams[b], S->rec, L - 1, &S->prof});
     qs.back().defer = true;
+    qs.back().sweeping = true;
   }
   const int cnt = (int)ids.size();
   std::vector<PrrluArgs> args(cnt);

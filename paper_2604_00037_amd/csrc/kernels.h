@@ -54,6 +54,10 @@ struct PrrluArgs {
   const double* M;
   Dim m, n, ldm;
   double tol;
+  // noise floor relative to the first pivot (0: none): the stop rules
+  // compare pivots with max(tol, tol_rel |first pivot|), for two-site
+  // tensors contracted in low precision
+  double tol_rel;
   int maxrank;
   int rule;
   int P;            // cooperating workgroups

@@ -289,6 +289,7 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   int k = 0;
   double eps = 0.0;
   int final_rank = 0;
+  double tol = a.tol;   // raised to the noise floor after the first pivot
   while (true) {
     if (k == kmax) {
       if (a.rule == RULE_EXCLUSIVE) eps = 0.0;
@@ -489,9 +490,10 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
     const int ql = q & 63;
 
     // ---- stop rules
+    if (k == 0) tol = fmax(a.tol, a.tol_rel * v);
     if (a.rule == RULE_EXCLUSIVE) {
       if (k == a.maxrank) { eps = v; final_rank = k; break; }
-      if (k >= 1 && v <= a.tol) { eps = v; final_rank = k; break; }
+      if (k >= 1 && v <= tol) { eps = v; final_rank = k; break; }
     } else if (k >= 1 && v == 0.0) {
       eps = 0.0;
       final_rank = k;
@@ -652,7 +654,7 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
     ++k;
     if (a.rule == RULE_LITERAL) {
       eps = v;
-      if (v <= a.tol || k == a.maxrank) {
+      if (v <= tol || k == a.maxrank) {
         final_rank = k;
         break;
       }

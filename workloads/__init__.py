@@ -13,6 +13,7 @@ from .tt import (
     tt_full,
     tt_eval,
     tt_svd,
+    tt_round,
     tt_ranks,
     tt_scale,
 )
@@ -31,6 +32,7 @@ from .fields import (
 from .configs import (
     random_pair,
     fourier3d_pair,
+    fourier3d_field,
     gp_field,
     random_init,
     velocity_set,
@@ -39,10 +41,10 @@ from .configs import (
 
 __all__ = [
     "random_tt", "left_orthogonalise", "tt_full", "tt_eval", "tt_svd",
-    "tt_ranks", "tt_scale",
+    "tt_ranks", "tt_scale", "tt_round",
     "quantics_points_1d", "quantics_to_grid", "grid_to_quantics",
     "gaussian_pair_full", "fourier1d_coeffs", "fourier1d_full",
     "fourier1d_product_coeffs", "fourier3d_modes", "fourier3d_full",
     "gp_vortex_full",
-    "random_pair", "fourier3d_pair", "gp_field", "random_init", "velocity_set", "min_ranks",
+    "random_pair", "fourier3d_pair", "fourier3d_field", "gp_field", "random_init", "velocity_set", "min_ranks",
 ]

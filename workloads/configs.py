@@ -72,6 +72,12 @@ def fourier3d_pair(R=10, kmax=32, chi=128, seeds=(2001, 2002), device=None, prog
     return tuple(out)
 
 
+def fourier3d_field(R=10, kmax=32, chi=128, seed=2001, device=None):
+    """One random 3D Fourier field of the main recipe compressed to rank chi."""
+    g = fourier3d_full(R, kmax, seed, device=device)
+    return _compress(g, R, 3, chi, device)
+
+
 def gp_field(R=14, chi=512, seed=5001, device=None, width_scale=1.0, waves=0, kmax=48):
     g = gp_vortex_full(R, seed, device=device, width_scale=width_scale, waves=waves, kmax=kmax)
     return _compress(g, R, 2, chi, device)

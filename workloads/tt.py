@@ -57,6 +57,30 @@ def left_orthogonalise(cores):
     return out
 
 
+def tt_round(cores, maxrank, rtol=0.0):
+    """TT rounding by QR and truncated SVD (I. Oseledets, TT-decomposition,
+    2011): right-to-left orthogonalisation, then a left-to-right sweep that
+    keeps at most ``maxrank`` singular values per bond and drops those below
+    ``rtol`` times the largest.  Returns new cores (the same tensor when no
+    value is dropped)."""
+    cores = [np.asarray(c) for c in cores]
+    L = len(cores)
+    out = [c.copy() for c in cores]
+    for s in range(L - 1, 0, -1):
+        r0, d, r1 = out[s].shape
+        q, r = np.linalg.qr(out[s].reshape(r0, d * r1).T, mode="reduced")
+        out[s] = np.ascontiguousarray(q.T.reshape(q.shape[1], d, r1))
+        out[s - 1] = np.einsum("asb,bc->asc", out[s - 1], r.T)
+    for s in range(L - 1):
+        r0, d, r1 = out[s].shape
+        u, sv, vt = np.linalg.svd(out[s].reshape(r0 * d, r1), full_matrices=False)
+        keep = int(min(maxrank, max(1, np.count_nonzero(sv > rtol * sv[0])))) if sv[0] > 0 else 1
+        out[s] = np.ascontiguousarray(u[:, :keep].reshape(r0, d, keep))
+        out[s + 1] = np.einsum("ab,bsc->asc", sv[:keep, None] * vt[:keep], out[s + 1])
+    out[-1] = np.ascontiguousarray(out[-1])
+    return out
+
+
 def tt_scale(cores, factor):
     out = [c.copy() for c in cores]
     out[0] = out[0] * factor

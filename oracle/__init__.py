@@ -15,6 +15,8 @@ the algorithms of Appendix B of the paper in their order:
 * ``left_frame``, ``right_frame``         -- Alg. 5 / Eq. (framesrecursive)
 * ``aci``             -- Alg. 1 (initialisation, sweeps, convergence)
 * ``splitmix64``      -- the counter-based generator of the default Y_init
+* ``sketch``          -- random index sketch as the initial guess (the
+                         RSI-style start of Sec. 2.8)
 * ``reference``       -- exact Kronecker-delta product and SVD rounding,
                          an independent route to the Hadamard product
 * ``proposal``        -- extension: row features, the small scoring network
@@ -38,6 +40,7 @@ from .prrlu import prrlu, PrrLU
 from .ci import cross_interpolate, local_update, left_frame, right_frame
 from .aci import aci, ACIResult, apply_op, default_init_ranks
 from .splitmix import splitmix64_stream, default_init
+from .sketch import sketch_init, sketch_ranks
 from . import reference
 from . import proposal
 from .tci import tci, TCIResult, two_site_points
@@ -47,6 +50,6 @@ from . import patched
 __all__ = [
     "prrlu", "PrrLU", "cross_interpolate", "local_update", "left_frame",
     "right_frame", "aci", "ACIResult", "apply_op", "default_init_ranks",
-    "splitmix64_stream", "default_init", "reference", "proposal",
+    "splitmix64_stream", "default_init", "sketch_init", "sketch_ranks", "reference", "proposal",
     "tci", "TCIResult", "two_site_points", "timestep", "patched",
 ]

@@ -43,6 +43,7 @@ import numpy as np
 
 from .ci import local_update, left_frame, right_frame
 from .prrlu import prrlu
+from .sketch import sketch_init
 from .splitmix import default_init
 
 OPS = ("product", "sum", "abs2_mul")
@@ -126,12 +127,14 @@ def _left_envs(inputs, Lf, l):
 
 
 def aci(inputs, op, tol, maxrank, maxiter=20, init=None, seed=0,
-        rule="exclusive", log_gaps=False, record=None):
+        rule="exclusive", log_gaps=False, record=None, sketch_rank=0):
     """Approximate f(x^1, ..., x^N) as a TT (Alg. 1).  ``inputs`` is a list
     of N TTs (lists of cores).  Returns an ``ACIResult``.  If ``record`` is
     a list, every local update appends its two-site matrix M, the left
     environments A^n and its pivots (training data of the learned
-    proposal)."""
+    proposal).  ``sketch_rank`` k > 0 (with no ``init``) starts from the
+    random index sketch of size k (``sketch.py``) instead of the default
+    random Y_init."""
     N = len(inputs)
     if N < 1:
         raise ValueError("need at least one input")
@@ -158,6 +161,8 @@ def aci(inputs, op, tol, maxrank, maxiter=20, init=None, seed=0,
     trace = []
 
     # ---- initialisation: CI-canonical form of Y_init, right to left
+    if init is None and sketch_rank > 0:
+        init = sketch_init(dims, sketch_rank, maxrank, seed, dtype=dtype)
     if init is None:
         init = default_init(default_init_ranks(inputs, maxrank), dims, seed, dtype=dtype)
     G = [np.array(c, dtype=dtype, copy=True) for c in init]

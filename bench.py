@@ -616,7 +616,9 @@ def time_to_solution(aci, device, kmax=2):
     pivot sits at tol can keep failing; the per-bond error estimates reach
     tol before the index sets are good enough, so neither is the stop here.)
     Modes, all to the same sampled error: plain FP64 sweeps (eager, and
-    replayed from a captured graph), the FP32 and BF16x3 precision ladders
+    replayed from a captured graph), FP64 sweeps started from a random index
+    sketch of size 128 or 256 (the RSI-style start), the FP32 and BF16x3
+    precision ladders
     (low-precision contractions, then FP64 sweeps), and the learned pivot
     proposal (network trained from the library's own sweeps on other fields
     of the same kind); plus nine convective products of |k| <= 1 velocity
@@ -672,6 +674,9 @@ def time_to_solution(aci, device, kmax=2):
     modes = {}
     modes["fp64"] = median_of(lambda: aci.Session(inputs, "product", TOL, 256, **common), f)
     modes["fp64_graph"] = median_of(lambda: aci.Session(inputs, "product", TOL, 256, use_graph=True, **common), f)
+    # RSI-style start: random index sketches of size k instead of the default Y_init (ranks = input ranks)
+    for k in (128, 256):
+        modes[f"sketch_{k}"] = median_of(lambda: aci.Session(inputs, "product", TOL, 256, sketch_rank=k, **common), f)
     for prec in ("fp32", "bf16x3"):
         modes[prec + "_ladder"] = median_of(
             lambda: aci.Session(inputs, "product", TOL, 256, precision=prec, use_graph=True, **common), f)

@@ -155,6 +155,21 @@ typedef struct {
   const double* coef;           /* host, ACI_OP_LINEAR_CUBIC only: a1..aN, b;
                                    N+1 doubles for ACI_F64, N+1 (re, im)
                                    pairs for ACI_C128; copied at the call */
+  int32_t sketch_rank;          /* k > 0 with init NULL: start from a random
+                                   index sketch of size k (the RSI-style start
+                                   of Sec. 2.8) instead of the default Y_init:
+                                   bond ranks rho_l = min(k, maxrank,
+                                   d_1..d_l, d_{l+1}..d_L); for sites
+                                   l = L..1, rho_{l-1} of the d_l rho_l
+                                   columns (sigma, b), id sigma rho_l + b, are
+                                   drawn without replacement from one
+                                   SplitMix64(seed) stream by a partial
+                                   Fisher-Yates shuffle (j = s + z mod (n - s),
+                                   swap, take a[s]), and core l is zero except
+                                   (1 - s 2^-11) / (1 - b 2^-11) at row s and
+                                   its drawn column, so that the initialisation
+                                   selects exactly the drawn index points;
+                                   0: off */
 } aci_options;
 
 /* Result of aci_elementwise.  Output cores are written compactly, site after

@@ -89,6 +89,7 @@ class AciOptions(C.Structure):
         ("pointwise", C.c_void_p),
         ("pointwise_user", C.c_void_p),
         ("coef", C.POINTER(C.c_double)),
+        ("sketch_rank", C.c_int32),
     ]
 
 

@@ -226,8 +226,9 @@ def _raise_pointwise(keep):
 
 
 def _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, profile,
-             low_precision_sweeps=0, use_graph=False, proposal=None, proposal_scans=0):
+             low_precision_sweeps=0, use_graph=False, proposal=None, proposal_scans=0, sketch_rank=0):
     opts = _lib.AciOptions()
+    opts.sketch_rank = int(sketch_rank)
     opts.low_precision_sweeps = int(low_precision_sweeps)
     opts.use_graph = 1 if use_graph else 0
     if proposal is not None:
@@ -311,7 +312,7 @@ def _unpack(res, out, dims, status, trace):
 
 def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
                 stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False,
-                low_precision_sweeps=0, proposal=None, proposal_scans=0, ctx=None):
+                low_precision_sweeps=0, proposal=None, proposal_scans=0, sketch_rank=0, ctx=None):
     """Alg. 1: returns (cores, info) with cores a list of device tensors of
     shape (r_{l-1}, d_l, r_l) approximating op(inputs) elementwise."""
     ctx = ctx or default_context()
@@ -319,7 +320,7 @@ def elementwise(inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed
     keep = []
     tts = _inputs(inputs, keep)
     opts = _options(keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps, False,
-                    low_precision_sweeps, False, proposal, proposal_scans)
+                    low_precision_sweeps, False, proposal, proposal_scans, sketch_rank)
     code = _op_code(op, opts, keep, _code(inputs[0][0]) == 1, len(inputs))
     out, cap = _out_buffer(inputs, maxrank)
     res = _lib.AciResult()
@@ -374,7 +375,7 @@ class Session:
     def __init__(self, inputs, op="product", tol=1e-12, maxrank=64, *, maxiter=20, seed=0, init=None,
                  stop_rule="exclusive", precision="fp64", trace=False, fixed_sweeps=False,
                  profile=False, low_precision_sweeps=0, use_graph=False, proposal=None, proposal_scans=0,
-                 tune=False, ctx=None):
+                 tune=False, sketch_rank=0, ctx=None):
         self.ctx = ctx or default_context()
         self.inputs = inputs            # the library reads these until close()
         self.maxrank = maxrank
@@ -382,7 +383,7 @@ class Session:
         self._keep = []
         tts = _inputs(inputs, self._keep)
         opts = _options(self._keep, maxiter, seed, init, stop_rule, precision, trace, fixed_sweeps,
-                        profile, low_precision_sweeps, use_graph, proposal, proposal_scans)
+                        profile, low_precision_sweeps, use_graph, proposal, proposal_scans, sketch_rank)
         opts.tune = 1 if tune else 0
         self._init = init
         h = C.c_void_p()

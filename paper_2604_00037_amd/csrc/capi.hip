@@ -176,6 +176,7 @@ struct Plan {
   int prec_req = PREC_FP64;   // requested contraction precision
   int prec = PREC_FP64;       // precision of the sweep being enqueued
   int low_max = 4;            // ladder: most low-precision sweeps (< 0: no limit)
+  int sketch = 0;             // size of the random index sketch that starts the sweeps (0: off)
   bool trace = false, fixed = false;
   // placement of the LDU launches (batches): XCD, group cap, launch kind
   int xcd = 0, max_groups = 0, cooperative = 1;
@@ -985,6 +986,7 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
   if (o.precision != ACI_PREC_FP64 && o.precision != ACI_PREC_FP32 && o.precision != ACI_PREC_BF16X3)
     return set_err(ctx, ACI_E_DTYPE, "unknown precision");
   if (o.stop_rule != 0 && o.stop_rule != 1) return set_err(ctx, ACI_E_INVALID, "stop_rule must be 0 or 1");
+  if (o.sketch_rank < 0) return set_err(ctx, ACI_E_INVALID, "sketch_rank must be >= 0");
   const int L = inputs[0].L;
   if (L < 2 || L > ACI_MAX_SITES) return set_err(ctx, ACI_E_LIMIT, "L out of range");
   p.L = L;
@@ -1039,6 +1041,11 @@ int plan_problem(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t d
       p.rho[l] = o.init->ranks[l];
       if (p.rho[l] > ACI_MAX_MATRIX) return set_err(ctx, ACI_E_LIMIT, "init rank above limit");
     }
+  } else if (o.sketch_rank > 0) {
+    // random index sketch: rho_l = min(k, maxrank, index points left and right of bond l)
+    p.sketch = o.sketch_rank;
+    p.rho[0] = p.rho[L] = 1;
+    for (int l = 1; l < L; ++l) p.rho[l] = std::min(std::min(o.sketch_rank, maxrank), std::min(p.capI[l], p.capJ[l + 1]));
   } else {
     p.rho[0] = p.rho[L] = 1;
     for (int l = 1; l < L; ++l) {
@@ -1372,7 +1379,30 @@ int session_create(aci_ctx* ctx, const aci_tt* inputs, int32_t n_inputs, int32_t
   HIPCHK(hipEventCreate(&S->e1));
   hipStream_t s = ctx->stream;
   const int L = p.L;
-  if (gen_init) {
+  if (gen_init && p.sketch > 0) {
+    // the random index sketch as a Y_init whose CI-canonical form selects
+    // exactly the drawn points: sites L..1, rho_{l-1} distinct columns of
+    // the d_l rho_l by partial Fisher-Yates, one non-zero per row
+    SplitMix64 rng{o.seed};
+    std::vector<double> h;
+    std::vector<int> a;
+    const double step = 0x1.0p-11;
+    for (int l = L; l >= 1; --l) {
+      const int r0 = p.rho[l - 1], r1 = p.rho[l], dl = p.d[l], n = dl * r1;
+      h.assign((size_t)p.ew * r0 * dl * r1, 0.0);
+      a.resize(n);
+      for (int i = 0; i < n; ++i) a[i] = i;
+      for (int s2 = 0; s2 < r0; ++s2) {
+        const int j = s2 + (int)(rng.next() % (uint64_t)(n - s2));
+        std::swap(a[s2], a[j]);
+        const int q = a[s2], b = q % r1;
+        h[(size_t)p.ew * ((size_t)s2 * n + q)] = (1.0 - s2 * step) / (1.0 - b * step);
+      }
+      HIPCHK(hipMemcpyAsync(p.Gin[l], h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+      p.Yin[l] = p.Gin[l];
+    }
+  } else if (gen_init) {
     SplitMix64 rng{o.seed};
     std::vector<double> h;
     for (int l = 1; l <= L; ++l) {

@@ -831,6 +831,54 @@ def time_contract(aci, device):
             "calls_per_case": list(CONTRACT_REPS)}
 
 
+def summarize_batch_gaps(directory, sweep_updates=58, warm=1, timed=2):
+    """Where the time of a joint batch sweep goes, from a kernel trace of
+    `--only batched --steps 6` (1 warm-up and 2 timed joint sweeps first):
+    over the timed joint sweeps (from the end of the warm-up sweep's last
+    batched LDU to the end of the last batched LDU), the share of the wall
+    time in which the batched LDU runs, in which some library kernel runs,
+    and in which none does (launch and dependency gaps: the most a single
+    persistent launch could take back)."""
+    import csv
+    import glob
+    fn = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)[0]
+    ks = []
+    with open(fn) as f:
+        for r in csv.DictReader(f):
+            if "aci::" in r["Kernel_Name"]:
+                ks.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    ks.sort()
+    ldu = [k for k in ks if "prrlu_batch_kernel" in k[2]][:sweep_updates * (warm + timed)]
+    t0 = ldu[sweep_updates * warm - 1][1]
+    t1 = ldu[-1][1]
+    inwin = [(max(a, t0), min(b, t1), n) for a, b, n in ks if b > t0 and a < t1]
+
+    def union(iv):
+        tot, cur_a, cur_b = 0, None, None
+        for a, b in sorted(iv):
+            if cur_b is None or a > cur_b:
+                if cur_b is not None:
+                    tot += cur_b - cur_a
+                cur_a, cur_b = a, b
+            else:
+                cur_b = max(cur_b, b)
+        if cur_b is not None:
+            tot += cur_b - cur_a
+        return tot
+    win = t1 - t0
+    busy = union([(a, b) for a, b, _ in inwin])
+    ldu_busy = union([(a, b) for a, b, n in inwin if "prrlu_batch_kernel" in n])
+    per_sweep = win / timed / 1e6
+    out = ["| quantity | ms per sweep | share of the sweep |", "|---|---|---|",
+           f"| wall time (timed joint sweeps) | {per_sweep:.2f} | 100 % |",
+           f"| batched LDU running | {ldu_busy / timed / 1e6:.2f} | {100 * ldu_busy / win:.1f} % |",
+           f"| some library kernel running | {busy / timed / 1e6:.2f} | {100 * busy / win:.1f} % |",
+           f"| no kernel running (gaps) | {(win - busy) / timed / 1e6:.2f} | {100 * (win - busy) / win:.1f} % |",
+           f"| other kernels only (contractions, gathers) | {(busy - ldu_busy) / timed / 1e6:.2f} | "
+           f"{100 * (busy - ldu_busy) / win:.1f} % |"]
+    return "\n".join(out)
+
+
 MFMA_COUNTERS = ["MfmaUtil", "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32",
                  "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE"]
 
@@ -1007,6 +1055,8 @@ def main():
     ap.add_argument("--only", choices=["gp", "batched", "contract", "tci", "step", "patched", "tts", "proposal"],
                     help="run just one section and print its JSON (for profiling that workload)")
     ap.add_argument("--summarize-contract", metavar="DIR", help="per-case table of a traced --only contract run")
+    ap.add_argument("--summarize-batch-gaps", metavar="DIR",
+                    help="busy and idle shares of the joint batch sweeps in a traced --only batched run")
     ap.add_argument("--summarize-mfma", nargs=2, metavar=("DIR", "MODE"),
                     help="matrix-core counters of a --pmc run (MODE contract: per --only contract case; sweep)")
     ap.add_argument("--summarize-stats", metavar="DIR",
@@ -1031,6 +1081,9 @@ def main():
         return
     if args.summarize_mfma:
         print(summarize_mfma(*args.summarize_mfma))
+        return
+    if args.summarize_batch_gaps:
+        print(summarize_batch_gaps(args.summarize_batch_gaps))
         return
     if args.summarize_stats:
         print("\n".join(kernel_stats_table(args.summarize_stats)))

@@ -1037,6 +1037,59 @@ def time_proposal(aci, device, steps=300):
     return out
 
 
+def time_proposal_c4(aci, device, n_train=8, steps=300):
+    """The learned proposal at the scale of the main workload (the fourth
+    configuration, scaled down in its training set): a network trained on
+    the GPU from the library's own FP64 sweeps (one sweep each) of products
+    of n_train pairs of 3D Fourier fields of the main recipe (L = 30, rank
+    128, seeds 4001..), used in the sweeps of held-out products at input
+    ranks 128, 192 and 256 (seeds 4501..), tol 1e-8, rank cap 256: seconds
+    per sweep and accepted proposals against the plain full-pivot sweep."""
+    import numpy as np
+    import torch
+    import workloads as W
+    t = time.perf_counter()
+    Xs, ys = [], []
+    for i in range(n_train):
+        u, v = W.fourier3d_pair(R=10, kmax=KMAX, chi=128, seeds=(4001 + 2 * i, 4002 + 2 * i), device=device)
+        X, y, _ = aci.proposal_dataset([[torch.from_numpy(c).to(device) for c in x] for x in (u, v)], "product",
+                                       TOL, MAXRANK, maxiter=1, seed=INIT_SEED, capacity=1 << 17)
+        Xs.append(X)
+        ys.append(y)
+    X, y = torch.cat(Xs), torch.cat(ys)
+    p = aci.mlp_init(7, device=device)
+    m_, v_ = torch.zeros_like(p), torch.zeros_like(p)
+    rng = np.random.default_rng(0)
+    for step in range(1, steps + 1):
+        idx = torch.from_numpy(rng.choice(X.shape[0], 512, replace=False)).to(device)
+        loss, _ = aci.mlp_train_step(p, m_, v_, step, X[idx].contiguous(), y[idx].contiguous(), lr=3e-3)
+    log(f"proposal at scale: {X.shape[0]} rows from {n_train} products, loss {loss:.3f} "
+        f"({time.perf_counter() - t:.1f} s)")
+    out = {"workload": f"u*v of held-out 3D Fourier fields (|k|<={KMAX}, 1024^3, L=30) at input ranks 128/192/256, "
+                       f"tol {TOL}, rank cap 256; network trained on {n_train} products of rank-128 fields (one "
+                       "sweep each)", "training_rows": int(X.shape[0]), "held_out": []}
+    for j, chi in enumerate((128, 192, 256)):
+        u, v = W.fourier3d_pair(R=10, kmax=KMAX, chi=chi, seeds=(4501 + 2 * j, 4502 + 2 * j), device=device)
+        d = [[torch.from_numpy(c).to(device) for c in x] for x in (u, v)]
+        row = {"chi": chi}
+        for name, prop in (("plain", None), ("proposal", p)):
+            S = aci.Session(d, "product", TOL, 256, maxiter=3, seed=INIT_SEED, proposal=prop, fixed_sweeps=True)
+            S.sweep(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = S.sweep(1)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            S.close()
+            row[name] = {"seconds_per_sweep": el, "max_eps": st["max_eps"],
+                         "proposals_tried": st["proposals_tried"], "proposals_accepted": st["proposals_accepted"]}
+        log(f"proposal at scale, chi {chi}: plain {row['plain']['seconds_per_sweep'] * 1e3:.1f} ms per sweep, "
+            f"with proposals {row['proposal']['seconds_per_sweep'] * 1e3:.1f} ms, accepted "
+            f"{row['proposal']['proposals_accepted']}/{row['proposal']['proposals_tried']}")
+        out["held_out"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -1120,7 +1173,8 @@ def main():
         print(json.dumps(time_batched(aci, max(2, args.steps // 3), 1, dev)), flush=True)
         return
     if args.only == "proposal":
-        print(json.dumps(time_proposal(aci, dev)), flush=True)
+        print(json.dumps({"proposal": time_proposal(aci, dev), "proposal_at_scale": time_proposal_c4(aci, dev)}),
+              flush=True)
         return
     u, v = make_inputs(args.bits, dev)
     inputs = [[torch.from_numpy(c).to(dev) for c in x] for x in (u, v)]
@@ -1218,6 +1272,7 @@ def main():
         out["batched"] = time_batched(aci, max(2, args.steps // 3), 1, dev)
     if not args.no_proposal:
         out["proposal"] = time_proposal(aci, dev)
+        out["proposal_at_scale"] = time_proposal_c4(aci, dev)
     if not args.no_gp:
         out["gp"] = time_c5(aci, dev)
     if not args.no_step:

@@ -43,13 +43,25 @@ constexpr int KC = 32;        // k per load chunk (FP64 stages one, FP32 / BF16x
 // Shape of a TM x TN output tile (TM, TN in {32, 64}).  One chunk of A (TM x
 // 32) and B (32 x TN, real view) is loaded by the 256 threads into
 // registers, EA and EB values per thread, while the previous chunk is
-// multiplied from LDS.
-//   A value e of thread t: row t / TPA, k EA (t % TPA) + e.
-//   B value e, real:    k t / TPB, column EB (t % TPB) + e.
-//   B value e, complex: k 2 ct + e / (EB/2), column 2 cj0 + e % (EB/2) with
-//     ct = t / TPC, cj0 = CE (t % TPC): complex B is read once per element
-//     (CE neighbouring elements per thread) and expanded in registers into
-//     its 2 x 2 real block.
+// multiplied from LDS.  Two assignments of values to threads (MAP):
+//   MAP_SPREAD (FP64, FP32; LDS tiles [k][row] and [k][col]):
+//     A value e of thread t: row t / TPA, k (t % TPA) + TPA e;
+//     B value e, real: k t / 16 + 16 (e / NC), column t % 16 + 16 (e % NC)
+//     (NC = TN / 16): a wave's stores of one value index cover 64 distinct
+//     banks of the padded tiles, and each load instruction reads whole
+//     segments of consecutive entries;
+//   MAP_PACKED (BF16x3; LDS tiles [row][k] and [col][k]): a thread holds
+//     consecutive k of one row of A (k EA (t % TPA) + e) and of one column
+//     of B (column t % TN, k EB (t / TN) + e), stored as one vector.
+//   Complex B is read once per element and expanded in registers into its
+//   2 x 2 real block (values 2q, 2q + 1: row 2 ct, columns 2 cj, 2 cj + 1;
+//   values EB/2 + 2q, EB/2 + 2q + 1: row 2 ct + 1, same columns), CE
+//   elements per thread: MAP_SPREAD: element q of thread t at complex k
+//   t / (TN/2) + (512/TN) q, complex column t % (TN/2) (a wave reads whole
+//   rows of elements and stores each real row pair as one vector);
+//   MAP_PACKED: k ct = t / TPC, columns cj0 + q with cj0 = CE (t % TPC).
+constexpr int MAP_SPREAD = 0, MAP_PACKED = 1;
+
 template <int TM_, int TN_>
 struct Tile {
   static constexpr int TM = TM_, TN = TN_;
@@ -57,48 +69,58 @@ struct Tile {
   static constexpr int EB = TN * KC / 256;
   static constexpr int TPA = KC / EA;
   static constexpr int TPB = TN / EB;
+  static constexpr int NC = TN / 16;
   static constexpr int CE = EB / 4;
   static constexpr int TPC = (TN / 2) / CE;
   static constexpr int MI = TM / 32;   // 16-row blocks per wave (waves are 2 x 2)
   static constexpr int NJ = TN / 32;   // 16-column blocks per wave
-  static constexpr int LDA = TM + 2;   // FP64 LDS pitches ([k][row], [k][col])
-  static constexpr int LDB = TN + 2;
+  // FP64 LDS pitches ([k][row], [k][col]), in doubles: rows of the tile 16
+  // doubles (128 bytes) apart modulo 256 bytes, so that the four k rows an
+  // MFMA operand read touches fall on distinct banks
+  static constexpr int LDA = TM + 16;
+  static constexpr int LDB = TN + 16;
   __device__ static int a_row(int t) { return t / TPA; }
-  __device__ static int a_k(int t, int e) { return (t % TPA) * EA + e; }
-  template <bool CPLX>
+  template <int MAP>
+  __device__ static int a_k(int t, int e) { return MAP == MAP_SPREAD ? (t % TPA) + TPA * e : (t % TPA) * EA + e; }
+  // complex B, MAP_SPREAD: element q of thread t
+  __device__ static int cb_k(int t, int q) { return t / (TN / 2) + (512 / TN) * q; }
+  __device__ static int cb_col(int t) { return t % (TN / 2); }
+  template <bool CPLX, int MAP>
   __device__ static int b_k(int t, int e) {
-    return CPLX ? 2 * (t / TPC) + e / (EB / 2) : t / TPB;
+    if (CPLX) return 2 * (t / TPC) + e / (EB / 2);
+    return MAP == MAP_SPREAD ? t / 16 + 16 * (e / NC) : (t / TN) * EB + e;
   }
-  template <bool CPLX>
+  template <bool CPLX, int MAP>
   __device__ static int b_col(int t, int e) {
-    return CPLX ? 2 * CE * (t % TPC) + e % (EB / 2) : (t % TPB) * EB + e;
+    if (CPLX) return 2 * CE * (t % TPC) + e % (EB / 2);
+    return MAP == MAP_SPREAD ? t % 16 + 16 * (e % NC) : t % TN;
   }
 };
 
-template <class TL, bool CPLX>
+template <class TL, bool CPLX, int MAP>
 __device__ __forceinline__ void load_chunk(const Term& T, int M, int N, int K, int lda, int ldb, int m0, int n0,
                                            int k0, int t, double (&av)[TL::EA], double (&bv)[TL::EB]) {
   const int gr = m0 + TL::a_row(t);
 #pragma unroll
   for (int e = 0; e < TL::EA; ++e) {
-    const int gk = k0 + TL::a_k(t, e);
+    const int gk = k0 + TL::template a_k<MAP>(t, e);
     av[e] = (gr < M && gk < K) ? T.A[(size_t)gr * lda + gk] : 0.0;
   }
   if (!CPLX) {
-    const int gk = k0 + TL::template b_k<false>(t, 0);
 #pragma unroll
     for (int e = 0; e < TL::EB; ++e) {
-      const int gc = n0 + TL::template b_col<false>(t, e);
+      const int gk = k0 + TL::template b_k<false, MAP>(t, e);
+      const int gc = n0 + TL::template b_col<false, MAP>(t, e);
       bv[e] = (gk < K && gc < N) ? T.B[(size_t)gk * ldb + gc] : 0.0;
     }
   } else {
-    const int ct = (k0 >> 1) + t / TL::TPC;
-    const int cj = (n0 >> 1) + TL::CE * (t % TL::TPC);
 #pragma unroll
     for (int q = 0; q < TL::CE; ++q) {
+      const int ct = (k0 >> 1) + (MAP == MAP_SPREAD ? TL::cb_k(t, q) : t / TL::TPC);
+      const int cjq = (n0 >> 1) + (MAP == MAP_SPREAD ? TL::cb_col(t) : TL::CE * (t % TL::TPC) + q);
       double re = 0.0, im = 0.0;
-      if (2 * ct < K && 2 * (cj + q) < N) {
-        const double* e = T.B + 2 * ((size_t)ct * ldb + cj + q);
+      if (2 * ct < K && 2 * cjq < N) {
+        const double* e = T.B + 2 * ((size_t)ct * ldb + cjq);
         re = e[0];
         im = e[1];
       }
@@ -214,8 +236,8 @@ __device__ __forceinline__ void store_tile(const Group& g, const v4d (&res)[MI][
 
 template <int OP, bool CPLX, class TL>
 __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
-  __shared__ double sA[KC * TL::LDA];
-  __shared__ double sB[KC * TL::LDB];
+  __shared__ __align__(16) double sA[KC * TL::LDA];
+  __shared__ __align__(16) double sB[KC * TL::LDB];
   constexpr int W = CPLX ? 2 : 1;
   constexpr int MI = TL::MI, NJ = TL::NJ;
   const Group& g = args.g[blockIdx.z];
@@ -244,16 +266,27 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
       for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
     double av[TL::EA], bv[TL::EB];
-    load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av, bv);
+    load_chunk<TL, CPLX, MAP_SPREAD>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av, bv);
     for (int k0 = 0; k0 < K; k0 += KC) {
 #pragma unroll
-      for (int e = 0; e < TL::EA; ++e) sA[TL::a_k(tid, e) * TL::LDA + TL::a_row(tid)] = av[e];
+      for (int e = 0; e < TL::EA; ++e) sA[TL::template a_k<MAP_SPREAD>(tid, e) * TL::LDA + TL::a_row(tid)] = av[e];
+      if constexpr (CPLX) {
 #pragma unroll
-      for (int e = 0; e < TL::EB; ++e)
-        sB[TL::template b_k<CPLX>(tid, e) * TL::LDB + TL::template b_col<CPLX>(tid, e)] = bv[e];
+        for (int q = 0; q < TL::CE; ++q) {
+          const int r = 2 * TL::cb_k(tid, q), c = 2 * TL::cb_col(tid);
+          *reinterpret_cast<double2*>(&sB[r * TL::LDB + c]) = double2{bv[2 * q], bv[2 * q + 1]};
+          *reinterpret_cast<double2*>(&sB[(r + 1) * TL::LDB + c]) =
+              double2{bv[TL::EB / 2 + 2 * q], bv[TL::EB / 2 + 2 * q + 1]};
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < TL::EB; ++e)
+          sB[TL::template b_k<false, MAP_SPREAD>(tid, e) * TL::LDB + TL::template b_col<false, MAP_SPREAD>(tid, e)] =
+              bv[e];
+      }
       __syncthreads();
       // the next chunk's loads are in flight while this one is multiplied
-      if (k0 + KC < K) load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KC, tid, av, bv);
+      if (k0 + KC < K) load_chunk<TL, CPLX, MAP_SPREAD>(T, M, N, K, lda, ldb, m0, n0, k0 + KC, tid, av, bv);
 #pragma unroll
       for (int ks = 0; ks < KC / 4; ++ks) {
         const int kr = ks * 4 + lk;
@@ -292,16 +325,26 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
 __device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
 template <int PREC, class TL>
-struct LpTiles;
+struct alignas(16) LpTiles;
 
 template <class TL>
-struct LpTiles<PREC_FP32, TL> {
-  float A[KL * (TL::TM + 4)];   // [k][row]
-  float B[KL * (TL::TN + 4)];   // [k][col]
+struct alignas(16) LpTiles<PREC_FP32, TL> {
+  float A[KL * (TL::TM + 16)];   // [k][row]
+  float B[KL * (TL::TN + 16)];   // [k][col]
 };
 
+// N bf16 bit patterns as one LDS store (N = 4 or 8; dst aligned to 2N bytes)
+template <int N>
+__device__ __forceinline__ void store_bf16s(unsigned short* dst, const unsigned short (&v)[N]) {
+  typedef unsigned short vec __attribute__((ext_vector_type(N)));
+  vec x;
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = v[i];
+  *reinterpret_cast<vec*>(dst) = x;
+}
+
 template <class TL>
-struct LpTiles<PREC_BF16X3, TL> {
+struct alignas(16) LpTiles<PREC_BF16X3, TL> {
   unsigned short Ah[TL::TM * LDH], Al[TL::TM * LDH];   // [row][k]
   unsigned short Bh[TL::TN * LDH], Bl[TL::TN * LDH];   // [col][k]
 };
@@ -311,7 +354,10 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
   __shared__ LpTiles<PREC, TL> sh;
   constexpr int W = CPLX ? 2 : 1;
   constexpr int MI = TL::MI, NJ = TL::NJ;
-  constexpr int LDFA = TL::TM + 4, LDFB = TL::TN + 4;
+  // FP32 pitches: k rows 16 words apart modulo 64 banks (MFMA operand reads
+  // conflict-free); the spread assignment makes the staging stores so too
+  constexpr int LDFA = TL::TM + 16, LDFB = TL::TN + 16;
+  constexpr int MAP = PREC == PREC_FP32 ? MAP_SPREAD : MAP_PACKED;
   const Group& g = args.g[blockIdx.z];
   const int M = dget(g.M);
   const int N = W * dget(g.N);
@@ -338,8 +384,8 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
       for (int j = 0; j < NJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
     double av[2][TL::EA], bv[2][TL::EB];
-    load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av[0], bv[0]);
-    load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, KC, tid, av[1], bv[1]);
+    load_chunk<TL, CPLX, MAP>(T, M, N, K, lda, ldb, m0, n0, 0, tid, av[0], bv[0]);
+    load_chunk<TL, CPLX, MAP>(T, M, N, K, lda, ldb, m0, n0, KC, tid, av[1], bv[1]);
     for (int k0 = 0; k0 < K; k0 += KL) {
       const int ar = TL::a_row(tid);
 #pragma unroll
@@ -348,35 +394,65 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
         if (PREC == PREC_FP32) {
           auto& S = reinterpret_cast<LpTiles<PREC_FP32, TL>&>(sh);
 #pragma unroll
-          for (int e = 0; e < TL::EA; ++e) S.A[(kh + TL::a_k(tid, e)) * LDFA + ar] = (float)av[h][e];
+          for (int e = 0; e < TL::EA; ++e) S.A[(kh + TL::template a_k<MAP>(tid, e)) * LDFA + ar] = (float)av[h][e];
+          if constexpr (CPLX) {
 #pragma unroll
-          for (int e = 0; e < TL::EB; ++e)
-            S.B[(kh + TL::template b_k<CPLX>(tid, e)) * LDFB + TL::template b_col<CPLX>(tid, e)] = (float)bv[h][e];
+            for (int q = 0; q < TL::CE; ++q) {
+              const int r = kh + 2 * TL::cb_k(tid, q), c = 2 * TL::cb_col(tid);
+              *reinterpret_cast<float2*>(&S.B[r * LDFB + c]) = float2{(float)bv[h][2 * q], (float)bv[h][2 * q + 1]};
+              *reinterpret_cast<float2*>(&S.B[(r + 1) * LDFB + c]) =
+                  float2{(float)bv[h][TL::EB / 2 + 2 * q], (float)bv[h][TL::EB / 2 + 2 * q + 1]};
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < TL::EB; ++e)
+              S.B[(kh + TL::template b_k<false, MAP>(tid, e)) * LDFB + TL::template b_col<false, MAP>(tid, e)] =
+                  (float)bv[h][e];
+          }
         } else {
           auto& S = reinterpret_cast<LpTiles<PREC_BF16X3, TL>&>(sh);
+          // this thread's EA consecutive k of one row: one vector store each
+          unsigned short ah_[TL::EA], al_[TL::EA];
 #pragma unroll
           for (int e = 0; e < TL::EA; ++e) {
-            const int ak = kh + TL::a_k(tid, e);
             const float fa = (float)av[h][e];
-            const unsigned short ha = bf16_bits(fa);
-            S.Ah[ar * LDH + ak] = ha;
-            S.Al[ar * LDH + ak] = bf16_bits(fa - bf16_value(ha));
+            ah_[e] = bf16_bits(fa);
+            al_[e] = bf16_bits(fa - bf16_value(ah_[e]));
           }
+          const int ak0 = kh + TL::template a_k<MAP_PACKED>(tid, 0);
+          store_bf16s<TL::EA>(&S.Ah[ar * LDH + ak0], ah_);
+          store_bf16s<TL::EA>(&S.Al[ar * LDH + ak0], al_);
+          if constexpr (!CPLX) {
+            // EB consecutive k of one column
+            unsigned short bh_[TL::EB], bl_[TL::EB];
 #pragma unroll
-          for (int e = 0; e < TL::EB; ++e) {
-            const int bk = kh + TL::template b_k<CPLX>(tid, e), bc = TL::template b_col<CPLX>(tid, e);
-            const float fb = (float)bv[h][e];
-            const unsigned short hb = bf16_bits(fb);
-            S.Bh[bc * LDH + bk] = hb;
-            S.Bl[bc * LDH + bk] = bf16_bits(fb - bf16_value(hb));
+            for (int e = 0; e < TL::EB; ++e) {
+              const float fb = (float)bv[h][e];
+              bh_[e] = bf16_bits(fb);
+              bl_[e] = bf16_bits(fb - bf16_value(bh_[e]));
+            }
+            const int bk0 = kh + TL::template b_k<false, MAP_PACKED>(tid, 0);
+            const int bc = TL::template b_col<false, MAP_PACKED>(tid, 0);
+            store_bf16s<TL::EB>(&S.Bh[bc * LDH + bk0], bh_);
+            store_bf16s<TL::EB>(&S.Bl[bc * LDH + bk0], bl_);
+          } else {
+#pragma unroll
+            for (int e = 0; e < TL::EB; ++e) {
+              const int bk = kh + TL::template b_k<true, MAP_PACKED>(tid, e);
+              const int bc = TL::template b_col<true, MAP_PACKED>(tid, e);
+              const float fb = (float)bv[h][e];
+              const unsigned short hb = bf16_bits(fb);
+              S.Bh[bc * LDH + bk] = hb;
+              S.Bl[bc * LDH + bk] = bf16_bits(fb - bf16_value(hb));
+            }
           }
         }
       }
       __syncthreads();
       // the next chunk's loads are in flight while this one is multiplied
       if (k0 + KL < K) {
-        load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL, tid, av[0], bv[0]);
-        load_chunk<TL, CPLX>(T, M, N, K, lda, ldb, m0, n0, k0 + KL + KC, tid, av[1], bv[1]);
+        load_chunk<TL, CPLX, MAP>(T, M, N, K, lda, ldb, m0, n0, k0 + KL, tid, av[0], bv[0]);
+        load_chunk<TL, CPLX, MAP>(T, M, N, K, lda, ldb, m0, n0, k0 + KL + KC, tid, av[1], bv[1]);
       }
       if (PREC == PREC_FP32) {
         auto& S = reinterpret_cast<LpTiles<PREC_FP32, TL>&>(sh);

@@ -1051,6 +1051,8 @@ def time_proposal_c4(aci, device, n_train=8, steps=300):
     t = time.perf_counter()
     Xs, ys = [], []
     for i in range(n_train):
+        if i % 20 == 0:
+            log(f"proposal at scale: training product {i} of {n_train}")
         u, v = W.fourier3d_pair(R=10, kmax=KMAX, chi=128, seeds=(4001 + 2 * i, 4002 + 2 * i), device=device)
         X, y, _ = aci.proposal_dataset([[torch.from_numpy(c).to(device) for c in x] for x in (u, v)], "product",
                                        TOL, MAXRANK, maxiter=1, seed=INIT_SEED, capacity=1 << 17)
@@ -1107,6 +1109,8 @@ def main():
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution product")
     ap.add_argument("--only", choices=["gp", "batched", "contract", "tci", "step", "patched", "tts", "proposal"],
                     help="run just one section and print its JSON (for profiling that workload)")
+    ap.add_argument("--c4-pairs", type=int, default=8,
+                    help="training products of the learned proposal at scale (the configuration names 200)")
     ap.add_argument("--summarize-contract", metavar="DIR", help="per-case table of a traced --only contract run")
     ap.add_argument("--summarize-batch-gaps", metavar="DIR",
                     help="busy and idle shares of the joint batch sweeps in a traced --only batched run")
@@ -1173,8 +1177,8 @@ def main():
         print(json.dumps(time_batched(aci, max(2, args.steps // 3), 1, dev)), flush=True)
         return
     if args.only == "proposal":
-        print(json.dumps({"proposal": time_proposal(aci, dev), "proposal_at_scale": time_proposal_c4(aci, dev)}),
-              flush=True)
+        print(json.dumps({"proposal": time_proposal(aci, dev),
+                          "proposal_at_scale": time_proposal_c4(aci, dev, n_train=args.c4_pairs)}), flush=True)
         return
     u, v = make_inputs(args.bits, dev)
     inputs = [[torch.from_numpy(c).to(dev) for c in x] for x in (u, v)]
@@ -1272,7 +1276,7 @@ def main():
         out["batched"] = time_batched(aci, max(2, args.steps // 3), 1, dev)
     if not args.no_proposal:
         out["proposal"] = time_proposal(aci, dev)
-        out["proposal_at_scale"] = time_proposal_c4(aci, dev)
+        out["proposal_at_scale"] = time_proposal_c4(aci, dev, n_train=args.c4_pairs)
     if not args.no_gp:
         out["gp"] = time_c5(aci, dev)
     if not args.no_step:

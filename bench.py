@@ -612,8 +612,9 @@ def time_to_solution(aci, device, kmax=2):
     the sampled relative error of the output against u*v at 4096 points is
     within tol + the output cores; each sweep and each output are timed on
     their own, the error check between sweeps is not.  (Alg. 1's own test
-    asks in addition for ranks that did not grow, which a bond whose last
-    pivot sits at tol can keep failing; the per-bond error estimates reach
+    asks in addition for ranks that did not grow, which fails in every sweep
+    here: the pivots of the middle bonds crowd around tol, so some of their
+    ranks move by a few in every sweep; the per-bond error estimates reach
     tol before the index sets are good enough, so neither is the stop here.)
     Modes, all to the same sampled error: plain FP64 sweeps (eager, and
     replayed from a captured graph), FP64 sweeps started from a random index

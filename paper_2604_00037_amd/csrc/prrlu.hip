@@ -161,6 +161,36 @@ __device__ __forceinline__ bool poll_words(const uint64_t* src, int cnt, uint32_
   return ok;
 }
 
+// Publish register row slot r0 of this wave (lane l: columns l, l + 64, ...)
+// as flagged words after the candidate words of its slot.
+template <int RS, int CS, bool CX>
+__device__ __forceinline__ void publish_row(uint64_t* mine, const double (&s)[RS][CS],
+                                            const double (&si)[CX ? RS : 1][CX ? CS : 1], int r0,
+                                            const bool (&cv)[CS], uint32_t flag, bool same_xcd) {
+  constexpr int EW = CX ? 2 : 1;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < RS; ++r)
+    if (r == r0) {
+#pragma unroll
+      for (int b = 0; b < CS; ++b)
+        if (cv[b]) {
+          const int j = lane + 64 * b;
+          xw_put(mine + 3 + 2 * EW * j, lo32(s[r][b]), flag, same_xcd);
+          xw_put(mine + 4 + 2 * EW * j, hi32(s[r][b]), flag, same_xcd);
+          if constexpr (CX) {
+            xw_put(mine + 5 + 4 * j, lo32(si[r][b]), flag, same_xcd);
+            xw_put(mine + 6 + 4 * j, hi32(si[r][b]), flag, same_xcd);
+          }
+        }
+    }
+}
+
+// Eager row publication across XCDs: a group publishes its candidate's row
+// together with the candidate only if the candidate's key reaches this
+// fraction of the next pivot key predicted from the last two.
+constexpr double kEagerFrac = 0.6;
+
 // Most workgroups one factorisation may use (one per CU).
 constexpr int kMaxGroups = 128;
 // LDS of a cooperative launch: candidate words at [0, kCandWords) (three per
@@ -292,6 +322,7 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   double eps = 0.0;
   int final_rank = 0;
   double tol = a.tol;   // raised to the noise floor after the first pivot
+  double last_key = 0.0, prev_key = 1.0;   // keys of the last two pivots
   while (true) {
     if (k == kmax) {
       if (a.rule == RULE_EXCLUSIVE) eps = 0.0;
@@ -380,26 +411,18 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
         const uint32_t d = lane == 0 ? lo32(ck) : (lane == 1 ? hi32(ck) : (uint32_t)ci);
         xw_put(mine + lane, d, flag, same_xcd);
       }
-      if (ck >= 0.0) {
+      // The candidate's row goes out with the candidate (saving a round
+      // trip for the winner) when the groups share one XCD: those stores
+      // end in its L2.  Across XCDs they travel further and up to 128 groups
+      // publish, so only groups whose candidate may win do: key at least
+      // kEagerFrac of the pivot key predicted from the last two (last key
+      // times the last ratio, at most 1).  A winner that did not publish
+      // does so once it knows; readers poll the row's flags either way, so
+      // the rule moves stores in time and changes no result.
+      const bool eager = same_xcd || k < 2 || ck >= kEagerFrac * last_key * fmin(1.0, last_key / prev_key);
+      if (eager && ck >= 0.0) {
         const int rho = ((ci >> 16) - w) / P;
-        if (wv == rho % WAVES) {
-          const int r0 = rho / WAVES;
-#pragma unroll
-          for (int r = 0; r < RS; ++r)
-            if (r == r0) {
-#pragma unroll
-              for (int b = 0; b < CS; ++b)
-                if (cv[b]) {
-                  const int j = lane + 64 * b;
-                  xw_put(mine + 3 + 2 * EW * j, lo32(s[r][b]), flag, same_xcd);
-                  xw_put(mine + 4 + 2 * EW * j, hi32(s[r][b]), flag, same_xcd);
-                  if constexpr (CX) {
-                    xw_put(mine + 5 + 4 * j, lo32(si[r][b]), flag, same_xcd);
-                    xw_put(mine + 6 + 4 * j, hi32(si[r][b]), flag, same_xcd);
-                  }
-                }
-            }
-        }
+        if (wv == rho % WAVES) publish_row<RS, CS, CX>(mine, s, si, rho / WAVES, cv, flag, same_xcd);
       }
       // round trip 1: the P candidates (thread t reads word t, and t + NT
       // when more than 85 groups cooperate)
@@ -456,8 +479,15 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
         v = 0.0;
         widx = 0;
       }
-      // round trip 2: the winner's row (already published with its candidate)
+      // round trip 2: the winner's row (published with its candidate, or
+      // now by the winner)
       const int wg = (widx >> 16) % P;
+      prev_key = last_key;
+      last_key = v;
+      if (!eager && w == wg && !failed) {
+        const int rho = ((widx >> 16) - w) / P;
+        if (wv == rho % WAVES) publish_row<RS, CS, CX>(mine, s, si, rho / WAVES, cv, flag, same_xcd);
+      }
       ok = poll_words<(128 * EW * CS + NT - 1) / NT, NT>(slot_base + (size_t)wg * per + 3, 2 * EW * n, want,
                                                      a.abort_word, a.spin_limit, xrow);
       if (!ok) failed = true;

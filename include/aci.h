@@ -327,6 +327,22 @@ const char* aci_last_error(const aci_ctx* ctx);
  * ACI_E_INVALID for stall_step < -1 or epoch_launches outside [0, 2^21 - 1]. */
 int aci_ctx_set_exchange_hooks(aci_ctx* ctx, uint32_t spin_limit, int32_t stall_step, int64_t epoch_launches);
 
+/* Row publication of LDU launches whose workgroups span several XCDs (the
+ * pivot exchange of Alg. 2 for 1024-column rows: complex ones, and real ones
+ * past one XCD's CUs).  Each workgroup publishes its pivot candidate; its
+ * candidate's row goes out with it ("eagerly") only if the candidate's key
+ * (|entry|, or |entry|^2 for complex) is at least eager_frac times the next
+ * pivot key predicted from the last two (last key times the last ratio, at
+ * most 1), and from the third step on; otherwise the winner publishes its
+ * row once every group knows the winner.  A tuning and test hook: results do
+ * not depend on it, only the time per pivot.  Launches whose workgroups share
+ * one XCD always publish eagerly.  Applies to LDU launches enqueued after the
+ * call.
+ *   eager_frac  0: every row eagerly; +INFINITY: only the first two steps
+ *               eagerly, every later winner late; default 0.6.
+ * ACI_E_INVALID for a negative or NaN eager_frac. */
+int aci_ctx_set_row_publication(aci_ctx* ctx, double eager_frac);
+
 /* Alg. 1: approximate f(x^1..x^N) as a TT with error estimate <= tol and bond
  * dimensions <= maxrank.
  *   inputs     host array of n_inputs TTs (device cores, dtype as given)

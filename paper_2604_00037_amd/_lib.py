@@ -29,7 +29,7 @@ EXPORTED = [
     "aci_batch_destroy", "aci_elementwise_batched", "aci_tune_prrlu", "aci_tune_contract", "aci_tci",
     "aci_proposal_features", "aci_mlp_forward", "aci_mlp_train_step", "aci_rook_lu", "aci_rook_check",
     "aci_rook_right_factor", "aci_mpo_stencil", "aci_mpo_apply", "aci_cubic_step", "aci_patched",
-    "aci_patched_free", "aci_ctx_set_exchange_hooks", "aci_prrlu_noalloc",
+    "aci_patched_free", "aci_ctx_set_exchange_hooks", "aci_ctx_set_row_publication", "aci_prrlu_noalloc",
     "aci_proposal_dataset", "aci_mlp_init",
 ]
 MLP_PARAMS = 7 * 64 + 64 + 64 * 64 + 64 + 64 + 1
@@ -184,6 +184,8 @@ def load(path=LIB_PATH):
     lib.aci_ctx_destroy.restype = None
     lib.aci_ctx_set_exchange_hooks.argtypes = [vp, C.c_uint32, i32, C.c_int64]
     lib.aci_ctx_set_exchange_hooks.restype = C.c_int
+    lib.aci_ctx_set_row_publication.argtypes = [vp, C.c_double]
+    lib.aci_ctx_set_row_publication.restype = C.c_int
     lib.aci_last_error.argtypes = [vp]
     lib.aci_last_error.restype = C.c_char_p
     lib.aci_elementwise.argtypes = [vp, C.POINTER(AciTT), i32, i32, i32, C.c_double, i32,

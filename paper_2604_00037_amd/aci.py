@@ -112,6 +112,12 @@ class Context:
         _check(self.lib, self.h, self.lib.aci_ctx_set_exchange_hooks(self.h, int(spin_limit), int(stall_step),
                                                                      int(epoch_launches)))
 
+    def set_row_publication(self, eager_frac=0.6):
+        """aci_ctx_set_row_publication: eager row publication of LDUs across
+        XCDs above this fraction of the predicted pivot key (0: always,
+        math.inf: winners publish late)."""
+        _check(self.lib, self.h, self.lib.aci_ctx_set_row_publication(self.h, float(eager_frac)))
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.aci_ctx_destroy(self.h)

@@ -39,6 +39,10 @@ struct aci_ctx {
   uint32_t poll_xor = 0;
   int stall_from = 0;
   uint64_t epoch_launches = 0;   // session epoch reset period (0: the default)
+  // LDUs across XCDs: eager row publication above this fraction of the
+  // predicted pivot key (aci_ctx_set_row_publication; 0.6 measured best on
+  // the complex 1024 x 1024 two-site matrices)
+  double eager_frac = 0.6;
   // small persistent workspace of the single-step entry points
   int* step_err = nullptr;     // [0] error flags, [1] abort word
   uint64_t* step_xbuf = nullptr;
@@ -96,6 +100,7 @@ void exchange_waits(const aci_ctx* c, PrrluArgs& a) {
   a.spin_limit = c->spin_limit;
   a.poll_xor = c->poll_xor;
   a.stall_from = c->stall_from;
+  a.eager_frac = c->eager_frac;
 }
 
 int set_err(aci_ctx* c, int code, const std::string& msg) {
@@ -1147,6 +1152,14 @@ int aci_ctx_set_exchange_hooks(aci_ctx* ctx, uint32_t spin_limit, int32_t stall_
   ctx->poll_xor = stall_step >= 0 ? 0x80000000u : 0u;
   ctx->stall_from = stall_step >= 0 ? stall_step : 0;
   ctx->epoch_launches = (uint64_t)epoch_launches;
+  return ACI_OK;
+}
+
+int aci_ctx_set_row_publication(aci_ctx* ctx, double eager_frac) {
+  if (!ctx) return ACI_E_INVALID;
+  ctx->err.clear();
+  if (!(eager_frac >= 0.0)) return set_err(ctx, ACI_E_INVALID, "eager_frac must be >= 0 (or +inf)");
+  ctx->eager_frac = eager_frac;
   return ACI_OK;
 }
 

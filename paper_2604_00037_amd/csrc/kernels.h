@@ -72,6 +72,10 @@ struct PrrluArgs {
   // wait ends at its spin limit (poll_xor 0: off)
   uint32_t poll_xor;
   int stall_from;
+  // groups spread over several XCDs publish their candidate's row with the
+  // candidate only when its key is at least eager_frac times the predicted
+  // next pivot key (0: always); the winner publishes late otherwise
+  double eager_frac;
   int* rows;        // out: pivot rows, pivot order
   int* cols;        // out: pivot columns
   int* rank;        // out: rank

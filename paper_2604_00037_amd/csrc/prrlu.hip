@@ -186,11 +186,6 @@ __device__ __forceinline__ void publish_row(uint64_t* mine, const double (&s)[RS
     }
 }
 
-// Eager row publication across XCDs: a group publishes its candidate's row
-// together with the candidate only if the candidate's key reaches this
-// fraction of the next pivot key predicted from the last two.
-constexpr double kEagerFrac = 0.6;
-
 // Most workgroups one factorisation may use (one per CU).
 constexpr int kMaxGroups = 128;
 // LDS of a cooperative launch: candidate words at [0, kCandWords) (three per
@@ -415,11 +410,11 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
       // trip for the winner) when the groups share one XCD: those stores
       // end in its L2.  Across XCDs they travel further and up to 128 groups
       // publish, so only groups whose candidate may win do: key at least
-      // kEagerFrac of the pivot key predicted from the last two (last key
+      // a.eager_frac of the pivot key predicted from the last two (last key
       // times the last ratio, at most 1).  A winner that did not publish
       // does so once it knows; readers poll the row's flags either way, so
       // the rule moves stores in time and changes no result.
-      const bool eager = same_xcd || k < 2 || ck >= kEagerFrac * last_key * fmin(1.0, last_key / prev_key);
+      const bool eager = same_xcd || k < 2 || ck >= a.eager_frac * last_key * fmin(1.0, last_key / prev_key);
       if (eager && ck >= 0.0) {
         const int rho = ((ci >> 16) - w) / P;
         if (wv == rho % WAVES) publish_row<RS, CS, CX>(mine, s, si, rho / WAVES, cv, flag, same_xcd);

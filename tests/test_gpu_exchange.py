@@ -169,6 +169,37 @@ def test_recycled_memory_with_flagged_words_does_not_leak_into_the_ldu():
     assert got["eps"] == ref.eps
 
 
+@pytest.mark.parametrize("m,n,cx", [(1024, 1024, True), (700, 1024, False)])
+def test_row_publication_rule_changes_no_pivot(m, n, cx):
+    """Groups spread over several XCDs publish their candidate's row with the
+    candidate only above a fraction of the predicted pivot key; otherwise the
+    winner publishes its row late.  All rows eager (0), the default mix (0.6)
+    and all winners late from the third step (inf) give the same pivots and
+    right factor bit for bit, and the oracle's pivots where no near tie
+    decides them."""
+    import math
+    rng = np.random.default_rng(m + 7 * n)
+    M = rng.standard_normal((m, n)) + (1j * rng.standard_normal((m, n)) if cx else 0.0)
+    rank = min(m, n) // 2
+    got = []
+    for frac in (0.0, 0.6, math.inf):
+        ctx = aci.Context()
+        try:
+            ctx.set_row_publication(frac)
+            r = aci.prrlu(dev(M), 0.0, rank, want_y=True, ctx=ctx)
+        finally:
+            ctx.close()
+        got.append((r["rows"], r["cols"], r["eps"], r["Y"].cpu().numpy()))
+    for g in got[1:]:
+        assert np.array_equal(g[0], got[0][0]) and np.array_equal(g[1], got[0][1]) and g[2] == got[0][2]
+        assert np.array_equal(g[3].view(np.uint8), got[0][3].view(np.uint8))
+    ref = oprrlu(M, 0.0, rank, log_gaps=True)
+    if min(ref.gaps) > 1e-10:
+        np.testing.assert_array_equal(got[0][0], ref.rows)
+        np.testing.assert_array_equal(got[0][1], ref.cols)
+        assert got[0][2] == ref.eps
+
+
 def test_hook_arguments_are_checked():
     ctx = aci.Context()
     try:
@@ -176,5 +207,9 @@ def test_hook_arguments_are_checked():
             ctx.set_exchange_hooks(stall_step=-2)
         with pytest.raises(_lib.HipError, match="ACI_E_INVALID"):
             ctx.set_exchange_hooks(epoch_launches=1 << 40)
+        with pytest.raises(_lib.HipError, match="ACI_E_INVALID"):
+            ctx.set_row_publication(-0.5)
+        with pytest.raises(_lib.HipError, match="ACI_E_INVALID"):
+            ctx.set_row_publication(float("nan"))
     finally:
         ctx.close()

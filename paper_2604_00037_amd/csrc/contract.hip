@@ -287,19 +287,32 @@ __global__ __launch_bounds__(256) void contract_kernel(ContractArgs args) {
       __syncthreads();
       // the next chunk's loads are in flight while this one is multiplied
       if (k0 + KC < K) load_chunk<TL, CPLX, MAP_SPREAD>(T, M, N, K, lda, ldb, m0, n0, k0 + KC, tid, av, bv);
+      // operands of step ks + 1 are read while step ks is multiplied (two
+      // register sets, so the reads need not wait for the MFMAs that use the
+      // previous set)
+      double a[2][MI], b[2][NJ];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) a[0][i] = sA[lk * TL::LDA + wm * (TL::TM / 2) + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[0][j] = sB[lk * TL::LDB + wn * (TL::TN / 2) + j * 16 + lr];
 #pragma unroll
       for (int ks = 0; ks < KC / 4; ++ks) {
-        const int kr = ks * 4 + lk;
-        double a[MI], b[NJ];
+        const int cur = ks & 1, nxt = cur ^ 1;
+        if (ks + 1 < KC / 4) {
+          const int kr = (ks + 1) * 4 + lk;
 #pragma unroll
-        for (int i = 0; i < MI; ++i) a[i] = sA[kr * TL::LDA + wm * (TL::TM / 2) + i * 16 + lr];
+          for (int i = 0; i < MI; ++i) a[nxt][i] = sA[kr * TL::LDA + wm * (TL::TM / 2) + i * 16 + lr];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) b[j] = sB[kr * TL::LDB + wn * (TL::TN / 2) + j * 16 + lr];
+          for (int j = 0; j < NJ; ++j) b[nxt][j] = sB[kr * TL::LDB + wn * (TL::TN / 2) + j * 16 + lr];
+        }
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < NJ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][i], b[cur][j], acc[i][j], 0, 0, 0);
+        // keep that order: the next step's LDS reads, then this step's MFMAs
+        if (ks + 1 < KC / 4) __builtin_amdgcn_sched_group_barrier(0x100, MI + NJ, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, MI * NJ, 0);
       }
       __syncthreads();
     }
@@ -456,19 +469,29 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
       }
       if (PREC == PREC_FP32) {
         auto& S = reinterpret_cast<LpTiles<PREC_FP32, TL>&>(sh);
+        // operands of step ks + 1 read while step ks is multiplied
+        float a[2][MI], b[2][NJ];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) a[0][i] = S.A[lg * LDFA + wm * (TL::TM / 2) + i * 16 + lr];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) b[0][j] = S.B[lg * LDFB + wn * (TL::TN / 2) + j * 16 + lr];
 #pragma unroll
         for (int ks = 0; ks < KL / 4; ++ks) {
-          const int kr = ks * 4 + lg;
-          float a[MI], b[NJ];
+          const int cur = ks & 1, nxt = cur ^ 1;
+          if (ks + 1 < KL / 4) {
+            const int kr = (ks + 1) * 4 + lg;
 #pragma unroll
-          for (int i = 0; i < MI; ++i) a[i] = S.A[kr * LDFA + wm * (TL::TM / 2) + i * 16 + lr];
+            for (int i = 0; i < MI; ++i) a[nxt][i] = S.A[kr * LDFA + wm * (TL::TM / 2) + i * 16 + lr];
 #pragma unroll
-          for (int j = 0; j < NJ; ++j) b[j] = S.B[kr * LDFB + wn * (TL::TN / 2) + j * 16 + lr];
+            for (int j = 0; j < NJ; ++j) b[nxt][j] = S.B[kr * LDFB + wn * (TL::TN / 2) + j * 16 + lr];
+          }
 #pragma unroll
           for (int i = 0; i < MI; ++i)
 #pragma unroll
             for (int j = 0; j < NJ; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[cur][i], b[cur][j], acc[i][j], 0, 0, 0);
+          if (ks + 1 < KL / 4) __builtin_amdgcn_sched_group_barrier(0x100, MI + NJ, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, MI * NJ, 0);
         }
       } else {
         auto& S = reinterpret_cast<LpTiles<PREC_BF16X3, TL>&>(sh);

@@ -211,7 +211,7 @@ __device__ __forceinline__ double cabs2(double re, double im) {
 //
 // The factorisation itself, run by group w (0 <= w < a.P) of the
 // cooperating groups.
-template <int RS, int CS, bool SOLO, bool CX, int WAVES>
+template <int RS, int CS, bool SOLO, bool CX, int WAVES, bool CROSS = false>
 __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   constexpr int NT = 64 * WAVES;   // threads of the workgroup
   // flags of this launch: step k uses fbase + k
@@ -317,7 +317,9 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   double eps = 0.0;
   int final_rank = 0;
   double tol = a.tol;   // raised to the noise floor after the first pivot
-  double last_key = 0.0, prev_key = 1.0;   // keys of the last two pivots
+  // across XCDs: keys of the last two pivots, and the candidate key from
+  // which a group publishes its row eagerly (see the exchange below)
+  double last_key = 0.0, prev_key = 1.0, eager_key = 0.0;
   while (true) {
     if (k == kmax) {
       if (a.rule == RULE_EXCLUSIVE) eps = 0.0;
@@ -414,10 +416,27 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
       // times the last ratio, at most 1).  A winner that did not publish
       // does so once it knows; readers poll the row's flags either way, so
       // the rule moves stores in time and changes no result.
-      const bool eager = same_xcd || k < 2 || ck >= a.eager_frac * last_key * fmin(1.0, last_key / prev_key);
+      const bool eager = !CROSS || same_xcd || k < 2 || ck >= eager_key;
       if (eager && ck >= 0.0) {
         const int rho = ((ci >> 16) - w) / P;
-        if (wv == rho % WAVES) publish_row<RS, CS, CX>(mine, s, si, rho / WAVES, cv, flag, same_xcd);
+        if (wv == rho % WAVES) {
+          const int r0 = rho / WAVES;
+#pragma unroll
+          for (int r = 0; r < RS; ++r)
+            if (r == r0) {
+#pragma unroll
+              for (int b = 0; b < CS; ++b)
+                if (cv[b]) {
+                  const int j = lane + 64 * b;
+                  xw_put(mine + 3 + 2 * EW * j, lo32(s[r][b]), flag, same_xcd);
+                  xw_put(mine + 4 + 2 * EW * j, hi32(s[r][b]), flag, same_xcd);
+                  if constexpr (CX) {
+                    xw_put(mine + 5 + 4 * j, lo32(si[r][b]), flag, same_xcd);
+                    xw_put(mine + 6 + 4 * j, hi32(si[r][b]), flag, same_xcd);
+                  }
+                }
+            }
+        }
       }
       // round trip 1: the P candidates (thread t reads word t, and t + NT
       // when more than 85 groups cooperate)
@@ -477,9 +496,14 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
       // round trip 2: the winner's row (published with its candidate, or
       // now by the winner)
       const int wg = (widx >> 16) % P;
-      prev_key = last_key;
-      last_key = v;
-      if (!eager && w == wg && !failed) {
+      if (CROSS && !same_xcd) {
+        // next step's threshold: eager_frac of last key times last ratio
+        // (at most 1), computed off the exchange's critical path
+        prev_key = last_key;
+        last_key = v;
+        eager_key = a.eager_frac * last_key * fmin(1.0, last_key / prev_key);
+      }
+      if (CROSS && !eager && w == wg && !failed) {
         const int rho = ((widx >> 16) - w) / P;
         if (wv == rho % WAVES) publish_row<RS, CS, CX>(mine, s, si, rho / WAVES, cv, flag, same_xcd);
       }
@@ -726,13 +750,16 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   }
 }
 
-template <int RS, int CS, bool SOLO, bool CX, int W>
+// CROSS: the instance for launches whose groups may span several XCDs
+// (stride 1), with the late row publication; launches kept on one XCD
+// (stride 8) use the instance without it, whose exchange code is shorter.
+template <int RS, int CS, bool SOLO, bool CX, int W, bool CROSS = false>
 __global__ __launch_bounds__(64 * W) void prrlu_kernel(PrrluArgs a) {
   if ((int)(blockIdx.x % a.stride) != (a.stride == 8 ? a.xcd : 0)) return;
   // a proposal already supplied this factorisation (every group reads the
   // same word, so the whole launch leaves together; the epoch is untouched)
   if (a.skip && *a.skip) return;
-  prrlu_body<RS, CS, SOLO, CX, W>(a, blockIdx.x / a.stride);
+  prrlu_body<RS, CS, SOLO, CX, W, CROSS>(a, blockIdx.x / a.stride);
 }
 
 // Several products' factorisations in one launch.  Workgroup b runs on XCD
@@ -839,10 +866,11 @@ hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
     return do_launch((const void*)prrlu_kernel<RS, CS, true, CX, WAVES>, dim3(args.stride), NT, lds, args, s);
   }
   const void* fn = (const void*)prrlu_kernel<RSG, CS, false, CX, WG>;
+  const void* fn_cross = (const void*)prrlu_kernel<RSG, CS, false, CX, WG, true>;
   const size_t lds = group_lds((size_t)(kCandWords + 128 * EW * CS) * 4);
   if (spread) {
     args.stride = 1;
-    return do_launch(fn, dim3(args.P), 64 * WG, lds, args, s);
+    return do_launch(fn_cross, dim3(args.P), 64 * WG, lds, args, s);
   }
   static int per_cu = resident_per_cu(fn, 64 * WG, lds);
   // Workgroups are dealt to the 8 XCDs round robin, so launching 8x the
@@ -851,7 +879,7 @@ hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
   // XCD's L2.  Only when they all fit.
   args.stride = (a.P <= per_cu * cus_per_xcd()) ? 8 : 1;
   if (!a.cooperative && args.stride != 8) return hipErrorInvalidValue;
-  return do_launch(fn, dim3(args.P * args.stride), 64 * WG, lds, args, s);
+  return do_launch(args.stride == 8 ? fn : fn_cross, dim3(args.P * args.stride), 64 * WG, lds, args, s);
 }
 
 // Register shapes of complex matrices (two doubles per entry).

@@ -750,16 +750,23 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   }
 }
 
-// CROSS: the instance for launches whose groups may span several XCDs
-// (stride 1), with the late row publication; launches kept on one XCD
-// (stride 8) use the instance without it, whose exchange code is shorter.
-template <int RS, int CS, bool SOLO, bool CX, int W, bool CROSS = false>
+template <int RS, int CS, bool SOLO, bool CX, int W>
 __global__ __launch_bounds__(64 * W) void prrlu_kernel(PrrluArgs a) {
   if ((int)(blockIdx.x % a.stride) != (a.stride == 8 ? a.xcd : 0)) return;
   // a proposal already supplied this factorisation (every group reads the
   // same word, so the whole launch leaves together; the epoch is untouched)
   if (a.skip && *a.skip) return;
-  prrlu_body<RS, CS, SOLO, CX, W, CROSS>(a, blockIdx.x / a.stride);
+  prrlu_body<RS, CS, SOLO, CX, W>(a, blockIdx.x / a.stride);
+}
+
+// The same for launches whose groups may span several XCDs (stride 1), with
+// the late row publication; launches kept on one XCD (stride 8) use
+// prrlu_kernel, whose exchange code is shorter without it.
+template <int RS, int CS, bool CX, int W>
+__global__ __launch_bounds__(64 * W) void prrlu_cross_kernel(PrrluArgs a) {
+  if ((int)(blockIdx.x % a.stride) != (a.stride == 8 ? a.xcd : 0)) return;
+  if (a.skip && *a.skip) return;
+  prrlu_body<RS, CS, false, CX, W, true>(a, blockIdx.x / a.stride);
 }
 
 // Several products' factorisations in one launch.  Workgroup b runs on XCD
@@ -866,7 +873,7 @@ hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
     return do_launch((const void*)prrlu_kernel<RS, CS, true, CX, WAVES>, dim3(args.stride), NT, lds, args, s);
   }
   const void* fn = (const void*)prrlu_kernel<RSG, CS, false, CX, WG>;
-  const void* fn_cross = (const void*)prrlu_kernel<RSG, CS, false, CX, WG, true>;
+  const void* fn_cross = (const void*)prrlu_cross_kernel<RSG, CS, CX, WG>;
   const size_t lds = group_lds((size_t)(kCandWords + 128 * EW * CS) * 4);
   if (spread) {
     args.stride = 1;

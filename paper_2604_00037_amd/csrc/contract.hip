@@ -449,14 +449,17 @@ __global__ __launch_bounds__(256) void contract_lp_kernel(ContractArgs args) {
             store_bf16s<TL::EB>(&S.Bh[bc * LDH + bk0], bh_);
             store_bf16s<TL::EB>(&S.Bl[bc * LDH + bk0], bl_);
           } else {
+            // value e and EB/2 + e share a column and are consecutive in k
+            // (real rows 2 ct and 2 ct + 1): one 32-bit store per column
+            const int bk = kh + TL::template b_k<true, MAP_PACKED>(tid, 0);
 #pragma unroll
-            for (int e = 0; e < TL::EB; ++e) {
-              const int bk = kh + TL::template b_k<true, MAP_PACKED>(tid, e);
+            for (int e = 0; e < TL::EB / 2; ++e) {
               const int bc = TL::template b_col<true, MAP_PACKED>(tid, e);
-              const float fb = (float)bv[h][e];
-              const unsigned short hb = bf16_bits(fb);
-              S.Bh[bc * LDH + bk] = hb;
-              S.Bl[bc * LDH + bk] = bf16_bits(fb - bf16_value(hb));
+              const float f0 = (float)bv[h][e], f1 = (float)bv[h][TL::EB / 2 + e];
+              const unsigned short h0 = bf16_bits(f0), h1 = bf16_bits(f1);
+              const unsigned short l0 = bf16_bits(f0 - bf16_value(h0)), l1 = bf16_bits(f1 - bf16_value(h1));
+              *reinterpret_cast<unsigned int*>(&S.Bh[bc * LDH + bk]) = (unsigned int)h0 | ((unsigned int)h1 << 16);
+              *reinterpret_cast<unsigned int*>(&S.Bl[bc * LDH + bk]) = (unsigned int)l0 | ((unsigned int)l1 << 16);
             }
           }
         }

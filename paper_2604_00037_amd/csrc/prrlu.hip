@@ -191,6 +191,10 @@ constexpr int kMaxGroups = 128;
 // LDS of a cooperative launch: candidate words at [0, kCandWords) (three per
 // group), the winner's row after them.
 constexpr int kCandWords = 3 * kMaxGroups;
+// LDS words of a launch: the candidates, the winner's row (flagged-word
+// payloads) and, for real rows, that row divided by the pivot (doubles).
+template <int CS, bool CX>
+constexpr int lds_words() { return kCandWords + 128 * (CX ? 2 : 1) * CS + (CX ? 0 : 128 * CS); }
 // a step index no pivot step uses (steps stay below ACI_MAX_MATRIX)
 constexpr uint32_t kXccFlagOffset = 1536;
 
@@ -218,6 +222,10 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   const uint32_t fbase = a.epoch ? __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                  : a.flag_base;
   constexpr int EW = CX ? 2 : 1;   // doubles per entry
+  // real groups of eight waves (two per SIMD) share the division of the
+  // pivot row for the rows of B through LDS; with four waves the extra
+  // barrier costs more than the divisions it saves
+  constexpr bool kShareNorm = !CX && !SOLO && WAVES == 8;
   // only complex rows of 1024 columns (two rows per wave) need more than 64
   // groups; every other shape keeps P <= 64, one candidate per lane
   constexpr bool WIDE = CX && CS == 16;
@@ -243,6 +251,8 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   // loads (complex rows: 14.4 against 15.2 us per 1024 x 1024 pivot step)
   extern __shared__ __align__(16) uint32_t xs[];
   uint32_t* xrow = xs + kCandWords;
+  // real rows of B: the winner's row divided by the pivot, once per group
+  double* xrn = reinterpret_cast<double*>(xs + kCandWords + 128 * EW * CS);
 
   double s[RS][CS];
   double si[CX ? RS : 1][CX ? CS : 1];
@@ -515,6 +525,14 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
       // a failed wait anywhere in the group fails the whole group, so that
       // every lane takes the same path out
       failed = gfail != 0;
+      if (kShareNorm && needY) {
+        // the pivot row divided by the pivot, for the rows of B: one division
+        // per entry for the whole group instead of one per entry and wave
+        const int qq = widx & 0xffff;
+        const double pv = join64(xrow[2 * qq], xrow[2 * qq + 1]);
+        for (int j = threadIdx.x; j < n; j += NT) xrn[j] = join64(xrow[2 * j], xrow[2 * j + 1]) / pv;
+        __syncthreads();
+      }
 #pragma unroll
       for (int b = 0; b < CS; ++b) {
         const int j = lane + 64 * b;
@@ -673,8 +691,12 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
           const double a1 = ur * piv, a2 = um * pivi, b1 = um * piv, b2 = ur * pivi;
           u[b] = (a1 + a2) / den;
           ui[b] = (b1 - b2) / den;
-        } else {
+        } else if (!kShareNorm) {
           u[b] = u[b] / piv;
+        } else {
+          // divided once per group after the row arrived; columns past n
+          // are never read
+          u[b] = cv[b] ? xrn[lane + 64 * b] : 0.0;
         }
       }
 #pragma unroll
@@ -869,12 +891,12 @@ hipError_t launch_shape(const PrrluArgs& a, hipStream_t s) {
   if (a.P == 1) {
     // one group: 8 workgroups of which the one on the requested XCD runs
     args.stride = (a.cooperative || spread) ? 1 : 8;
-    const size_t lds = (size_t)(kCandWords + 128 * EW * CS) * 4;
+    const size_t lds = (size_t)lds_words<CS, CX>() * 4;
     return do_launch((const void*)prrlu_kernel<RS, CS, true, CX, WAVES>, dim3(args.stride), NT, lds, args, s);
   }
   const void* fn = (const void*)prrlu_kernel<RSG, CS, false, CX, WG>;
   const void* fn_cross = (const void*)prrlu_cross_kernel<RSG, CS, CX, WG>;
-  const size_t lds = group_lds((size_t)(kCandWords + 128 * EW * CS) * 4);
+  const size_t lds = group_lds((size_t)lds_words<CS, CX>() * 4);
   if (spread) {
     args.stride = 1;
     return do_launch(fn_cross, dim3(args.P), 64 * WG, lds, args, s);
@@ -1074,7 +1096,7 @@ hipError_t launch_batch_shape(const PrrluBatchArgs& bt, int slots, hipStream_t s
   constexpr bool W8 = eight_waves<RS, CS, CX>();
   constexpr int RSG = W8 ? RS / 2 : RS, WG = W8 ? 8 : WAVES;
   const void* fn = (const void*)prrlu_batch_kernel<RSG, CS, CX, WG>;
-  const size_t lds = group_lds((size_t)(kCandWords + 128 * EW * CS) * 4);
+  const size_t lds = group_lds((size_t)lds_words<CS, CX>() * 4);
   PrrluBatchArgs args = bt;
   void* kp[] = {&args};
   const hipError_t e = hipLaunchKernel(fn, dim3(8 * slots), dim3(64 * WG), kp, lds, s);

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-Readings of the printed algorithm (listed in the design doc, readings R1--R5):
+Readings of the printed algorithm:
 
 * the rank counter is advanced after every accepted pivot;
 * the Schur complement update is the textbook one,

@@ -194,7 +194,7 @@ constexpr int kCandWords = 3 * kMaxGroups;
 // LDS words of a launch: the candidates, the winner's row (flagged-word
 // payloads) and, for real rows, that row divided by the pivot (doubles).
 template <int CS, bool CX>
-constexpr int lds_words() { return kCandWords + 128 * (CX ? 2 : 1) * CS + (CX ? 0 : 128 * CS); }
+constexpr int lds_words() { return kCandWords + 2 * 128 * (CX ? 2 : 1) * CS; }
 // a step index no pivot step uses (steps stay below ACI_MAX_MATRIX)
 constexpr uint32_t kXccFlagOffset = 1536;
 
@@ -222,10 +222,10 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
   const uint32_t fbase = a.epoch ? __hip_atomic_load(a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                  : a.flag_base;
   constexpr int EW = CX ? 2 : 1;   // doubles per entry
-  // real groups of eight waves (two per SIMD) share the division of the
-  // pivot row for the rows of B through LDS; with four waves the extra
-  // barrier costs more than the divisions it saves
-  constexpr bool kShareNorm = !CX && !SOLO && WAVES == 8;
+  // real groups of eight waves (two per SIMD) and complex groups share the
+  // division of the pivot row for the rows of B through LDS; for real rows
+  // in four waves the extra barrier costs more than the divisions it saves
+  constexpr bool kShareNorm = !SOLO && (CX || WAVES == 8);
   // only complex rows of 1024 columns (two rows per wave) need more than 64
   // groups; every other shape keeps P <= 64, one candidate per lane
   constexpr bool WIDE = CX && CS == 16;
@@ -529,8 +529,19 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
         // the pivot row divided by the pivot, for the rows of B: one division
         // per entry for the whole group instead of one per entry and wave
         const int qq = widx & 0xffff;
-        const double pv = join64(xrow[2 * qq], xrow[2 * qq + 1]);
-        for (int j = threadIdx.x; j < n; j += NT) xrn[j] = join64(xrow[2 * j], xrow[2 * j + 1]) / pv;
+        if constexpr (CX) {
+          const double pr = join64(xrow[4 * qq], xrow[4 * qq + 1]), pm = join64(xrow[4 * qq + 2], xrow[4 * qq + 3]);
+          const double dd = cabs2(pr, pm);
+          for (int j = threadIdx.x; j < n; j += NT) {
+            const double ur = join64(xrow[4 * j], xrow[4 * j + 1]), um = join64(xrow[4 * j + 2], xrow[4 * j + 3]);
+            const double a1 = ur * pr, a2 = um * pm, b1 = um * pr, b2 = ur * pm;
+            xrn[2 * j] = (a1 + a2) / dd;
+            xrn[2 * j + 1] = (b1 - b2) / dd;
+          }
+        } else {
+          const double pv = join64(xrow[2 * qq], xrow[2 * qq + 1]);
+          for (int j = threadIdx.x; j < n; j += NT) xrn[j] = join64(xrow[2 * j], xrow[2 * j + 1]) / pv;
+        }
         __syncthreads();
       }
 #pragma unroll
@@ -686,7 +697,11 @@ __device__ __forceinline__ void prrlu_body(const PrrluArgs& a, const int w) {
       // row normalised by the pivot (Gauss-Jordan), so that B[:, J] = I
 #pragma unroll
       for (int b = 0; b < CS; ++b) {
-        if constexpr (CX) {
+        if constexpr (CX && kShareNorm) {
+          const int j = lane + 64 * b;
+          u[b] = cv[b] ? xrn[2 * j] : 0.0;
+          ui[b] = cv[b] ? xrn[2 * j + 1] : 0.0;
+        } else if constexpr (CX) {
           const double ur = u[b], um = ui[b];
           const double a1 = ur * piv, a2 = um * pivi, b1 = um * piv, b2 = ur * pivi;
           u[b] = (a1 + a2) / den;

@@ -133,7 +133,7 @@ def test_prrlu_bit_identical_to_oracle(m, n, kind, rule):
 
 
 @pytest.mark.parametrize("m,n,maxrank", [(3, 5, 5), (37, 61, 20), (128, 200, 128), (384, 384, 192),
-                                         (300, 512, 160), (1000, 700, 100)])
+                                         (300, 512, 160), (1000, 700, 100), (384, 300, 150), (480, 380, 190)])
 def test_right_factor_matches_triangular_solve(m, n, maxrank):
     M = _matrix("lowrank", m, n, seed=m + n)
     A, B, ref = cross_interpolate(M, 1e-7, maxrank, "right")
